@@ -1,0 +1,328 @@
+"""Seeded synthetic scenes shaped like the paper's tabletop workloads.
+
+The paper's objects are learned voxel models (Fig. 1 caption): a point cloud is
+discretised at a fixed resolution and a cube is placed at every occupied cell.
+The YCB meshes it uses are not available, so seeded voxel blobs of the same
+construction stand in for them. Everything here is random draws and geometry
+layout; renders are produced by a caller-supplied function.
+
+Conventions (shared by both sides of every test, stated once here):
+  * lengths in metres, 1 voxel = 1 cm cube, 8 unshared vertices and 12
+    triangles per voxel, counter-clockwise winding seen from outside;
+  * camera frame is +z forward, +x right, +y down; a pose is a 4x4 row-major
+    object-to-camera transform;
+  * hypothesis grids are described by ``GridSpec`` (centre pose, per-axis
+    half-extent and count, delta rotations); expanding a spec into poses is
+    the method's first step and is done by each side itself.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+VOXEL = 0.01  # voxel edge, metres
+
+# Corner k of a unit cube has coordinates ((k>>0)&1, (k>>1)&1, (k>>2)&1).
+# Each face is two triangles with outward normals (counter-clockwise from
+# outside).
+_CUBE_TRIS = np.array(
+    [
+        [0, 4, 6], [0, 6, 2],  # -x
+        [1, 3, 7], [1, 7, 5],  # +x
+        [0, 1, 5], [0, 5, 4],  # -y
+        [2, 6, 7], [2, 7, 3],  # +y
+        [0, 2, 3], [0, 3, 1],  # -z
+        [4, 5, 7], [4, 7, 6],  # +z
+    ],
+    dtype=np.int32,
+)
+_CUBE_CORNERS = np.array([[(k >> 0) & 1, (k >> 1) & 1, (k >> 2) & 1] for k in range(8)], dtype=np.float64)
+
+
+@dataclasses.dataclass
+class Camera:
+    """Pinhole intrinsics (pixels) and image size."""
+
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    H: int
+    W: int
+    z_near: float = 0.01
+
+
+@dataclasses.dataclass
+class GridSpec:
+    """A hypothesis grid around a centre pose.
+
+    Hypothesis n = r * (nx*ny*nz) + (ix*ny + iy)*nz + iz has translation
+    t_c + (dx[ix], dy[iy], dz[iz]) and rotation dR[r] @ R_c.  Per-axis offsets
+    are ``linspace(-h, h, n)`` (``cell_centres=False``; a single sample sits at
+    0) or the centres of n equal cells of [-h, h] (``cell_centres=True``, the
+    partition form of a coarse-to-fine schedule).  ``rotations`` holds explicit
+    delta rotations; when it is None, ``n_rot`` perturbations with angle at
+    most ``rot_max_angle`` are drawn from the counter-based generator (index 0
+    is the identity).
+    """
+
+    center: np.ndarray
+    half_extent: Tuple[float, float, float]
+    count: Tuple[int, int, int]
+    cell_centres: bool = False
+    rotations: Optional[np.ndarray] = None
+    n_rot: int = 1
+    rot_max_angle: float = 0.0
+
+    @property
+    def n_trans(self) -> int:
+        return int(self.count[0]) * int(self.count[1]) * int(self.count[2])
+
+    @property
+    def n_rotations(self) -> int:
+        return int(self.rotations.shape[0]) if self.rotations is not None else int(self.n_rot)
+
+    @property
+    def N(self) -> int:
+        return self.n_trans * self.n_rotations
+
+
+@dataclasses.dataclass
+class ScoreParams:
+    sigma: float
+    p_out: float
+    outlier_volume: float
+    window: int
+    norm_M: float = 0.0  # <= 0 means H*W
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    verts: np.ndarray  # [V,3] float64, object frame
+    tris: np.ndarray  # [T,3] int32
+    camera: Camera
+    true_pose: np.ndarray  # [4,4]
+    grid: GridSpec
+    score: ScoreParams
+    noise: dict  # gauss [H,W], outlier_mask [H,W] bool, outlier_depth [H,W]
+    occluder: Optional[Tuple[np.ndarray, np.ndarray, np.ndarray]] = None  # verts, tris, pose
+    occluder_target: Optional[float] = None
+    statics: List[Tuple[np.ndarray, np.ndarray, np.ndarray]] = dataclasses.field(default_factory=list)
+    seeds: dict = dataclasses.field(default_factory=dict)
+
+
+def pose_matrix(R: np.ndarray, t: Sequence[float]) -> np.ndarray:
+    P = np.eye(4)
+    P[:3, :3] = R
+    P[:3, 3] = t
+    return P
+
+
+def voxel_blob(n_vox: int, rng: np.random.Generator, radius: Optional[float] = None) -> np.ndarray:
+    """Centres of ``n_vox`` distinct 1 cm lattice cells inside a ball.
+
+    The ball radius is max(10 cm, 1 cm * (6 n / 4 pi)^(1/3)), which keeps the
+    occupied fraction at most one half.  Returns [n_vox, 3] float64 centres.
+    """
+    if radius is None:
+        radius = max(0.10, VOXEL * (6.0 * n_vox / (4.0 * np.pi)) ** (1.0 / 3.0))
+    m = int(np.floor(radius / VOXEL))
+    ax = np.arange(-m, m + 1)
+    g = np.stack(np.meshgrid(ax, ax, ax, indexing="ij"), -1).reshape(-1, 3)
+    inside = g[(g.astype(np.float64) ** 2).sum(1) * VOXEL**2 <= radius**2]
+    if n_vox > inside.shape[0]:
+        raise ValueError("ball too small for the requested voxel count")
+    pick = rng.choice(inside.shape[0], size=n_vox, replace=False)
+    return inside[np.sort(pick)].astype(np.float64) * VOXEL
+
+
+def box_mesh(size: Sequence[float], centre: Sequence[float] = (0.0, 0.0, 0.0)) -> Tuple[np.ndarray, np.ndarray]:
+    """Axis-aligned box of the given edge lengths: 8 vertices, 12 triangles."""
+    size = np.asarray(size, dtype=np.float64)
+    v = (_CUBE_CORNERS - 0.5) * size + np.asarray(centre, dtype=np.float64)
+    return v, _CUBE_TRIS.copy()
+
+
+def voxel_mesh(centres: np.ndarray, edge: float = VOXEL) -> Tuple[np.ndarray, np.ndarray]:
+    """One cube per voxel centre; vertices are not shared between voxels."""
+    centres = np.asarray(centres, dtype=np.float64)
+    n = centres.shape[0]
+    verts = centres[:, None, :] + (_CUBE_CORNERS[None, :, :] - 0.5) * edge
+    tris = _CUBE_TRIS[None, :, :] + 8 * np.arange(n, dtype=np.int32)[:, None, None]
+    return verts.reshape(-1, 3), tris.reshape(-1, 3).astype(np.int32)
+
+
+def shoemake_rotations(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Uniform random rotations by Shoemake's method (Graphics Gems III)."""
+    u = rng.random((n, 3))
+    a, b = np.sqrt(1.0 - u[:, 0]), np.sqrt(u[:, 0])
+    qx, qy = a * np.sin(2 * np.pi * u[:, 1]), a * np.cos(2 * np.pi * u[:, 1])
+    qz, qw = b * np.sin(2 * np.pi * u[:, 2]), b * np.cos(2 * np.pi * u[:, 2])
+    R = np.empty((n, 3, 3))
+    R[:, 0, 0] = 1 - 2 * (qy * qy + qz * qz)
+    R[:, 0, 1] = 2 * (qx * qy - qz * qw)
+    R[:, 0, 2] = 2 * (qx * qz + qy * qw)
+    R[:, 1, 0] = 2 * (qx * qy + qz * qw)
+    R[:, 1, 1] = 1 - 2 * (qx * qx + qz * qz)
+    R[:, 1, 2] = 2 * (qy * qz - qx * qw)
+    R[:, 2, 0] = 2 * (qx * qz - qy * qw)
+    R[:, 2, 1] = 2 * (qy * qz + qx * qw)
+    R[:, 2, 2] = 1 - 2 * (qx * qx + qy * qy)
+    return R
+
+
+def observation_noise(H: int, W: int, rng: np.random.Generator, depth_noise: float, outlier_frac: float,
+                      depth_range: Tuple[float, float] = (0.3, 1.5)) -> dict:
+    """Per-pixel draws for the synthetic observation process.
+
+    Every surface pixel gets N(0, depth_noise) added to its depth; then every
+    pixel, with probability ``outlier_frac``, is replaced by a depth drawn
+    uniformly from ``depth_range``.
+    """
+    return {
+        "gauss": rng.normal(0.0, depth_noise, size=(H, W)),
+        "outlier_mask": rng.random((H, W)) < outlier_frac,
+        "outlier_depth": rng.uniform(depth_range[0], depth_range[1], size=(H, W)),
+    }
+
+
+RenderFn = Callable[[List[Tuple[np.ndarray, np.ndarray, np.ndarray]], Camera], np.ndarray]
+
+
+def assemble_observed_depth(render: RenderFn, wl: "Workload") -> np.ndarray:
+    """Observed depth image [H,W] for a workload.
+
+    ``render(objects, camera)`` must return the depth image [H,W] of the list
+    of (verts, tris, pose) objects (0 where empty).  The object at its true
+    pose, the static objects and the occluder (if any) are rendered together;
+    surface pixels get the Gaussian draw added; outlier pixels are replaced.
+    """
+    objs = [(wl.verts, wl.tris, wl.true_pose)] + list(wl.statics)
+    if wl.occluder is not None:
+        objs.append(wl.occluder)
+    z = np.asarray(render(objs, wl.camera), dtype=np.float64)
+    z = np.where(z > 0, z + wl.noise["gauss"], 0.0)
+    return np.where(wl.noise["outlier_mask"], wl.noise["outlier_depth"], z)
+
+
+def place_occluder(render: RenderFn, verts: np.ndarray, tris: np.ndarray, pose: np.ndarray, cam: Camera,
+                   rng: np.random.Generator, target: float, tol: float, front_z: float = 0.6,
+                   thickness: float = 0.06, side: float = 0.2) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Slide a box occluder across the object until it hides ``target`` of it.
+
+    The box (``side`` x ``side`` x ``thickness``, front face at ``front_z``) is
+    turned about the optical axis by a seeded angle and moved along a seeded
+    image direction; bisection on the offset stops once the covered fraction of
+    the object's pixels is within ``tol`` of ``target``.
+    """
+    bv, bt = box_mesh((side, side, thickness))
+    theta = rng.uniform(0, 2 * np.pi)
+    psi = theta + rng.uniform(0.2, 0.6)
+    c, s = np.cos(psi), np.sin(psi)
+    Rz = np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+    obj = np.asarray(render([(verts, tris, pose)], cam)) > 0
+    n_obj = int(obj.sum())
+    if n_obj == 0:
+        raise ValueError("object not visible")
+    axis_pt = pose[:3, 3] * ((front_z + thickness / 2) / pose[2, 3])
+    dirv = np.array([np.cos(theta), np.sin(theta), 0.0])
+
+    def occ_pose(off):
+        return pose_matrix(Rz, axis_pt + off * dirv)
+
+    def frac(off):
+        occ = np.asarray(render([(bv, bt, occ_pose(off))], cam)) > 0
+        return float((occ & obj).sum()) / n_obj
+
+    lo, hi = 0.0, 0.5  # frac(lo) ~ 1, frac(hi) = 0
+    for _ in range(80):
+        mid = 0.5 * (lo + hi)
+        f = frac(mid)
+        if abs(f - target) <= tol:
+            return bv, bt, occ_pose(mid)
+        if f > target:
+            lo = mid
+        else:
+            hi = mid
+    raise RuntimeError("occluder bisection did not reach the target coverage")
+
+
+def _config0() -> Workload:
+    k = 0
+    rs, ro = np.random.default_rng(1000 + k), np.random.default_rng(2000 + k)
+    verts, tris = voxel_mesh(voxel_blob(500, rs, radius=0.10))
+    cam = Camera(60.0, 60.0, 32.0, 24.0, 48, 64)
+    true_pose = pose_matrix(np.eye(3), (0.0, 0.0, 0.8))
+    grid = GridSpec(center=true_pose.copy(), half_extent=(0.05, 0.05, 0.05), count=(8, 8, 4))
+    noise = observation_noise(cam.H, cam.W, ro, 0.002, 0.05)
+    return Workload("plain-small 64x48 6k tris 256 hyp", verts, tris, cam, true_pose, grid,
+                    ScoreParams(0.005, 0.01, 1.0, 3), noise,
+                    seeds={"scene": 1000 + k, "obs": 2000 + k, "hyp": 3000 + k, "sampler": 4000 + k})
+
+
+def _config1() -> Workload:
+    k = 1
+    rs, ro, rh = (np.random.default_rng(s + k) for s in (1000, 2000, 3000))
+    verts, tris = voxel_mesh(voxel_blob(2000, rs))
+    cam = Camera(150.0, 150.0, 80.0, 60.0, 120, 160)
+    rots = shoemake_rotations(50, rh)
+    centre = pose_matrix(np.eye(3), (0.0, 0.0, 0.8))
+    true_pose = pose_matrix(rots[0], (0.0, 0.0, 0.8))
+    grid = GridSpec(center=centre, half_extent=(0.04, 0.04, 0.0), count=(10, 10, 1), rotations=rots)
+    noise = observation_noise(cam.H, cam.W, ro, 0.002, 0.03)
+    wl = Workload("plain-paper-scale 160x120 24k tris 5000 hyp", verts, tris, cam, true_pose, grid,
+                  ScoreParams(0.003, 0.01, 1.0, 5), noise, occluder_target=0.20,
+                  seeds={"scene": 1000 + k, "obs": 2000 + k, "hyp": 3000 + k, "sampler": 4000 + k})
+    wl.seeds["occluder_rng"] = ro  # the occluder's draws continue the observation stream
+    return wl
+
+
+def make_config(k: int, render: Optional[RenderFn] = None) -> Workload:
+    """Workload k (0: 64x48/6k tris/256 hypotheses; 1: 160x120/24k tris/5000).
+
+    When the workload has an occluder, ``render`` is needed to place it.
+    """
+    if k == 0:
+        return _config0()
+    if k == 1:
+        wl = _config1()
+        ro = wl.seeds.pop("occluder_rng")
+        if render is not None:
+            wl.occluder = place_occluder(render, wl.verts, wl.tris, wl.true_pose, wl.camera, ro,
+                                         target=wl.occluder_target, tol=0.005)
+        return wl
+    raise ValueError(f"unknown workload {k}")
+
+
+def tiny_scene(rng: np.random.Generator, n_vox: int, H: int, W: int, f: float = 40.0,
+               depth: float = 0.5) -> Tuple[np.ndarray, np.ndarray, Camera]:
+    """A few-voxel object and a small camera for brute-force checks."""
+    centres = voxel_blob(n_vox, rng, radius=0.04)
+    verts, tris = voxel_mesh(centres)
+    return verts, tris, Camera(f, f, W / 2.0 + 0.13, H / 2.0 - 0.21, H, W)
+
+
+def random_poses(rng: np.random.Generator, n: int, depth: float, spread: float) -> np.ndarray:
+    """Uniform rotations with translations near (0, 0, depth)."""
+    R = shoemake_rotations(n, rng)
+    P = np.tile(np.eye(4), (n, 1, 1))
+    P[:, :3, :3] = R
+    P[:, :3, 3] = rng.uniform(-spread, spread, size=(n, 3)) + np.array([0.0, 0.0, depth])
+    return P
+
+
+def random_scene_batch(rng: np.random.Generator, n_scenes: int):
+    """Scene shapes for the many-scenes batch (object counts, voxel counts, sizes, N)."""
+    sizes = [(120, 160), (180, 240), (240, 320)]
+    out = []
+    for _ in range(n_scenes):
+        n_obj = int(np.round(np.exp(rng.uniform(np.log(1), np.log(8)))))
+        vox = [int(np.round(np.exp(rng.uniform(np.log(500), np.log(8000))))) for _ in range(n_obj)]
+        H, W = sizes[rng.integers(0, 3)]
+        N = int(np.round(np.exp(rng.uniform(np.log(1000), np.log(20000)))))
+        out.append({"n_obj": n_obj, "voxels": vox, "H": H, "W": W, "N": N})
+    return out
