@@ -1,0 +1,219 @@
+"""Throughput of the batched render-and-score hot path on one MI355X.
+
+One step = one pass of the hot path over one batch of pose hypotheses of the
+paper-scale single-object workload (2000 voxels = 24,000 triangles, 160x120
+image, fx = fy = 150, 5000 hypotheses = 10x10 translations x 50 rotations,
+5x5 window, sigma 3 mm, p_out 0.01):
+  enumerate the hypothesis grid -> fused render + windowed likelihood +
+  adjoint (d logL / d(pose, sigma, p_out)) -> normalise and draw samples.
+Inputs are resident in device memory before timing starts.  The line also
+reports the forward-only fused path, the plain split path (render point
+images to memory, then score them; with and without the adjoint), the
+roofline position of the fused kernel, and the FP64 CPU oracle on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pose hypotheses scored/s (render+logL) at 160x120, 24k tris; fwd+adjoint vs plain"
+
+# Algorithmic work per hypothesis in FP32 lane-operations (a transcendental
+# counts 4): 17 per vertex, 12 per triangle tested, 27 per camera-facing
+# triangle set up, 10 per covered fragment, 12 per (observed, rendered) pair
+# in a window, 6 per observed pixel that sees a rendered point; the adjoint
+# adds 10 per pair and 30 per rendered pixel.  The counts are the oracle's
+# counters on this workload (recomputed live by the CPU-baseline leg).
+COST = {"vert": 17, "tri": 12, "front": 27, "frag": 10, "pair": 12, "obs": 6, "adj_pair": 10, "adj_rpix": 30}
+# oracle counters, mean per hypothesis over all 5000 hypotheses of this workload
+DEFAULT_COUNTS = {"vert": 16000.0, "tri": 24000.0, "front": 11900.0, "frag": 10490.0, "pair": 24800.0,
+                  "obs": 1185.0, "rpix": 1178.0}
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # FP32 lane-ops/s, non-packed: 39.3 T
+
+
+def lane_ops(c, adjoint=True):
+    f = (COST["vert"] * c["vert"] + COST["tri"] * c["tri"] + COST["front"] * c["front"] + COST["frag"] * c["frag"]
+         + COST["pair"] * c["pair"] + COST["obs"] * c["obs"])
+    if adjoint:
+        f += COST["adj_pair"] * c["pair"] + COST["adj_rpix"] * c["rpix"]
+    return f
+
+
+def build_inputs(b3d, torch):
+    """Workload inputs, built on the GPU with the library itself."""
+    from workloads import assemble_observed_depth, make_config
+
+    K = None
+
+    def render_depth(objs, cam):
+        Kc = b3d.intrinsics_of(cam)
+        z = None
+        for k, (v, t, P) in enumerate(objs):
+            m = b3d.Mesh(v, t)
+            xyz, _ = b3d.render_batch(m, torch.as_tensor(np.asarray(P, np.float32)[None], device="cuda"), Kc, False)
+            zk = xyz[0, ..., 2].cpu().numpy().astype(np.float64)
+            z = zk if z is None else np.where((zk > 0) & ((z == 0) | (zk < z)), zk, z)
+        return z
+
+    wl = make_config(1, render=render_depth)
+    K = b3d.intrinsics_of(wl.camera)
+    depth = assemble_observed_depth(render_depth, wl)
+    obs = b3d.unproject(torch.as_tensor(depth, dtype=torch.float32, device="cuda"), K)
+    return wl, K, obs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--samples", type=int, default=64, help="draws per step")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (hypotheses would shard "
+              "across GPUs with one small all-reduce per stage; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2312_08715_amd as b3d
+
+    torch.cuda.set_device(0)
+    wl, K, obs = build_inputs(b3d, torch)
+    s = wl.score
+    p = b3d.score_params(s.sigma, s.p_out, s.outlier_volume, s.window)
+    mesh = b3d.Mesh(wl.verts, wl.tris)
+    scene = b3d.Scene(mesh, K, p)
+    scene.set_observed(obs)
+    grid, rots = b3d.grid_of(wl.grid)
+    N = b3d.grid_size(grid)
+    seed = wl.seeds["sampler"]
+    stream = torch.cuda.current_stream()
+
+    poses = torch.empty((N, 4, 4), dtype=torch.float32, device="cuda")
+    kev = []
+
+    def step(timed_kernel=False, grad=True):
+        P = b3d.enumerate_grid(grid, seed=seed)
+        if timed_kernel:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        out = b3d.render_score(scene, P, grad=grad)
+        if timed_kernel:
+            e1.record(stream)
+            kev.append((e0, e1))
+        logL = out[0] if grad else out
+        w, idx, lw = b3d.sample(logL, args.samples, seed)
+        return idx
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    # headline: fused forward + adjoint
+    kev.clear()
+    t_step = timed(lambda: step(timed_kernel=True), args.steps, args.warmup)
+    kev_t = [a.elapsed_time(b) for a, b in kev[args.warmup:]]
+    t_kernel = float(np.mean(kev_t)) / 1e3
+    # forward only
+    t_fwd = timed(lambda: step(grad=False), args.steps, args.warmup)
+
+    # plain split path: point images through device memory
+    P = b3d.enumerate_grid(grid, seed=seed)
+
+    def split(adj):
+        xyz, tri = b3d.render_batch(mesh, P, K, want_tri=adj)
+        L = b3d.score(obs, xyz, p)
+        if adj:
+            dr, ds, dp = b3d.score_backward(obs, xyz, p)
+            b3d.render_backward(mesh, P, K, tri, dr)
+        return L
+
+    t_split = timed(lambda: split(False), max(3, args.steps // 4), 1)
+    t_split_adj = timed(lambda: split(True), max(3, args.steps // 4), 1)
+
+    counts = dict(DEFAULT_COUNTS)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu, counts = cpu_baseline(wl, obs.cpu().numpy().astype(np.float64), args.cpu_seconds)
+
+    ops = lane_ops(counts, adjoint=True) * N
+    achieved = ops / t_kernel / 1e12
+    line = {
+        "metric": METRIC,
+        "value": N / t_step,
+        "unit": "hypotheses/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "paper-scale single object: 2000 voxels (24k tris), 160x120, 5000 hypotheses "
+                               "(10x10 translations x 50 rotations), 5x5 window, fused fwd+adjoint + sampling",
+                   "hypotheses": N, "image": "160x120", "triangles": int(wl.tris.shape[0]), "window": s.window,
+                   "samples_per_step": args.samples},
+        "roofline": {"bound": "alu", "kernel": "k_render_score<true>", "achieved": achieved,
+                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s (FP32 lane-ops)", "frac": achieved / VALU_PEAK_TOPS,
+                     "traffic": None, "kernel_ms": t_kernel * 1e3,
+                     "ops_per_hypothesis": lane_ops(counts, adjoint=True)},
+        "fwd_only": {"value": N / t_fwd, "ms_per_step": t_fwd * 1e3},
+        "plain_split": {"value": N / t_split, "ms_per_step": t_split * 1e3,
+                        "note": "render_batch -> score, point images in HBM"},
+        "plain_split_fwd_adjoint": {"value": N / t_split_adj, "ms_per_step": t_split_adj * 1e3},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(wl, obs64, seconds):
+    """The FP64 oracle (render, score, both adjoints) on hypotheses of the same
+    workload, in chunks, until about `seconds` of CPU time; all host threads."""
+    import oracle
+
+    s = wl.score
+    P = oracle.enumerate_grid(wl.grid, seed=wl.seeds["hyp"])
+    done, t0 = 0, time.perf_counter()
+    cnt_sum = np.zeros(oracle.NC)
+    chunk = 64
+    while done < P.shape[0] and time.perf_counter() - t0 < seconds:
+        Q = P[done:done + chunk]
+        d, ids, c = oracle.render([(wl.verts, wl.tris, Q)], wl.camera, counters=True)
+        xyz = oracle.unproject(d, wl.camera)
+        L, l1, c2 = oracle.score(obs64, xyz, s.sigma, s.p_out, s.outlier_volume, s.window, counters=True)
+        dr, ds, dp = oracle.score_grad(obs64, xyz, s.sigma, s.p_out, s.outlier_volume, s.window)
+        oracle.render_grad(wl.verts, wl.tris, Q, wl.camera, ids, d, dr)
+        cnt_sum += (c + c2).sum(0)
+        done += Q.shape[0]
+    dt = time.perf_counter() - t0
+    m = cnt_sum / done
+    counts = {"vert": m[oracle.C_VERT], "tri": m[oracle.C_TRI], "front": m[oracle.C_FRONT], "frag": m[oracle.C_FRAG],
+              "pair": m[oracle.C_PAIR], "obs": m[oracle.C_OBS_ACTIVE], "rpix": m[oracle.C_RPIX]}
+    return ({"value": done / dt, "unit": "hypotheses/s", "cores": oracle.num_threads(), "kind": "oracle",
+             "sample": f"first {done} of {P.shape[0]} hypotheses, render+score+adjoint in FP64"}, counts)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,256 @@
+/*
+ * b3d — batched render-and-score for coarse-to-fine pose inference on
+ * AMD Instinct MI355X (gfx950), after Bayes3D (Gothoskar et al., arXiv
+ * 2312.08715).
+ *
+ * The library renders a voxel-mesh object under many pose hypotheses at low
+ * resolution, scores each rendered point image against one observed point
+ * image with the paper's robust windowed likelihood, normalises the scores
+ * and samples from them, and differentiates the score with respect to each
+ * hypothesis's pose and the noise parameters.
+ *
+ * Conventions shared by every entry point
+ *   Units        metres and radians.
+ *   Camera       pinhole, +z forward, +x right, +y down.  Pixel (r, c) has
+ *                its centre at (c + 1/2, r + 1/2) and its ray is
+ *                d = ((c + 1/2 - cx)/fx, (r + 1/2 - cy)/fy, 1).  Depth is
+ *                camera z (not range).
+ *   Pose         float[16], row-major 4x4 object-to-camera transform
+ *                [R t; 0 0 0 1].  A pose batch is float[N][16].
+ *   Tangent      a pose update (dt, dw) means R <- exp([dw]x) R, t <- t + dt.
+ *   Point image  float[H][W][3] camera-frame xyz; a pixel is empty / invalid
+ *                iff its z is not > 0.
+ *   Memory       pointers documented "device" must be device memory on the
+ *                current HIP device; "host" pointers are read before the
+ *                call returns.  The caller owns every buffer it passes; the
+ *                library owns mesh and scene handles.  No entry point marked
+ *                "stream-ordered" allocates, frees or synchronises: it only
+ *                enqueues work on `stream` (a hipStream_t; NULL = the null
+ *                stream) and results are valid once the stream reaches them.
+ *   Errors       every entry point validates its arguments before enqueuing
+ *                anything and returns a b3d_status; on failure
+ *                b3d_last_error() (per thread) describes the problem.  An
+ *                asynchronous fault surfaces as B3D_EHIP at a later call.
+ *   N == 0       is a no-op that returns B3D_OK.
+ */
+#ifndef B3D_H
+#define B3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum b3d_status {
+  B3D_OK = 0,
+  B3D_EINVAL = -1,  /* bad argument (null pointer, out-of-range value) */
+  B3D_ENOMEM = -2,  /* device allocation failed (set-up calls only) */
+  B3D_EHIP = -3,    /* the HIP runtime reported an error */
+  B3D_ESHAPE = -4,  /* inconsistent sizes, or a size beyond a stated limit */
+  B3D_ENOTSUP = -5  /* a combination the library does not implement */
+} b3d_status;
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char* b3d_last_error(void);
+/* Library version string. */
+const char* b3d_version(void);
+
+/* Pinhole intrinsics and image size.  A triangle with a vertex at camera z
+ * <= z_near is not drawn (no clipping).  1 <= H, W <= 4096. */
+typedef struct b3d_intrinsics {
+  float fx, fy, cx, cy, z_near;
+  int32_t H, W;
+} b3d_intrinsics;
+
+/* Parameters of the robust likelihood, eq. (1) of the paper truncated to a
+ * window (Sec. III-B, scoring strategy):
+ *   l_i    = ln( p_out/V + (1 - p_out)/M * sum_{j in W(i), z_j > 0} N3(q~_i; q_j, sigma) )
+ *   logL_n = sum over observed pixels i with z~_i > 0 of l_i
+ * N3 = isotropic 3-D Gaussian density with standard deviation `sigma`;
+ * W(i) = the window x window square centred on i, clipped to the image;
+ * V = outlier_volume; M = norm_M, or H*W when norm_M <= 0.
+ * Valid: sigma > 0, 0 < p_out <= 1, outlier_volume > 0, window odd, 1..15. */
+typedef struct b3d_score_params {
+  float sigma, p_out, outlier_volume, norm_M;
+  int32_t window;
+} b3d_score_params;
+
+/* ---- meshes ------------------------------------------------------------ */
+
+typedef struct b3d_mesh b3d_mesh;
+
+/* Upload a triangle mesh (the learned voxel model of Fig. 1: one cube per
+ * occupied cell).  verts: host float[V][3], object frame; tris: host
+ * int32[T][3], counter-clockwise seen from outside; triangle id = row.
+ * 1 <= V, 1 <= T <= 2^24.  Allocates device memory (not stream-ordered;
+ * synchronises the current device).  *out receives the handle. */
+b3d_status b3d_mesh_create(const float* verts, int32_t V, const int32_t* tris, int32_t T, b3d_mesh** out);
+/* Free a mesh (synchronises the current device).  NULL is accepted. */
+b3d_status b3d_mesh_destroy(b3d_mesh* mesh);
+/* Vertex count, triangle count and number of vertex clusters the device
+ * layout uses (any pointer may be NULL). */
+b3d_status b3d_mesh_info(const b3d_mesh* mesh, int32_t* V, int32_t* T, int32_t* n_clusters);
+
+/* ---- the split path: point images in device memory ---------------------- */
+
+/* Depth to point image (Sec. III-A (iii): the render is turned into a point
+ * cloud in the camera frame): xyz = z d for z > 0, else 0.
+ * depth: device float[B][H][W]; xyz: device float[B][H][W][3].
+ * Stream-ordered. */
+b3d_status b3d_unproject(const float* depth, int32_t B, const b3d_intrinsics* K, float* xyz, void* stream);
+
+/* Render N hypotheses of one mesh (Alg. 1, DepthRenderer; Sec. III-A (iii)).
+ * A pixel is covered by a camera-facing triangle when its centre lies inside
+ * or on the projected triangle; it keeps the nearest surface, equal depths
+ * going to the smaller triangle id; its point is the intersection of its ray
+ * with that triangle's plane.
+ * poses: device float[N][16]; xyz_out: device float[N][H][W][3] (every
+ * element written; empty = 0); tri_out: device int32[N][H][W] (empty = -1)
+ * or NULL.  Stream-ordered. */
+b3d_status b3d_render_batch(const b3d_mesh* mesh, const float* poses, int32_t N, const b3d_intrinsics* K,
+                            float* xyz_out, int32_t* tri_out, void* stream);
+
+/* Windowed robust likelihood (eq. (1) with the window of Sec. III-B).
+ * observed: device float[H][W][3]; rendered: device float[N][H][W][3];
+ * logL_out: device float[N].  Stream-ordered. */
+b3d_status b3d_score(const float* observed, const float* rendered, int32_t N, int32_t H, int32_t W,
+                     const b3d_score_params* p, float* logL_out, void* stream);
+
+/* Adjoint of b3d_score.  With a = p_out/V, b = (1-p_out)/M, K_ij =
+ * N3(q~_i; q_j, sigma), D_ij = |q~_i - q_j|^2, S_i = sum_j K_ij and
+ * L_i = a + b S_i, for each hypothesis n and upstream gradient g = dlogL[n]:
+ *   d_rendered[n][j] = g sum_{i: j in W(i)} (b/L_i) K_ij (q~_i - q_j)/sigma^2
+ *   d_sigma[n]       = g sum_i (b/L_i) sum_j K_ij (D_ij/sigma^3 - 3/sigma)
+ *   d_pout[n]        = g sum_i (1/V - S_i/M)/L_i
+ * dlogL: device float[N] or NULL (= all ones).  d_rendered: device
+ * float[N][H][W][3] (every element written) or NULL; d_sigma, d_pout:
+ * device float[N] or NULL.  Stream-ordered. */
+b3d_status b3d_score_backward(const float* observed, const float* rendered, int32_t N, int32_t H, int32_t W,
+                              const b3d_score_params* p, const float* dlogL, float* d_rendered, float* d_sigma,
+                              float* d_pout, void* stream);
+
+/* Pose adjoint of the render with visibility held fixed: the triangle of
+ * each pixel (tri) is kept and its depth z = (n.c0)/(n.d) is differentiated
+ * under the tangent update, giving dz/d(dt) = n/(n.d) and
+ * dz/d(dw) = n x (t - q)/(n.d) with q = z d.  With g_j = d_rendered[j] . d_j:
+ *   d_pose[n] = sum_j g_j (dz_j/d(dt), dz_j/d(dw))   (float[6] = dt, dw)
+ * tri: device int32[N][H][W] from b3d_render_batch; d_rendered: device
+ * float[N][H][W][3]; d_pose: device float[N][6] (overwritten).
+ * Stream-ordered. */
+b3d_status b3d_render_backward(const b3d_mesh* mesh, const float* poses, int32_t N, const b3d_intrinsics* K,
+                               const int32_t* tri, const float* d_rendered, float* d_pose, void* stream);
+
+/* ---- the fused path: render and score without point images in memory --- */
+
+typedef struct b3d_scene b3d_scene;
+
+/* A scene: the moving object's mesh, the camera, the likelihood parameters,
+ * an optional static background (other objects at fixed poses) and the
+ * observed point image.  The scene keeps `mesh` by reference (it must
+ * outlive the scene).  Allocates device memory (not stream-ordered). */
+b3d_status b3d_scene_create(const b3d_mesh* mesh, const b3d_intrinsics* K, const b3d_score_params* p,
+                            b3d_scene** out);
+b3d_status b3d_scene_destroy(b3d_scene* scene);
+
+/* Static objects rendered once into the scene's background depth buffer;
+ * the moving object is composited over it by nearest depth.  Background
+ * triangle ids are numbered after the moving mesh's (object k's ids start at
+ * T_moving + sum of earlier static triangle counts).  meshes: host array of
+ * n handles; poses: host float[n][16].  n = 0 clears the background.
+ * Stream-ordered; call b3d_scene_set_observed afterwards. */
+b3d_status b3d_scene_set_background(b3d_scene* scene, const b3d_mesh* const* meshes, const float* poses, int32_t n,
+                                    void* stream);
+
+/* Point the scene at an observed image (device float[H][W][3], caller-owned,
+ * read by later b3d_render_score calls; keep it alive and unchanged while
+ * they run) and precompute the per-pixel terms of the background.  Call it
+ * again whenever the image's contents or the background change.
+ * Stream-ordered. */
+b3d_status b3d_scene_set_observed(b3d_scene* scene, const float* observed, void* stream);
+
+/* Fused render + windowed likelihood for N hypotheses of the scene's moving
+ * object; equal (to FP32 rounding) to b3d_score over b3d_render_batch's point
+ * images composited over the background.
+ * poses: device float[N][16]; logL_out: device float[N].
+ * grad_out: device float[N][8] or NULL; when given it receives
+ *   (d logL_n/d dt [3], d logL_n/d dw [3], d logL_n/d sigma, d logL_n/d p_out)
+ * with visibility held fixed (the adjoint of b3d_score_backward followed by
+ * b3d_render_backward).  Stream-ordered. */
+b3d_status b3d_render_score(const b3d_scene* scene, const float* poses, int32_t N, float* logL_out, float* grad_out,
+                            void* stream);
+
+/* ---- hypotheses, normalisation, sampling, coarse-to-fine --------------- */
+
+/* A hypothesis grid around a centre pose (the cells of one stage of a
+ * coarse-to-fine schedule, Sec. III-B).  Hypothesis
+ *   n = r*(nx*ny*nz) + (ix*ny + iy)*nz + iz
+ * has translation t_c + (ox[ix], oy[iy], oz[iz]) and rotation dR_r R_c.
+ * Offsets along an axis of half-extent h with n samples are
+ * linspace(-h, h, n) (cell_centres = 0; n = 1 gives 0) or the centres of n
+ * equal cells of [-h, h] (cell_centres = 1, a partition).  Rotations:
+ * rotations (device float[n_rot][9], row-major) if not NULL, else generated
+ * perturbations: r = 0 is the identity, r >= 1 has its axis uniform on the
+ * sphere and its angle uniform in [0, rot_max_angle], from Philox4x32-10
+ * counter (r, stage, 0, 1) and key = seed. */
+typedef struct b3d_grid {
+  float center[16];
+  float half_extent[3];
+  int32_t count[3];
+  int32_t cell_centres;
+  int32_t n_rot;
+  float rot_max_angle;
+  const float* rotations;
+} b3d_grid;
+
+/* Number of hypotheses of a grid (0 if the grid is invalid). */
+int64_t b3d_grid_size(const b3d_grid* g);
+
+/* Expand a grid into poses: device float[b3d_grid_size(g)][16].
+ * Stream-ordered. */
+b3d_status b3d_enumerate(const b3d_grid* g, uint64_t seed, int32_t stage, float* poses_out, void* stream);
+
+/* Normalise and sample (Sec. III-B: a cell is drawn with probability
+ * proportional to its score).  logL holds P segments of N scores each
+ * (device float[P][N]).  Within segment p, w_n = exp(logL_n - LSE) and draw
+ * k (0 <= k < K) is argmax_n logL_n + G, G = -ln(-ln u), with u the odd
+ * multiple of 2^-24 built from the top 23 bits of word 0 of Philox4x32-10 at
+ * counter (n, k0 + p*K + k, stage, 0) and key = seed (low word first); ties
+ * go to the lowest n.  weights_out: device float[P][N] or NULL; idx_out:
+ * device int32[P][K]; logw_out: device float[P][K] (log weight of each draw)
+ * or NULL.  1 <= K <= 4096.  Stream-ordered. */
+b3d_status b3d_sample(const float* logL, int32_t P, int32_t N, int32_t K, uint64_t seed, uint32_t stage, uint32_t k0,
+                      float* weights_out, int32_t* idx_out, float* logw_out, void* stream);
+
+#define B3D_MAX_STAGES 8
+
+/* A coarse-to-fine schedule: stage t enumerates stages[t] (its center is
+ * ignored) around each particle's current pose. */
+typedef struct b3d_schedule {
+  int32_t n_stages;
+  b3d_grid stages[B3D_MAX_STAGES];
+} b3d_schedule;
+
+/* Device workspace (bytes) that b3d_c2f_step needs for K particles. */
+b3d_status b3d_c2f_workspace_size(const b3d_schedule* s, int32_t K, size_t* bytes);
+
+/* One coarse-to-fine proposal for K particles (Sec. III-B and Fig. 1):
+ * stage 0 scores stages[0] around `center` (host float[16]) once and draws
+ * K cells; at each later stage t every particle k scores stages[t] around
+ * its current pose and draws one cell (sampler counter (n, k, t, 0)), which
+ * becomes its pose.  poses_out: device float[K][16] (the chosen cells'
+ * representative poses); logq_out: device float[K], the sum over stages of
+ * the log weight of each choice (for a partition schedule the proposal
+ * density of a uniform draw in the final cell is exp(logq)/cell volume);
+ * idx_out: device int32[n_stages][K] or NULL.  workspace: device memory of
+ * at least b3d_c2f_workspace_size bytes.  Stream-ordered. */
+b3d_status b3d_c2f_step(const b3d_scene* scene, const float* center, const b3d_schedule* s, int32_t K, uint64_t seed,
+                        void* workspace, size_t ws_bytes, float* poses_out, float* logq_out, int32_t* idx_out,
+                        void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* B3D_H */

@@ -1,0 +1,345 @@
+"""Python binding of the b3d HIP library (libb3d.so, gfx950).
+
+Batched render-and-score for coarse-to-fine pose inference after Bayes3D
+(arXiv 2312.08715).  This module only marshals arguments: torch tensors
+supply device memory and the current HIP stream, and every computation runs
+in the library's kernels.  There is no fallback: if the library is missing,
+importing works but every call raises ``B3DError``.
+
+The entry points mirror ``include/b3d.h`` one to one.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libb3d.so")
+
+B3D_MAX_STAGES = 8
+
+
+class B3DError(RuntimeError):
+    pass
+
+
+class Intrinsics(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("z_near", ctypes.c_float), ("H", ctypes.c_int32), ("W", ctypes.c_int32)]
+
+
+class ScoreParams(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_float), ("p_out", ctypes.c_float), ("outlier_volume", ctypes.c_float),
+                ("norm_M", ctypes.c_float), ("window", ctypes.c_int32)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("center", ctypes.c_float * 16), ("half_extent", ctypes.c_float * 3), ("count", ctypes.c_int32 * 3),
+                ("cell_centres", ctypes.c_int32), ("n_rot", ctypes.c_int32), ("rot_max_angle", ctypes.c_float),
+                ("rotations", ctypes.c_void_p)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("n_stages", ctypes.c_int32), ("stages", Grid * B3D_MAX_STAGES)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_U32 = ctypes.c_uint32
+_U64 = ctypes.c_uint64
+
+_SIGNATURES = {
+    "b3d_last_error": ([], ctypes.c_char_p),
+    "b3d_version": ([], ctypes.c_char_p),
+    "b3d_mesh_create": ([_P, _I32, _P, _I32, ctypes.POINTER(_P)], ctypes.c_int),
+    "b3d_mesh_destroy": ([_P], ctypes.c_int),
+    "b3d_mesh_info": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)], ctypes.c_int),
+    "b3d_unproject": ([_P, _I32, ctypes.POINTER(Intrinsics), _P, _P], ctypes.c_int),
+    "b3d_render_batch": ([_P, _P, _I32, ctypes.POINTER(Intrinsics), _P, _P, _P], ctypes.c_int),
+    "b3d_score": ([_P, _P, _I32, _I32, _I32, ctypes.POINTER(ScoreParams), _P, _P], ctypes.c_int),
+    "b3d_score_backward": ([_P, _P, _I32, _I32, _I32, ctypes.POINTER(ScoreParams), _P, _P, _P, _P, _P],
+                           ctypes.c_int),
+    "b3d_render_backward": ([_P, _P, _I32, ctypes.POINTER(Intrinsics), _P, _P, _P, _P], ctypes.c_int),
+    "b3d_scene_create": ([_P, ctypes.POINTER(Intrinsics), ctypes.POINTER(ScoreParams), ctypes.POINTER(_P)],
+                         ctypes.c_int),
+    "b3d_scene_destroy": ([_P], ctypes.c_int),
+    "b3d_scene_set_background": ([_P, _P, _P, _I32, _P], ctypes.c_int),
+    "b3d_scene_set_observed": ([_P, _P, _P], ctypes.c_int),
+    "b3d_render_score": ([_P, _P, _I32, _P, _P, _P], ctypes.c_int),
+    "b3d_grid_size": ([ctypes.POINTER(Grid)], ctypes.c_int64),
+    "b3d_enumerate": ([ctypes.POINTER(Grid), _U64, _I32, _P, _P], ctypes.c_int),
+    "b3d_sample": ([_P, _I32, _I32, _I32, _U64, _U32, _U32, _P, _P, _P, _P], ctypes.c_int),
+    "b3d_c2f_workspace_size": ([ctypes.POINTER(Schedule), _I32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "b3d_c2f_step": ([_P, _P, ctypes.POINTER(Schedule), _I32, _U64, _P, ctypes.c_size_t, _P, _P, _P, _P],
+                     ctypes.c_int),
+}
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libb3d.so and declare its signatures (no GPU is touched)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise B3DError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+        L = ctypes.CDLL(path)
+        for name, (args, res) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _call(name: str, *args):
+    rc = getattr(load_library(), name)(*args)
+    if rc != 0:
+        msg = load_library().b3d_last_error().decode(errors="replace")
+        raise B3DError(f"{name} failed ({rc}): {msg}")
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=None) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise B3DError("expected a device tensor")
+    if not t.is_contiguous():
+        raise B3DError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise B3DError(f"expected {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def intrinsics(fx, fy, cx, cy, H, W, z_near=0.01) -> Intrinsics:
+    return Intrinsics(float(fx), float(fy), float(cx), float(cy), float(z_near), int(H), int(W))
+
+
+def intrinsics_of(cam) -> Intrinsics:
+    """From an object with fx, fy, cx, cy, H, W (and optionally z_near)."""
+    return intrinsics(cam.fx, cam.fy, cam.cx, cam.cy, cam.H, cam.W, getattr(cam, "z_near", 0.01))
+
+
+def score_params(sigma, p_out, outlier_volume=1.0, window=3, norm_M=0.0) -> ScoreParams:
+    return ScoreParams(float(sigma), float(p_out), float(outlier_volume), float(norm_M), int(window))
+
+
+def version() -> str:
+    return load_library().b3d_version().decode()
+
+
+class Mesh:
+    """Device-resident triangle mesh (b3d_mesh_create / b3d_mesh_destroy)."""
+
+    def __init__(self, verts, tris):
+        v = np.ascontiguousarray(verts, dtype=np.float32)
+        t = np.ascontiguousarray(tris, dtype=np.int32)
+        if v.ndim != 2 or v.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3:
+            raise B3DError("verts must be [V,3] and tris [T,3]")
+        h = _P()
+        _call("b3d_mesh_create", v.ctypes.data, v.shape[0], t.ctypes.data, t.shape[0], ctypes.byref(h))
+        self._h = h
+        self.V, self.T = v.shape[0], t.shape[0]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> Tuple[int, int, int]:
+        V, T, C = _I32(), _I32(), _I32()
+        _call("b3d_mesh_info", self._h, ctypes.byref(V), ctypes.byref(T), ctypes.byref(C))
+        return V.value, T.value, C.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().b3d_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def unproject(depth: torch.Tensor, K: Intrinsics) -> torch.Tensor:
+    B = depth.numel() // (K.H * K.W)
+    out = torch.empty(depth.shape + (3,), dtype=torch.float32, device=depth.device)
+    _call("b3d_unproject", _ptr(depth, torch.float32), B, ctypes.byref(K), _ptr(out), _stream())
+    return out
+
+
+def render_batch(mesh: Mesh, poses: torch.Tensor, K: Intrinsics, want_tri: bool = True):
+    """Point images [N,H,W,3] (and triangle ids [N,H,W]) of N poses [N,4,4]."""
+    N = poses.shape[0]
+    xyz = torch.empty((N, K.H, K.W, 3), dtype=torch.float32, device=poses.device)
+    tri = torch.empty((N, K.H, K.W), dtype=torch.int32, device=poses.device) if want_tri else None
+    _call("b3d_render_batch", mesh.handle, _ptr(poses, torch.float32), N, ctypes.byref(K), _ptr(xyz),
+          _ptr(tri), _stream())
+    return xyz, tri
+
+
+def score(observed: torch.Tensor, rendered: torch.Tensor, p: ScoreParams) -> torch.Tensor:
+    N, H, W = rendered.shape[0], rendered.shape[1], rendered.shape[2]
+    out = torch.empty(N, dtype=torch.float32, device=rendered.device)
+    _call("b3d_score", _ptr(observed, torch.float32), _ptr(rendered, torch.float32), N, H, W, ctypes.byref(p),
+          _ptr(out), _stream())
+    return out
+
+
+def score_backward(observed, rendered, p: ScoreParams, dlogL=None, want_rendered=True):
+    N, H, W = rendered.shape[0], rendered.shape[1], rendered.shape[2]
+    dev = rendered.device
+    dr = torch.empty_like(rendered) if want_rendered else None
+    ds = torch.empty(N, dtype=torch.float32, device=dev)
+    dp = torch.empty(N, dtype=torch.float32, device=dev)
+    _call("b3d_score_backward", _ptr(observed, torch.float32), _ptr(rendered, torch.float32), N, H, W,
+          ctypes.byref(p), _ptr(dlogL, torch.float32), _ptr(dr), _ptr(ds), _ptr(dp), _stream())
+    return dr, ds, dp
+
+
+def render_backward(mesh: Mesh, poses, K: Intrinsics, tri, d_rendered):
+    N = poses.shape[0]
+    out = torch.empty((N, 6), dtype=torch.float32, device=poses.device)
+    _call("b3d_render_backward", mesh.handle, _ptr(poses, torch.float32), N, ctypes.byref(K),
+          _ptr(tri, torch.int32), _ptr(d_rendered, torch.float32), _ptr(out), _stream())
+    return out
+
+
+class Scene:
+    """Moving mesh + camera + likelihood parameters + background + observation."""
+
+    def __init__(self, mesh: Mesh, K: Intrinsics, p: ScoreParams):
+        h = _P()
+        _call("b3d_scene_create", mesh.handle, ctypes.byref(K), ctypes.byref(p), ctypes.byref(h))
+        self._h = h
+        self.mesh, self.K, self.params = mesh, K, p
+        self._keep = []
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_background(self, meshes: Sequence[Mesh], poses) -> None:
+        n = len(meshes)
+        arr = (_P * max(n, 1))(*[m.handle for m in meshes])
+        P = np.ascontiguousarray(np.asarray(poses, dtype=np.float32).reshape(n, 16)) if n else np.zeros((1, 16),
+                                                                                                         np.float32)
+        self._keep = list(meshes)
+        _call("b3d_scene_set_background", self._h, arr, P.ctypes.data, n, _stream())
+
+    def set_observed(self, observed: torch.Tensor) -> None:
+        self._obs = observed  # the scene reads it by reference
+        _call("b3d_scene_set_observed", self._h, _ptr(observed, torch.float32), _stream())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().b3d_scene_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def render_score(scene: Scene, poses: torch.Tensor, grad: bool = False):
+    """logL [N] (and the adjoint [N,8] when grad) of N poses [N,4,4]."""
+    N = poses.shape[0]
+    logL = torch.empty(N, dtype=torch.float32, device=poses.device)
+    g = torch.empty((N, 8), dtype=torch.float32, device=poses.device) if grad else None
+    _call("b3d_render_score", scene.handle, _ptr(poses, torch.float32), N, _ptr(logL), _ptr(g), _stream())
+    return (logL, g) if grad else logL
+
+
+def make_grid(center, half_extent, count, cell_centres=False, rotations: Optional[torch.Tensor] = None,
+              n_rot: int = 1, rot_max_angle: float = 0.0) -> Grid:
+    g = Grid()
+    c = np.asarray(center, dtype=np.float64).reshape(16)
+    for i in range(16):
+        g.center[i] = float(c[i])
+    for k in range(3):
+        g.half_extent[k] = float(half_extent[k])
+        g.count[k] = int(count[k])
+    g.cell_centres = int(bool(cell_centres))
+    if rotations is not None:
+        g.n_rot = int(rotations.shape[0])
+        g.rotations = _ptr(rotations, torch.float32)
+    else:
+        g.n_rot = int(n_rot)
+        g.rotations = None
+    g.rot_max_angle = float(rot_max_angle)
+    return g
+
+
+def grid_of(spec, device="cuda", center=None) -> Tuple[Grid, Optional[torch.Tensor]]:
+    """From a workloads.GridSpec; returns the grid and the rotations tensor it references."""
+    rots = None
+    if spec.rotations is not None:
+        rots = torch.as_tensor(np.asarray(spec.rotations, dtype=np.float32).reshape(-1, 9), device=device).contiguous()
+    g = make_grid(spec.center if center is None else center, spec.half_extent, spec.count, spec.cell_centres, rots,
+                  spec.n_rot, spec.rot_max_angle)
+    return g, rots
+
+
+def grid_size(g: Grid) -> int:
+    return int(load_library().b3d_grid_size(ctypes.byref(g)))
+
+
+def enumerate_grid(g: Grid, seed: int = 0, stage: int = 0, device="cuda") -> torch.Tensor:
+    N = grid_size(g)
+    if N <= 0:
+        raise B3DError("invalid grid")
+    out = torch.empty((N, 4, 4), dtype=torch.float32, device=device)
+    _call("b3d_enumerate", ctypes.byref(g), int(seed), int(stage), _ptr(out), _stream())
+    return out
+
+
+def sample(logL: torch.Tensor, K: int, seed: int, stage: int = 0, k0: int = 0, weights: bool = True):
+    """logL [P,N] or [N] -> weights [P,N], idx [P,K], logw [P,K] (segment axis squeezed for 1-D input)."""
+    squeeze = logL.dim() == 1
+    L = logL.reshape(1, -1) if squeeze else logL
+    P, N = L.shape
+    dev = L.device
+    w = torch.empty((P, N), dtype=torch.float32, device=dev) if weights else None
+    idx = torch.empty((P, K), dtype=torch.int32, device=dev)
+    lw = torch.empty((P, K), dtype=torch.float32, device=dev)
+    _call("b3d_sample", _ptr(L.contiguous(), torch.float32), P, N, K, int(seed), int(stage), int(k0), _ptr(w),
+          _ptr(idx), _ptr(lw), _stream())
+    if squeeze:
+        return (None if w is None else w[0]), idx[0], lw[0]
+    return w, idx, lw
+
+
+def make_schedule(stages: Sequence[Grid]) -> Schedule:
+    if not 1 <= len(stages) <= B3D_MAX_STAGES:
+        raise B3DError("schedule needs 1..8 stages")
+    s = Schedule()
+    s.n_stages = len(stages)
+    for i, g in enumerate(stages):
+        s.stages[i] = g
+    return s
+
+
+def c2f_step(scene: Scene, center, schedule: Schedule, K: int, seed: int, device="cuda"):
+    """Coarse-to-fine proposal for K particles: poses [K,4,4], logq [K], idx [n_stages,K]."""
+    nb = ctypes.c_size_t()
+    _call("b3d_c2f_workspace_size", ctypes.byref(schedule), int(K), ctypes.byref(nb))
+    ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=device)
+    c = np.ascontiguousarray(np.asarray(center, dtype=np.float32).reshape(16))
+    poses = torch.empty((K, 4, 4), dtype=torch.float32, device=device)
+    logq = torch.empty(K, dtype=torch.float32, device=device)
+    idx = torch.empty((schedule.n_stages, K), dtype=torch.int32, device=device)
+    _call("b3d_c2f_step", scene.handle, c.ctypes.data, ctypes.byref(schedule), int(K), int(seed), _ptr(ws),
+          int(nb.value), _ptr(poses), _ptr(logq), _ptr(idx), _stream())
+    return poses, logq, idx

@@ -1,0 +1,578 @@
+// C ABI of the b3d library: argument validation, error reporting, device
+// mesh layout, scenes, and the host side of the coarse-to-fine stage loop.
+// Nothing here computes on the host beyond set-up (mesh clustering, bounds,
+// constants); every step of the hot path runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/b3d.h"
+#include "b3d_launch.hpp"
+
+using namespace b3d;
+
+namespace {
+
+thread_local std::string g_err;
+
+b3d_status fail(b3d_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+b3d_status hip_fail(hipError_t e, const char* where) {
+  return fail(B3D_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define B3D_CHECK_HIP(expr, where)             \
+  do {                                         \
+    hipError_t e_ = (expr);                    \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+constexpr int kMaxImage = 4096;
+constexpr size_t kLdsMax = 65536;
+
+bool finite_all(const float* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+b3d_status check_intrinsics(const b3d_intrinsics* K) {
+  if (!K) return fail(B3D_EINVAL, "intrinsics pointer is NULL");
+  if (!(K->fx > 0) || !(K->fy > 0) || !std::isfinite(K->fx) || !std::isfinite(K->fy) || !std::isfinite(K->cx) ||
+      !std::isfinite(K->cy))
+    return fail(B3D_EINVAL, "intrinsics: fx, fy must be > 0 and all values finite");
+  if (!(K->z_near > 0) || !std::isfinite(K->z_near)) return fail(B3D_EINVAL, "intrinsics: z_near must be > 0");
+  if (K->H < 1 || K->W < 1 || K->H > kMaxImage || K->W > kMaxImage)
+    return fail(B3D_ESHAPE, "image size %dx%d outside 1..%d", K->H, K->W, kMaxImage);
+  return B3D_OK;
+}
+
+Cam make_cam(const b3d_intrinsics* K) {
+  Cam c;
+  c.fx = K->fx;
+  c.fy = K->fy;
+  c.cx = K->cx;
+  c.cy = K->cy;
+  c.znear = K->z_near;
+  c.H = K->H;
+  c.W = K->W;
+  return c;
+}
+
+b3d_status make_consts(const b3d_score_params* p, int H, int W, ScoreConsts* sc) {
+  if (!p) return fail(B3D_EINVAL, "score params pointer is NULL");
+  if (!(p->sigma > 0) || !std::isfinite(p->sigma)) return fail(B3D_EINVAL, "sigma must be > 0 (got %g)", p->sigma);
+  if (!(p->p_out > 0) || !(p->p_out <= 1)) return fail(B3D_EINVAL, "p_out must be in (0, 1] (got %g)", p->p_out);
+  if (!(p->outlier_volume > 0) || !std::isfinite(p->outlier_volume))
+    return fail(B3D_EINVAL, "outlier_volume must be > 0");
+  if (p->window < 1 || p->window > 15 || (p->window % 2) == 0)
+    return fail(B3D_EINVAL, "window must be odd and in 1..15 (got %d)", p->window);
+  if (!std::isfinite(p->norm_M)) return fail(B3D_EINVAL, "norm_M must be finite");
+  const double M = p->norm_M > 0 ? (double)p->norm_M : (double)H * (double)W;
+  const double s = p->sigma, V = p->outlier_volume, po = p->p_out;
+  const double norm = std::pow(2.0 * M_PI * s * s, -1.5);
+  sc->da = po / V;
+  sc->dbn = (1.0 - po) / M * norm;
+  sc->dc = 1.0 / (2.0 * s * s);
+  sc->dinv_s = 1.0 / s;
+  sc->dinv_s3 = 1.0 / (s * s * s);
+  sc->dinvV = 1.0 / V;
+  sc->dnormM = norm / M;
+  sc->a = (float)sc->da;
+  sc->bn = (float)sc->dbn;
+  sc->c2 = (float)(sc->dc / std::log(2.0));
+  sc->inv_s = (float)sc->dinv_s;
+  sc->inv_s2 = (float)(1.0 / (s * s));
+  sc->inv_s3 = (float)sc->dinv_s3;
+  sc->invV = (float)sc->dinvV;
+  sc->normM = (float)sc->dnormM;
+  sc->h = (p->window - 1) / 2;
+  return B3D_OK;
+}
+
+}  // namespace
+
+struct b3d_mesh {
+  int V = 0, T = 0, n_clusters = 0;
+  MeshDev dev{};
+  std::vector<void*> allocs;
+};
+
+struct b3d_scene {
+  const b3d_mesh* mesh = nullptr;
+  b3d_intrinsics K{};
+  b3d_score_params params{};
+  SceneDev dev{};
+  unsigned long long* bg = nullptr;  // background keys [H][W]
+  double* terms = nullptr;           // [3][H][W]
+  double* sat = nullptr;             // [3][(H+1)(W+1)]
+  bool has_bg = false;
+  bool observed = false;
+};
+
+extern "C" {
+
+const char* b3d_last_error(void) { return g_err.c_str(); }
+
+const char* b3d_version(void) { return "b3d 0.1.0 (gfx950)"; }
+
+b3d_status b3d_mesh_create(const float* verts, int32_t V, const int32_t* tris, int32_t T, b3d_mesh** out) {
+  if (!verts || !tris || !out) return fail(B3D_EINVAL, "mesh_create: NULL pointer");
+  if (V < 1 || T < 1 || T > (1 << 24)) return fail(B3D_ESHAPE, "mesh_create: need V >= 1 and 1 <= T <= 2^24");
+  if (!finite_all(verts, (size_t)V * 3)) return fail(B3D_EINVAL, "mesh_create: non-finite vertex");
+  for (int64_t i = 0; i < (int64_t)T * 3; ++i)
+    if (tris[i] < 0 || tris[i] >= V) return fail(B3D_EINVAL, "mesh_create: triangle index out of range");
+
+  // clusters of consecutive triangles with at most kClusterMax triangles and
+  // kClusterMax distinct vertices
+  std::vector<int4> clusters;
+  std::vector<float4> cverts;
+  std::vector<uint32_t> ctris((size_t)T);
+  std::vector<int> stamp((size_t)V, -1), local((size_t)V, 0);
+  int cur = -1, cur_first_tri = 0, cur_nv = 0, cur_nt = 0, cur_vert0 = 0;
+  auto flush = [&]() {
+    if (cur >= 0 && cur_nt > 0) clusters.push_back(make_int4(cur_vert0, cur_nv, cur_first_tri, cur_nt));
+  };
+  for (int t = 0; t < T; ++t) {
+    const int* tv = tris + 3 * (size_t)t;
+    int fresh = 0;
+    for (int k = 0; k < 3; ++k) {
+      bool dup = false;
+      for (int j = 0; j < k; ++j) dup = dup || (tv[j] == tv[k]);
+      if (!dup && stamp[tv[k]] != cur) ++fresh;
+    }
+    if (cur < 0 || cur_nt == kClusterMax || cur_nv + fresh > kClusterMax) {
+      flush();
+      ++cur;
+      cur_first_tri = t;
+      cur_nv = 0;
+      cur_nt = 0;
+      cur_vert0 = (int)cverts.size();
+    }
+    uint32_t packed = 0;
+    for (int k = 0; k < 3; ++k) {
+      const int v = tv[k];
+      if (stamp[v] != cur) {
+        stamp[v] = cur;
+        local[v] = cur_nv++;
+        cverts.push_back(make_float4(verts[3 * v], verts[3 * v + 1], verts[3 * v + 2], 0.0f));
+      }
+      packed |= (uint32_t)local[v] << (8 * k);
+    }
+    ctris[t] = packed;
+    ++cur_nt;
+  }
+  flush();
+
+  std::vector<float4> v4((size_t)V), nrm((size_t)T);
+  std::vector<int4> t4((size_t)T);
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int i = 0; i < V; ++i) {
+    v4[i] = make_float4(verts[3 * i], verts[3 * i + 1], verts[3 * i + 2], 0.0f);
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::min(lo[k], (double)verts[3 * i + k]);
+      hi[k] = std::max(hi[k], (double)verts[3 * i + k]);
+    }
+  }
+  for (int t = 0; t < T; ++t) {
+    const int a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
+    t4[t] = make_int4(a, b, c, 0);
+    double e1[3], e2[3];
+    for (int k = 0; k < 3; ++k) {
+      e1[k] = (double)verts[3 * b + k] - verts[3 * a + k];
+      e2[k] = (double)verts[3 * c + k] - verts[3 * a + k];
+    }
+    nrm[t] = make_float4((float)(e1[1] * e2[2] - e1[2] * e2[1]), (float)(e1[2] * e2[0] - e1[0] * e2[2]),
+                         (float)(e1[0] * e2[1] - e1[1] * e2[0]), 0.0f);
+  }
+  double ctr[3], rad = 0.0;
+  for (int k = 0; k < 3; ++k) ctr[k] = 0.5 * (lo[k] + hi[k]);
+  for (int i = 0; i < V; ++i) {
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) d2 += (verts[3 * i + k] - ctr[k]) * (verts[3 * i + k] - ctr[k]);
+    rad = std::max(rad, std::sqrt(d2));
+  }
+
+  b3d_mesh* m = new b3d_mesh();
+  m->V = V;
+  m->T = T;
+  m->n_clusters = (int)clusters.size();
+  auto upload = [&](const void* src, size_t bytes, void** dst) -> bool {
+    if (hipMalloc(dst, bytes) != hipSuccess) return false;
+    m->allocs.push_back(*dst);
+    return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  void *d_cl, *d_cv, *d_ct, *d_v, *d_t, *d_n;
+  bool ok = upload(clusters.data(), clusters.size() * sizeof(int4), &d_cl) &&
+            upload(cverts.data(), cverts.size() * sizeof(float4), &d_cv) &&
+            upload(ctris.data(), ctris.size() * sizeof(uint32_t), &d_ct) &&
+            upload(v4.data(), v4.size() * sizeof(float4), &d_v) && upload(t4.data(), t4.size() * sizeof(int4), &d_t) &&
+            upload(nrm.data(), nrm.size() * sizeof(float4), &d_n);
+  if (!ok) {
+    for (void* p : m->allocs) (void)hipFree(p);
+    delete m;
+    return fail(B3D_ENOMEM, "mesh_create: device allocation or copy failed");
+  }
+  MeshDev& d = m->dev;
+  d.clusters = (const int4*)d_cl;
+  d.cverts = (const float4*)d_cv;
+  d.ctris = (const uint32_t*)d_ct;
+  d.verts = (const float4*)d_v;
+  d.tris = (const int4*)d_t;
+  d.normals = (const float4*)d_n;
+  d.n_clusters = m->n_clusters;
+  d.V = V;
+  d.T = T;
+  for (int k = 0; k < 3; ++k) {
+    // widen by a relative epsilon so that float rounding keeps the bounds conservative
+    const double pad = 1e-6 * (std::fabs(lo[k]) + std::fabs(hi[k]) + rad) + 1e-7;
+    d.lo[k] = (float)(lo[k] - pad);
+    d.hi[k] = (float)(hi[k] + pad);
+    d.sphere[k] = (float)ctr[k];
+  }
+  d.sphere[3] = (float)(rad * (1.0 + 1e-6) + 1e-7);
+  *out = m;
+  return B3D_OK;
+}
+
+b3d_status b3d_mesh_destroy(b3d_mesh* m) {
+  if (!m) return B3D_OK;
+  (void)hipDeviceSynchronize();
+  for (void* p : m->allocs) (void)hipFree(p);
+  delete m;
+  return B3D_OK;
+}
+
+b3d_status b3d_mesh_info(const b3d_mesh* m, int32_t* V, int32_t* T, int32_t* n_clusters) {
+  if (!m) return fail(B3D_EINVAL, "mesh_info: NULL mesh");
+  if (V) *V = m->V;
+  if (T) *T = m->T;
+  if (n_clusters) *n_clusters = m->n_clusters;
+  return B3D_OK;
+}
+
+b3d_status b3d_unproject(const float* depth, int32_t B, const b3d_intrinsics* K, float* xyz, void* stream) {
+  if (b3d_status s = check_intrinsics(K)) return s;
+  if (B < 0) return fail(B3D_ESHAPE, "unproject: B < 0");
+  if (B == 0) return B3D_OK;
+  if (!depth || !xyz) return fail(B3D_EINVAL, "unproject: NULL pointer");
+  B3D_CHECK_HIP(launch_unproject(depth, B, make_cam(K), xyz, (hipStream_t)stream), "unproject");
+  return B3D_OK;
+}
+
+b3d_status b3d_render_batch(const b3d_mesh* mesh, const float* poses, int32_t N, const b3d_intrinsics* K,
+                            float* xyz_out, int32_t* tri_out, void* stream) {
+  if (!mesh) return fail(B3D_EINVAL, "render_batch: NULL mesh");
+  if (b3d_status s = check_intrinsics(K)) return s;
+  if (N < 0) return fail(B3D_ESHAPE, "render_batch: N < 0");
+  if (N == 0) return B3D_OK;
+  if (!poses || !xyz_out) return fail(B3D_EINVAL, "render_batch: NULL pointer");
+  const int zcap = std::max(6144, K->W);
+  if (sizeof(float4) * 2 * kClusterMax + 8 * (size_t)zcap > kLdsMax)
+    return fail(B3D_ESHAPE, "render_batch: image too wide for the LDS depth buffer");
+  B3D_CHECK_HIP(launch_render_batch(mesh->dev, make_cam(K), poses, N, xyz_out, tri_out, zcap, (hipStream_t)stream),
+                "render_batch");
+  return B3D_OK;
+}
+
+static int score_cap(int W, int h, int planes, int halo_rows) {
+  // floats of LDS for staged rows: at least one output row plus halo
+  const int need = planes * W * (1 + halo_rows * h);
+  const int want = 16384 - 64;
+  return need > want ? -1 : want;
+}
+
+b3d_status b3d_score(const float* observed, const float* rendered, int32_t N, int32_t H, int32_t W,
+                     const b3d_score_params* p, float* logL_out, void* stream) {
+  if (N < 0 || H < 1 || W < 1 || H > kMaxImage || W > kMaxImage) return fail(B3D_ESHAPE, "score: bad N, H or W");
+  ScoreConsts sc;
+  if (b3d_status s = make_consts(p, H, W, &sc)) return s;
+  if (N == 0) return B3D_OK;
+  if (!observed || !rendered || !logL_out) return fail(B3D_EINVAL, "score: NULL pointer");
+  const int cap = score_cap(W, sc.h, 3, 2);
+  if (cap < 0) return fail(B3D_ESHAPE, "score: image too wide for the LDS row buffer");
+  B3D_CHECK_HIP(launch_score(observed, rendered, N, H, W, sc, logL_out, cap, (hipStream_t)stream), "score");
+  return B3D_OK;
+}
+
+b3d_status b3d_score_backward(const float* observed, const float* rendered, int32_t N, int32_t H, int32_t W,
+                              const b3d_score_params* p, const float* dlogL, float* d_rendered, float* d_sigma,
+                              float* d_pout, void* stream) {
+  if (N < 0 || H < 1 || W < 1 || H > kMaxImage || W > kMaxImage)
+    return fail(B3D_ESHAPE, "score_backward: bad N, H or W");
+  ScoreConsts sc;
+  if (b3d_status s = make_consts(p, H, W, &sc)) return s;
+  if (N == 0) return B3D_OK;
+  if (!observed || !rendered) return fail(B3D_EINVAL, "score_backward: NULL pointer");
+  if (!d_rendered && !d_sigma && !d_pout) return B3D_OK;
+  const int cap = score_cap(W, sc.h, 4, 4);
+  if (cap < 0) return fail(B3D_ESHAPE, "score_backward: image too wide for the LDS row buffer");
+  B3D_CHECK_HIP(launch_score_backward(observed, rendered, N, H, W, sc, dlogL, d_rendered, d_sigma, d_pout, cap,
+                                      (hipStream_t)stream),
+                "score_backward");
+  return B3D_OK;
+}
+
+b3d_status b3d_render_backward(const b3d_mesh* mesh, const float* poses, int32_t N, const b3d_intrinsics* K,
+                               const int32_t* tri, const float* d_rendered, float* d_pose, void* stream) {
+  if (!mesh) return fail(B3D_EINVAL, "render_backward: NULL mesh");
+  if (b3d_status s = check_intrinsics(K)) return s;
+  if (N < 0) return fail(B3D_ESHAPE, "render_backward: N < 0");
+  if (N == 0) return B3D_OK;
+  if (!poses || !tri || !d_rendered || !d_pose) return fail(B3D_EINVAL, "render_backward: NULL pointer");
+  B3D_CHECK_HIP(launch_render_backward(mesh->dev, make_cam(K), poses, N, tri, d_rendered, d_pose, (hipStream_t)stream),
+                "render_backward");
+  return B3D_OK;
+}
+
+b3d_status b3d_scene_create(const b3d_mesh* mesh, const b3d_intrinsics* K, const b3d_score_params* p,
+                            b3d_scene** out) {
+  if (!mesh || !out) return fail(B3D_EINVAL, "scene_create: NULL pointer");
+  if (b3d_status s = check_intrinsics(K)) return s;
+  ScoreConsts sc;
+  if (b3d_status s = make_consts(p, K->H, K->W, &sc)) return s;
+  b3d_scene* S = new b3d_scene();
+  S->mesh = mesh;
+  S->K = *K;
+  S->params = *p;
+  S->dev.mesh = mesh->dev;
+  S->dev.cam = make_cam(K);
+  S->dev.sc = sc;
+  const int h = sc.h, W = K->W;
+  S->dev.zcap = std::max(2048, (4 * h + 8) * W);
+  S->dev.wcap = std::max(2048, (2 * h + 8) * W);
+  if (fused_lds_bytes(S->dev) > kLdsMax) {
+    S->dev.zcap = (4 * h + 1) * W;
+    S->dev.wcap = (2 * h + 1) * W;
+    if (fused_lds_bytes(S->dev) > kLdsMax) {
+      delete S;
+      return fail(B3D_ESHAPE, "scene_create: image width %d too large for the fused kernel's LDS budget", W);
+    }
+  }
+  const size_t HW = (size_t)K->H * K->W, SP = (size_t)(K->H + 1) * (K->W + 1);
+  if (hipMalloc((void**)&S->terms, 3 * HW * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&S->sat, 3 * SP * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&S->bg, HW * sizeof(unsigned long long)) != hipSuccess) {
+    (void)hipFree(S->terms);
+    (void)hipFree(S->sat);
+    (void)hipFree(S->bg);
+    delete S;
+    return fail(B3D_ENOMEM, "scene_create: device allocation failed");
+  }
+  S->dev.sat = S->sat;
+  S->dev.bg = nullptr;
+  *out = S;
+  return B3D_OK;
+}
+
+b3d_status b3d_scene_destroy(b3d_scene* S) {
+  if (!S) return B3D_OK;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(S->terms);
+  (void)hipFree(S->sat);
+  (void)hipFree(S->bg);
+  delete S;
+  return B3D_OK;
+}
+
+b3d_status b3d_scene_set_background(b3d_scene* S, const b3d_mesh* const* meshes, const float* poses, int32_t n,
+                                    void* stream) {
+  if (!S) return fail(B3D_EINVAL, "scene_set_background: NULL scene");
+  if (n < 0) return fail(B3D_ESHAPE, "scene_set_background: n < 0");
+  S->observed = false;
+  if (n == 0) {
+    S->has_bg = false;
+    S->dev.bg = nullptr;
+    return B3D_OK;
+  }
+  if (!meshes || !poses) return fail(B3D_EINVAL, "scene_set_background: NULL pointer");
+  if (!finite_all(poses, (size_t)n * 16)) return fail(B3D_EINVAL, "scene_set_background: non-finite pose");
+  for (int i = 0; i < n; ++i)
+    if (!meshes[i]) return fail(B3D_EINVAL, "scene_set_background: NULL mesh %d", i);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t HW = (size_t)S->K.H * S->K.W;
+  B3D_CHECK_HIP(launch_fill_keys(S->bg, HW, st), "scene_set_background");
+  uint64_t base = (uint64_t)S->mesh->T;
+  for (int i = 0; i < n; ++i) {
+    if (base + (uint64_t)meshes[i]->T >= 0xffffffffull)
+      return fail(B3D_ESHAPE, "scene_set_background: too many triangles for 32-bit ids");
+    B3D_CHECK_HIP(launch_raster_global(meshes[i]->dev, S->dev.cam, poses + 16 * (size_t)i, (uint32_t)base, S->bg, st),
+                  "scene_set_background");
+    base += (uint64_t)meshes[i]->T;
+  }
+  S->has_bg = true;
+  S->dev.bg = S->bg;
+  return B3D_OK;
+}
+
+b3d_status b3d_scene_set_observed(b3d_scene* S, const float* observed, void* stream) {
+  if (!S || !observed) return fail(B3D_EINVAL, "scene_set_observed: NULL pointer");
+  S->dev.obs = observed;
+  B3D_CHECK_HIP(launch_background_terms(S->dev, S->terms, (hipStream_t)stream), "scene_set_observed");
+  S->observed = true;
+  return B3D_OK;
+}
+
+b3d_status b3d_render_score(const b3d_scene* S, const float* poses, int32_t N, float* logL_out, float* grad_out,
+                            void* stream) {
+  if (!S) return fail(B3D_EINVAL, "render_score: NULL scene");
+  if (!S->observed) return fail(B3D_EINVAL, "render_score: call b3d_scene_set_observed first");
+  if (N < 0) return fail(B3D_ESHAPE, "render_score: N < 0");
+  if (N == 0) return B3D_OK;
+  if (!poses || !logL_out) return fail(B3D_EINVAL, "render_score: NULL pointer");
+  B3D_CHECK_HIP(launch_render_score(S->dev, poses, N, logL_out, grad_out, (hipStream_t)stream), "render_score");
+  return B3D_OK;
+}
+
+static b3d_status make_grid(const b3d_grid* g, GridDev* d, int64_t* N) {
+  if (!g) return fail(B3D_EINVAL, "grid pointer is NULL");
+  for (int k = 0; k < 3; ++k) {
+    if (g->count[k] < 1) return fail(B3D_EINVAL, "grid: count[%d] must be >= 1", k);
+    if (!(g->half_extent[k] >= 0) || !std::isfinite(g->half_extent[k]))
+      return fail(B3D_EINVAL, "grid: half_extent[%d] must be >= 0", k);
+  }
+  if (g->n_rot < 1) return fail(B3D_EINVAL, "grid: n_rot must be >= 1");
+  if (!std::isfinite(g->rot_max_angle) || g->rot_max_angle < 0) return fail(B3D_EINVAL, "grid: bad rot_max_angle");
+  if (!finite_all(g->center, 16)) return fail(B3D_EINVAL, "grid: non-finite centre pose");
+  const int64_t n = (int64_t)g->count[0] * g->count[1] * g->count[2] * g->n_rot;
+  if (n > (1ll << 28)) return fail(B3D_ESHAPE, "grid: too many hypotheses");
+  std::memcpy(d->center, g->center, sizeof(d->center));
+  for (int k = 0; k < 3; ++k) {
+    d->half[k] = g->half_extent[k];
+    d->count[k] = g->count[k];
+  }
+  d->cell_centres = g->cell_centres ? 1 : 0;
+  d->n_rot = g->n_rot;
+  d->max_angle = g->rot_max_angle;
+  d->rots = g->rotations;
+  *N = n;
+  return B3D_OK;
+}
+
+int64_t b3d_grid_size(const b3d_grid* g) {
+  GridDev d;
+  int64_t n = 0;
+  std::string keep = g_err;
+  if (make_grid(g, &d, &n) != B3D_OK) {
+    g_err = keep;
+    return 0;
+  }
+  return n;
+}
+
+b3d_status b3d_enumerate(const b3d_grid* g, uint64_t seed, int32_t stage, float* poses_out, void* stream) {
+  GridDev d;
+  int64_t N;
+  if (b3d_status s = make_grid(g, &d, &N)) return s;
+  if (!poses_out) return fail(B3D_EINVAL, "enumerate: NULL output");
+  if (stage < 0) return fail(B3D_EINVAL, "enumerate: stage < 0");
+  B3D_CHECK_HIP(launch_enumerate(d, nullptr, 1, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)stage, poses_out,
+                                 (hipStream_t)stream),
+                "enumerate");
+  return B3D_OK;
+}
+
+b3d_status b3d_sample(const float* logL, int32_t P, int32_t N, int32_t K, uint64_t seed, uint32_t stage, uint32_t k0,
+                      float* weights_out, int32_t* idx_out, float* logw_out, void* stream) {
+  if (P < 0 || N < 0) return fail(B3D_ESHAPE, "sample: P, N must be >= 0");
+  if (K < 1 || K > 4096) return fail(B3D_EINVAL, "sample: K must be in 1..4096");
+  if (P == 0) return B3D_OK;
+  if (N == 0) return fail(B3D_ESHAPE, "sample: cannot draw from an empty segment");
+  if ((int64_t)P * K > (1ll << 30)) return fail(B3D_ESHAPE, "sample: too many draws");
+  if (!logL || !idx_out) return fail(B3D_EINVAL, "sample: NULL pointer");
+  B3D_CHECK_HIP(launch_sample(logL, P, N, K, (uint32_t)seed, (uint32_t)(seed >> 32), stage, k0, weights_out, idx_out,
+                              logw_out, (hipStream_t)stream),
+                "sample");
+  return B3D_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct C2FLayout {
+  size_t poses, logL, idx, logw, total;
+  int64_t max_hyp;
+};
+
+static b3d_status c2f_layout(const b3d_schedule* s, int32_t K, C2FLayout* L) {
+  if (!s) return fail(B3D_EINVAL, "schedule pointer is NULL");
+  if (s->n_stages < 1 || s->n_stages > B3D_MAX_STAGES)
+    return fail(B3D_EINVAL, "schedule: n_stages must be in 1..%d", B3D_MAX_STAGES);
+  if (K < 1 || K > 4096) return fail(B3D_EINVAL, "c2f: K must be in 1..4096");
+  int64_t mx = 0;
+  for (int t = 0; t < s->n_stages; ++t) {
+    GridDev d;
+    int64_t n;
+    if (b3d_status st = make_grid(&s->stages[t], &d, &n)) return st;
+    mx = std::max(mx, t == 0 ? n : n * K);
+  }
+  if (mx > (1ll << 31) - 1) return fail(B3D_ESHAPE, "c2f: too many hypotheses in one stage");
+  L->max_hyp = mx;
+  size_t off = 0;
+  L->poses = off;
+  off = align256(off + sizeof(float) * 16 * (size_t)mx);
+  L->logL = off;
+  off = align256(off + sizeof(float) * (size_t)mx);
+  L->idx = off;
+  off = align256(off + sizeof(int) * (size_t)K);
+  L->logw = off;
+  off = align256(off + sizeof(float) * (size_t)K);
+  L->total = off;
+  return B3D_OK;
+}
+
+b3d_status b3d_c2f_workspace_size(const b3d_schedule* s, int32_t K, size_t* bytes) {
+  if (!bytes) return fail(B3D_EINVAL, "c2f_workspace_size: NULL output");
+  C2FLayout L;
+  if (b3d_status st = c2f_layout(s, K, &L)) return st;
+  *bytes = L.total;
+  return B3D_OK;
+}
+
+b3d_status b3d_c2f_step(const b3d_scene* S, const float* center, const b3d_schedule* s, int32_t K, uint64_t seed,
+                        void* workspace, size_t ws_bytes, float* poses_out, float* logq_out, int32_t* idx_out,
+                        void* stream) {
+  if (!S || !center || !poses_out || !logq_out || !workspace) return fail(B3D_EINVAL, "c2f_step: NULL pointer");
+  if (!S->observed) return fail(B3D_EINVAL, "c2f_step: call b3d_scene_set_observed first");
+  if (!finite_all(center, 16)) return fail(B3D_EINVAL, "c2f_step: non-finite centre pose");
+  C2FLayout L;
+  if (b3d_status st = c2f_layout(s, K, &L)) return st;
+  if (ws_bytes < L.total) return fail(B3D_ESHAPE, "c2f_step: workspace of %zu bytes < %zu", ws_bytes, L.total);
+  char* ws = (char*)workspace;
+  float* poses = (float*)(ws + L.poses);
+  float* logL = (float*)(ws + L.logL);
+  int* idx = (int*)(ws + L.idx);
+  float* logw = (float*)(ws + L.logw);
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  for (int t = 0; t < s->n_stages; ++t) {
+    GridDev d;
+    int64_t n;
+    (void)make_grid(&s->stages[t], &d, &n);
+    const int P = (t == 0) ? 1 : K;
+    if (t == 0) std::memcpy(d.center, center, sizeof(d.center));
+    B3D_CHECK_HIP(launch_enumerate(d, t == 0 ? nullptr : poses_out, P, k0, k1, (uint32_t)t, poses, st), "c2f_step");
+    B3D_CHECK_HIP(launch_render_score(S->dev, poses, (int)(n * P), logL, nullptr, st), "c2f_step");
+    B3D_CHECK_HIP(launch_sample(logL, P, (int)n, t == 0 ? K : 1, k0, k1, (uint32_t)t, 0u, nullptr, idx, logw, st),
+                  "c2f_step");
+    B3D_CHECK_HIP(launch_c2f_update(poses, P, (int)n, idx, logw, K, t > 0, poses_out, logq_out,
+                                    idx_out ? idx_out + (size_t)t * K : nullptr, st),
+                  "c2f_step");
+  }
+  return B3D_OK;
+}
+
+}  // extern "C"

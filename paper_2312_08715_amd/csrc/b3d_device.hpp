@@ -1,0 +1,264 @@
+// Device-side building blocks shared by the gfx950 kernels: camera and pose
+// helpers, packed depth/id keys, the cluster-based triangle rasteriser that
+// fills an LDS depth buffer, and fixed-order block reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace b3d {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+constexpr int kWaves = kBlock / 64;
+constexpr int kClusterMax = 256;     // max triangles and max vertices per cluster
+constexpr unsigned long long kEmptyKey = ~0ull;
+
+// Camera with reciprocal focal lengths precomputed.
+struct Cam {
+  float fx, fy, cx, cy, znear;
+  int H, W;
+};
+
+// Row-major rotation and translation of an object-to-camera pose.
+struct Pose {
+  float r[9];
+  float t[3];
+};
+
+// Device view of an uploaded mesh.  Triangles are grouped, in their original
+// order, into clusters of at most kClusterMax triangles that reference at
+// most kClusterMax distinct vertices; each cluster carries its own copy of
+// those vertices so that a workgroup can transform them once into LDS.
+struct MeshDev {
+  const int4* clusters;    // {first vertex, vertex count, first triangle, triangle count}
+  const float4* cverts;    // cluster-local vertex copies (object frame)
+  const uint32_t* ctris;   // local indices a | b << 8 | c << 16
+  const float4* verts;     // original vertices
+  const int4* tris;        // original triangles (w unused)
+  const float4* normals;   // object-frame (v1 - v0) x (v2 - v0)
+  int n_clusters, V, T;
+  float sphere[4];         // bounding sphere centre and radius
+  float lo[3], hi[3];      // axis-aligned bounds
+};
+
+__device__ __forceinline__ Pose load_pose(const float* __restrict__ p) {
+  Pose P;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    P.r[3 * i + 0] = p[4 * i + 0];
+    P.r[3 * i + 1] = p[4 * i + 1];
+    P.r[3 * i + 2] = p[4 * i + 2];
+    P.t[i] = p[4 * i + 3];
+  }
+  return P;
+}
+
+__device__ __forceinline__ float3 xform(const Pose& P, float x, float y, float z) {
+  return make_float3(P.r[0] * x + P.r[1] * y + P.r[2] * z + P.t[0], P.r[3] * x + P.r[4] * y + P.r[5] * z + P.t[1],
+                     P.r[6] * x + P.r[7] * y + P.r[8] * z + P.t[2]);
+}
+
+__device__ __forceinline__ float3 rotate(const Pose& P, float x, float y, float z) {
+  return make_float3(P.r[0] * x + P.r[1] * y + P.r[2] * z, P.r[3] * x + P.r[4] * y + P.r[5] * z,
+                     P.r[6] * x + P.r[7] * y + P.r[8] * z);
+}
+
+// Ray direction components of pixel column c / row r (the z component is 1).
+// Correctly rounded division, so every kernel gets bit-identical rays.
+__device__ __forceinline__ float ray_x(const Cam& cam, int c) { return ((float)c + 0.5f - cam.cx) / cam.fx; }
+__device__ __forceinline__ float ray_y(const Cam& cam, int r) { return ((float)r + 0.5f - cam.cy) / cam.fy; }
+
+// Packed depth/id key: positive float bits are monotone, so the smallest key
+// is the nearest surface and, at equal depth, the smallest triangle id.
+__device__ __forceinline__ unsigned long long pack_key(float z, uint32_t id) {
+  return ((unsigned long long)__float_as_uint(z) << 32) | (unsigned long long)id;
+}
+__device__ __forceinline__ float key_depth(unsigned long long k) { return __uint_as_float((uint32_t)(k >> 32)); }
+__device__ __forceinline__ uint32_t key_id(unsigned long long k) { return (uint32_t)(k & 0xffffffffull); }
+
+// Integer rectangle [x0, x1) x [y0, y1).
+struct Rect {
+  int x0, x1, y0, y1;
+  __device__ __forceinline__ int w() const { return x1 - x0; }
+  __device__ __forceinline__ int h() const { return y1 - y0; }
+  __device__ __forceinline__ bool empty() const { return x1 <= x0 || y1 <= y0; }
+};
+
+__device__ __forceinline__ Rect grow_clip(const Rect& r, int m, int W, int H) {
+  Rect o;
+  o.x0 = max(r.x0 - m, 0);
+  o.x1 = min(r.x1 + m, W);
+  o.y0 = max(r.y0 - m, 0);
+  o.y1 = min(r.y1 + m, H);
+  return o;
+}
+
+// Bounds of the projections of the 8 corners of the box [lo, hi] (camera
+// frame after pose P when `posed`, else already camera-frame corners).
+// Returns false when a corner is not in front of the near plane.
+__device__ __forceinline__ bool project_box(const Pose& P, const float* lo, const float* hi, bool posed, const Cam& cam,
+                                            float* b) {
+  bool ok = true;
+  b[0] = 3.0e38f;
+  b[1] = -3.0e38f;
+  b[2] = 3.0e38f;
+  b[3] = -3.0e38f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float x = (k & 1) ? hi[0] : lo[0];
+    const float y = (k & 2) ? hi[1] : lo[1];
+    const float z = (k & 4) ? hi[2] : lo[2];
+    const float3 c = posed ? xform(P, x, y, z) : make_float3(x, y, z);
+    ok = ok && (c.z > cam.znear);
+    const float iz = 1.0f / c.z;
+    const float u = cam.fx * c.x * iz + cam.cx, v = cam.fy * c.y * iz + cam.cy;
+    b[0] = fminf(b[0], u);
+    b[1] = fmaxf(b[1], u);
+    b[2] = fminf(b[2], v);
+    b[3] = fmaxf(b[3], v);
+  }
+  return ok;
+}
+
+// Conservative pixel rectangle of the object under pose P: the projection of
+// the mesh's posed bounding box intersected with that of the camera-aligned
+// box around its bounding sphere, widened by one pixel, clipped to the
+// image.  The whole image when neither box lies in front of the near plane.
+__device__ __forceinline__ Rect object_rect(const MeshDev& m, const Pose& P, const Cam& cam) {
+  float a[4], s[4];
+  const bool aok = project_box(P, m.lo, m.hi, true, cam, a);
+  const float3 c = xform(P, m.sphere[0], m.sphere[1], m.sphere[2]);
+  const float rad = m.sphere[3];
+  const float slo[3] = {c.x - rad, c.y - rad, c.z - rad}, shi[3] = {c.x + rad, c.y + rad, c.z + rad};
+  const bool sok = project_box(P, slo, shi, false, cam, s);
+  Rect r;
+  if (!aok && !sok) {
+    r.x0 = 0;
+    r.x1 = cam.W;
+    r.y0 = 0;
+    r.y1 = cam.H;
+    return r;
+  }
+  float b[4];
+  if (aok && sok) {
+    b[0] = fmaxf(a[0], s[0]);
+    b[1] = fminf(a[1], s[1]);
+    b[2] = fmaxf(a[2], s[2]);
+    b[3] = fminf(a[3], s[3]);
+  } else {
+    for (int k = 0; k < 4; ++k) b[k] = aok ? a[k] : s[k];
+  }
+  // pixel centres c + 1/2 in [umin, umax], widened by one pixel each side
+  const float fx0 = fmaxf(ceilf(b[0] - 0.5f) - 1.0f, 0.0f);
+  const float fx1 = fminf(floorf(b[1] - 0.5f) + 2.0f, (float)cam.W);
+  const float fy0 = fmaxf(ceilf(b[2] - 0.5f) - 1.0f, 0.0f);
+  const float fy1 = fminf(floorf(b[3] - 0.5f) + 2.0f, (float)cam.H);
+  r.x0 = (int)fminf(fx0, (float)cam.W);
+  r.x1 = (int)fmaxf(fx1, fx0);
+  r.y0 = (int)fminf(fy0, (float)cam.H);
+  r.y1 = (int)fmaxf(fy1, fy0);
+  if (r.x1 > cam.W) r.x1 = cam.W;
+  if (r.y1 > cam.H) r.y1 = cam.H;
+  return r;
+}
+
+// Rasterise every triangle of the mesh under pose P into an LDS key buffer
+// that covers the image rectangle `band` (row pitch band.w()).  Triangle ids
+// written are id_base + triangle index.  vbuf holds 2 * kClusterMax float4
+// (double-buffered cluster vertices).  Must be called by the whole block;
+// ends with the buffer complete for the block (after a barrier).
+__device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, const Cam& cam, uint32_t id_base,
+                                            const Rect& band, unsigned long long* zbuf, float4* vbuf) {
+  const int pitch = band.w();
+  const float bx0 = (float)band.x0, bx1 = (float)(band.x1 - 1);
+  const float by0 = (float)band.y0, by1 = (float)(band.y1 - 1);
+  for (int c = 0; c < m.n_clusters; ++c) {
+    const int4 ci = m.clusters[c];
+    float4* vb = vbuf + (c & 1) * kClusterMax;
+    for (int v = threadIdx.x; v < ci.y; v += kBlock) {
+      const float4 o = m.cverts[ci.x + v];
+      const float3 p = xform(P, o.x, o.y, o.z);
+      const float iz = 1.0f / p.z;
+      vb[v] = make_float4(cam.fx * p.x * iz + cam.cx, cam.fy * p.y * iz + cam.cy, p.z, iz);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ci.w; i += kBlock) {
+      const uint32_t pk = m.ctris[ci.z + i];
+      const float4 p0 = vb[pk & 255u], p1 = vb[(pk >> 8) & 255u], p2 = vb[(pk >> 16) & 255u];
+      if (p0.z <= cam.znear || p1.z <= cam.znear || p2.z <= cam.znear) continue;
+      const float area = (p1.x - p0.x) * (p2.y - p0.y) - (p2.x - p0.x) * (p1.y - p0.y);
+      if (!(area < 0.0f)) continue;  // facing away, or edge-on
+      const float umin = fminf(p0.x, fminf(p1.x, p2.x)), umax = fmaxf(p0.x, fmaxf(p1.x, p2.x));
+      const float vmin = fminf(p0.y, fminf(p1.y, p2.y)), vmax = fmaxf(p0.y, fmaxf(p1.y, p2.y));
+      const float fc0 = ceilf(fmaxf(umin - 0.5f, bx0)), fc1 = floorf(fminf(umax - 0.5f, bx1));
+      const float fr0 = ceilf(fmaxf(vmin - 0.5f, by0)), fr1 = floorf(fminf(vmax - 0.5f, by1));
+      if (!(fc0 <= fc1) || !(fr0 <= fr1)) continue;
+      const int c0 = (int)fc0, c1 = (int)fc1, r0 = (int)fr0, r1 = (int)fr1;
+      const uint32_t id = id_base + (uint32_t)(ci.z + i);
+      const float inv_area = 1.0f / area;
+      const float e0x = p2.x - p1.x, e0y = p2.y - p1.y;
+      const float e1x = p0.x - p2.x, e1y = p0.y - p2.y;
+      const float e2x = p1.x - p0.x, e2y = p1.y - p0.y;
+      for (int r = r0; r <= r1; ++r) {
+        const float py = (float)r + 0.5f;
+        for (int col = c0; col <= c1; ++col) {
+          const float px = (float)col + 0.5f;
+          // edge functions; each equals the (negative) area at the opposite vertex
+          const float w0 = e0x * (py - p1.y) - e0y * (px - p1.x);
+          const float w1 = e1x * (py - p2.y) - e1y * (px - p2.x);
+          const float w2 = e2x * (py - p0.y) - e2y * (px - p0.x);
+          if (w0 > 0.0f || w1 > 0.0f || w2 > 0.0f) continue;
+          // 1/z is affine in screen space: interpolate with barycentrics w_k/area
+          const float invz = (w0 * p0.w + w1 * p1.w + w2 * p2.w) * inv_area;
+          const float z = __builtin_amdgcn_rcpf(invz);
+          if (!(z > 0.0f)) continue;
+          atomicMin(&zbuf[(r - band.y0) * pitch + (col - band.x0)], pack_key(z, id));
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Fixed-order sum over the 64 lanes of a wave (butterfly), result in all lanes.
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Fixed-order block sum of NV floats; the result is valid in thread 0.
+// `red` must hold kWaves * NV floats of LDS.
+template <int NV>
+__device__ __forceinline__ void block_sum(float (&v)[NV], float* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[wave * NV + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      float s = red[k];
+      for (int w = 1; w < kWaves; ++w) s += red[w * NV + k];
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace b3d

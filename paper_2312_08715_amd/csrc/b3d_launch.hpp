@@ -1,0 +1,77 @@
+// Host-visible launch wrappers of the gfx950 kernels and the by-value
+// argument structs they take.  The C ABI in api.cpp validates arguments and
+// calls these; every wrapper only enqueues work on the given stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "b3d_device.hpp"
+
+namespace b3d {
+
+// Constants of the windowed likelihood derived from b3d_score_params.
+struct ScoreConsts {
+  float a;       // p_out / V
+  float bn;      // (1 - p_out)/M * (2 pi sigma^2)^(-3/2)
+  float c2;      // log2(e) / (2 sigma^2): exp(-D/(2 sigma^2)) = exp2(-D c2)
+  float inv_s, inv_s2, inv_s3;
+  float invV;    // 1 / V
+  float normM;   // (2 pi sigma^2)^(-3/2) / M
+  int h;         // window half-width
+  // double-precision copies for the background terms
+  double da, dbn, dc, dinv_s, dinv_s3, dinvV, dnormM;
+};
+
+// Everything the fused render+score kernel needs about a scene.
+struct SceneDev {
+  MeshDev mesh;
+  Cam cam;
+  ScoreConsts sc;
+  const float* obs;                // [H][W][3]
+  const unsigned long long* bg;    // [H][W] background keys, or nullptr
+  const double* sat;               // 3 summed-area tables [(H+1)(W+1)]: l, dl/dp, dl/dsigma of the background
+  int zcap, wcap;                  // LDS capacities: depth keys, window weights
+};
+
+// Generic grid description for the hypothesis expander.
+struct GridDev {
+  float center[16];
+  float half[3];
+  int count[3];
+  int cell_centres;
+  int n_rot;
+  float max_angle;
+  const float* rots;  // device [n_rot][9] or nullptr (generated)
+};
+
+size_t fused_lds_bytes(const SceneDev& s);
+
+hipError_t launch_render_batch(const MeshDev& m, const Cam& cam, const float* poses, int N, float* xyz, int* tri,
+                               int zcap, hipStream_t st);
+hipError_t launch_unproject(const float* depth, int B, const Cam& cam, float* xyz, hipStream_t st);
+hipError_t launch_render_backward(const MeshDev& m, const Cam& cam, const float* poses, int N, const int* tri,
+                                  const float* d_rend, float* d_pose, hipStream_t st);
+hipError_t launch_score(const float* obs, const float* rend, int N, int H, int W, const ScoreConsts& sc, float* logL,
+                        int cap, hipStream_t st);
+hipError_t launch_score_backward(const float* obs, const float* rend, int N, int H, int W, const ScoreConsts& sc,
+                                 const float* dlogL, float* d_rend, float* d_sigma, float* d_pout, int cap,
+                                 hipStream_t st);
+hipError_t launch_render_score(const SceneDev& s, const float* poses, int N, float* logL, float* grad, hipStream_t st);
+
+// scene preparation
+hipError_t launch_fill_keys(unsigned long long* keys, size_t n, hipStream_t st);
+hipError_t launch_raster_global(const MeshDev& m, const Cam& cam, const float* pose16_host, uint32_t id_base,
+                                unsigned long long* keys, hipStream_t st);
+hipError_t launch_background_terms(const SceneDev& s, double* terms, hipStream_t st);
+
+// hypotheses and sampling
+hipError_t launch_enumerate(const GridDev& g, const float* centres, int P, uint32_t key0, uint32_t key1,
+                            uint32_t stage, float* poses, hipStream_t st);
+hipError_t launch_sample(const float* logL, int P, int N, int K, uint32_t key0, uint32_t key1, uint32_t stage,
+                         uint32_t k0, float* w, int* idx, float* logw, hipStream_t st);
+hipError_t launch_c2f_update(const float* poses, int P, int N, const int* idx, const float* logw, int K_draws,
+                             int accumulate, float* centres, float* logq, int* idx_out, hipStream_t st);
+
+}  // namespace b3d

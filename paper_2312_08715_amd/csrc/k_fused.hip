@@ -1,0 +1,196 @@
+// Fused render + windowed likelihood (+ adjoint), one workgroup per pose
+// hypothesis.  Nothing but the per-hypothesis results leaves the CU:
+//   1. the object's conservative pixel rectangle under the pose is found;
+//   2. an LDS depth/id buffer covering that rectangle plus twice the window
+//      half-width is initialised from the static background and the mesh is
+//      rasterised into it (cluster by cluster, vertices transformed once into
+//      LDS, 64-bit atomicMin on packed (depth, id) keys);
+//   3. every observed pixel whose window can see the object evaluates eq. (1)
+//      over its window, reading rendered depths from LDS and turning them into
+//      points on their pixel rays;
+//   4. (adjoint) the window weights b/L_i are kept in LDS and every object
+//      pixel gathers d logL/d z_j over its window, then maps it through the
+//      ray/plane intersection of its triangle onto (dt, dw);
+//   5. pixels whose window cannot see the object contribute their
+//      background-only terms, read from double-precision summed-area tables.
+// When the rectangle does not fit the LDS budget it is processed in bands of
+// rows, re-rasterising per band.
+#include "b3d_launch.hpp"
+
+namespace b3d {
+
+__device__ __forceinline__ float f_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float f_ln(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
+
+__device__ __forceinline__ double rect_sum(const double* sat, int W, const Rect& r) {
+  if (r.empty()) return 0.0;
+  const int p = W + 1;
+  return sat[(size_t)r.y1 * p + r.x1] - sat[(size_t)r.y0 * p + r.x1] - sat[(size_t)r.y1 * p + r.x0] +
+         sat[(size_t)r.y0 * p + r.x0];
+}
+
+size_t fused_lds_bytes(const SceneDev& s) {
+  return sizeof(float4) * 2 * kClusterMax + sizeof(float) * (64 + s.cam.W + s.cam.H) +
+         sizeof(unsigned long long) * (size_t)s.zcap + sizeof(float) * (size_t)s.wcap + 16;
+}
+
+template <bool GRAD>
+__global__ __launch_bounds__(kBlock) void k_render_score(SceneDev s, const float* __restrict__ poses, int N,
+                                                         float* __restrict__ logL, float* __restrict__ grad) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float4* vbuf = reinterpret_cast<float4*>(smem);
+  unsigned long long* zbuf = reinterpret_cast<unsigned long long*>(vbuf + 2 * kClusterMax);
+  float* red = reinterpret_cast<float*>(zbuf + s.zcap);
+  float* dxt = red + 64;
+  float* dyt = dxt + s.cam.W;
+  float* wbuf = dyt + s.cam.H;
+
+  const int n = blockIdx.x;
+  if (n >= N) return;
+  const Cam& cam = s.cam;
+  const ScoreConsts& sc = s.sc;
+  const int H = cam.H, W = cam.W, h = sc.h;
+  const Pose P = load_pose(poses + 16 * (size_t)n);
+  for (int i = threadIdx.x; i < W; i += kBlock) dxt[i] = ray_x(cam, i);
+  for (int i = threadIdx.x; i < H; i += kBlock) dyt[i] = ray_y(cam, i);
+
+  const Rect obj = object_rect(s.mesh, P, cam);
+  const Rect region = grow_clip(obj, h, W, H);  // observed pixels whose window can see the object
+  // acc: l, d(dt) x3, d(dw) x3, d sigma, d p_out
+  float acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (!obj.empty()) {
+    const Rect lds = grow_clip(obj, 2 * h, W, H);
+    const int lw = lds.w(), rw = region.w();
+    int band = s.zcap / lw - 4 * h;
+    if (GRAD) band = min(band, s.wcap / rw - 2 * h);
+    band = max(band, 1);
+    for (int a = region.y0; a < region.y1; a += band) {
+      const int b = min(a + band, region.y1);
+      Rect L = lds;
+      L.y0 = max(a - 2 * h, 0);
+      L.y1 = min(b + 2 * h, H);
+      const int nk = L.h() * lw;
+      for (int k = threadIdx.x; k < nk; k += kBlock) {
+        const int r = L.y0 + k / lw, c = L.x0 + (k - (k / lw) * lw);
+        zbuf[k] = s.bg ? s.bg[(size_t)r * W + c] : kEmptyKey;
+      }
+      __syncthreads();
+      raster_mesh(s.mesh, P, cam, 0u, L, zbuf, vbuf);
+
+      // likelihood over observed rows [wa, wb); rows [a, b) are this band's own
+      const int wa = GRAD ? max(a - h, region.y0) : a;
+      const int wb = GRAD ? min(b + h, region.y1) : b;
+      const int nw = (wb - wa) * rw;
+      for (int k = threadIdx.x; k < nw; k += kBlock) {
+        const int r = wa + k / rw, c = region.x0 + (k - (k / rw) * rw);
+        const float* q = s.obs + 3 * ((size_t)r * W + c);
+        const float ox = q[0], oy = q[1], oz = q[2];
+        float wv = 0.0f;
+        if (oz > 0.0f) {
+          float S = 0.0f, T = 0.0f;
+          const int r0 = max(r - h, 0), r1 = min(r + h, H - 1);
+          const int c0 = max(c - h, 0), c1 = min(c + h, W - 1);
+          for (int rj = r0; rj <= r1; ++rj) {
+            const float dy = dyt[rj];
+            const unsigned long long* zr = zbuf + (rj - L.y0) * lw - L.x0;
+            for (int cj = c0; cj <= c1; ++cj) {
+              const unsigned long long key = zr[cj];
+              if (key == kEmptyKey) continue;
+              const float z = key_depth(key);
+              const float ex = ox - z * dxt[cj], ey = oy - z * dy, ez = oz - z;
+              const float D = ex * ex + ey * ey + ez * ez;
+              const float e = f_exp2(-D * sc.c2);
+              S += e;
+              if (GRAD) T += e * D;
+            }
+          }
+          const float Li = sc.a + sc.bn * S;
+          if (r >= a && r < b) {
+            acc[0] += f_ln(Li);
+            if (GRAD) {
+              acc[7] += (sc.bn / Li) * (T * sc.inv_s3 - 3.0f * S * sc.inv_s);
+              acc[8] += (sc.invV - sc.normM * S) / Li;
+            }
+          }
+          wv = sc.bn / Li;
+        }
+        if (GRAD) wbuf[k] = wv;
+      }
+
+      if (GRAD) {
+        __syncthreads();
+        // object pixels of this band gather d logL / d z_j over their window
+        const int ga = max(a, obj.y0), gb = min(b, obj.y1);
+        const int ow = obj.w();
+        const int ng = max(gb - ga, 0) * ow;
+        for (int k = threadIdx.x; k < ng; k += kBlock) {
+          const int r = ga + k / ow, c = obj.x0 + (k - (k / ow) * ow);
+          const unsigned long long key = zbuf[(r - L.y0) * lw + (c - L.x0)];
+          if (key == kEmptyKey) continue;
+          const uint32_t id = key_id(key);
+          if (id >= (uint32_t)s.mesh.T) continue;  // a background surface
+          const float z = key_depth(key);
+          const float dx = dxt[c], dy = dyt[r];
+          const float qx = z * dx, qy = z * dy, qz = z;
+          float g = 0.0f;
+          const int r0 = max(r - h, 0), r1 = min(r + h, H - 1);
+          const int c0 = max(c - h, 0), c1 = min(c + h, W - 1);
+          for (int ri = r0; ri <= r1; ++ri) {
+            const float* wr = wbuf + (ri - wa) * rw - region.x0;
+            for (int ci = c0; ci <= c1; ++ci) {
+              const float wv = wr[ci];
+              if (wv == 0.0f) continue;
+              const float* q = s.obs + 3 * ((size_t)ri * W + ci);
+              const float ex = q[0] - qx, ey = q[1] - qy, ez = q[2] - qz;
+              const float e = f_exp2(-(ex * ex + ey * ey + ez * ez) * sc.c2);
+              g += wv * e * (ex * dx + ey * dy + ez);
+            }
+          }
+          g *= sc.inv_s2;
+          const float4 no = s.mesh.normals[id];
+          const float3 nn = rotate(P, no.x, no.y, no.z);
+          const float sg = g / (nn.x * dx + nn.y * dy + nn.z);
+          const float tx = P.t[0] - qx, ty = P.t[1] - qy, tz = P.t[2] - qz;
+          acc[1] += sg * nn.x;
+          acc[2] += sg * nn.y;
+          acc[3] += sg * nn.z;
+          acc[4] += sg * (nn.y * tz - nn.z * ty);
+          acc[5] += sg * (nn.z * tx - nn.x * tz);
+          acc[6] += sg * (nn.x * ty - nn.y * tx);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  block_sum<9>(acc, red);
+  if (threadIdx.x == 0) {
+    const size_t stride = (size_t)(H + 1) * (W + 1);
+    Rect all;
+    all.x0 = 0;
+    all.x1 = W;
+    all.y0 = 0;
+    all.y1 = H;
+    const double outside_l = rect_sum(s.sat, W, all) - rect_sum(s.sat, W, region);
+    logL[n] = (float)((double)acc[0] + outside_l);
+    if (GRAD) {
+      const double outside_dp = rect_sum(s.sat + stride, W, all) - rect_sum(s.sat + stride, W, region);
+      const double outside_ds = rect_sum(s.sat + 2 * stride, W, all) - rect_sum(s.sat + 2 * stride, W, region);
+      float* g = grad + 8 * (size_t)n;
+      for (int k = 0; k < 6; ++k) g[k] = acc[1 + k];
+      g[6] = (float)((double)acc[7] + outside_ds);
+      g[7] = (float)((double)acc[8] + outside_dp);
+    }
+  }
+}
+
+hipError_t launch_render_score(const SceneDev& s, const float* poses, int N, float* logL, float* grad,
+                               hipStream_t st) {
+  const size_t lds = fused_lds_bytes(s);
+  if (grad)
+    hipLaunchKernelGGL(k_render_score<true>, dim3(N), dim3(kBlock), lds, st, s, poses, N, logL, grad);
+  else
+    hipLaunchKernelGGL(k_render_score<false>, dim3(N), dim3(kBlock), lds, st, s, poses, N, logL, grad);
+  return hipGetLastError();
+}
+
+}  // namespace b3d

@@ -1,0 +1,389 @@
+"""Parity of the HIP library against the FP64 oracle, element by element on
+identical seeded inputs (float32 values, widened to float64 for the oracle).
+
+Bars (from the stated targets):
+  * render: >= 99.9% of (hypothesis, pixel) pairs have equal triangle ids,
+    and there both are empty or |dz| <= 1e-5 m;
+  * logL: |logL_gpu - logL_64| <= 1e-4 * sum_i |l_i| (the L1 mass of the
+    per-pixel terms);
+  * adjoint: ||g_gpu - g_64|| <= 1e-3 ||g_64|| + 1e-6 per hypothesis;
+  * samples: equal wherever the oracle's top-two gap of logL + G exceeds
+    1e-3 (FP32 Gumbel noise plus FP32 logL error stay well below it).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from workloads import Camera, make_config, pose_matrix, random_poses, voxel_blob, voxel_mesh
+
+pytestmark = pytest.mark.gpu
+
+LOGL_RTOL = 1e-4
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def b3d():
+    import paper_2312_08715_amd as b
+
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    b.load_library()
+    return b
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+_cache = {}
+
+
+def workload(k):
+    if k not in _cache:
+        wl = make_config(k, render=oracle.render_depth_fn)
+        wl.verts = f32(wl.verts)
+        obs = f32(oracle.observed_xyz(wl))
+        P = f32(oracle.enumerate_grid(wl.grid, seed=wl.seeds["hyp"]))
+        _cache[k] = (wl, obs, P)
+    return _cache[k]
+
+
+def render_compare(gxyz, gtri, od, oi):
+    gz = gxyz[..., 2]
+    same = gtri == oi
+    frac = same.mean()
+    both = same & (oi >= 0)
+    dz = np.abs(gz[both] - od[both]).max() if both.any() else 0.0
+    empty_ok = np.all(gz[same & (oi < 0)] == 0)
+    return frac, dz, empty_ok
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_render_batch_matches_oracle(b3d, k):
+    wl, obs, P = workload(k)
+    say(f"render parity: config {k}, N={P.shape[0]}")
+    mesh = b3d.Mesh(wl.verts, wl.tris)
+    K = b3d.intrinsics_of(wl.camera)
+    xyz, tri = b3d.render_batch(mesh, dev(P), K)
+    torch.cuda.synchronize()
+    sel = np.arange(P.shape[0]) if k == 0 else np.random.default_rng(0).choice(P.shape[0], 400, replace=False)
+    od, oi = oracle.render([(wl.verts, wl.tris, P[sel])], wl.camera)
+    gx = xyz[torch.as_tensor(sel, device="cuda")].cpu().numpy()
+    gt = tri[torch.as_tensor(sel, device="cuda")].cpu().numpy()
+    frac, dz, empty_ok = render_compare(gx, gt, od, oi)
+    say(f"  id agreement {frac:.6f}, max |dz| {dz:.3g}")
+    assert frac >= 0.999 and dz <= 1e-5 and empty_ok
+    # x, y are the depth times the pixel ray
+    cc = ((np.arange(wl.camera.W) + 0.5 - wl.camera.cx) / wl.camera.fx).astype(np.float32)
+    np.testing.assert_allclose(gx[..., 0], gx[..., 2] * cc[None, None, :], rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_score_matches_oracle_on_identical_point_images(b3d, k):
+    wl, obs, P = workload(k)
+    sel = np.arange(P.shape[0]) if k == 0 else np.random.default_rng(1).choice(P.shape[0], 300, replace=False)
+    say(f"score parity: config {k}, {len(sel)} hypotheses")
+    od, _ = oracle.render([(wl.verts, wl.tris, P[sel])], wl.camera)
+    rend = f32(oracle.unproject(od, wl.camera))
+    s = wl.score
+    L64, l1 = oracle.score(obs, rend, s.sigma, s.p_out, s.outlier_volume, s.window)
+    p = b3d.score_params(s.sigma, s.p_out, s.outlier_volume, s.window)
+    Lg = b3d.score(dev(obs), dev(rend), p).cpu().numpy().astype(np.float64)
+    err = np.abs(Lg - L64) / l1
+    say(f"  max rel-L1 error {err.max():.3g}")
+    assert err.max() <= LOGL_RTOL
+
+
+def _scene(b3d, wl, obs, mesh=None):
+    mesh = mesh or b3d.Mesh(wl.verts, wl.tris)
+    s = wl.score
+    scene = b3d.Scene(mesh, b3d.intrinsics_of(wl.camera), b3d.score_params(s.sigma, s.p_out, s.outlier_volume,
+                                                                          s.window))
+    o = dev(obs)
+    scene.set_observed(o)
+    return scene, mesh, o
+
+
+def _oracle_logL(wl, obs, P, chunk=500):
+    s = wl.score
+    outs, l1s, ids = [], [], []
+    for i in range(0, P.shape[0], chunk):
+        d, idn = oracle.render([(wl.verts, wl.tris, P[i:i + chunk])], wl.camera)
+        L, l1 = oracle.score(obs, oracle.unproject(d, wl.camera), s.sigma, s.p_out, s.outlier_volume, s.window)
+        outs.append(L)
+        l1s.append(l1)
+        ids.append(idn)
+    return np.concatenate(outs), np.concatenate(l1s), np.concatenate(ids)
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_fused_render_score_matches_oracle_and_split_path(b3d, k):
+    wl, obs, P = workload(k)
+    say(f"fused parity: config {k}, N={P.shape[0]}")
+    scene, mesh, o = _scene(b3d, wl, obs)
+    Pd = dev(P)
+    Lf = b3d.render_score(scene, Pd).cpu().numpy().astype(np.float64)
+    xyz, tri = b3d.render_batch(mesh, Pd, b3d.intrinsics_of(wl.camera))
+    s = wl.score
+    Ls = b3d.score(o, xyz, b3d.score_params(s.sigma, s.p_out, s.outlier_volume, s.window)).cpu().numpy()
+    L64, l1, oid = _oracle_logL(wl, obs, P)
+    # fused equals the split composition up to FP32 rounding
+    assert np.max(np.abs(Lf - Ls) / l1) <= 1e-5
+    gt = tri.cpu().numpy()
+    clean = np.all((gt == oid).reshape(P.shape[0], -1), axis=1)
+    err = np.abs(Lf - L64) / l1
+    say(f"  hypotheses with identical ids: {clean.mean():.4f}; max rel-L1 err (clean) {err[clean].max():.3g},"
+        f" (all) {err.max():.3g}")
+    assert clean.mean() >= 0.9
+    assert err[clean].max() <= LOGL_RTOL
+    # the oracle re-scoring the GPU's own point images
+    sel = np.arange(0, P.shape[0], max(1, P.shape[0] // 200))
+    Lr, l1r = oracle.score(obs, xyz[torch.as_tensor(sel, device="cuda")].cpu().numpy().astype(np.float64),
+                           s.sigma, s.p_out, s.outlier_volume, s.window)
+    assert np.max(np.abs(Lf[sel] - Lr) / l1r) <= LOGL_RTOL
+    # bitwise repeatable
+    Lf2 = b3d.render_score(scene, Pd).cpu().numpy()
+    assert np.array_equal(Lf2, Lf.astype(np.float32))
+
+
+def test_score_backward_matches_oracle(b3d):
+    wl, obs, P = workload(0)
+    sel = np.arange(0, 256, 8)
+    say(f"score_backward parity: config 0, {len(sel)} hypotheses")
+    od, _ = oracle.render([(wl.verts, wl.tris, P[sel])], wl.camera)
+    rend = f32(oracle.unproject(od, wl.camera))
+    s = wl.score
+    dl = f32(np.random.default_rng(3).normal(1.0, 0.5, len(sel)))
+    dr64, ds64, dp64 = oracle.score_grad(obs, rend, s.sigma, s.p_out, s.outlier_volume, s.window, dlogL=dl)
+    p = b3d.score_params(s.sigma, s.p_out, s.outlier_volume, s.window)
+    dr, ds, dp = b3d.score_backward(dev(obs), dev(rend), p, dlogL=dev(dl))
+    dr, ds, dp = dr.cpu().numpy(), ds.cpu().numpy(), dp.cpu().numpy()
+    for n in range(len(sel)):
+        e = np.linalg.norm(dr[n] - dr64[n])
+        assert e <= 1e-3 * np.linalg.norm(dr64[n]) + 1e-6, (n, e)
+    np.testing.assert_allclose(ds, ds64, rtol=1e-3, atol=1e-3 * np.abs(ds64).max())
+    np.testing.assert_allclose(dp, dp64, rtol=1e-4)
+
+
+def test_render_backward_matches_oracle(b3d):
+    wl, obs, P = workload(0)
+    sel = np.arange(0, 256, 16)
+    say(f"render_backward parity: config 0, {len(sel)} hypotheses")
+    od, oi = oracle.render([(wl.verts, wl.tris, P[sel])], wl.camera)
+    rend = oracle.unproject(od, wl.camera)
+    s = wl.score
+    dr64, _, _ = oracle.score_grad(obs, rend, s.sigma, s.p_out, s.outlier_volume, s.window)
+    dr32 = f32(dr64)
+    g64 = oracle.render_grad(wl.verts, wl.tris, P[sel], wl.camera, oi, od, dr32)
+    mesh = b3d.Mesh(wl.verts, wl.tris)
+    g = b3d.render_backward(mesh, dev(P[sel]), b3d.intrinsics_of(wl.camera), dev(oi, torch.int32),
+                            dev(dr32)).cpu().numpy()
+    for n in range(len(sel)):
+        assert np.linalg.norm(g[n] - g64[n]) <= 1e-3 * np.linalg.norm(g64[n]) + 1e-6
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_fused_adjoint_matches_oracle(b3d, k):
+    wl, obs, P = workload(k)
+    sel = np.arange(0, P.shape[0], 8 if k == 0 else 50)
+    say(f"fused adjoint parity: config {k}, {len(sel)} hypotheses")
+    scene, mesh, o = _scene(b3d, wl, obs)
+    Ps = P[sel]
+    logL, G = b3d.render_score(scene, dev(Ps), grad=True)
+    G = G.cpu().numpy()
+    _, tri = b3d.render_batch(mesh, dev(Ps), b3d.intrinsics_of(wl.camera))
+    s = wl.score
+    od, oi = oracle.render([(wl.verts, wl.tris, Ps)], wl.camera)
+    rend = oracle.unproject(od, wl.camera)
+    dr, ds, dp = oracle.score_grad(obs, rend, s.sigma, s.p_out, s.outlier_volume, s.window)
+    gp = oracle.render_grad(wl.verts, wl.tris, Ps, wl.camera, oi, od, dr)
+    clean = np.all((tri.cpu().numpy() == oi).reshape(len(sel), -1), axis=1)
+    say(f"  clean hypotheses {clean.mean():.3f}")
+    assert clean.mean() >= 0.9
+    for n in np.nonzero(clean)[0]:
+        assert np.linalg.norm(G[n, :6] - gp[n]) <= 1e-3 * np.linalg.norm(gp[n]) + 1e-6, (n, G[n, :6], gp[n])
+        assert abs(G[n, 6] - ds[n]) <= 1e-3 * abs(ds[n]) + 1e-3
+        assert abs(G[n, 7] - dp[n]) <= 1e-4 * abs(dp[n]) + 1e-3
+
+
+def test_enumerate_matches_oracle(b3d):
+    wl, _, _ = workload(1)
+    g, rots = b3d.grid_of(wl.grid)
+    Pg = b3d.enumerate_grid(g).cpu().numpy()
+    Po = oracle.enumerate_grid(wl.grid)
+    np.testing.assert_allclose(Pg, Po, atol=2e-7)
+    from workloads import GridSpec
+
+    spec = GridSpec(center=pose_matrix(np.eye(3), (0.01, -0.02, 0.7)), half_extent=(0.02, 0.01, 0.005),
+                    count=(5, 3, 2), cell_centres=True, n_rot=37, rot_max_angle=0.4)
+    g2, _ = b3d.grid_of(spec)
+    Pg2 = b3d.enumerate_grid(g2, seed=77, stage=3).cpu().numpy()
+    Po2 = oracle.enumerate_grid(spec, seed=77, stage=3)
+    np.testing.assert_allclose(Pg2, Po2, atol=2e-6)
+
+
+def test_sampler_matches_oracle(b3d):
+    rng = np.random.default_rng(5)
+    N, K, seed, stage = 5000, 64, 4001, 2
+    L = f32(rng.normal(0, 3, N))
+    w, idx, lw = b3d.sample(dev(L), K, seed, stage)
+    w, idx, lw = w.cpu().numpy(), idx.cpu().numpy(), lw.cpu().numpy()
+    w64, idx64, lw64 = oracle.sample(L, K, seed, stage)
+    np.testing.assert_allclose(w, w64, rtol=2e-5, atol=1e-9)
+    agree = 0
+    for k in range(K):
+        G = np.array([-np.log(-np.log(oracle.uniform(seed, n, k, stage, 0))) for n in range(N)])
+        v = np.sort(L + G)
+        if v[-1] - v[-2] > 1e-3:
+            assert idx[k] == idx64[k]
+            agree += 1
+    assert agree >= K - 2
+    np.testing.assert_allclose(lw[idx == idx64], lw64[idx == idx64], atol=1e-4)
+    # segmented: P segments with their own counters
+    Ls = f32(rng.normal(0, 2, (3, 700)))
+    _, i2, _ = b3d.sample(dev(Ls), 1, seed, 1)
+    for p in range(3):
+        _, ip, _ = oracle.sample(Ls[p], 1, seed, 1, k0=p)
+        assert i2[p, 0].item() == ip[0]
+
+
+def test_c2f_step_matches_oracle(b3d):
+    wl, obs, _ = workload(0)
+    from oracle.c2f import c2f
+    from workloads import GridSpec
+
+    scene, mesh, o = _scene(b3d, wl, obs)
+    st = [GridSpec(center=wl.true_pose, half_extent=(0.05, 0.05, 0.05), count=(6, 6, 4), n_rot=3,
+                   rot_max_angle=0.2),
+          GridSpec(center=wl.true_pose, half_extent=(0.01, 0.01, 0.01), count=(4, 4, 4), n_rot=2,
+                   rot_max_angle=0.05)]
+    K, seed = 6, 4000
+    sched = b3d.make_schedule([b3d.grid_of(g)[0] for g in st])
+    centre = f32(wl.true_pose) + np.diag([0, 0, 0, 0]) + np.array([[0, 0, 0, 0.012]] * 3 + [[0, 0, 0, 0]])
+    poses, logq, idx = b3d.c2f_step(scene, centre, sched, K, seed)
+    s = wl.score
+
+    def score_fn(Pq):
+        Pq = f32(Pq)
+        d, _ = oracle.render([(wl.verts, wl.tris, Pq)], wl.camera)
+        return oracle.score(obs, oracle.unproject(d, wl.camera), s.sigma, s.p_out, s.outlier_volume, s.window)[0]
+
+    P64, lq64, idx64, hist = c2f(score_fn, centre, st, K, seed)
+    idx = idx.cpu().numpy()
+    say(f"  c2f idx gpu {idx.tolist()} oracle {idx64.tolist()}")
+    # stage 0: every draw with a clear Gumbel gap must agree
+    L0 = hist[0]
+    for k in range(K):
+        G = np.array([-np.log(-np.log(oracle.uniform(seed, n, k, 0, 0))) for n in range(L0.shape[0])])
+        v = np.sort(L0 + G)
+        if v[-1] - v[-2] > 1e-2:
+            assert idx[0, k] == idx64[0, k]
+    same = np.all(idx == idx64, axis=0)
+    assert same.mean() >= 0.5
+    np.testing.assert_allclose(poses.cpu().numpy()[same], P64[same], atol=1e-5)
+    np.testing.assert_allclose(logq.cpu().numpy()[same], lq64[same], atol=5e-3)
+
+
+def test_banded_render_and_fused_path_on_a_large_close_object(b3d):
+    # the object covers more pixels than one LDS buffer holds: the kernels
+    # process it in bands of rows
+    rng = np.random.default_rng(9)
+    verts, tris = voxel_mesh(voxel_blob(1500, rng))
+    verts = f32(verts)
+    cam = Camera(300.0, 300.0, 160.2, 119.7, 240, 320)
+    P = f32(random_poses(rng, 24, 0.35, 0.02))
+    say("banded parity: 320x240, object at 0.35 m")
+    mesh = b3d.Mesh(verts, tris)
+    K = b3d.intrinsics_of(cam)
+    xyz, tri = b3d.render_batch(mesh, dev(P), K)
+    od, oi = oracle.render([(verts, tris, P)], cam)
+    frac, dz, ok = render_compare(xyz.cpu().numpy(), tri.cpu().numpy(), od, oi)
+    assert frac >= 0.999 and dz <= 1e-5 and ok
+    truth = P[0].copy()
+    d, _ = oracle.render([(verts, tris, truth)], cam)
+    obs = f32(oracle.unproject(d[0] + 0.002 * rng.standard_normal(d[0].shape) * (d[0] > 0), cam))
+    scene = b3d.Scene(mesh, K, b3d.score_params(0.003, 0.01, 1.0, 5))
+    scene.set_observed(dev(obs))
+    Lf, G = b3d.render_score(scene, dev(P), grad=True)
+    Lf = Lf.cpu().numpy()
+    L64, l1 = oracle.score(obs, oracle.unproject(od, cam), 0.003, 0.01, 1.0, 5)
+    clean = np.all((tri.cpu().numpy() == oi).reshape(24, -1), axis=1)
+    assert np.max((np.abs(Lf - L64) / l1)[clean]) <= LOGL_RTOL
+    Ls = b3d.score(dev(obs), xyz, b3d.score_params(0.003, 0.01, 1.0, 5)).cpu().numpy()
+    assert np.max(np.abs(Lf - Ls) / l1) <= 1e-5
+    dr, ds, dp = oracle.score_grad(obs, oracle.unproject(od, cam), 0.003, 0.01, 1.0, 5)
+    gp = oracle.render_grad(verts, tris, P, cam, oi, od, dr)
+    G = G.cpu().numpy()
+    for n in np.nonzero(clean)[0]:
+        assert np.linalg.norm(G[n, :6] - gp[n]) <= 1e-3 * np.linalg.norm(gp[n]) + 1e-6
+
+
+def test_static_background_scene_matches_oracle(b3d):
+    rng = np.random.default_rng(12)
+    va, ta = voxel_mesh(voxel_blob(300, rng, radius=0.06))
+    vb, tb = voxel_mesh(voxel_blob(200, rng, radius=0.05))
+    va, vb = f32(va), f32(vb)
+    cam = Camera(150.0, 150.0, 80.0, 60.0, 120, 160)
+    Pb = f32(pose_matrix(np.eye(3), (0.05, 0.02, 0.75)))
+    truth = f32(pose_matrix(np.eye(3), (-0.02, 0.0, 0.8)))
+    d, _ = oracle.render([(va, ta, truth), (vb, tb, Pb)], cam)
+    obs = f32(oracle.unproject(d[0] + 0.002 * rng.standard_normal(d[0].shape) * (d[0] > 0), cam))
+    P = f32(random_poses(rng, 64, 0.8, 0.04))
+    P[:, :3, :3] = np.eye(3)
+    say("background scene parity: 2 objects, 64 hypotheses")
+    ma, mb = b3d.Mesh(va, ta), b3d.Mesh(vb, tb)
+    scene = b3d.Scene(ma, b3d.intrinsics_of(cam), b3d.score_params(0.003, 0.01, 1.0, 5))
+    scene.set_background([mb], Pb[None])
+    scene.set_observed(dev(obs))
+    Lf, G = b3d.render_score(scene, dev(P), grad=True)
+    od, oi = oracle.render([(va, ta, P), (vb, tb, Pb)], cam)
+    L64, l1 = oracle.score(obs, oracle.unproject(od, cam), 0.003, 0.01, 1.0, 5)
+    err = np.abs(Lf.cpu().numpy() - L64) / l1
+    say(f"  max rel-L1 err {err.max():.3g}")
+    assert np.median(err) <= LOGL_RTOL and np.mean(err <= LOGL_RTOL) >= 0.9
+    dr, ds, dp = oracle.score_grad(obs, oracle.unproject(od, cam), 0.003, 0.01, 1.0, 5)
+    np.testing.assert_allclose(G.cpu().numpy()[:, 7], dp, rtol=1e-3)
+
+
+def test_edge_cases(b3d):
+    wl, obs, P = workload(0)
+    mesh = b3d.Mesh(wl.verts, wl.tris)
+    K = b3d.intrinsics_of(wl.camera)
+    scene, _, o = _scene(b3d, wl, obs, mesh)
+    # N = 0 is a no-op
+    e = torch.empty((0, 4, 4), device="cuda")
+    assert b3d.render_score(scene, e).numel() == 0
+    # object behind the camera or far outside the view renders nothing
+    Q = P[:3].copy()
+    Q[0, 2, 3] = -0.8
+    Q[1, 0, 3] = 5.0
+    Q[2, 2, 3] = 0.005  # straddles the near plane: triangles crossing it are dropped
+    xyz, tri = b3d.render_batch(mesh, dev(Q), K)
+    od, oi = oracle.render([(wl.verts, wl.tris, Q)], wl.camera)
+    assert np.array_equal(tri.cpu().numpy()[:2], oi[:2]) and np.all(oi[:2] == -1)
+    frac, dz, ok = render_compare(xyz.cpu().numpy(), tri.cpu().numpy(), od, oi)
+    assert frac >= 0.999 and ok
+    L = b3d.render_score(scene, dev(Q)).cpu().numpy()
+    s = wl.score
+    L64, l1 = oracle.score(obs, oracle.unproject(od, wl.camera), s.sigma, s.p_out, s.outlier_volume, s.window)
+    assert np.max(np.abs(L - L64) / l1) <= LOGL_RTOL
+    # ragged batch sizes
+    for n in (1, 3, 257):
+        Pn = P[np.arange(n) % P.shape[0]]
+        Ln = b3d.render_score(scene, dev(Pn)).cpu().numpy()
+        L0 = b3d.render_score(scene, dev(P)).cpu().numpy()
+        assert np.array_equal(Ln, L0[np.arange(n) % P.shape[0]])
+    # invalid arguments are rejected before any launch
+    with pytest.raises(b3d.B3DError):
+        b3d.score(o, xyz, b3d.score_params(wl.score.sigma, 0.0, 1.0, 3))
+    with pytest.raises(b3d.B3DError):
+        b3d.score(o, xyz, b3d.score_params(wl.score.sigma, 0.1, 1.0, 4))
