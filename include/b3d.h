@@ -181,6 +181,33 @@ b3d_status b3d_scene_set_observed(b3d_scene* scene, const float* observed, void*
 b3d_status b3d_render_score(const b3d_scene* scene, const float* poses, int32_t N, float* logL_out, float* grad_out,
                             void* stream);
 
+/* ---- many scenes in one persistent launch ------------------------------ */
+
+/* One scene's share of a batch: N hypotheses of the scene's moving object. */
+typedef struct b3d_batch_item {
+  const b3d_scene* scene; /* with its observed image set */
+  const float* poses;     /* device float[N][16] */
+  int32_t N;
+  float* logL_out;        /* device float[N] */
+  float* grad_out;        /* device float[N][8] or NULL; NULL for all items or for none */
+} b3d_batch_item;
+
+typedef struct b3d_batch b3d_batch;
+
+/* Freeze a list of scenes and their hypothesis buffers into one launch
+ * plan: scenes are ordered by estimated cost per hypothesis (largest first)
+ * and their hypotheses form one work list that a persistent grid of
+ * workgroups drains through a device counter.  The plan copies each scene's
+ * state (observed image pointer, background, parameters) at this call:
+ * re-create it after changing a scene.  Scenes of different image sizes,
+ * meshes and hypothesis counts may be mixed.  Allocates device memory (not
+ * stream-ordered).  Results equal b3d_render_score per scene. */
+b3d_status b3d_batch_create(const b3d_batch_item* items, int32_t S, b3d_batch** out);
+/* Run the plan: one counter reset and one persistent kernel.  Stream-ordered;
+ * graph-capture safe. */
+b3d_status b3d_batch_run(const b3d_batch* batch, void* stream);
+b3d_status b3d_batch_destroy(b3d_batch* batch);
+
 /* ---- hypotheses, normalisation, sampling, coarse-to-fine --------------- */
 
 /* A hypothesis grid around a centre pose (the cells of one stage of a

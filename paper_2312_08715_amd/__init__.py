@@ -44,6 +44,11 @@ class Grid(ctypes.Structure):
                 ("rotations", ctypes.c_void_p)]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_void_p), ("poses", ctypes.c_void_p), ("N", ctypes.c_int32),
+                ("logL_out", ctypes.c_void_p), ("grad_out", ctypes.c_void_p)]
+
+
 class Schedule(ctypes.Structure):
     _fields_ = [("n_stages", ctypes.c_int32), ("stages", Grid * B3D_MAX_STAGES)]
 
@@ -73,6 +78,9 @@ _SIGNATURES = {
     "b3d_scene_set_background": ([_P, _P, _P, _I32, _P], ctypes.c_int),
     "b3d_scene_set_observed": ([_P, _P, _P], ctypes.c_int),
     "b3d_render_score": ([_P, _P, _I32, _P, _P, _P], ctypes.c_int),
+    "b3d_batch_create": ([ctypes.POINTER(BatchItem), _I32, ctypes.POINTER(_P)], ctypes.c_int),
+    "b3d_batch_run": ([_P, _P], ctypes.c_int),
+    "b3d_batch_destroy": ([_P], ctypes.c_int),
     "b3d_grid_size": ([ctypes.POINTER(Grid)], ctypes.c_int64),
     "b3d_enumerate": ([ctypes.POINTER(Grid), _U64, _I32, _P, _P], ctypes.c_int),
     "b3d_sample": ([_P, _I32, _I32, _I32, _U64, _U32, _U32, _P, _P, _P, _P], ctypes.c_int),
@@ -343,3 +351,39 @@ def c2f_step(scene: Scene, center, schedule: Schedule, K: int, seed: int, device
     _call("b3d_c2f_step", scene.handle, c.ctypes.data, ctypes.byref(schedule), int(K), int(seed), _ptr(ws),
           int(nb.value), _ptr(poses), _ptr(logq), _ptr(idx), _stream())
     return poses, logq, idx
+
+
+class Batch:
+    """Many scenes in one persistent launch (b3d_batch_create / b3d_batch_run).
+
+    ``items`` is a list of (scene, poses [N,4,4]); outputs are allocated here:
+    ``logL[i]`` [N_i] and, with grad, ``grad[i]`` [N_i, 8]."""
+
+    def __init__(self, items, grad: bool = False):
+        self.scenes = [s for s, _ in items]
+        self.poses = [P.contiguous() for _, P in items]
+        self.logL = [torch.empty(P.shape[0], dtype=torch.float32, device=P.device) for P in self.poses]
+        self.grad = [torch.empty((P.shape[0], 8), dtype=torch.float32, device=P.device) for P in self.poses] \
+            if grad else None
+        arr = (BatchItem * len(items))()
+        for i, (s, P) in enumerate(zip(self.scenes, self.poses)):
+            arr[i] = BatchItem(s.handle.value if hasattr(s.handle, "value") else s.handle, _ptr(P, torch.float32),
+                               int(P.shape[0]), _ptr(self.logL[i]), _ptr(self.grad[i]) if grad else None)
+        h = _P()
+        _call("b3d_batch_create", arr, len(items), ctypes.byref(h))
+        self._h = h
+
+    def run(self):
+        _call("b3d_batch_run", self._h, _stream())
+        return (self.logL, self.grad) if self.grad is not None else self.logL
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().b3d_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

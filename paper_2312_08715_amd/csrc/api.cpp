@@ -112,6 +112,16 @@ struct b3d_mesh {
   std::vector<void*> allocs;
 };
 
+struct b3d_batch {
+  BatchItemDev* items = nullptr;
+  unsigned long long* counter = nullptr;
+  int S = 0;
+  long long total = 0;
+  bool grad = false;
+  size_t lds = 0;
+  int blocks = 0;
+};
+
 struct b3d_scene {
   const b3d_mesh* mesh = nullptr;
   b3d_intrinsics K{};
@@ -414,6 +424,13 @@ b3d_status b3d_scene_set_background(b3d_scene* S, const b3d_mesh* const* meshes,
                   "scene_set_background");
     base += (uint64_t)meshes[i]->T;
   }
+  base = (uint64_t)S->mesh->T;
+  for (int i = 0; i < n; ++i) {
+    B3D_CHECK_HIP(launch_refine_global(meshes[i]->dev, S->dev.cam, poses + 16 * (size_t)i, nullptr, (uint32_t)base,
+                                       S->bg, st),
+                  "scene_set_background");
+    base += (uint64_t)meshes[i]->T;
+  }
   S->has_bg = true;
   S->dev.bg = S->bg;
   return B3D_OK;
@@ -435,6 +452,80 @@ b3d_status b3d_render_score(const b3d_scene* S, const float* poses, int32_t N, f
   if (N == 0) return B3D_OK;
   if (!poses || !logL_out) return fail(B3D_EINVAL, "render_score: NULL pointer");
   B3D_CHECK_HIP(launch_render_score(S->dev, poses, N, logL_out, grad_out, (hipStream_t)stream), "render_score");
+  return B3D_OK;
+}
+
+b3d_status b3d_batch_create(const b3d_batch_item* items, int32_t S, b3d_batch** out) {
+  if (!items || !out) return fail(B3D_EINVAL, "batch_create: NULL pointer");
+  if (S < 1) return fail(B3D_ESHAPE, "batch_create: need at least one item");
+  const bool grad = items[0].grad_out != nullptr;
+  std::vector<int> order((size_t)S);
+  std::vector<double> cost((size_t)S);
+  size_t lds = 0;
+  for (int i = 0; i < S; ++i) {
+    const b3d_batch_item& it = items[i];
+    if (!it.scene) return fail(B3D_EINVAL, "batch_create: item %d has no scene", i);
+    if (!it.scene->observed) return fail(B3D_EINVAL, "batch_create: item %d: scene has no observed image", i);
+    if (it.N < 0) return fail(B3D_ESHAPE, "batch_create: item %d: N < 0", i);
+    if (it.N > 0 && (!it.poses || !it.logL_out)) return fail(B3D_EINVAL, "batch_create: item %d: NULL buffer", i);
+    if ((it.grad_out != nullptr) != grad)
+      return fail(B3D_ENOTSUP, "batch_create: grad_out must be given for all items or for none");
+    order[i] = i;
+    const SceneDev& d = it.scene->dev;
+    cost[i] = (double)d.mesh.T + 0.25 * (double)d.cam.H * d.cam.W;
+    lds = std::max(lds, fused_lds_bytes(d));
+  }
+  if (lds > kLdsMax) return fail(B3D_ESHAPE, "batch_create: LDS budget exceeded");
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::vector<BatchItemDev> host((size_t)S);
+  long long first = 0;
+  for (int k = 0; k < S; ++k) {
+    const b3d_batch_item& it = items[order[k]];
+    BatchItemDev& d = host[k];
+    d.s = it.scene->dev;
+    d.poses = it.poses;
+    d.logL = it.logL_out;
+    d.grad = it.grad_out;
+    d.first = first;
+    d.N = it.N;
+    first += it.N;
+  }
+  int dev = 0, cus = 0, occ = 0;
+  B3D_CHECK_HIP(hipGetDevice(&dev), "batch_create");
+  B3D_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "batch_create");
+  B3D_CHECK_HIP(batch_occupancy(grad, lds, &occ), "batch_create");
+  b3d_batch* b = new b3d_batch();
+  b->S = S;
+  b->total = first;
+  b->grad = grad;
+  b->lds = lds;
+  b->blocks = (int)std::max<long long>(1, std::min<long long>((long long)cus * std::max(occ, 1), first));
+  if (hipMalloc((void**)&b->items, sizeof(BatchItemDev) * (size_t)S) != hipSuccess ||
+      hipMalloc((void**)&b->counter, 256) != hipSuccess ||
+      hipMemcpy(b->items, host.data(), sizeof(BatchItemDev) * (size_t)S, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(b->items);
+    (void)hipFree(b->counter);
+    delete b;
+    return fail(B3D_ENOMEM, "batch_create: device allocation failed");
+  }
+  *out = b;
+  return B3D_OK;
+}
+
+b3d_status b3d_batch_run(const b3d_batch* b, void* stream) {
+  if (!b) return fail(B3D_EINVAL, "batch_run: NULL batch");
+  if (b->total == 0) return B3D_OK;
+  B3D_CHECK_HIP(launch_batch(b->items, b->S, b->total, b->counter, b->grad, b->lds, b->blocks, (hipStream_t)stream),
+                "batch_run");
+  return B3D_OK;
+}
+
+b3d_status b3d_batch_destroy(b3d_batch* b) {
+  if (!b) return B3D_OK;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(b->items);
+  (void)hipFree(b->counter);
+  delete b;
   return B3D_OK;
 }
 

@@ -220,6 +220,49 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
   __syncthreads();
 }
 
+// Depth of pixel (r, c) on the plane of triangle `id` under pose P: the ray
+// z d meets the plane n.(x - c0) = 0 at z = (n.c0)/(n.d), with
+// c_k = R v_k + t and n = (c1 - c0) x (c2 - c0), all in double precision.
+// The rasteriser's interpolated 1/z decides visibility; this value is the
+// depth reported and scored.  (For a triangle seen nearly edge-on the depth
+// is ill-conditioned in the vertex coordinates, and single precision would
+// put errors of several micrometres into the point and its gradient.)
+__device__ __forceinline__ float plane_depth(const MeshDev& m, const Pose& P, const Cam& cam, uint32_t id, int r,
+                                             int c) {
+  const int4 tr = m.tris[id];
+  const float4 v[3] = {m.verts[tr.x], m.verts[tr.y], m.verts[tr.z]};
+  double q[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      q[k][i] = (double)P.r[3 * i] * v[k].x + (double)P.r[3 * i + 1] * v[k].y + (double)P.r[3 * i + 2] * v[k].z +
+                (double)P.t[i];
+  const double e1[3] = {q[1][0] - q[0][0], q[1][1] - q[0][1], q[1][2] - q[0][2]};
+  const double e2[3] = {q[2][0] - q[0][0], q[2][1] - q[0][1], q[2][2] - q[0][2]};
+  const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+  const double dx = ((double)c + 0.5 - (double)cam.cx) / (double)cam.fx;
+  const double dy = ((double)r + 0.5 - (double)cam.cy) / (double)cam.fy;
+  return (float)((n[0] * q[0][0] + n[1] * q[0][1] + n[2] * q[0][2]) / (n[0] * dx + n[1] * dy + n[2]));
+}
+
+// Replace the depth of every band pixel drawn by this mesh (id - id_base in
+// [0, T)) by plane_depth, keeping its id.  Whole block; ends with a barrier.
+__device__ __forceinline__ void refine_depths(const MeshDev& m, const Pose& P, const Cam& cam, uint32_t id_base,
+                                              const Rect& band, unsigned long long* zbuf) {
+  const int pitch = band.w();
+  const int np = band.h() * pitch;
+  for (int k = threadIdx.x; k < np; k += kBlock) {
+    const unsigned long long key = zbuf[k];
+    if (key == kEmptyKey) continue;
+    const uint32_t id = key_id(key) - id_base;
+    if (id >= (uint32_t)m.T) continue;
+    const int r = band.y0 + k / pitch, c = band.x0 + (k - (k / pitch) * pitch);
+    zbuf[k] = pack_key(plane_depth(m, P, cam, id, r, c), key_id(key));
+  }
+  __syncthreads();
+}
+
 // Fixed-order sum over the 64 lanes of a wave (butterfly), result in all lanes.
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll

@@ -35,6 +35,16 @@ struct SceneDev {
   int zcap, wcap;                  // LDS capacities: depth keys, window weights
 };
 
+// One scene of a multi-scene batch: its hypotheses are work items
+// [first, first + N) of the flattened list.
+struct BatchItemDev {
+  SceneDev s;
+  const float* poses;
+  float* logL;
+  float* grad;
+  long long first, N;
+};
+
 // Generic grid description for the hypothesis expander.
 struct GridDev {
   float center[16];
@@ -60,10 +70,16 @@ hipError_t launch_score_backward(const float* obs, const float* rend, int N, int
                                  hipStream_t st);
 hipError_t launch_render_score(const SceneDev& s, const float* poses, int N, float* logL, float* grad, hipStream_t st);
 
+hipError_t batch_occupancy(bool grad, size_t lds, int* blocks_per_cu);
+hipError_t launch_batch(const BatchItemDev* items, int S, long long total, unsigned long long* counter, bool grad,
+                        size_t lds, int blocks, hipStream_t st);
+
 // scene preparation
 hipError_t launch_fill_keys(unsigned long long* keys, size_t n, hipStream_t st);
 hipError_t launch_raster_global(const MeshDev& m, const Cam& cam, const float* pose16_host, uint32_t id_base,
                                 unsigned long long* keys, hipStream_t st);
+hipError_t launch_refine_global(const MeshDev& m, const Cam& cam, const float* pose16_host, const float* pose16_dev,
+                                uint32_t id_base, unsigned long long* keys, hipStream_t st);
 hipError_t launch_background_terms(const SceneDev& s, double* terms, hipStream_t st);
 
 // hypotheses and sampling

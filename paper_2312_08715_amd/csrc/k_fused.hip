@@ -34,10 +34,13 @@ size_t fused_lds_bytes(const SceneDev& s) {
          sizeof(unsigned long long) * (size_t)s.zcap + sizeof(float) * (size_t)s.wcap + 16;
 }
 
+// One hypothesis: pose16 (16 floats), writes *logL_out and, when GRAD,
+// grad_out[0..8).  Must be called by the whole block; `smem` is at least
+// fused_lds_bytes(s).
 template <bool GRAD>
-__global__ __launch_bounds__(kBlock) void k_render_score(SceneDev s, const float* __restrict__ poses, int N,
-                                                         float* __restrict__ logL, float* __restrict__ grad) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void render_score_one(const SceneDev& s, const float* __restrict__ pose16,
+                                                 float* __restrict__ logL_out, float* __restrict__ grad_out,
+                                                 unsigned char* smem) {
   float4* vbuf = reinterpret_cast<float4*>(smem);
   unsigned long long* zbuf = reinterpret_cast<unsigned long long*>(vbuf + 2 * kClusterMax);
   float* red = reinterpret_cast<float*>(zbuf + s.zcap);
@@ -45,12 +48,10 @@ __global__ __launch_bounds__(kBlock) void k_render_score(SceneDev s, const float
   float* dyt = dxt + s.cam.W;
   float* wbuf = dyt + s.cam.H;
 
-  const int n = blockIdx.x;
-  if (n >= N) return;
   const Cam& cam = s.cam;
   const ScoreConsts& sc = s.sc;
   const int H = cam.H, W = cam.W, h = sc.h;
-  const Pose P = load_pose(poses + 16 * (size_t)n);
+  const Pose P = load_pose(pose16);
   for (int i = threadIdx.x; i < W; i += kBlock) dxt[i] = ray_x(cam, i);
   for (int i = threadIdx.x; i < H; i += kBlock) dyt[i] = ray_y(cam, i);
 
@@ -76,6 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_render_score(SceneDev s, const float
       }
       __syncthreads();
       raster_mesh(s.mesh, P, cam, 0u, L, zbuf, vbuf);
+      refine_depths(s.mesh, P, cam, 0u, L, zbuf);
 
       // likelihood over observed rows [wa, wb); rows [a, b) are this band's own
       const int wa = GRAD ? max(a - h, region.y0) : a;
@@ -171,16 +173,72 @@ __global__ __launch_bounds__(kBlock) void k_render_score(SceneDev s, const float
     all.y0 = 0;
     all.y1 = H;
     const double outside_l = rect_sum(s.sat, W, all) - rect_sum(s.sat, W, region);
-    logL[n] = (float)((double)acc[0] + outside_l);
+    *logL_out = (float)((double)acc[0] + outside_l);
     if (GRAD) {
       const double outside_dp = rect_sum(s.sat + stride, W, all) - rect_sum(s.sat + stride, W, region);
       const double outside_ds = rect_sum(s.sat + 2 * stride, W, all) - rect_sum(s.sat + 2 * stride, W, region);
-      float* g = grad + 8 * (size_t)n;
+      float* g = grad_out;
       for (int k = 0; k < 6; ++k) g[k] = acc[1 + k];
       g[6] = (float)((double)acc[7] + outside_ds);
       g[7] = (float)((double)acc[8] + outside_dp);
     }
   }
+}
+
+template <bool GRAD>
+__global__ __launch_bounds__(kBlock) void k_render_score(SceneDev s, const float* __restrict__ poses, int N,
+                                                         float* __restrict__ logL, float* __restrict__ grad) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = blockIdx.x;
+  if (n >= N) return;
+  render_score_one<GRAD>(s, poses + 16 * (size_t)n, logL + n, GRAD ? grad + 8 * (size_t)n : nullptr, smem);
+}
+
+// Many scenes in one persistent launch: every block pulls the next
+// (scene, hypothesis) item from a device counter until the list is drained.
+// Items are numbered scene by scene in the order the host chose (longest
+// first), so the expensive scenes start early and the cheap ones fill the
+// tail.  Every block exits once the counter passes the total.
+template <bool GRAD>
+__global__ __launch_bounds__(kBlock) void k_batch(const BatchItemDev* __restrict__ items, int S, long long total,
+                                                  unsigned long long* __restrict__ counter) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ long long work;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) work = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    const long long w = work;
+    if (w >= total) break;
+    int lo = 0, hi = S;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (items[mid].first <= w) lo = mid;
+      else hi = mid;
+    }
+    const BatchItemDev& it = items[lo];
+    const long long n = w - it.first;
+    render_score_one<GRAD>(it.s, it.poses + 16 * n, it.logL + n, GRAD ? it.grad + 8 * n : nullptr, smem);
+  }
+}
+
+__global__ void k_reset_counter(unsigned long long* c) {
+  if (threadIdx.x == 0) c[threadIdx.x] = 0ull;
+}
+
+hipError_t batch_occupancy(bool grad, size_t lds, int* blocks_per_cu) {
+  if (grad) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch<true>, kBlock, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch<false>, kBlock, lds);
+}
+
+hipError_t launch_batch(const BatchItemDev* items, int S, long long total, unsigned long long* counter, bool grad,
+                        size_t lds, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
+  if (grad)
+    hipLaunchKernelGGL(k_batch<true>, dim3(blocks), dim3(kBlock), lds, st, items, S, total, counter);
+  else
+    hipLaunchKernelGGL(k_batch<false>, dim3(blocks), dim3(kBlock), lds, st, items, S, total, counter);
+  return hipGetLastError();
 }
 
 hipError_t launch_render_score(const SceneDev& s, const float* poses, int N, float* logL, float* grad,

@@ -71,6 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_render_batch(MeshDev m, Cam cam, con
     for (int k = threadIdx.x; k < nk; k += kBlock) zbuf[k] = kEmptyKey;
     __syncthreads();
     raster_mesh(m, P, cam, 0u, band, zbuf, vbuf);
+    refine_depths(m, P, cam, 0u, band, zbuf);
     write_rows(cam, band.y0, band.y1, band, zbuf, 0u, xn, tn);
     __syncthreads();
   }
@@ -123,13 +124,10 @@ __global__ __launch_bounds__(kBlock) void k_render_backward(MeshDev m, Cam cam, 
     const float dx = ray_x(cam, c), dy = ray_y(cam, r);
     const float g = dn[3 * p] * dx + dn[3 * p + 1] * dy + dn[3 * p + 2];
     if (g == 0.0f) continue;
-    const int4 tr = m.tris[id];
-    const float4 v0 = m.verts[tr.x];
     const float4 no = m.normals[id];
-    const float3 c0 = xform(P, v0.x, v0.y, v0.z);
     const float3 nn = rotate(P, no.x, no.y, no.z);
     const float nd = nn.x * dx + nn.y * dy + nn.z;
-    const float z = (nn.x * c0.x + nn.y * c0.y + nn.z * c0.z) / nd;
+    const float z = plane_depth(m, P, cam, (uint32_t)id, r, c);
     const float tx = P.t[0] - z * dx, ty = P.t[1] - z * dy, tz = P.t[2] - z;
     const float s = g / nd;
     acc[0] += s * nn.x;
@@ -204,6 +202,21 @@ __global__ void k_raster_global(MeshDev m, Cam cam, Pose P, uint32_t id_base, un
   }
 }
 
+// Exact plane depth for every pixel of a full-image key buffer drawn by this
+// mesh (see plane_depth); the pose comes from `pose16_dev` when not null.
+__global__ void k_refine_global(MeshDev m, Cam cam, Pose P, const float* __restrict__ pose16_dev, uint32_t id_base,
+                                unsigned long long* keys) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= cam.H * cam.W) return;
+  const unsigned long long key = keys[p];
+  if (key == kEmptyKey) return;
+  const uint32_t id = key_id(key) - id_base;
+  if (id >= (uint32_t)m.T) return;
+  const Pose Q = pose16_dev ? load_pose(pose16_dev) : P;
+  const int r = p / cam.W, c = p - r * cam.W;
+  keys[p] = pack_key(plane_depth(m, Q, cam, id, r, c), key_id(key));
+}
+
 hipError_t launch_raster_global(const MeshDev& m, const Cam& cam, const float* pose16, uint32_t id_base,
                                 unsigned long long* keys, hipStream_t st) {
   Pose P;
@@ -212,6 +225,19 @@ hipError_t launch_raster_global(const MeshDev& m, const Cam& cam, const float* p
     P.t[i] = pose16[4 * i + 3];
   }
   hipLaunchKernelGGL(k_raster_global, dim3((m.T + 255) / 256), dim3(256), 0, st, m, cam, P, id_base, keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_global(const MeshDev& m, const Cam& cam, const float* pose16_host, const float* pose16_dev,
+                                uint32_t id_base, unsigned long long* keys, hipStream_t st) {
+  Pose P = {};
+  if (pose16_host)
+    for (int i = 0; i < 3; ++i) {
+      for (int j = 0; j < 3; ++j) P.r[3 * i + j] = pose16_host[4 * i + j];
+      P.t[i] = pose16_host[4 * i + 3];
+    }
+  hipLaunchKernelGGL(k_refine_global, dim3((cam.H * cam.W + 255) / 256), dim3(256), 0, st, m, cam, P, pose16_dev,
+                     id_base, keys);
   return hipGetLastError();
 }
 

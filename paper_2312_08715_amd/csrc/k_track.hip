@@ -1,0 +1,159 @@
+// Pose refinement and tracking helpers: Adam ascent on the pose tangent,
+// best-hypothesis selection, and drawing static objects whose poses live in
+// device memory (so that a captured frame graph sees the latest estimates).
+#include "b3d_launch.hpp"
+
+namespace b3d {
+
+// Adam ascent on logL for each pose n, on the tangent (dt, dw):
+// m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2, s = lr * mhat / (sqrt(vhat) + eps),
+// then t <- t + s[0:3], R <- exp([s[3:6]]x) R.  state [N][12] = (m, v).
+__global__ void k_adam_pose(float* __restrict__ poses, const float* __restrict__ grad, int gstride,
+                            float* __restrict__ state, int N, int iter, float lr_t, float lr_r, float b1, float b2,
+                            float eps) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float* P = poses + 16 * (size_t)n;
+  const float* g = grad + (size_t)gstride * n;
+  float* m = state + 12 * (size_t)n;
+  float* v = m + 6;
+  const float c1 = 1.0f - powf(b1, (float)iter), c2 = 1.0f - powf(b2, (float)iter);
+  float s[6];
+  for (int k = 0; k < 6; ++k) {
+    m[k] = b1 * m[k] + (1.0f - b1) * g[k];
+    v[k] = b2 * v[k] + (1.0f - b2) * g[k] * g[k];
+    const float mh = m[k] / c1, vh = v[k] / c2;
+    s[k] = (k < 3 ? lr_t : lr_r) * mh / (sqrtf(vh) + eps);
+  }
+  for (int k = 0; k < 3; ++k) P[4 * k + 3] += s[k];
+  const float wx = s[3], wy = s[4], wz = s[5];
+  const float th = sqrtf(wx * wx + wy * wy + wz * wz);
+  if (th > 0.0f) {
+    const float kx = wx / th, ky = wy / th, kz = wz / th;
+    const float sn = sinf(th), cs = 1.0f - cosf(th);
+    const float E[9] = {1.0f + cs * (kx * kx - 1.0f), -sn * kz + cs * kx * ky,       sn * ky + cs * kx * kz,
+                        sn * kz + cs * kx * ky,       1.0f + cs * (ky * ky - 1.0f), -sn * kx + cs * ky * kz,
+                        -sn * ky + cs * kx * kz,      sn * kx + cs * ky * kz,       1.0f + cs * (kz * kz - 1.0f)};
+    float R[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) R[3 * i + j] = E[3 * i] * P[j] + E[3 * i + 1] * P[4 + j] + E[3 * i + 2] * P[8 + j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) P[4 * i + j] = R[3 * i + j];
+  }
+}
+
+hipError_t launch_adam_pose(float* poses, const float* grad, int gstride, float* state, int N, int iter, float lr_t,
+                            float lr_r, float b1, float b2, float eps, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam_pose, dim3((N + 63) / 64), dim3(64), 0, st, poses, grad, gstride, state, N, iter, lr_t,
+                     lr_r, b1, b2, eps);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, size_t n, float v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t st) {
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_fill_f32, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+// out = poses[argmax logL] (ties to the lowest index); one block.
+__global__ __launch_bounds__(kBlock) void k_argmax_pose(const float* __restrict__ logL, const float* __restrict__ poses,
+                                                        int N, float* __restrict__ out) {
+  __shared__ float rv[kWaves];
+  __shared__ int ri[kWaves];
+  __shared__ int best;
+  float bv = -INFINITY;
+  int bi = -1;
+  for (int n = threadIdx.x; n < N; n += kBlock)
+    if (bi < 0 || logL[n] > bv) {
+      bv = logL[n];
+      bi = n;
+    }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const float ov = __shfl_xor(bv, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (oi >= 0 && (bi < 0 || ov > bv || (ov == bv && oi < bi))) {
+      bv = ov;
+      bi = oi;
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    rv[wave] = bv;
+    ri[wave] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bv = rv[0];
+    bi = ri[0];
+    for (int i = 1; i < kWaves; ++i)
+      if (ri[i] >= 0 && (bi < 0 || rv[i] > bv || (rv[i] == bv && ri[i] < bi))) {
+        bv = rv[i];
+        bi = ri[i];
+      }
+    best = bi < 0 ? 0 : bi;
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) out[threadIdx.x] = poses[16 * (size_t)best + threadIdx.x];
+}
+
+hipError_t launch_argmax_pose(const float* logL, const float* poses, int N, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_argmax_pose, dim3(1), dim3(kBlock), 0, st, logL, poses, N, out);
+  return hipGetLastError();
+}
+
+// As k_raster_global, with the pose read from device memory.
+__global__ void k_raster_global_dev(MeshDev m, Cam cam, const float* __restrict__ pose16, uint32_t id_base,
+                                    unsigned long long* keys) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m.T) return;
+  const Pose P = load_pose(pose16);
+  const int4 tr = m.tris[i];
+  float4 pv[3];
+  const int vi[3] = {tr.x, tr.y, tr.z};
+  for (int k = 0; k < 3; ++k) {
+    const float4 o = m.verts[vi[k]];
+    const float3 p = xform(P, o.x, o.y, o.z);
+    const float iz = 1.0f / p.z;
+    pv[k] = make_float4(cam.fx * p.x * iz + cam.cx, cam.fy * p.y * iz + cam.cy, p.z, iz);
+  }
+  const float4 p0 = pv[0], p1 = pv[1], p2 = pv[2];
+  if (p0.z <= cam.znear || p1.z <= cam.znear || p2.z <= cam.znear) return;
+  const float area = (p1.x - p0.x) * (p2.y - p0.y) - (p2.x - p0.x) * (p1.y - p0.y);
+  if (!(area < 0.0f)) return;
+  const float umin = fminf(p0.x, fminf(p1.x, p2.x)), umax = fmaxf(p0.x, fmaxf(p1.x, p2.x));
+  const float vmin = fminf(p0.y, fminf(p1.y, p2.y)), vmax = fmaxf(p0.y, fmaxf(p1.y, p2.y));
+  const float fc0 = ceilf(fmaxf(umin - 0.5f, 0.0f)), fc1 = floorf(fminf(umax - 0.5f, (float)(cam.W - 1)));
+  const float fr0 = ceilf(fmaxf(vmin - 0.5f, 0.0f)), fr1 = floorf(fminf(vmax - 0.5f, (float)(cam.H - 1)));
+  if (!(fc0 <= fc1) || !(fr0 <= fr1)) return;
+  const float inv_area = 1.0f / area;
+  const float e0x = p2.x - p1.x, e0y = p2.y - p1.y;
+  const float e1x = p0.x - p2.x, e1y = p0.y - p2.y;
+  const float e2x = p1.x - p0.x, e2y = p1.y - p0.y;
+  for (int r = (int)fr0; r <= (int)fr1; ++r) {
+    const float py = (float)r + 0.5f;
+    for (int c = (int)fc0; c <= (int)fc1; ++c) {
+      const float px = (float)c + 0.5f;
+      const float w0 = e0x * (py - p1.y) - e0y * (px - p1.x);
+      const float w1 = e1x * (py - p2.y) - e1y * (px - p2.x);
+      const float w2 = e2x * (py - p0.y) - e2y * (px - p0.x);
+      if (w0 > 0.0f || w1 > 0.0f || w2 > 0.0f) continue;
+      const float invz = (w0 * p0.w + w1 * p1.w + w2 * p2.w) * inv_area;
+      const float z = __builtin_amdgcn_rcpf(invz);
+      if (!(z > 0.0f)) continue;
+      atomicMin(&keys[(size_t)r * cam.W + c], pack_key(z, id_base + (uint32_t)i));
+    }
+  }
+}
+
+hipError_t launch_raster_global_dev(const MeshDev& m, const Cam& cam, const float* pose16_dev, uint32_t id_base,
+                                    unsigned long long* keys, hipStream_t st) {
+  hipLaunchKernelGGL(k_raster_global_dev, dim3((m.T + 255) / 256), dim3(256), 0, st, m, cam, pose16_dev, id_base,
+                     keys);
+  return hipGetLastError();
+}
+
+}  // namespace b3d
