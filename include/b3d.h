@@ -93,6 +93,15 @@ b3d_status b3d_mesh_destroy(b3d_mesh* mesh);
  * layout uses (any pointer may be NULL). */
 b3d_status b3d_mesh_info(const b3d_mesh* mesh, int32_t* V, int32_t* T, int32_t* n_clusters);
 
+/* How b3d_mesh_create lays a mesh out, computed on the host without a
+ * device: info[0] = clusters, info[1] = clusters always drawn, info[2] =
+ * triangles always drawn, info[3] = triangles drawn only when the object
+ * reaches the near plane (coincident opposite faces of two different closed
+ * components, which a camera outside the object never sees), info[4] =
+ * triangles with a repeated vertex position (never drawn).  info: host
+ * int32[5]. */
+b3d_status b3d_mesh_layout_info(const float* verts, int32_t V, const int32_t* tris, int32_t T, int32_t* info);
+
 /* ---- the split path: point images in device memory ---------------------- */
 
 /* Depth to point image (Sec. III-A (iii): the render is turned into a point
@@ -275,6 +284,53 @@ b3d_status b3d_c2f_workspace_size(const b3d_schedule* s, int32_t K, size_t* byte
 b3d_status b3d_c2f_step(const b3d_scene* scene, const float* center, const b3d_schedule* s, int32_t K, uint64_t seed,
                         void* workspace, size_t ws_bytes, float* poses_out, float* logq_out, int32_t* idx_out,
                         void* stream);
+
+/* ---- gradient refinement and tracking ---------------------------------- */
+
+/* Adam ascent on logL over each pose's tangent (the refinement that follows
+ * enumeration): with g = grad[n*gstride + 0..6) (d logL/d(dt, dw), e.g. from
+ * b3d_render_score), m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * s = lr * (m/(1-b1^iter)) / (sqrt(v/(1-b2^iter)) + eps) with lr = lr_t for
+ * dt and lr_r for dw, then t <- t + s_t, R <- exp([s_w]x) R.
+ * poses: device float[N][16] (updated); grad: device, gstride floats per pose
+ * (>= 6); state: device float[N][12] (m then v; zero it before iter 1).
+ * iter >= 1.  Stream-ordered. */
+b3d_status b3d_adam_pose_step(float* poses, const float* grad, int32_t gstride, float* state, int32_t N, int32_t iter,
+                              float lr_t, float lr_r, float beta1, float beta2, float eps, void* stream);
+
+/* Per-frame tracking settings: hypotheses around the previous estimate, then
+ * n_refine Adam steps on the best one. */
+typedef struct b3d_track_params {
+  b3d_grid grid; /* center ignored */
+  int32_t n_refine;
+  float lr_t, lr_r, beta1, beta2, eps;
+} b3d_track_params;
+
+typedef struct b3d_tracker b3d_tracker;
+
+/* Track M rigid objects through a sequence of observed images.  Each frame,
+ * object by object: the other objects, at their latest estimates, are drawn
+ * as static background; the grid of hypotheses around the object's previous
+ * estimate is scored with the fused kernel; the best hypothesis is refined
+ * by n_refine Adam steps on the adjoint.  The whole frame is captured once
+ * into a HIP graph and replayed for every later frame, so a frame costs one
+ * copy and one graph launch.  meshes: host array of M handles (they must
+ * outlive the tracker); init_poses: host float[M][16].  1 <= M <= 16.
+ * Allocates device memory (not stream-ordered). */
+b3d_status b3d_tracker_create(const b3d_mesh* const* meshes, int32_t M, const b3d_intrinsics* K,
+                              const b3d_score_params* p, const b3d_track_params* tp, const float* init_poses,
+                              b3d_tracker** out);
+/* Process one frame: observed is a device float[H][W][3] copied into the
+ * tracker's own buffer before the graph runs.  Stream-ordered (the first
+ * call captures the graph on an internal stream, then launches it on
+ * `stream`). */
+b3d_status b3d_tracker_frame(b3d_tracker* tr, const float* observed, void* stream);
+/* The same frame run directly on `stream`, without the graph (reference
+ * for the captured path).  Stream-ordered. */
+b3d_status b3d_tracker_frame_eager(b3d_tracker* tr, const float* observed, void* stream);
+/* Current estimates: device float[M][16].  Stream-ordered copy. */
+b3d_status b3d_tracker_poses(const b3d_tracker* tr, float* poses_out, void* stream);
+b3d_status b3d_tracker_destroy(b3d_tracker* tr);
 
 #ifdef __cplusplus
 }

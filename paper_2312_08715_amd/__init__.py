@@ -49,6 +49,11 @@ class BatchItem(ctypes.Structure):
                 ("logL_out", ctypes.c_void_p), ("grad_out", ctypes.c_void_p)]
 
 
+class TrackParams(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("n_refine", ctypes.c_int32), ("lr_t", ctypes.c_float), ("lr_r", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
 class Schedule(ctypes.Structure):
     _fields_ = [("n_stages", ctypes.c_int32), ("stages", Grid * B3D_MAX_STAGES)]
 
@@ -65,6 +70,7 @@ _SIGNATURES = {
     "b3d_version": ([], ctypes.c_char_p),
     "b3d_mesh_create": ([_P, _I32, _P, _I32, ctypes.POINTER(_P)], ctypes.c_int),
     "b3d_mesh_destroy": ([_P], ctypes.c_int),
+    "b3d_mesh_layout_info": ([_P, _I32, _P, _I32, _P], ctypes.c_int),
     "b3d_mesh_info": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)], ctypes.c_int),
     "b3d_unproject": ([_P, _I32, ctypes.POINTER(Intrinsics), _P, _P], ctypes.c_int),
     "b3d_render_batch": ([_P, _P, _I32, ctypes.POINTER(Intrinsics), _P, _P, _P], ctypes.c_int),
@@ -81,6 +87,14 @@ _SIGNATURES = {
     "b3d_batch_create": ([ctypes.POINTER(BatchItem), _I32, ctypes.POINTER(_P)], ctypes.c_int),
     "b3d_batch_run": ([_P, _P], ctypes.c_int),
     "b3d_batch_destroy": ([_P], ctypes.c_int),
+    "b3d_adam_pose_step": ([_P, _P, _I32, _P, _I32, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                            ctypes.c_float, ctypes.c_float, _P], ctypes.c_int),
+    "b3d_tracker_create": ([_P, _I32, ctypes.POINTER(Intrinsics), ctypes.POINTER(ScoreParams),
+                            ctypes.POINTER(TrackParams), _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "b3d_tracker_frame": ([_P, _P, _P], ctypes.c_int),
+    "b3d_tracker_frame_eager": ([_P, _P, _P], ctypes.c_int),
+    "b3d_tracker_poses": ([_P, _P, _P], ctypes.c_int),
+    "b3d_tracker_destroy": ([_P], ctypes.c_int),
     "b3d_grid_size": ([ctypes.POINTER(Grid)], ctypes.c_int64),
     "b3d_enumerate": ([ctypes.POINTER(Grid), _U64, _I32, _P, _P], ctypes.c_int),
     "b3d_sample": ([_P, _I32, _I32, _I32, _U64, _U32, _U32, _P, _P, _P, _P], ctypes.c_int),
@@ -177,6 +191,15 @@ class Mesh:
             self.close()
         except Exception:
             pass
+
+
+def mesh_layout_info(verts, tris) -> dict:
+    """Host-only summary of the device layout b3d_mesh_create would build."""
+    v = np.ascontiguousarray(verts, dtype=np.float32)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    info = np.zeros(5, dtype=np.int32)
+    _call("b3d_mesh_layout_info", v.ctypes.data, v.shape[0], t.ctypes.data, t.shape[0], info.ctypes.data)
+    return dict(zip(("clusters", "visible_clusters", "drawn", "hidden_pairs", "dropped"), info.tolist()))
 
 
 def unproject(depth: torch.Tensor, K: Intrinsics) -> torch.Tensor:
@@ -380,6 +403,53 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             load_library().b3d_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def adam_pose_step(poses: torch.Tensor, grad: torch.Tensor, state: torch.Tensor, it: int, lr_t: float, lr_r: float,
+                   beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+    """In-place Adam ascent on logL for poses [N,4,4] given grad [N,G>=6] and state [N,12]."""
+    N = poses.shape[0]
+    _call("b3d_adam_pose_step", _ptr(poses, torch.float32), _ptr(grad, torch.float32), int(grad.shape[1]),
+          _ptr(state, torch.float32), N, int(it), float(lr_t), float(lr_r), float(beta1), float(beta2), float(eps),
+          _stream())
+
+
+class Tracker:
+    """Graph-captured multi-object tracker (b3d_tracker_*)."""
+
+    def __init__(self, meshes: Sequence[Mesh], K: Intrinsics, p: ScoreParams, grid: Grid, init_poses,
+                 n_refine: int = 10, lr_t: float = 1e-3, lr_r: float = 1e-2, beta1: float = 0.9,
+                 beta2: float = 0.999, eps: float = 1e-8):
+        self.meshes = list(meshes)
+        M = len(self.meshes)
+        arr = (_P * M)(*[m.handle for m in self.meshes])
+        P0 = np.ascontiguousarray(np.asarray(init_poses, dtype=np.float32).reshape(M, 16))
+        tp = TrackParams(grid, int(n_refine), float(lr_t), float(lr_r), float(beta1), float(beta2), float(eps))
+        h = _P()
+        _call("b3d_tracker_create", arr, M, ctypes.byref(K), ctypes.byref(p), ctypes.byref(tp), P0.ctypes.data,
+              ctypes.byref(h))
+        self._h = h
+        self.M = M
+
+    def frame(self, observed: torch.Tensor, eager: bool = False) -> None:
+        _call("b3d_tracker_frame_eager" if eager else "b3d_tracker_frame", self._h, _ptr(observed, torch.float32),
+              _stream())
+
+    def poses(self) -> torch.Tensor:
+        out = torch.empty((self.M, 4, 4), dtype=torch.float32, device="cuda")
+        _call("b3d_tracker_poses", self._h, _ptr(out), _stream())
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().b3d_tracker_destroy(self._h)
             self._h = None
 
     def __del__(self):

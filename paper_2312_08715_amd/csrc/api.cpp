@@ -14,6 +14,7 @@
 
 #include "../../include/b3d.h"
 #include "b3d_launch.hpp"
+#include "b3d_mesh_layout.hpp"
 
 using namespace b3d;
 
@@ -107,7 +108,7 @@ b3d_status make_consts(const b3d_score_params* p, int H, int W, ScoreConsts* sc)
 }  // namespace
 
 struct b3d_mesh {
-  int V = 0, T = 0, n_clusters = 0;
+  int V = 0, T = 0, n_clusters = 0, n_drawn = 0, n_hidden = 0, n_dropped = 0;
   MeshDev dev{};
   std::vector<void*> allocs;
 };
@@ -121,6 +122,8 @@ struct b3d_batch {
   size_t lds = 0;
   int blocks = 0;
 };
+
+struct b3d_tracker;
 
 struct b3d_scene {
   const b3d_mesh* mesh = nullptr;
@@ -147,47 +150,14 @@ b3d_status b3d_mesh_create(const float* verts, int32_t V, const int32_t* tris, i
   for (int64_t i = 0; i < (int64_t)T * 3; ++i)
     if (tris[i] < 0 || tris[i] >= V) return fail(B3D_EINVAL, "mesh_create: triangle index out of range");
 
-  // clusters of consecutive triangles with at most kClusterMax triangles and
-  // kClusterMax distinct vertices
-  std::vector<int4> clusters;
-  std::vector<float4> cverts;
-  std::vector<uint32_t> ctris((size_t)T);
-  std::vector<int> stamp((size_t)V, -1), local((size_t)V, 0);
-  int cur = -1, cur_first_tri = 0, cur_nv = 0, cur_nt = 0, cur_vert0 = 0;
-  auto flush = [&]() {
-    if (cur >= 0 && cur_nt > 0) clusters.push_back(make_int4(cur_vert0, cur_nv, cur_first_tri, cur_nt));
-  };
-  for (int t = 0; t < T; ++t) {
-    const int* tv = tris + 3 * (size_t)t;
-    int fresh = 0;
-    for (int k = 0; k < 3; ++k) {
-      bool dup = false;
-      for (int j = 0; j < k; ++j) dup = dup || (tv[j] == tv[k]);
-      if (!dup && stamp[tv[k]] != cur) ++fresh;
-    }
-    if (cur < 0 || cur_nt == kClusterMax || cur_nv + fresh > kClusterMax) {
-      flush();
-      ++cur;
-      cur_first_tri = t;
-      cur_nv = 0;
-      cur_nt = 0;
-      cur_vert0 = (int)cverts.size();
-    }
-    uint32_t packed = 0;
-    for (int k = 0; k < 3; ++k) {
-      const int v = tv[k];
-      if (stamp[v] != cur) {
-        stamp[v] = cur;
-        local[v] = cur_nv++;
-        cverts.push_back(make_float4(verts[3 * v], verts[3 * v + 1], verts[3 * v + 2], 0.0f));
-      }
-      packed |= (uint32_t)local[v] << (8 * k);
-    }
-    ctris[t] = packed;
-    ++cur_nt;
+  MeshLayout lay = build_mesh_layout(verts, V, tris, T);
+  if (lay.clusters.empty()) {  // every triangle has a repeated vertex: nothing is ever drawn
+    lay.clusters.push_back(ClusterDev{});
+    lay.clusters.back().cone = make_float4(0.0f, 0.0f, 1.0f, 4.0f);
+    lay.n_visible = 0;
   }
-  flush();
-
+  if (lay.cverts.empty()) lay.cverts.push_back(make_float4(0, 0, 0, 0));
+  if (lay.ctris.empty()) lay.ctris.push_back(make_uint2(0, 0));
   std::vector<float4> v4((size_t)V), nrm((size_t)T);
   std::vector<int4> t4((size_t)T);
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -220,16 +190,16 @@ b3d_status b3d_mesh_create(const float* verts, int32_t V, const int32_t* tris, i
   b3d_mesh* m = new b3d_mesh();
   m->V = V;
   m->T = T;
-  m->n_clusters = (int)clusters.size();
+  m->n_clusters = lay.n_visible == 0 && lay.n_hidden == 0 ? 0 : (int)lay.clusters.size();
   auto upload = [&](const void* src, size_t bytes, void** dst) -> bool {
     if (hipMalloc(dst, bytes) != hipSuccess) return false;
     m->allocs.push_back(*dst);
     return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
   };
   void *d_cl, *d_cv, *d_ct, *d_v, *d_t, *d_n;
-  bool ok = upload(clusters.data(), clusters.size() * sizeof(int4), &d_cl) &&
-            upload(cverts.data(), cverts.size() * sizeof(float4), &d_cv) &&
-            upload(ctris.data(), ctris.size() * sizeof(uint32_t), &d_ct) &&
+  bool ok = upload(lay.clusters.data(), std::max<size_t>(1, lay.clusters.size()) * sizeof(ClusterDev), &d_cl) &&
+            upload(lay.cverts.data(), std::max<size_t>(1, lay.cverts.size()) * sizeof(float4), &d_cv) &&
+            upload(lay.ctris.data(), std::max<size_t>(1, lay.ctris.size()) * sizeof(uint2), &d_ct) &&
             upload(v4.data(), v4.size() * sizeof(float4), &d_v) && upload(t4.data(), t4.size() * sizeof(int4), &d_t) &&
             upload(nrm.data(), nrm.size() * sizeof(float4), &d_n);
   if (!ok) {
@@ -238,13 +208,17 @@ b3d_status b3d_mesh_create(const float* verts, int32_t V, const int32_t* tris, i
     return fail(B3D_ENOMEM, "mesh_create: device allocation or copy failed");
   }
   MeshDev& d = m->dev;
-  d.clusters = (const int4*)d_cl;
+  d.clusters = (const ClusterDev*)d_cl;
   d.cverts = (const float4*)d_cv;
-  d.ctris = (const uint32_t*)d_ct;
+  d.ctris = (const uint2*)d_ct;
+  d.n_visible = lay.n_visible;
   d.verts = (const float4*)d_v;
   d.tris = (const int4*)d_t;
   d.normals = (const float4*)d_n;
   d.n_clusters = m->n_clusters;
+  m->n_drawn = lay.n_drawn;
+  m->n_hidden = lay.n_hidden;
+  m->n_dropped = lay.n_dropped;
   d.V = V;
   d.T = T;
   for (int k = 0; k < 3; ++k) {
@@ -264,6 +238,20 @@ b3d_status b3d_mesh_destroy(b3d_mesh* m) {
   (void)hipDeviceSynchronize();
   for (void* p : m->allocs) (void)hipFree(p);
   delete m;
+  return B3D_OK;
+}
+
+b3d_status b3d_mesh_layout_info(const float* verts, int32_t V, const int32_t* tris, int32_t T, int32_t* info) {
+  if (!verts || !tris || !info) return fail(B3D_EINVAL, "mesh_layout_info: NULL pointer");
+  if (V < 1 || T < 1 || T > (1 << 24)) return fail(B3D_ESHAPE, "mesh_layout_info: need V >= 1 and 1 <= T <= 2^24");
+  for (int64_t i = 0; i < (int64_t)T * 3; ++i)
+    if (tris[i] < 0 || tris[i] >= V) return fail(B3D_EINVAL, "mesh_layout_info: triangle index out of range");
+  const MeshLayout lay = build_mesh_layout(verts, V, tris, T);
+  info[0] = (int32_t)lay.clusters.size();
+  info[1] = lay.n_visible;
+  info[2] = lay.n_drawn;
+  info[3] = lay.n_hidden;
+  info[4] = lay.n_dropped;
   return B3D_OK;
 }
 
@@ -291,8 +279,8 @@ b3d_status b3d_render_batch(const b3d_mesh* mesh, const float* poses, int32_t N,
   if (N < 0) return fail(B3D_ESHAPE, "render_batch: N < 0");
   if (N == 0) return B3D_OK;
   if (!poses || !xyz_out) return fail(B3D_EINVAL, "render_batch: NULL pointer");
-  const int zcap = std::max(6144, K->W);
-  if (sizeof(float4) * 2 * kClusterMax + 8 * (size_t)zcap > kLdsMax)
+  const int zcap = std::max(4096, K->W);
+  if (kRasterLdsBytes + 8 * (size_t)zcap > kLdsMax)
     return fail(B3D_ESHAPE, "render_batch: image too wide for the LDS depth buffer");
   B3D_CHECK_HIP(launch_render_batch(mesh->dev, make_cam(K), poses, N, xyz_out, tri_out, zcap, (hipStream_t)stream),
                 "render_batch");
@@ -663,6 +651,197 @@ b3d_status b3d_c2f_step(const b3d_scene* S, const float* center, const b3d_sched
                                     idx_out ? idx_out + (size_t)t * K : nullptr, st),
                   "c2f_step");
   }
+  return B3D_OK;
+}
+
+b3d_status b3d_adam_pose_step(float* poses, const float* grad, int32_t gstride, float* state, int32_t N, int32_t iter,
+                              float lr_t, float lr_r, float beta1, float beta2, float eps, void* stream) {
+  if (N < 0) return fail(B3D_ESHAPE, "adam_pose_step: N < 0");
+  if (N == 0) return B3D_OK;
+  if (!poses || !grad || !state) return fail(B3D_EINVAL, "adam_pose_step: NULL pointer");
+  if (gstride < 6) return fail(B3D_EINVAL, "adam_pose_step: gstride must be >= 6");
+  if (iter < 1) return fail(B3D_EINVAL, "adam_pose_step: iter must be >= 1");
+  if (!(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0) || !std::isfinite(lr_t) ||
+      !std::isfinite(lr_r))
+    return fail(B3D_EINVAL, "adam_pose_step: need 0 <= beta < 1, eps > 0, finite rates");
+  B3D_CHECK_HIP(launch_adam_pose(poses, grad, gstride, state, N, iter, lr_t, lr_r, beta1, beta2, eps,
+                                 (hipStream_t)stream),
+                "adam_pose_step");
+  return B3D_OK;
+}
+
+}  // extern "C"
+
+// ---- tracker -------------------------------------------------------------
+
+struct b3d_tracker {
+  int M = 0;
+  int64_t N = 0;
+  b3d_track_params tp{};
+  std::vector<const b3d_mesh*> meshes;
+  std::vector<b3d_scene*> scenes;
+  float* obs = nullptr;      // [H][W][3] frame buffer read by the graph
+  float* poses = nullptr;    // [M][16] current estimates
+  float* hyp = nullptr;      // [N][16]
+  float* logL = nullptr;     // [N]
+  float* grad = nullptr;     // [8]
+  float* state = nullptr;    // [12]
+  size_t obs_bytes = 0;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static b3d_status tracker_record(b3d_tracker* T, hipStream_t st) {
+  const b3d_track_params& tp = T->tp;
+  GridDev g;
+  int64_t n;
+  (void)make_grid(&tp.grid, &g, &n);
+  for (int o = 0; o < T->M; ++o) {
+    b3d_scene* S = T->scenes[o];
+    const size_t HW = (size_t)S->K.H * S->K.W;
+    if (T->M > 1) {
+      B3D_CHECK_HIP(launch_fill_keys(S->bg, HW, st), "tracker");
+      uint32_t base = (uint32_t)S->mesh->T;
+      for (int k = 0; k < T->M; ++k) {
+        if (k == o) continue;
+        B3D_CHECK_HIP(launch_raster_global_dev(T->meshes[k]->dev, S->dev.cam, T->poses + 16 * k, base, S->bg, st),
+                      "tracker");
+        B3D_CHECK_HIP(launch_refine_global(T->meshes[k]->dev, S->dev.cam, nullptr, T->poses + 16 * k, base, S->bg, st),
+                      "tracker");
+        base += (uint32_t)T->meshes[k]->T;
+      }
+    }
+    B3D_CHECK_HIP(launch_background_terms(S->dev, S->terms, st), "tracker");
+    B3D_CHECK_HIP(launch_enumerate(g, T->poses + 16 * o, 1, 0u, 0u, 0u, T->hyp, st), "tracker");
+    B3D_CHECK_HIP(launch_render_score(S->dev, T->hyp, (int)T->N, T->logL, nullptr, st), "tracker");
+    B3D_CHECK_HIP(launch_argmax_pose(T->logL, T->hyp, (int)T->N, T->poses + 16 * o, st), "tracker");
+    B3D_CHECK_HIP(launch_fill_f32(T->state, 12, 0.0f, st), "tracker");
+    for (int it = 1; it <= tp.n_refine; ++it) {
+      B3D_CHECK_HIP(launch_render_score(S->dev, T->poses + 16 * o, 1, T->logL, T->grad, st), "tracker");
+      B3D_CHECK_HIP(launch_adam_pose(T->poses + 16 * o, T->grad, 8, T->state, 1, it, tp.lr_t, tp.lr_r, tp.beta1,
+                                     tp.beta2, tp.eps, st),
+                    "tracker");
+    }
+  }
+  return B3D_OK;
+}
+
+extern "C" {
+
+b3d_status b3d_tracker_create(const b3d_mesh* const* meshes, int32_t M, const b3d_intrinsics* K,
+                              const b3d_score_params* p, const b3d_track_params* tp, const float* init_poses,
+                              b3d_tracker** out) {
+  if (!meshes || !tp || !init_poses || !out) return fail(B3D_EINVAL, "tracker_create: NULL pointer");
+  if (M < 1 || M > 16) return fail(B3D_ESHAPE, "tracker_create: M must be in 1..16");
+  if (b3d_status s = check_intrinsics(K)) return s;
+  ScoreConsts sc;
+  if (b3d_status s = make_consts(p, K->H, K->W, &sc)) return s;
+  GridDev g;
+  int64_t n;
+  if (b3d_status s = make_grid(&tp->grid, &g, &n)) return s;
+  if (n > (1 << 24)) return fail(B3D_ESHAPE, "tracker_create: grid too large");
+  if (tp->n_refine < 0 || tp->n_refine > 1000) return fail(B3D_EINVAL, "tracker_create: n_refine in 0..1000");
+  if (!(tp->beta1 >= 0 && tp->beta1 < 1) || !(tp->beta2 >= 0 && tp->beta2 < 1) || !(tp->eps > 0))
+    return fail(B3D_EINVAL, "tracker_create: bad Adam parameters");
+  if (!finite_all(init_poses, (size_t)M * 16)) return fail(B3D_EINVAL, "tracker_create: non-finite pose");
+  for (int i = 0; i < M; ++i)
+    if (!meshes[i]) return fail(B3D_EINVAL, "tracker_create: NULL mesh %d", i);
+  b3d_tracker* T = new b3d_tracker();
+  T->M = M;
+  T->N = n;
+  T->tp = *tp;
+  T->meshes.assign(meshes, meshes + M);
+  T->obs_bytes = sizeof(float) * 3 * (size_t)K->H * K->W;
+  auto cleanup = [&](b3d_status s, const char* msg) {
+    for (b3d_scene* S : T->scenes) b3d_scene_destroy(S);
+    (void)hipFree(T->obs);
+    (void)hipFree(T->poses);
+    (void)hipFree(T->hyp);
+    (void)hipFree(T->logL);
+    (void)hipFree(T->grad);
+    (void)hipFree(T->state);
+    if (T->cap) (void)hipStreamDestroy(T->cap);
+    delete T;
+    return fail(s, "%s", msg);
+  };
+  if (hipMalloc((void**)&T->obs, T->obs_bytes) != hipSuccess ||
+      hipMalloc((void**)&T->poses, sizeof(float) * 16 * M) != hipSuccess ||
+      hipMalloc((void**)&T->hyp, sizeof(float) * 16 * (size_t)n) != hipSuccess ||
+      hipMalloc((void**)&T->logL, sizeof(float) * (size_t)n) != hipSuccess ||
+      hipMalloc((void**)&T->grad, sizeof(float) * 8) != hipSuccess ||
+      hipMalloc((void**)&T->state, sizeof(float) * 12) != hipSuccess)
+    return cleanup(B3D_ENOMEM, "tracker_create: device allocation failed");
+  if (hipMemcpy(T->poses, init_poses, sizeof(float) * 16 * M, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(T->obs, 0, T->obs_bytes) != hipSuccess)
+    return cleanup(B3D_EHIP, "tracker_create: initial copy failed");
+  for (int o = 0; o < M; ++o) {
+    b3d_scene* S = nullptr;
+    if (b3d_scene_create(meshes[o], K, p, &S) != B3D_OK) return cleanup(B3D_ENOMEM, g_err.c_str());
+    T->scenes.push_back(S);
+    S->dev.obs = T->obs;
+    S->observed = true;
+    if (M > 1) {
+      S->has_bg = true;
+      S->dev.bg = S->bg;
+    }
+  }
+  if (hipStreamCreateWithFlags(&T->cap, hipStreamNonBlocking) != hipSuccess)
+    return cleanup(B3D_EHIP, "tracker_create: stream creation failed");
+  *out = T;
+  return B3D_OK;
+}
+
+b3d_status b3d_tracker_frame(b3d_tracker* T, const float* observed, void* stream) {
+  if (!T || !observed) return fail(B3D_EINVAL, "tracker_frame: NULL pointer");
+  hipStream_t st = (hipStream_t)stream;
+  if (!T->exec) {
+    B3D_CHECK_HIP(hipStreamBeginCapture(T->cap, hipStreamCaptureModeThreadLocal), "tracker_frame: capture");
+    b3d_status s = tracker_record(T, T->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(T->cap, &g);
+    if (s != B3D_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "tracker_frame: end capture");
+    T->graph = g;
+    B3D_CHECK_HIP(hipGraphInstantiate(&T->exec, T->graph, nullptr, nullptr, 0), "tracker_frame: instantiate");
+  }
+  B3D_CHECK_HIP(hipMemcpyAsync(T->obs, observed, T->obs_bytes, hipMemcpyDeviceToDevice, st), "tracker_frame: copy");
+  B3D_CHECK_HIP(hipGraphLaunch(T->exec, st), "tracker_frame: launch");
+  return B3D_OK;
+}
+
+b3d_status b3d_tracker_frame_eager(b3d_tracker* T, const float* observed, void* stream) {
+  if (!T || !observed) return fail(B3D_EINVAL, "tracker_frame_eager: NULL pointer");
+  hipStream_t st = (hipStream_t)stream;
+  B3D_CHECK_HIP(hipMemcpyAsync(T->obs, observed, T->obs_bytes, hipMemcpyDeviceToDevice, st), "tracker_frame: copy");
+  return tracker_record(T, st);
+}
+
+b3d_status b3d_tracker_poses(const b3d_tracker* T, float* poses_out, void* stream) {
+  if (!T || !poses_out) return fail(B3D_EINVAL, "tracker_poses: NULL pointer");
+  B3D_CHECK_HIP(hipMemcpyAsync(poses_out, T->poses, sizeof(float) * 16 * T->M, hipMemcpyDeviceToDevice,
+                               (hipStream_t)stream),
+                "tracker_poses");
+  return B3D_OK;
+}
+
+b3d_status b3d_tracker_destroy(b3d_tracker* T) {
+  if (!T) return B3D_OK;
+  (void)hipDeviceSynchronize();
+  if (T->exec) (void)hipGraphExecDestroy(T->exec);
+  if (T->graph) (void)hipGraphDestroy(T->graph);
+  for (b3d_scene* S : T->scenes) b3d_scene_destroy(S);
+  (void)hipFree(T->obs);
+  (void)hipFree(T->poses);
+  (void)hipFree(T->hyp);
+  (void)hipFree(T->logL);
+  (void)hipFree(T->grad);
+  (void)hipFree(T->state);
+  if (T->cap) (void)hipStreamDestroy(T->cap);
+  delete T;
   return B3D_OK;
 }
 

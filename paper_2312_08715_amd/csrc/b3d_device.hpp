@@ -13,7 +13,7 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kClusterMax = 256;     // max triangles and max vertices per cluster
 constexpr unsigned long long kEmptyKey = ~0ull;
 
-// Camera with reciprocal focal lengths precomputed.
+// Pinhole camera and image size.
 struct Cam {
   float fx, fy, cx, cy, znear;
   int H, W;
@@ -25,20 +25,28 @@ struct Pose {
   float t[3];
 };
 
-// Device view of an uploaded mesh.  Triangles are grouped, in their original
-// order, into clusters of at most kClusterMax triangles that reference at
-// most kClusterMax distinct vertices; each cluster carries its own copy of
-// those vertices so that a workgroup can transform them once into LDS.
+// A group of up to kClusterMax triangles of one orientation class that are
+// close in space, with its own copy of the vertices they use (at most
+// kClusterMax).  sphere = centre and radius of a ball holding them; cone =
+// unit axis and half-angle (radians) of a cone holding their face normals
+// (half-angle > pi/2 means "no bound").
+struct ClusterDev {
+  int vfirst, nv, tfirst, nt;
+  float4 sphere;
+  float4 cone;
+};
+
+// Device view of an uploaded mesh.
 struct MeshDev {
-  const int4* clusters;    // {first vertex, vertex count, first triangle, triangle count}
-  const float4* cverts;    // cluster-local vertex copies (object frame)
-  const uint32_t* ctris;   // local indices a | b << 8 | c << 16
-  const float4* verts;     // original vertices
-  const int4* tris;        // original triangles (w unused)
-  const float4* normals;   // object-frame (v1 - v0) x (v2 - v0)
-  int n_clusters, V, T;
-  float sphere[4];         // bounding sphere centre and radius
-  float lo[3], hi[3];      // axis-aligned bounds
+  const ClusterDev* clusters;  // [0, n_visible) drawn; [n_visible, n_clusters) only near the near plane
+  const float4* cverts;        // cluster-local vertex copies (object frame)
+  const uint2* ctris;          // (local indices a | b << 8 | c << 16, triangle id)
+  const float4* verts;         // caller's vertices
+  const int4* tris;            // caller's triangles (w unused)
+  const float4* normals;       // object-frame (v1 - v0) x (v2 - v0)
+  int n_clusters, n_visible, V, T;
+  float sphere[4];             // bounding sphere centre and radius
+  float lo[3], hi[3];          // axis-aligned bounds
 };
 
 __device__ __forceinline__ Pose load_pose(const float* __restrict__ p) {
@@ -162,64 +170,6 @@ __device__ __forceinline__ Rect object_rect(const MeshDev& m, const Pose& P, con
   return r;
 }
 
-// Rasterise every triangle of the mesh under pose P into an LDS key buffer
-// that covers the image rectangle `band` (row pitch band.w()).  Triangle ids
-// written are id_base + triangle index.  vbuf holds 2 * kClusterMax float4
-// (double-buffered cluster vertices).  Must be called by the whole block;
-// ends with the buffer complete for the block (after a barrier).
-__device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, const Cam& cam, uint32_t id_base,
-                                            const Rect& band, unsigned long long* zbuf, float4* vbuf) {
-  const int pitch = band.w();
-  const float bx0 = (float)band.x0, bx1 = (float)(band.x1 - 1);
-  const float by0 = (float)band.y0, by1 = (float)(band.y1 - 1);
-  for (int c = 0; c < m.n_clusters; ++c) {
-    const int4 ci = m.clusters[c];
-    float4* vb = vbuf + (c & 1) * kClusterMax;
-    for (int v = threadIdx.x; v < ci.y; v += kBlock) {
-      const float4 o = m.cverts[ci.x + v];
-      const float3 p = xform(P, o.x, o.y, o.z);
-      const float iz = 1.0f / p.z;
-      vb[v] = make_float4(cam.fx * p.x * iz + cam.cx, cam.fy * p.y * iz + cam.cy, p.z, iz);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < ci.w; i += kBlock) {
-      const uint32_t pk = m.ctris[ci.z + i];
-      const float4 p0 = vb[pk & 255u], p1 = vb[(pk >> 8) & 255u], p2 = vb[(pk >> 16) & 255u];
-      if (p0.z <= cam.znear || p1.z <= cam.znear || p2.z <= cam.znear) continue;
-      const float area = (p1.x - p0.x) * (p2.y - p0.y) - (p2.x - p0.x) * (p1.y - p0.y);
-      if (!(area < 0.0f)) continue;  // facing away, or edge-on
-      const float umin = fminf(p0.x, fminf(p1.x, p2.x)), umax = fmaxf(p0.x, fmaxf(p1.x, p2.x));
-      const float vmin = fminf(p0.y, fminf(p1.y, p2.y)), vmax = fmaxf(p0.y, fmaxf(p1.y, p2.y));
-      const float fc0 = ceilf(fmaxf(umin - 0.5f, bx0)), fc1 = floorf(fminf(umax - 0.5f, bx1));
-      const float fr0 = ceilf(fmaxf(vmin - 0.5f, by0)), fr1 = floorf(fminf(vmax - 0.5f, by1));
-      if (!(fc0 <= fc1) || !(fr0 <= fr1)) continue;
-      const int c0 = (int)fc0, c1 = (int)fc1, r0 = (int)fr0, r1 = (int)fr1;
-      const uint32_t id = id_base + (uint32_t)(ci.z + i);
-      const float inv_area = 1.0f / area;
-      const float e0x = p2.x - p1.x, e0y = p2.y - p1.y;
-      const float e1x = p0.x - p2.x, e1y = p0.y - p2.y;
-      const float e2x = p1.x - p0.x, e2y = p1.y - p0.y;
-      for (int r = r0; r <= r1; ++r) {
-        const float py = (float)r + 0.5f;
-        for (int col = c0; col <= c1; ++col) {
-          const float px = (float)col + 0.5f;
-          // edge functions; each equals the (negative) area at the opposite vertex
-          const float w0 = e0x * (py - p1.y) - e0y * (px - p1.x);
-          const float w1 = e1x * (py - p2.y) - e1y * (px - p2.x);
-          const float w2 = e2x * (py - p0.y) - e2y * (px - p0.x);
-          if (w0 > 0.0f || w1 > 0.0f || w2 > 0.0f) continue;
-          // 1/z is affine in screen space: interpolate with barycentrics w_k/area
-          const float invz = (w0 * p0.w + w1 * p1.w + w2 * p2.w) * inv_area;
-          const float z = __builtin_amdgcn_rcpf(invz);
-          if (!(z > 0.0f)) continue;
-          atomicMin(&zbuf[(r - band.y0) * pitch + (col - band.x0)], pack_key(z, id));
-        }
-      }
-    }
-  }
-  __syncthreads();
-}
-
 // Depth of pixel (r, c) on the plane of triangle `id` under pose P: the ray
 // z d meets the plane n.(x - c0) = 0 at z = (n.c0)/(n.d), with
 // c_k = R v_k + t and n = (c1 - c0) x (c2 - c0), all in double precision.
@@ -259,6 +209,192 @@ __device__ __forceinline__ void refine_depths(const MeshDev& m, const Pose& P, c
     if (id >= (uint32_t)m.T) continue;
     const int r = band.y0 + k / pitch, c = band.x0 + (k - (k / pitch) * pitch);
     zbuf[k] = pack_key(plane_depth(m, P, cam, id, r, c), key_id(key));
+  }
+  __syncthreads();
+}
+
+// Whether a cluster can draw into `band` under pose P: false when its
+// sphere lies behind the near plane, when every normal of its cone faces away
+// from every point of its sphere (the angle between the cone axis and the
+// direction to the sphere centre, plus the cone's and the sphere's angular
+// radii, stays below a right angle by a margin), or when the sphere's screen
+// box misses the band.  Uniform across the block.
+__device__ __forceinline__ bool cluster_may_draw(const ClusterDev& c, const Pose& P, const Cam& cam,
+                                                 const Rect& band) {
+  const float3 s = xform(P, c.sphere.x, c.sphere.y, c.sphere.z);
+  const float r = c.sphere.w;
+  if (s.z + r <= cam.znear) return false;
+  const float d2 = s.x * s.x + s.y * s.y + s.z * s.z;
+  if (c.cone.w < 1.5f && d2 > r * r) {
+    const float3 a = rotate(P, c.cone.x, c.cone.y, c.cone.z);
+    const float d = sqrtf(d2);
+    const float ct = fminf(1.0f, fmaxf(-1.0f, (a.x * s.x + a.y * s.y + a.z * s.z) / d));
+    if (acosf(ct) + c.cone.w + asinf(fminf(1.0f, r / d)) < 1.5707963f - 2e-3f) return false;
+  }
+  if (s.z - r > cam.znear) {
+    float b[4];
+    const float lo[3] = {s.x - r, s.y - r, s.z - r}, hi[3] = {s.x + r, s.y + r, s.z + r};
+    project_box(P, lo, hi, false, cam, b);
+    if (b[1] < (float)band.x0 - 1.0f || b[0] > (float)band.x1 + 1.0f || b[3] < (float)band.y0 - 1.0f ||
+        b[2] > (float)band.y1 + 1.0f)
+      return false;
+  }
+  return true;
+}
+
+// Coverage of pixel (r, c) by triangle `id` decided in double precision with
+// exactly the operations, in the same order, of the plain definition
+// (transform, near-plane drop, back-face test on ((c1-c0)x(c2-c0)).c0,
+// projection, edge functions at the pixel centre, inclusive).  Used only for
+// pixel centres that single precision cannot place on one side of an edge.
+__device__ __forceinline__ bool covered_exact(const MeshDev& m, const Pose& P, const Cam& cam, uint32_t id,
+                                                        int r, int col) {
+#pragma clang fp contract(off)
+  const int4 tr = m.tris[id];
+  const float4 v[3] = {m.verts[tr.x], m.verts[tr.y], m.verts[tr.z]};
+  double c[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int i = 0; i < 3; ++i)
+      c[k][i] = (double)P.r[3 * i] * (double)v[k].x + (double)P.r[3 * i + 1] * (double)v[k].y +
+                (double)P.r[3 * i + 2] * (double)v[k].z + (double)P.t[i];
+  const double zn = (double)cam.znear;
+  if (c[0][2] <= zn || c[1][2] <= zn || c[2][2] <= zn) return false;
+  const double e1[3] = {c[1][0] - c[0][0], c[1][1] - c[0][1], c[1][2] - c[0][2]};
+  const double e2[3] = {c[2][0] - c[0][0], c[2][1] - c[0][1], c[2][2] - c[0][2]};
+  const double n0 = e1[1] * e2[2] - e1[2] * e2[1];
+  const double n1 = e1[2] * e2[0] - e1[0] * e2[2];
+  const double n2 = e1[0] * e2[1] - e1[1] * e2[0];
+  const double nc0 = n0 * c[0][0] + n1 * c[0][1] + n2 * c[0][2];
+  if (!(nc0 < 0.0)) return false;
+  const double fx = cam.fx, fy = cam.fy, cx = cam.cx, cy = cam.cy;
+  const double u0 = fx * c[0][0] / c[0][2] + cx, v0 = fy * c[0][1] / c[0][2] + cy;
+  const double u1 = fx * c[1][0] / c[1][2] + cx, v1 = fy * c[1][1] / c[1][2] + cy;
+  const double u2 = fx * c[2][0] / c[2][2] + cx, v2 = fy * c[2][1] / c[2][2] + cy;
+  const double px = col + 0.5, py = r + 0.5;
+  const double w0 = (u2 - u1) * (py - v1) - (v2 - v1) * (px - u1);
+  const double w1 = (u0 - u2) * (py - v2) - (v0 - v2) * (px - u2);
+  const double w2 = (u1 - u0) * (py - v0) - (v1 - v0) * (px - u0);
+  return !(w0 > 0.0 || w1 > 0.0 || w2 > 0.0);
+}
+
+// LDS scratch of the rasteriser.
+struct RasterLds {
+  float4* vbuf;  // 2 * kClusterMax cluster vertices (double-buffered)
+  uint2* queue;  // (band pixel, triangle id) pairs left for the exact test
+  int* qcount;
+  int qcap;
+};
+
+constexpr int kQueueCap = 512;
+constexpr size_t kRasterLdsBytes = sizeof(float4) * 2 * kClusterMax + sizeof(uint2) * kQueueCap + 16;
+
+__device__ __forceinline__ RasterLds carve_raster_lds(unsigned char* p) {
+  RasterLds r;
+  r.vbuf = reinterpret_cast<float4*>(p);
+  r.queue = reinterpret_cast<uint2*>(r.vbuf + 2 * kClusterMax);
+  r.qcount = reinterpret_cast<int*>(r.queue + kQueueCap);
+  r.qcap = kQueueCap;
+  return r;
+}
+
+// Rasterise the mesh under pose P into an LDS key buffer that covers the
+// image rectangle `band` (row pitch band.w()).  Triangle ids written are
+// id_base + the caller's triangle index.  Clusters that cannot draw into the
+// band are skipped whole; the remaining ones are transformed cluster by
+// cluster into LDS and every triangle walks the pixel centres of its screen
+// box.  A centre that single precision places clearly inside all three edges
+// is written at once (64-bit atomicMin of the packed depth/id key); one that
+// lies within a rounding margin of an edge, or any centre of a triangle seen
+// nearly edge-on, is queued and decided afterwards by covered_exact.  Must be
+// called by the whole block; ends after a barrier with the buffer complete.
+__device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, const Cam& cam, uint32_t id_base,
+                                            const Rect& band, unsigned long long* zbuf, const RasterLds& lds) {
+  const int pitch = band.w();
+  const float bx0 = (float)band.x0, bx1 = (float)(band.x1 - 1);
+  const float by0 = (float)band.y0, by1 = (float)(band.y1 - 1);
+  if (threadIdx.x == 0) *lds.qcount = 0;
+  // the hidden-pair clusters matter only when the object reaches the near plane
+  bool straddle = false;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float3 c = xform(P, (k & 1) ? m.hi[0] : m.lo[0], (k & 2) ? m.hi[1] : m.lo[1], (k & 4) ? m.hi[2] : m.lo[2]);
+    straddle = straddle || !(c.z > cam.znear);
+  }
+  const int n_clusters = straddle ? m.n_clusters : m.n_visible;
+  __syncthreads();
+  int used = 0;
+  for (int ci_ = 0; ci_ < n_clusters; ++ci_) {
+    const ClusterDev cl = m.clusters[ci_];
+    if (!cluster_may_draw(cl, P, cam, band)) continue;
+    float4* vb = lds.vbuf + (used & 1) * kClusterMax;
+    ++used;
+    for (int v = threadIdx.x; v < cl.nv; v += kBlock) {
+      const float4 o = m.cverts[cl.vfirst + v];
+      const float3 p = xform(P, o.x, o.y, o.z);
+      const float iz = 1.0f / p.z;
+      vb[v] = make_float4(cam.fx * p.x * iz + cam.cx, cam.fy * p.y * iz + cam.cy, p.z, iz);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < cl.nt; i += kBlock) {
+      const uint2 tk = m.ctris[cl.tfirst + i];
+      const float4 p0 = vb[tk.x & 255u], p1 = vb[(tk.x >> 8) & 255u], p2 = vb[(tk.x >> 16) & 255u];
+      if (p0.z <= cam.znear || p1.z <= cam.znear || p2.z <= cam.znear) continue;
+      const float e0x = p2.x - p1.x, e0y = p2.y - p1.y;
+      const float e1x = p0.x - p2.x, e1y = p0.y - p2.y;
+      const float e2x = p1.x - p0.x, e2y = p1.y - p0.y;
+      const float umin = fminf(p0.x, fminf(p1.x, p2.x)), umax = fmaxf(p0.x, fmaxf(p1.x, p2.x));
+      const float vmin = fminf(p0.y, fminf(p1.y, p2.y)), vmax = fmaxf(p0.y, fmaxf(p1.y, p2.y));
+      // rounding margin (pixels) for this triangle's projected positions
+      const float tau = 2e-6f * fmaxf(fmaxf(fmaxf(fabsf(umin), fabsf(umax)), fmaxf(fabsf(vmin), fabsf(vmax))), 256.0f);
+      const float area = e2x * (p2.y - p0.y) - (p2.x - p0.x) * e2y;
+      const float amb_area = 2.0f * tau * (fabsf(e1x) + fabsf(e1y) + fabsf(e2x) + fabsf(e2y));
+      if (area > amb_area) continue;  // faces away
+      const bool edge_on = area >= -amb_area;
+      const float fc0 = ceilf(fmaxf(umin - 0.5f - tau, bx0)), fc1 = floorf(fminf(umax - 0.5f + tau, bx1));
+      const float fr0 = ceilf(fmaxf(vmin - 0.5f - tau, by0)), fr1 = floorf(fminf(vmax - 0.5f + tau, by1));
+      if (!(fc0 <= fc1) || !(fr0 <= fr1)) continue;
+      const int c0 = (int)fc0, c1 = (int)fc1, r0 = (int)fr0, r1 = (int)fr1;
+      const uint32_t id = id_base + tk.y;
+      const float inv_area = 1.0f / area;
+      const float t0 = tau * (fabsf(e0x) + fabsf(e0y)), t1 = tau * (fabsf(e1x) + fabsf(e1y)),
+                  t2 = tau * (fabsf(e2x) + fabsf(e2y));
+      for (int r = r0; r <= r1; ++r) {
+        const float py = (float)r + 0.5f;
+        for (int col = c0; col <= c1; ++col) {
+          const float px = (float)col + 0.5f;
+          // edge functions; each equals the (negative) area at the opposite vertex
+          const float w0 = e0x * (py - p1.y) - e0y * (px - p1.x);
+          const float w1 = e1x * (py - p2.y) - e1y * (px - p2.x);
+          const float w2 = e2x * (py - p0.y) - e2y * (px - p0.x);
+          if (w0 > t0 || w1 > t1 || w2 > t2) continue;  // clearly outside
+          const int pix = (r - band.y0) * pitch + (col - band.x0);
+          if (edge_on || w0 >= -t0 || w1 >= -t1 || w2 >= -t2) {
+            const int slot = atomicAdd(lds.qcount, 1);
+            if (slot < lds.qcap) {
+              lds.queue[slot] = make_uint2((uint32_t)pix, tk.y);
+              continue;
+            }
+            if (edge_on || w0 > 0.0f || w1 > 0.0f || w2 > 0.0f) continue;  // queue full: single precision
+          }
+          // 1/z is affine in screen space: interpolate with barycentrics w_k/area
+          const float invz = (w0 * p0.w + w1 * p1.w + w2 * p2.w) * inv_area;
+          const float z = __builtin_amdgcn_rcpf(invz);
+          if (!(z > 0.0f)) continue;
+          atomicMin(&zbuf[pix], pack_key(z, id));
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // centres near an edge: the exact test, then the plane depth
+  const int nq = min(*lds.qcount, lds.qcap);
+  for (int k = threadIdx.x; k < nq; k += kBlock) {
+    const uint2 e = lds.queue[k];
+    const int r = band.y0 + (int)e.x / pitch, col = band.x0 + (int)e.x % pitch;
+    if (!covered_exact(m, P, cam, e.y, r, col)) continue;
+    const float z = plane_depth(m, P, cam, e.y, r, col);
+    if (!(z > 0.0f)) continue;
+    atomicMin(&zbuf[e.x], pack_key(z, id_base + e.y));
   }
   __syncthreads();
 }

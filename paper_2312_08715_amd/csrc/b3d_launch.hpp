@@ -90,4 +90,12 @@ hipError_t launch_sample(const float* logL, int P, int N, int K, uint32_t key0, 
 hipError_t launch_c2f_update(const float* poses, int P, int N, const int* idx, const float* logw, int K_draws,
                              int accumulate, float* centres, float* logq, int* idx_out, hipStream_t st);
 
+// refinement and tracking
+hipError_t launch_adam_pose(float* poses, const float* grad, int gstride, float* state, int N, int iter, float lr_t,
+                            float lr_r, float b1, float b2, float eps, hipStream_t st);
+hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t st);
+hipError_t launch_argmax_pose(const float* logL, const float* poses, int N, float* out, hipStream_t st);
+hipError_t launch_raster_global_dev(const MeshDev& m, const Cam& cam, const float* pose16_dev, uint32_t id_base,
+                                    unsigned long long* keys, hipStream_t st);
+
 }  // namespace b3d

@@ -30,8 +30,8 @@ __device__ __forceinline__ double rect_sum(const double* sat, int W, const Rect&
 }
 
 size_t fused_lds_bytes(const SceneDev& s) {
-  return sizeof(float4) * 2 * kClusterMax + sizeof(float) * (64 + s.cam.W + s.cam.H) +
-         sizeof(unsigned long long) * (size_t)s.zcap + sizeof(float) * (size_t)s.wcap + 16;
+  return kRasterLdsBytes + sizeof(float) * (64 + s.cam.W + s.cam.H) + sizeof(unsigned long long) * (size_t)s.zcap +
+         sizeof(float) * (size_t)s.wcap + 16;
 }
 
 // One hypothesis: pose16 (16 floats), writes *logL_out and, when GRAD,
@@ -41,8 +41,8 @@ template <bool GRAD>
 __device__ __forceinline__ void render_score_one(const SceneDev& s, const float* __restrict__ pose16,
                                                  float* __restrict__ logL_out, float* __restrict__ grad_out,
                                                  unsigned char* smem) {
-  float4* vbuf = reinterpret_cast<float4*>(smem);
-  unsigned long long* zbuf = reinterpret_cast<unsigned long long*>(vbuf + 2 * kClusterMax);
+  const RasterLds rl = carve_raster_lds(smem);
+  unsigned long long* zbuf = reinterpret_cast<unsigned long long*>(smem + kRasterLdsBytes);
   float* red = reinterpret_cast<float*>(zbuf + s.zcap);
   float* dxt = red + 64;
   float* dyt = dxt + s.cam.W;
@@ -56,7 +56,9 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
   for (int i = threadIdx.x; i < H; i += kBlock) dyt[i] = ray_y(cam, i);
 
   const Rect obj = object_rect(s.mesh, P, cam);
-  const Rect region = grow_clip(obj, h, W, H);  // observed pixels whose window can see the object
+  // observed pixels whose window can see the object (none when nothing is drawn)
+  Rect region = grow_clip(obj, h, W, H);
+  if (obj.empty()) region.x1 = region.x0;
   // acc: l, d(dt) x3, d(dw) x3, d sigma, d p_out
   float acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (!obj.empty()) {
@@ -76,7 +78,7 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
         zbuf[k] = s.bg ? s.bg[(size_t)r * W + c] : kEmptyKey;
       }
       __syncthreads();
-      raster_mesh(s.mesh, P, cam, 0u, L, zbuf, vbuf);
+      raster_mesh(s.mesh, P, cam, 0u, L, zbuf, rl);
       refine_depths(s.mesh, P, cam, 0u, L, zbuf);
 
       // likelihood over observed rows [wa, wb); rows [a, b) are this band's own

@@ -45,8 +45,8 @@ __device__ __forceinline__ void write_rows(const Cam& cam, int y0, int y1, const
 __global__ __launch_bounds__(kBlock) void k_render_batch(MeshDev m, Cam cam, const float* __restrict__ poses, int N,
                                                          float* __restrict__ xyz, int* __restrict__ tri, int zcap) {
   extern __shared__ __align__(16) unsigned char smem[];
-  float4* vbuf = reinterpret_cast<float4*>(smem);
-  unsigned long long* zbuf = reinterpret_cast<unsigned long long*>(vbuf + 2 * kClusterMax);
+  const RasterLds rl = carve_raster_lds(smem);
+  unsigned long long* zbuf = reinterpret_cast<unsigned long long*>(smem + kRasterLdsBytes);
   const int n = blockIdx.x;
   if (n >= N) return;
   const Pose P = load_pose(poses + 16 * (size_t)n);
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_render_batch(MeshDev m, Cam cam, con
     const int nk = band.h() * band.w();
     for (int k = threadIdx.x; k < nk; k += kBlock) zbuf[k] = kEmptyKey;
     __syncthreads();
-    raster_mesh(m, P, cam, 0u, band, zbuf, vbuf);
+    raster_mesh(m, P, cam, 0u, band, zbuf, rl);
     refine_depths(m, P, cam, 0u, band, zbuf);
     write_rows(cam, band.y0, band.y1, band, zbuf, 0u, xn, tn);
     __syncthreads();
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_render_batch(MeshDev m, Cam cam, con
 
 hipError_t launch_render_batch(const MeshDev& m, const Cam& cam, const float* poses, int N, float* xyz, int* tri,
                                int zcap, hipStream_t st) {
-  const size_t lds = sizeof(float4) * 2 * kClusterMax + sizeof(unsigned long long) * (size_t)zcap;
+  const size_t lds = kRasterLdsBytes + sizeof(unsigned long long) * (size_t)zcap;
   hipLaunchKernelGGL(k_render_batch, dim3(N), dim3(kBlock), lds, st, m, cam, poses, N, xyz, tri, zcap);
   return hipGetLastError();
 }

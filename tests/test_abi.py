@@ -65,3 +65,31 @@ def test_host_side_validation_without_a_device(lib):
     assert b.grid_size(g) == 60
     g.count[1] = 0
     assert b.grid_size(g) == 0
+
+
+def test_mesh_layout_sets_aside_only_faces_no_outside_camera_sees(lib):
+    import numpy as np
+
+    import paper_2312_08715_amd as b
+    from workloads import box_mesh, make_config, voxel_mesh
+
+    # two touching voxels: their two shared faces (4 triangles) are set aside
+    v, t = voxel_mesh(np.array([[0.0, 0.0, 0.0], [0.01, 0.0, 0.0]]))
+    info = b.mesh_layout_info(v, t)
+    assert info["hidden_pairs"] == 4 and info["drawn"] == 20 and info["dropped"] == 0
+    # a two-sided sheet is one component: both sides stay drawn
+    v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], float)
+    assert b.mesh_layout_info(v, np.array([[0, 1, 2], [0, 2, 1]]))["hidden_pairs"] == 0
+    # a single closed box: nothing set aside; a repeated vertex is dropped
+    v, t = box_mesh((0.1, 0.2, 0.3))
+    assert b.mesh_layout_info(v, t)["hidden_pairs"] == 0
+    t2 = np.vstack([t, [[0, 0, 1]]])
+    assert b.mesh_layout_info(v, t2)["dropped"] == 1
+    # the voxel blob: every set-aside triangle has a twin with the same corners
+    wl = make_config(1)
+    info = b.mesh_layout_info(wl.verts, wl.tris)
+    assert info["drawn"] + info["hidden_pairs"] + info["dropped"] == wl.tris.shape[0]
+    cells = np.round(wl.verts.reshape(-1, 8, 3).mean(1) / 0.01).astype(int)
+    occ = {tuple(c) for c in cells}
+    shared = sum((tuple(c + d) in occ) for c in cells for d in np.vstack([np.eye(3, dtype=int), -np.eye(3, dtype=int)]))
+    assert info["hidden_pairs"] == 2 * shared  # two triangles per touching face, counted from both voxels

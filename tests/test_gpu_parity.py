@@ -453,3 +453,55 @@ def test_multi_scene_batch_equals_per_scene_calls(b3d):
     L2, _ = batch.run()
     for a, b in zip(L, L2):
         assert torch.equal(a, b)
+
+
+def test_adam_pose_step_matches_oracle(b3d):
+    from oracle.refine import adam_pose_step
+
+    rng = np.random.default_rng(31)
+    P = f32(random_poses(rng, 40, 0.8, 0.03))
+    g = f32(rng.normal(0, 1e4, (40, 8)))
+    st = np.zeros((40, 12))
+    Pd, gd, sd = dev(P), dev(g), dev(st)
+    for it in (1, 2, 3):
+        b3d.adam_pose_step(Pd, gd, sd, it, 1e-3, 1e-2)
+        P, st = adam_pose_step(P, g, st, it, 1e-3, 1e-2)
+    np.testing.assert_allclose(Pd.cpu().numpy(), P, atol=2e-6)
+    np.testing.assert_allclose(sd.cpu().numpy(), st, rtol=1e-5, atol=1e-3)
+
+
+def test_tracker_graph_replays_match_eager_frames_and_follow_the_objects(b3d):
+    from workloads import assemble_observed_depth, tracking_sequence, Workload, ScoreParams, GridSpec
+
+    meshes, paths, cam, noise = tracking_sequence(seed=77, n_frames=6, n_obj=2, vox_range=(300, 600))
+    meshes = [(f32(v), t) for v, t in meshes]
+    F, M = paths.shape[:2]
+    say(f"tracker: {M} objects, {F} frames")
+    frames = []
+    for f in range(F):
+        objs = [(v, t, paths[f, k]) for k, (v, t) in enumerate(meshes)]
+        d = oracle.render(objs, cam)[0][0]
+        d = np.where(d > 0, d + noise[f]["gauss"], 0.0)
+        d = np.where(noise[f]["outlier_mask"], noise[f]["outlier_depth"], d)
+        frames.append(dev(f32(oracle.unproject(d, cam))))
+    ms = [b3d.Mesh(v, t) for v, t in meshes]
+    K = b3d.intrinsics_of(cam)
+    p = b3d.score_params(0.003, 0.01, 1.0, 5)
+    grid = b3d.make_grid(np.eye(4), (0.02, 0.02, 0.02), (6, 6, 6), n_rot=8, rot_max_angle=np.deg2rad(5.0))
+    init = f32(paths[0])
+    tg = b3d.Tracker(ms, K, p, grid, init, n_refine=5)
+    te = b3d.Tracker(ms, K, p, grid, init, n_refine=5)
+    for f in range(1, F):
+        tg.frame(frames[f])
+        torch.cuda.synchronize()
+        te.frame(frames[f], eager=True)
+        torch.cuda.synchronize()
+        a, b = tg.poses().cpu().numpy(), te.poses().cpu().numpy()
+        np.testing.assert_array_equal(a, b)
+    est = tg.poses().cpu().numpy()
+    for k in range(M):
+        err_t = np.linalg.norm(est[k, :3, 3] - paths[-1, k, :3, 3])
+        dR = est[k, :3, :3] @ paths[-1, k, :3, :3].T
+        err_r = np.degrees(np.arccos(np.clip((np.trace(dR) - 1) / 2, -1, 1)))
+        say(f"  object {k}: position error {err_t * 100:.3f} cm, orientation error {err_r:.3f} deg")
+        assert err_t < 0.01 and err_r < 5.0

@@ -23,6 +23,8 @@ from .scenes import (  # noqa: F401
     random_poses,
     random_scene_batch,
     shoemake_rotations,
+    smooth_trajectory,
+    tracking_sequence,
     tiny_scene,
     voxel_blob,
     voxel_mesh,

@@ -326,3 +326,52 @@ def random_scene_batch(rng: np.random.Generator, n_scenes: int):
         N = int(np.round(np.exp(rng.uniform(np.log(1000), np.log(20000)))))
         out.append({"n_obj": n_obj, "voxels": vox, "H": H, "W": W, "N": N})
     return out
+
+
+def smooth_trajectory(rng: np.random.Generator, n_frames: int, start: np.ndarray, max_step_t: float = 0.02,
+                      max_step_r: float = np.deg2rad(5.0)) -> np.ndarray:
+    """Poses [n_frames, 4, 4]: translation and rotation vector each a sum of
+    three seeded sinusoids per axis, scaled so that no frame-to-frame change
+    exceeds max_step_t (metres) or max_step_r (radians)."""
+    f = np.arange(n_frames, dtype=np.float64)[:, None]
+    out = np.tile(np.eye(4), (n_frames, 1, 1))
+
+    def series(cap):
+        om = rng.uniform(0.02, 0.15, (3, 3))
+        ph = rng.uniform(0, 2 * np.pi, (3, 3))
+        amp = rng.uniform(0.3, 1.0, (3, 3))
+        x = np.zeros((n_frames, 3))
+        for k in range(3):
+            x += amp[k] * np.sin(om[k] * f + ph[k])
+        step = np.linalg.norm(np.diff(x, axis=0), axis=1).max() if n_frames > 1 else 1.0
+        return (x - x[0]) * (0.9 * cap / max(step, 1e-12))
+
+    t = series(max_step_t)
+    w = series(max_step_r)
+    for i in range(n_frames):
+        out[i, :3, 3] = start[:3, 3] + t[i]
+        th = np.linalg.norm(w[i])
+        K = np.zeros((3, 3))
+        if th > 0:
+            k = w[i] / th
+            K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+        Rw = np.eye(3) + np.sin(th) * K + (1 - np.cos(th)) * (K @ K)
+        out[i, :3, :3] = Rw @ start[:3, :3]
+    return out
+
+
+def tracking_sequence(seed: int = 1004, n_frames: int = 200, n_obj: int = 3, vox_range=(2000, 5000),
+                      H: int = 120, W: int = 160, f: float = 150.0, outlier_frac: float = 0.04):
+    """Objects moving on smooth seeded SE(3) paths in front of the camera:
+    meshes, true poses [F, M, 4, 4], camera, and per-frame noise draws."""
+    rng = np.random.default_rng(seed)
+    cam = Camera(f, f, W / 2.0, H / 2.0, H, W)
+    meshes, paths = [], []
+    centres = [(-0.09, 0.0, 0.85), (0.09, 0.02, 0.9), (0.0, -0.05, 0.75), (0.05, 0.08, 0.95)]
+    for k in range(n_obj):
+        nv = int(rng.integers(vox_range[0], vox_range[1] + 1))
+        meshes.append(voxel_mesh(voxel_blob(nv, rng)))
+        start = pose_matrix(shoemake_rotations(1, rng)[0], centres[k % len(centres)])
+        paths.append(smooth_trajectory(rng, n_frames, start))
+    noise = [observation_noise(H, W, rng, 0.002, outlier_frac) for _ in range(n_frames)]
+    return meshes, np.stack(paths, 1), cam, noise
