@@ -351,15 +351,12 @@ b3d_status b3d_scene_create(const b3d_mesh* mesh, const b3d_intrinsics* K, const
   S->dev.cam = make_cam(K);
   S->dev.sc = sc;
   const int h = sc.h, W = K->W;
-  S->dev.zcap = std::max(2048, (4 * h + 8) * W);
-  S->dev.wcap = std::max(2048, (2 * h + 8) * W);
-  if (fused_lds_bytes(S->dev) > kLdsMax) {
-    S->dev.zcap = (4 * h + 1) * W;
-    S->dev.wcap = (2 * h + 1) * W;
-    if (fused_lds_bytes(S->dev) > kLdsMax) {
-      delete S;
-      return fail(B3D_ESHAPE, "scene_create: image width %d too large for the fused kernel's LDS budget", W);
-    }
+  // window weights live in the rasteriser's scratch once the depth buffer is done
+  S->dev.wcap = (int)(kRasterLdsBytes / sizeof(float));
+  S->dev.zcap = std::max(2048, (4 * h + 2) * W);
+  if ((2 * h + 1) * W > S->dev.wcap || fused_lds_bytes(S->dev) > kLdsMax) {
+    delete S;
+    return fail(B3D_ESHAPE, "scene_create: image width %d too large for the fused kernel's LDS budget", W);
   }
   const size_t HW = (size_t)K->H * K->W, SP = (size_t)(K->H + 1) * (K->W + 1);
   if (hipMalloc((void**)&S->terms, 3 * HW * sizeof(double)) != hipSuccess ||

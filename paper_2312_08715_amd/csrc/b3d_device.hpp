@@ -277,22 +277,25 @@ __device__ __forceinline__ bool covered_exact(const MeshDev& m, const Pose& P, c
   return !(w0 > 0.0 || w1 > 0.0 || w2 > 0.0);
 }
 
-// LDS scratch of the rasteriser.
+// LDS scratch of the rasteriser (free again once raster_mesh returns).
 struct RasterLds {
   float4* vbuf;  // 2 * kClusterMax cluster vertices (double-buffered)
   uint2* queue;  // (band pixel, triangle id) pairs left for the exact test
-  int* qcount;
+  int* list;     // drawable clusters of the current group of kBlock
+  int* counts;   // [0] queue fill, [1..kWaves] per-wave drawable counts
   int qcap;
 };
 
 constexpr int kQueueCap = 512;
-constexpr size_t kRasterLdsBytes = sizeof(float4) * 2 * kClusterMax + sizeof(uint2) * kQueueCap + 16;
+constexpr size_t kRasterLdsBytes =
+    sizeof(float4) * 2 * kClusterMax + sizeof(uint2) * kQueueCap + sizeof(int) * kBlock + sizeof(int) * 16;
 
 __device__ __forceinline__ RasterLds carve_raster_lds(unsigned char* p) {
   RasterLds r;
   r.vbuf = reinterpret_cast<float4*>(p);
   r.queue = reinterpret_cast<uint2*>(r.vbuf + 2 * kClusterMax);
-  r.qcount = reinterpret_cast<int*>(r.queue + kQueueCap);
+  r.list = reinterpret_cast<int*>(r.queue + kQueueCap);
+  r.counts = r.list + kBlock;
   r.qcap = kQueueCap;
   return r;
 }
@@ -312,7 +315,7 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
   const int pitch = band.w();
   const float bx0 = (float)band.x0, bx1 = (float)(band.x1 - 1);
   const float by0 = (float)band.y0, by1 = (float)(band.y1 - 1);
-  if (threadIdx.x == 0) *lds.qcount = 0;
+  if (threadIdx.x == 0) lds.counts[0] = 0;
   // the hidden-pair clusters matter only when the object reaches the near plane
   bool straddle = false;
 #pragma unroll
@@ -321,73 +324,92 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
     straddle = straddle || !(c.z > cam.znear);
   }
   const int n_clusters = straddle ? m.n_clusters : m.n_visible;
-  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int used = 0;
-  for (int ci_ = 0; ci_ < n_clusters; ++ci_) {
-    const ClusterDev cl = m.clusters[ci_];
-    if (!cluster_may_draw(cl, P, cam, band)) continue;
-    float4* vb = lds.vbuf + (used & 1) * kClusterMax;
-    ++used;
-    for (int v = threadIdx.x; v < cl.nv; v += kBlock) {
-      const float4 o = m.cverts[cl.vfirst + v];
-      const float3 p = xform(P, o.x, o.y, o.z);
-      const float iz = 1.0f / p.z;
-      vb[v] = make_float4(cam.fx * p.x * iz + cam.cx, cam.fy * p.y * iz + cam.cy, p.z, iz);
+  for (int base = 0; base < n_clusters; base += kBlock) {
+    // each thread tests one cluster; the drawable ones are compacted into `list`
+    const int mine = base + threadIdx.x;
+    const bool draw = mine < n_clusters && cluster_may_draw(m.clusters[mine], P, cam, band);
+    const unsigned long long mask = __ballot(draw);
+    __syncthreads();  // the previous group's list is no longer read
+    if (lane == 0) lds.counts[1 + wave] = __popcll(mask);
+    __syncthreads();
+    int off = 0, total = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      off += (w < wave) ? lds.counts[1 + w] : 0;
+      total += lds.counts[1 + w];
+    }
+    if (draw) {
+      const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+      lds.list[off + rank] = mine;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < cl.nt; i += kBlock) {
-      const uint2 tk = m.ctris[cl.tfirst + i];
-      const float4 p0 = vb[tk.x & 255u], p1 = vb[(tk.x >> 8) & 255u], p2 = vb[(tk.x >> 16) & 255u];
-      if (p0.z <= cam.znear || p1.z <= cam.znear || p2.z <= cam.znear) continue;
-      const float e0x = p2.x - p1.x, e0y = p2.y - p1.y;
-      const float e1x = p0.x - p2.x, e1y = p0.y - p2.y;
-      const float e2x = p1.x - p0.x, e2y = p1.y - p0.y;
-      const float umin = fminf(p0.x, fminf(p1.x, p2.x)), umax = fmaxf(p0.x, fmaxf(p1.x, p2.x));
-      const float vmin = fminf(p0.y, fminf(p1.y, p2.y)), vmax = fmaxf(p0.y, fmaxf(p1.y, p2.y));
-      // rounding margin (pixels) for this triangle's projected positions
-      const float tau = 2e-6f * fmaxf(fmaxf(fmaxf(fabsf(umin), fabsf(umax)), fmaxf(fabsf(vmin), fabsf(vmax))), 256.0f);
-      const float area = e2x * (p2.y - p0.y) - (p2.x - p0.x) * e2y;
-      const float amb_area = 2.0f * tau * (fabsf(e1x) + fabsf(e1y) + fabsf(e2x) + fabsf(e2y));
-      if (area > amb_area) continue;  // faces away
-      const bool edge_on = area >= -amb_area;
-      const float fc0 = ceilf(fmaxf(umin - 0.5f - tau, bx0)), fc1 = floorf(fminf(umax - 0.5f + tau, bx1));
-      const float fr0 = ceilf(fmaxf(vmin - 0.5f - tau, by0)), fr1 = floorf(fminf(vmax - 0.5f + tau, by1));
-      if (!(fc0 <= fc1) || !(fr0 <= fr1)) continue;
-      const int c0 = (int)fc0, c1 = (int)fc1, r0 = (int)fr0, r1 = (int)fr1;
-      const uint32_t id = id_base + tk.y;
-      const float inv_area = 1.0f / area;
-      const float t0 = tau * (fabsf(e0x) + fabsf(e0y)), t1 = tau * (fabsf(e1x) + fabsf(e1y)),
-                  t2 = tau * (fabsf(e2x) + fabsf(e2y));
-      for (int r = r0; r <= r1; ++r) {
-        const float py = (float)r + 0.5f;
-        for (int col = c0; col <= c1; ++col) {
-          const float px = (float)col + 0.5f;
-          // edge functions; each equals the (negative) area at the opposite vertex
-          const float w0 = e0x * (py - p1.y) - e0y * (px - p1.x);
-          const float w1 = e1x * (py - p2.y) - e1y * (px - p2.x);
-          const float w2 = e2x * (py - p0.y) - e2y * (px - p0.x);
-          if (w0 > t0 || w1 > t1 || w2 > t2) continue;  // clearly outside
-          const int pix = (r - band.y0) * pitch + (col - band.x0);
-          if (edge_on || w0 >= -t0 || w1 >= -t1 || w2 >= -t2) {
-            const int slot = atomicAdd(lds.qcount, 1);
-            if (slot < lds.qcap) {
-              lds.queue[slot] = make_uint2((uint32_t)pix, tk.y);
-              continue;
+    for (int q = 0; q < total; ++q) {
+      const ClusterDev cl = m.clusters[lds.list[q]];
+      float4* vb = lds.vbuf + (used & 1) * kClusterMax;
+      ++used;
+      for (int v = threadIdx.x; v < cl.nv; v += kBlock) {
+        const float4 o = m.cverts[cl.vfirst + v];
+        const float3 p = xform(P, o.x, o.y, o.z);
+        const float iz = 1.0f / p.z;
+        vb[v] = make_float4(cam.fx * p.x * iz + cam.cx, cam.fy * p.y * iz + cam.cy, p.z, iz);
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < cl.nt; i += kBlock) {
+        const uint2 tk = m.ctris[cl.tfirst + i];
+        const float4 p0 = vb[tk.x & 255u], p1 = vb[(tk.x >> 8) & 255u], p2 = vb[(tk.x >> 16) & 255u];
+        if (p0.z <= cam.znear || p1.z <= cam.znear || p2.z <= cam.znear) continue;
+        const float e0x = p2.x - p1.x, e0y = p2.y - p1.y;
+        const float e1x = p0.x - p2.x, e1y = p0.y - p2.y;
+        const float e2x = p1.x - p0.x, e2y = p1.y - p0.y;
+        const float umin = fminf(p0.x, fminf(p1.x, p2.x)), umax = fmaxf(p0.x, fmaxf(p1.x, p2.x));
+        const float vmin = fminf(p0.y, fminf(p1.y, p2.y)), vmax = fmaxf(p0.y, fmaxf(p1.y, p2.y));
+        // rounding margin (pixels) for this triangle's projected positions
+        const float tau =
+            2e-6f * fmaxf(fmaxf(fmaxf(fabsf(umin), fabsf(umax)), fmaxf(fabsf(vmin), fabsf(vmax))), 256.0f);
+        const float area = e2x * (p2.y - p0.y) - (p2.x - p0.x) * e2y;
+        const float amb_area = 2.0f * tau * (fabsf(e1x) + fabsf(e1y) + fabsf(e2x) + fabsf(e2y));
+        if (area > amb_area) continue;  // faces away
+        const bool edge_on = area >= -amb_area;
+        const float fc0 = ceilf(fmaxf(umin - 0.5f - tau, bx0)), fc1 = floorf(fminf(umax - 0.5f + tau, bx1));
+        const float fr0 = ceilf(fmaxf(vmin - 0.5f - tau, by0)), fr1 = floorf(fminf(vmax - 0.5f + tau, by1));
+        if (!(fc0 <= fc1) || !(fr0 <= fr1)) continue;
+        const int c0 = (int)fc0, c1 = (int)fc1, r0 = (int)fr0, r1 = (int)fr1;
+        const uint32_t id = id_base + tk.y;
+        const float inv_area = 1.0f / area;
+        const float t0 = tau * (fabsf(e0x) + fabsf(e0y)), t1 = tau * (fabsf(e1x) + fabsf(e1y)),
+                    t2 = tau * (fabsf(e2x) + fabsf(e2y));
+        for (int r = r0; r <= r1; ++r) {
+          const float py = (float)r + 0.5f;
+          for (int col = c0; col <= c1; ++col) {
+            const float px = (float)col + 0.5f;
+            // edge functions; each equals the (negative) area at the opposite vertex
+            const float w0 = e0x * (py - p1.y) - e0y * (px - p1.x);
+            const float w1 = e1x * (py - p2.y) - e1y * (px - p2.x);
+            const float w2 = e2x * (py - p0.y) - e2y * (px - p0.x);
+            if (w0 > t0 || w1 > t1 || w2 > t2) continue;  // clearly outside
+            const int pix = (r - band.y0) * pitch + (col - band.x0);
+            if (edge_on || w0 >= -t0 || w1 >= -t1 || w2 >= -t2) {
+              const int slot = atomicAdd(&lds.counts[0], 1);
+              if (slot < lds.qcap) {
+                lds.queue[slot] = make_uint2((uint32_t)pix, tk.y);
+                continue;
+              }
+              if (edge_on || w0 > 0.0f || w1 > 0.0f || w2 > 0.0f) continue;  // queue full: single precision
             }
-            if (edge_on || w0 > 0.0f || w1 > 0.0f || w2 > 0.0f) continue;  // queue full: single precision
+            // 1/z is affine in screen space: interpolate with barycentrics w_k/area
+            const float invz = (w0 * p0.w + w1 * p1.w + w2 * p2.w) * inv_area;
+            const float z = __builtin_amdgcn_rcpf(invz);
+            if (!(z > 0.0f)) continue;
+            atomicMin(&zbuf[pix], pack_key(z, id));
           }
-          // 1/z is affine in screen space: interpolate with barycentrics w_k/area
-          const float invz = (w0 * p0.w + w1 * p1.w + w2 * p2.w) * inv_area;
-          const float z = __builtin_amdgcn_rcpf(invz);
-          if (!(z > 0.0f)) continue;
-          atomicMin(&zbuf[pix], pack_key(z, id));
         }
       }
     }
   }
   __syncthreads();
   // centres near an edge: the exact test, then the plane depth
-  const int nq = min(*lds.qcount, lds.qcap);
+  const int nq = min(lds.counts[0], lds.qcap);
   for (int k = threadIdx.x; k < nq; k += kBlock) {
     const uint2 e = lds.queue[k];
     const int r = band.y0 + (int)e.x / pitch, col = band.x0 + (int)e.x % pitch;

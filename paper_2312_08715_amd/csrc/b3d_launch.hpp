@@ -32,7 +32,7 @@ struct SceneDev {
   const float* obs;                // [H][W][3]
   const unsigned long long* bg;    // [H][W] background keys, or nullptr
   const double* sat;               // 3 summed-area tables [(H+1)(W+1)]: l, dl/dp, dl/dsigma of the background
-  int zcap, wcap;                  // LDS capacities: depth keys, window weights
+  int zcap, wcap;                  // LDS capacities: depth keys, window weights (wcap <= kRasterLdsBytes / 4)
 };
 
 // One scene of a multi-scene batch: its hypotheses are work items

@@ -29,9 +29,10 @@ __device__ __forceinline__ double rect_sum(const double* sat, int W, const Rect&
          sat[(size_t)r.y0 * p + r.x0];
 }
 
+// LDS: rasteriser scratch (reused for the window weights once the depth
+// buffer is complete) | depth keys [zcap] | reduction [64] | ray tables [W], [H].
 size_t fused_lds_bytes(const SceneDev& s) {
-  return kRasterLdsBytes + sizeof(float) * (64 + s.cam.W + s.cam.H) + sizeof(unsigned long long) * (size_t)s.zcap +
-         sizeof(float) * (size_t)s.wcap + 16;
+  return kRasterLdsBytes + sizeof(unsigned long long) * (size_t)s.zcap + sizeof(float) * (64 + s.cam.W + s.cam.H);
 }
 
 // One hypothesis: pose16 (16 floats), writes *logL_out and, when GRAD,
@@ -42,11 +43,11 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
                                                  float* __restrict__ logL_out, float* __restrict__ grad_out,
                                                  unsigned char* smem) {
   const RasterLds rl = carve_raster_lds(smem);
+  float* wbuf = reinterpret_cast<float*>(smem);  // after rasterisation
   unsigned long long* zbuf = reinterpret_cast<unsigned long long*>(smem + kRasterLdsBytes);
   float* red = reinterpret_cast<float*>(zbuf + s.zcap);
   float* dxt = red + 64;
   float* dyt = dxt + s.cam.W;
-  float* wbuf = dyt + s.cam.H;
 
   const Cam& cam = s.cam;
   const ScoreConsts& sc = s.sc;

@@ -463,9 +463,11 @@ def test_adam_pose_step_matches_oracle(b3d):
     g = f32(rng.normal(0, 1e4, (40, 8)))
     st = np.zeros((40, 12))
     Pd, gd, sd = dev(P), dev(g), dev(st)
+    b1, b2, eps = (float(np.float32(x)) for x in (0.9, 0.999, 1e-8))
+    lr_t, lr_r = float(np.float32(1e-3)), float(np.float32(1e-2))
     for it in (1, 2, 3):
-        b3d.adam_pose_step(Pd, gd, sd, it, 1e-3, 1e-2)
-        P, st = adam_pose_step(P, g, st, it, 1e-3, 1e-2)
+        b3d.adam_pose_step(Pd, gd, sd, it, lr_t, lr_r, b1, b2, eps)
+        P, st = adam_pose_step(P, g, st, it, lr_t, lr_r, b1, b2, eps)
     np.testing.assert_allclose(Pd.cpu().numpy(), P, atol=2e-6)
     np.testing.assert_allclose(sd.cpu().numpy(), st, rtol=1e-5, atol=1e-3)
 
