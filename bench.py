@@ -29,16 +29,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pose hypotheses scored/s (render+logL) at 160x120, 24k tris; fwd+adjoint vs plain"
 
-# Algorithmic work per hypothesis in FP32 lane-operations (a transcendental
-# counts 4): 17 per vertex, 12 per triangle tested, 27 per camera-facing
-# triangle set up, 10 per covered fragment, 12 per (observed, rendered) pair
-# in a window, 6 per observed pixel that sees a rendered point; the adjoint
-# adds 10 per pair and 30 per rendered pixel.  The counts are the oracle's
-# counters on this workload (recomputed live by the CPU-baseline leg).
+# Algorithmic work in FP32 lane-operations (a transcendental counts 4): 17 per
+# vertex transformed, 12 per triangle tested, 27 per camera-facing triangle set
+# up, 10 per covered pixel centre, 12 per (observed, rendered) window pair, 6 per
+# observed pixel that sees a rendered point; the adjoint adds 10 per pair and 30
+# per rendered object pixel.  For the fused kernel the items are counted by its
+# instrumented instantiation on the same launch (the work of the algorithm as
+# run, after cluster culling); for the plain method they are the oracle's
+# counters (every triangle of the mesh).
 COST = {"vert": 17, "tri": 12, "front": 27, "frag": 10, "pair": 12, "obs": 6, "adj_pair": 10, "adj_rpix": 30}
-# oracle counters, mean per hypothesis over all 5000 hypotheses of this workload
-DEFAULT_COUNTS = {"vert": 16000.0, "tri": 24000.0, "front": 11900.0, "frag": 10490.0, "pair": 24800.0,
-                  "obs": 1185.0, "rpix": 1178.0}
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # FP32 lane-ops/s, non-packed: 39.3 T
 
 
@@ -48,6 +47,12 @@ def lane_ops(c, adjoint=True):
     if adjoint:
         f += COST["adj_pair"] * c["pair"] + COST["adj_rpix"] * c["rpix"]
     return f
+
+
+def counted_work(b3d, scene, P):
+    w = b3d.render_score_work(scene, P)
+    return {"vert": w["vertices"], "tri": w["triangles"], "front": w["setup"], "frag": w["fragments"],
+            "pair": w["pairs"], "obs": w["observed"], "rpix": w["adjoint_pixels"], "exact": w["exact_tests"]}
 
 
 def build_inputs(b3d, torch):
@@ -151,13 +156,12 @@ def main():
     t_split = timed(lambda: split(False), max(3, args.steps // 4), 1)
     t_split_adj = timed(lambda: split(True), max(3, args.steps // 4), 1)
 
-    counts = dict(DEFAULT_COUNTS)
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu, counts = cpu_baseline(wl, obs.cpu().numpy().astype(np.float64), args.cpu_seconds)
-
-    ops = lane_ops(counts, adjoint=True) * N
+    work = counted_work(b3d, scene, P)
+    ops = lane_ops(work, adjoint=True)
     achieved = ops / t_kernel / 1e12
+    cpu, plain_counts = None, None
+    if not args.no_cpu_baseline:
+        cpu, plain_counts = cpu_baseline(wl, obs.cpu().numpy().astype(np.float64), args.cpu_seconds)
     line = {
         "metric": METRIC,
         "value": N / t_step,
@@ -178,7 +182,9 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_render_score<true>", "achieved": achieved,
                      "peak": VALU_PEAK_TOPS, "unit": "TOP/s (FP32 lane-ops)", "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": None, "kernel_ms": t_kernel * 1e3,
-                     "ops_per_hypothesis": lane_ops(counts, adjoint=True)},
+                     "ops_per_hypothesis": ops / N,
+                     "work_per_hypothesis": {k: v / N for k, v in work.items()},
+                     "plain_method_ops_per_hypothesis": (lane_ops(plain_counts) if plain_counts else None)},
         "fwd_only": {"value": N / t_fwd, "ms_per_step": t_fwd * 1e3},
         "plain_split": {"value": N / t_split, "ms_per_step": t_split * 1e3,
                         "note": "render_batch -> score, point images in HBM"},

@@ -190,6 +190,17 @@ b3d_status b3d_scene_set_observed(b3d_scene* scene, const float* observed, void*
 b3d_status b3d_render_score(const b3d_scene* scene, const float* poses, int32_t N, float* logL_out, float* grad_out,
                             void* stream);
 
+/* b3d_render_score with the adjoint, from an instrumented build of the same
+ * kernel that also adds the launch's work items to work (device uint64[8],
+ * accumulated, zero it first): [0] vertices transformed, [1] triangles
+ * tested, [2] triangles set up (facing the camera, box on screen),
+ * [3] covered pixel centres, [4] (observed, rendered) window pairs,
+ * [5] observed pixels whose window held a point, [6] object pixels of the
+ * adjoint, [7] pixel centres decided by the exact double-precision test.
+ * For measurement; slower than b3d_render_score.  Stream-ordered. */
+b3d_status b3d_render_score_work(const b3d_scene* scene, const float* poses, int32_t N, float* logL_out,
+                                 float* grad_out, unsigned long long* work, void* stream);
+
 /* ---- many scenes in one persistent launch ------------------------------ */
 
 /* One scene's share of a batch: N hypotheses of the scene's moving object. */

@@ -84,6 +84,7 @@ _SIGNATURES = {
     "b3d_scene_set_background": ([_P, _P, _P, _I32, _P], ctypes.c_int),
     "b3d_scene_set_observed": ([_P, _P, _P], ctypes.c_int),
     "b3d_render_score": ([_P, _P, _I32, _P, _P, _P], ctypes.c_int),
+    "b3d_render_score_work": ([_P, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "b3d_batch_create": ([ctypes.POINTER(BatchItem), _I32, ctypes.POINTER(_P)], ctypes.c_int),
     "b3d_batch_run": ([_P, _P], ctypes.c_int),
     "b3d_batch_destroy": ([_P], ctypes.c_int),
@@ -291,6 +292,20 @@ def render_score(scene: Scene, poses: torch.Tensor, grad: bool = False):
     g = torch.empty((N, 8), dtype=torch.float32, device=poses.device) if grad else None
     _call("b3d_render_score", scene.handle, _ptr(poses, torch.float32), N, _ptr(logL), _ptr(g), _stream())
     return (logL, g) if grad else logL
+
+
+WORK_ITEMS = ("vertices", "triangles", "setup", "fragments", "pairs", "observed", "adjoint_pixels", "exact_tests")
+
+
+def render_score_work(scene: Scene, poses: torch.Tensor) -> dict:
+    """Work items of one fused forward+adjoint launch (instrumented kernel)."""
+    N = poses.shape[0]
+    logL = torch.empty(N, dtype=torch.float32, device=poses.device)
+    g = torch.empty((N, 8), dtype=torch.float32, device=poses.device)
+    work = torch.zeros(8, dtype=torch.int64, device=poses.device)
+    _call("b3d_render_score_work", scene.handle, _ptr(poses, torch.float32), N, _ptr(logL), _ptr(g), _ptr(work),
+          _stream())
+    return dict(zip(WORK_ITEMS, work.cpu().tolist()))
 
 
 def make_grid(center, half_extent, count, cell_centres=False, rotations: Optional[torch.Tensor] = None,

@@ -514,6 +514,18 @@ b3d_status b3d_batch_destroy(b3d_batch* b) {
   return B3D_OK;
 }
 
+b3d_status b3d_render_score_work(const b3d_scene* S, const float* poses, int32_t N, float* logL_out, float* grad_out,
+                                 unsigned long long* work, void* stream) {
+  if (!S) return fail(B3D_EINVAL, "render_score_work: NULL scene");
+  if (!S->observed) return fail(B3D_EINVAL, "render_score_work: call b3d_scene_set_observed first");
+  if (N < 0) return fail(B3D_ESHAPE, "render_score_work: N < 0");
+  if (N == 0) return B3D_OK;
+  if (!poses || !logL_out || !grad_out || !work) return fail(B3D_EINVAL, "render_score_work: NULL pointer");
+  B3D_CHECK_HIP(launch_render_score_count(S->dev, poses, N, logL_out, grad_out, work, (hipStream_t)stream),
+                "render_score_work");
+  return B3D_OK;
+}
+
 static b3d_status make_grid(const b3d_grid* g, GridDev* d, int64_t* N) {
   if (!g) return fail(B3D_EINVAL, "grid pointer is NULL");
   for (int k = 0; k < 3; ++k) {

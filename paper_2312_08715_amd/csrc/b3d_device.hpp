@@ -310,8 +310,17 @@ __device__ __forceinline__ RasterLds carve_raster_lds(unsigned char* p) {
 // lies within a rounding margin of an edge, or any centre of a triangle seen
 // nearly edge-on, is queued and decided afterwards by covered_exact.  Must be
 // called by the whole block; ends after a barrier with the buffer complete.
+// Work counters of the counting instantiation (indices into a per-block
+// array): vertices transformed, triangles tested, triangles set up, covered
+// pixel centres, window pairs, observed pixels that saw a point, object pixels
+// of the adjoint, centres decided by the exact test.
+enum { kCntVert = 0, kCntTri, kCntSetup, kCntFrag, kCntPair, kCntObs, kCntAdj, kCntExact, kCntN };
+
+template <bool COUNT = false>
 __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, const Cam& cam, uint32_t id_base,
-                                            const Rect& band, unsigned long long* zbuf, const RasterLds& lds) {
+                                            const Rect& band, unsigned long long* zbuf, const RasterLds& lds,
+                                            unsigned* cnt = nullptr) {
+  unsigned c_vert = 0, c_tri = 0, c_setup = 0, c_frag = 0, c_exact = 0;
   const int pitch = band.w();
   const float bx0 = (float)band.x0, bx1 = (float)(band.x1 - 1);
   const float by0 = (float)band.y0, by1 = (float)(band.y1 - 1);
@@ -348,6 +357,10 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
       const ClusterDev cl = m.clusters[lds.list[q]];
       float4* vb = lds.vbuf + (used & 1) * kClusterMax;
       ++used;
+      if (COUNT && threadIdx.x == 0) {
+        c_vert += cl.nv;
+        c_tri += cl.nt;
+      }
       for (int v = threadIdx.x; v < cl.nv; v += kBlock) {
         const float4 o = m.cverts[cl.vfirst + v];
         const float3 p = xform(P, o.x, o.y, o.z);
@@ -376,6 +389,7 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
         if (!(fc0 <= fc1) || !(fr0 <= fr1)) continue;
         const int c0 = (int)fc0, c1 = (int)fc1, r0 = (int)fr0, r1 = (int)fr1;
         const uint32_t id = id_base + tk.y;
+        if (COUNT) ++c_setup;
         const float inv_area = 1.0f / area;
         const float t0 = tau * (fabsf(e0x) + fabsf(e0y)), t1 = tau * (fabsf(e1x) + fabsf(e1y)),
                     t2 = tau * (fabsf(e2x) + fabsf(e2y));
@@ -401,6 +415,7 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
             const float invz = (w0 * p0.w + w1 * p1.w + w2 * p2.w) * inv_area;
             const float z = __builtin_amdgcn_rcpf(invz);
             if (!(z > 0.0f)) continue;
+            if (COUNT) ++c_frag;
             atomicMin(&zbuf[pix], pack_key(z, id));
           }
         }
@@ -413,10 +428,19 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
   for (int k = threadIdx.x; k < nq; k += kBlock) {
     const uint2 e = lds.queue[k];
     const int r = band.y0 + (int)e.x / pitch, col = band.x0 + (int)e.x % pitch;
+    if (COUNT) ++c_exact;
     if (!covered_exact(m, P, cam, e.y, r, col)) continue;
     const float z = plane_depth(m, P, cam, e.y, r, col);
     if (!(z > 0.0f)) continue;
+    if (COUNT) ++c_frag;
     atomicMin(&zbuf[e.x], pack_key(z, id_base + e.y));
+  }
+  if (COUNT) {
+    atomicAdd(&cnt[kCntVert], c_vert);
+    atomicAdd(&cnt[kCntTri], c_tri);
+    atomicAdd(&cnt[kCntSetup], c_setup);
+    atomicAdd(&cnt[kCntFrag], c_frag);
+    atomicAdd(&cnt[kCntExact], c_exact);
   }
   __syncthreads();
 }

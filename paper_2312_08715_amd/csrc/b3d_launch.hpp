@@ -69,6 +69,8 @@ hipError_t launch_score_backward(const float* obs, const float* rend, int N, int
                                  const float* dlogL, float* d_rend, float* d_sigma, float* d_pout, int cap,
                                  hipStream_t st);
 hipError_t launch_render_score(const SceneDev& s, const float* poses, int N, float* logL, float* grad, hipStream_t st);
+hipError_t launch_render_score_count(const SceneDev& s, const float* poses, int N, float* logL, float* grad,
+                                     unsigned long long* work, hipStream_t st);
 
 hipError_t batch_occupancy(bool grad, size_t lds, int* blocks_per_cu);
 hipError_t launch_batch(const BatchItemDev* items, int S, long long total, unsigned long long* counter, bool grad,

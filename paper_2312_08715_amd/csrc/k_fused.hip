@@ -38,10 +38,11 @@ size_t fused_lds_bytes(const SceneDev& s) {
 // One hypothesis: pose16 (16 floats), writes *logL_out and, when GRAD,
 // grad_out[0..8).  Must be called by the whole block; `smem` is at least
 // fused_lds_bytes(s).
-template <bool GRAD>
+template <bool GRAD, bool COUNT = false>
 __device__ __forceinline__ void render_score_one(const SceneDev& s, const float* __restrict__ pose16,
                                                  float* __restrict__ logL_out, float* __restrict__ grad_out,
-                                                 unsigned char* smem) {
+                                                 unsigned char* smem, unsigned* cnt = nullptr) {
+  unsigned c_pair = 0, c_obs = 0, c_adj = 0;
   const RasterLds rl = carve_raster_lds(smem);
   float* wbuf = reinterpret_cast<float*>(smem);  // after rasterisation
   unsigned long long* zbuf = reinterpret_cast<unsigned long long*>(smem + kRasterLdsBytes);
@@ -79,7 +80,7 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
         zbuf[k] = s.bg ? s.bg[(size_t)r * W + c] : kEmptyKey;
       }
       __syncthreads();
-      raster_mesh(s.mesh, P, cam, 0u, L, zbuf, rl);
+      raster_mesh<COUNT>(s.mesh, P, cam, 0u, L, zbuf, rl, cnt);
       refine_depths(s.mesh, P, cam, 0u, L, zbuf);
 
       // likelihood over observed rows [wa, wb); rows [a, b) are this band's own
@@ -107,10 +108,12 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
               const float e = f_exp2(-D * sc.c2);
               S += e;
               if (GRAD) T += e * D;
+              if (COUNT && r >= a && r < b) ++c_pair;
             }
           }
           const float Li = sc.a + sc.bn * S;
           if (r >= a && r < b) {
+            if (COUNT && S > 0.0f) ++c_obs;
             acc[0] += f_ln(Li);
             if (GRAD) {
               acc[7] += (sc.bn / Li) * (T * sc.inv_s3 - 3.0f * S * sc.inv_s);
@@ -134,6 +137,7 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
           if (key == kEmptyKey) continue;
           const uint32_t id = key_id(key);
           if (id >= (uint32_t)s.mesh.T) continue;  // a background surface
+          if (COUNT) ++c_adj;
           const float z = key_depth(key);
           const float dx = dxt[c], dy = dyt[r];
           const float qx = z * dx, qy = z * dy, qz = z;
@@ -166,6 +170,11 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
       }
       __syncthreads();
     }
+  }
+  if (COUNT) {
+    atomicAdd(&cnt[kCntPair], c_pair);
+    atomicAdd(&cnt[kCntObs], c_obs);
+    atomicAdd(&cnt[kCntAdj], c_adj);
   }
   block_sum<9>(acc, red);
   if (threadIdx.x == 0) {
@@ -241,6 +250,29 @@ hipError_t launch_batch(const BatchItemDev* items, int S, long long total, unsig
     hipLaunchKernelGGL(k_batch<true>, dim3(blocks), dim3(kBlock), lds, st, items, S, total, counter);
   else
     hipLaunchKernelGGL(k_batch<false>, dim3(blocks), dim3(kBlock), lds, st, items, S, total, counter);
+  return hipGetLastError();
+}
+
+// The counting instantiation: same work, plus per-launch totals of the work
+// items in work[kCntN] (64-bit, accumulated).
+__global__ __launch_bounds__(kBlock) void k_render_score_count(SceneDev s, const float* __restrict__ poses, int N,
+                                                               float* __restrict__ logL, float* __restrict__ grad,
+                                                               unsigned long long* __restrict__ work) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ unsigned cnt[kCntN];
+  const int n = blockIdx.x;
+  if (n >= N) return;
+  if (threadIdx.x < kCntN) cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  render_score_one<true, true>(s, poses + 16 * (size_t)n, logL + n, grad + 8 * (size_t)n, smem, cnt);
+  __syncthreads();
+  if (threadIdx.x < kCntN) atomicAdd(&work[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+}
+
+hipError_t launch_render_score_count(const SceneDev& s, const float* poses, int N, float* logL, float* grad,
+                                     unsigned long long* work, hipStream_t st) {
+  hipLaunchKernelGGL(k_render_score_count, dim3(N), dim3(kBlock), fused_lds_bytes(s), st, s, poses, N, logL, grad,
+                     work);
   return hipGetLastError();
 }
 
