@@ -86,6 +86,9 @@ def main():
     ap.add_argument("--samples", type=int, default=64, help="draws per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--fused-only", action="store_true", help="skip the split-path comparison")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (hypotheses would shard "
@@ -153,8 +156,16 @@ def main():
             b3d.render_backward(mesh, P, K, tri, dr)
         return L
 
-    t_split = timed(lambda: split(False), max(3, args.steps // 4), 1)
-    t_split_adj = timed(lambda: split(True), max(3, args.steps // 4), 1)
+    t_split = t_split_adj = float("nan")
+    if not args.fused_only:
+        t_split = timed(lambda: split(False), max(3, args.steps // 4), 1)
+        t_split_adj = timed(lambda: split(True), max(3, args.steps // 4), 1)
+    if args.copy_calibration:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     work = counted_work(b3d, scene, P)
     ops = lane_ops(work, adjoint=True)

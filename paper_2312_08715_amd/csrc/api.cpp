@@ -353,7 +353,11 @@ b3d_status b3d_scene_create(const b3d_mesh* mesh, const b3d_intrinsics* K, const
   const int h = sc.h, W = K->W;
   // window weights live in the rasteriser's scratch once the depth buffer is done
   S->dev.wcap = (int)(kRasterLdsBytes / sizeof(float));
-  S->dev.zcap = std::max(2048, (4 * h + 2) * W);
+  // depth keys: as many as leave room for four workgroups per CU (160 KB of LDS)
+  S->dev.zcap = 0;
+  const size_t share = 40 * 1024;
+  const size_t rest = fused_lds_bytes(S->dev);
+  S->dev.zcap = std::max((int)((share > rest ? share - rest : 0) / sizeof(unsigned long long)), (4 * h + 2) * W);
   if ((2 * h + 1) * W > S->dev.wcap || fused_lds_bytes(S->dev) > kLdsMax) {
     delete S;
     return fail(B3D_ESHAPE, "scene_create: image width %d too large for the fused kernel's LDS budget", W);
