@@ -10,7 +10,8 @@ namespace b3d {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kWaves = kBlock / 64;
-constexpr int kClusterMax = 256;     // max triangles and max vertices per cluster
+constexpr int kClusterTris = 64;     // max triangles per cluster (one per lane of a wave)
+constexpr int kClusterVerts = 128;   // max vertices per cluster
 constexpr unsigned long long kEmptyKey = ~0ull;
 
 // Pinhole camera and image size.
@@ -25,9 +26,9 @@ struct Pose {
   float t[3];
 };
 
-// A group of up to kClusterMax triangles of one orientation class that are
+// A group of up to kClusterTris triangles of one orientation class that are
 // close in space, with its own copy of the vertices they use (at most
-// kClusterMax).  sphere = centre and radius of a ball holding them; cone =
+// kClusterVerts).  sphere = centre and radius of a ball holding them; cone =
 // unit axis and half-angle (radians) of a cone holding their face normals
 // (half-angle > pi/2 means "no bound").
 struct ClusterDev {
@@ -279,43 +280,45 @@ __device__ __forceinline__ bool covered_exact(const MeshDev& m, const Pose& P, c
 
 // LDS scratch of the rasteriser (free again once raster_mesh returns).
 struct RasterLds {
-  float4* vbuf;  // 2 * kClusterMax cluster vertices (double-buffered)
+  float4* vbuf;  // kWaves * kClusterVerts projected vertices (one buffer per wave)
   uint2* queue;  // (band pixel, triangle id) pairs left for the exact test
   int* list;     // drawable clusters of the current group of kBlock
-  int* counts;   // [0] queue fill, [1..kWaves] per-wave drawable counts
+  int* counts;   // [0] queue fill, [1..kWaves] per-wave drawable counts, [kWaves + 1] next list entry
   int qcap;
 };
 
 constexpr int kQueueCap = 512;
 constexpr size_t kRasterLdsBytes =
-    sizeof(float4) * 2 * kClusterMax + sizeof(uint2) * kQueueCap + sizeof(int) * kBlock + sizeof(int) * 16;
+    sizeof(float4) * kWaves * kClusterVerts + sizeof(uint2) * kQueueCap + sizeof(int) * kBlock + sizeof(int) * 16;
 
 __device__ __forceinline__ RasterLds carve_raster_lds(unsigned char* p) {
   RasterLds r;
   r.vbuf = reinterpret_cast<float4*>(p);
-  r.queue = reinterpret_cast<uint2*>(r.vbuf + 2 * kClusterMax);
+  r.queue = reinterpret_cast<uint2*>(r.vbuf + kWaves * kClusterVerts);
   r.list = reinterpret_cast<int*>(r.queue + kQueueCap);
   r.counts = r.list + kBlock;
   r.qcap = kQueueCap;
   return r;
 }
 
-// Rasterise the mesh under pose P into an LDS key buffer that covers the
-// image rectangle `band` (row pitch band.w()).  Triangle ids written are
-// id_base + the caller's triangle index.  Clusters that cannot draw into the
-// band are skipped whole; the remaining ones are transformed cluster by
-// cluster into LDS and every triangle walks the pixel centres of its screen
-// box.  A centre that single precision places clearly inside all three edges
-// is written at once (64-bit atomicMin of the packed depth/id key); one that
-// lies within a rounding margin of an edge, or any centre of a triangle seen
-// nearly edge-on, is queued and decided afterwards by covered_exact.  Must be
-// called by the whole block; ends after a barrier with the buffer complete.
 // Work counters of the counting instantiation (indices into a per-block
 // array): vertices transformed, triangles tested, triangles set up, covered
 // pixel centres, window pairs, observed pixels that saw a point, object pixels
 // of the adjoint, centres decided by the exact test.
 enum { kCntVert = 0, kCntTri, kCntSetup, kCntFrag, kCntPair, kCntObs, kCntAdj, kCntExact, kCntN };
 
+// Rasterise the mesh under pose P into an LDS key buffer that covers the
+// image rectangle `band` (row pitch band.w()).  Triangle ids written are
+// id_base + the caller's triangle index.  Clusters are tested for drawing,
+// kBlock at a time, and the drawable ones compacted into a list; the four
+// waves then take clusters from the list independently: a wave transforms
+// its cluster's vertices into its own LDS buffer and each lane takes one
+// triangle, walking the pixel centres of its screen box.  A centre that single
+// precision places clearly inside all three edges is written at once (64-bit
+// atomicMin of the packed depth/id key); one that lies within a rounding
+// margin of an edge, or any centre of a triangle seen nearly edge-on, is
+// queued and decided afterwards by covered_exact.  Must be called by the whole
+// block; ends after a barrier with the buffer complete.
 template <bool COUNT = false>
 __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, const Cam& cam, uint32_t id_base,
                                             const Rect& band, unsigned long long* zbuf, const RasterLds& lds,
@@ -334,7 +337,7 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
   }
   const int n_clusters = straddle ? m.n_clusters : m.n_visible;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int used = 0;
+  float4* vb = lds.vbuf + wave * kClusterVerts;
   for (int base = 0; base < n_clusters; base += kBlock) {
     // each thread tests one cluster; the drawable ones are compacted into `list`
     const int mine = base + threadIdx.x;
@@ -342,36 +345,39 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
     const unsigned long long mask = __ballot(draw);
     __syncthreads();  // the previous group's list is no longer read
     if (lane == 0) lds.counts[1 + wave] = __popcll(mask);
+    if (threadIdx.x == 0) lds.counts[1 + kWaves] = 0;
     __syncthreads();
     int off = 0, total = 0;
     for (int w = 0; w < kWaves; ++w) {
       off += (w < wave) ? lds.counts[1 + w] : 0;
       total += lds.counts[1 + w];
     }
-    if (draw) {
-      const int rank = __popcll(mask & ((1ull << lane) - 1ull));
-      lds.list[off + rank] = mine;
-    }
+    if (draw) lds.list[off + __popcll(mask & ((1ull << lane) - 1ull))] = mine;
     __syncthreads();
-    for (int q = 0; q < total; ++q) {
+    for (;;) {
+      int q = 0;
+      if (lane == 0) q = atomicAdd(&lds.counts[1 + kWaves], 1);
+      q = __shfl(q, 0, 64);
+      if (q >= total) break;
       const ClusterDev cl = m.clusters[lds.list[q]];
-      float4* vb = lds.vbuf + (used & 1) * kClusterMax;
-      ++used;
-      if (COUNT && threadIdx.x == 0) {
+      if (COUNT && lane == 0) {
         c_vert += cl.nv;
         c_tri += cl.nt;
       }
-      for (int v = threadIdx.x; v < cl.nv; v += kBlock) {
+      for (int v = lane; v < cl.nv; v += 64) {
         const float4 o = m.cverts[cl.vfirst + v];
         const float3 p = xform(P, o.x, o.y, o.z);
         const float iz = 1.0f / p.z;
         vb[v] = make_float4(cam.fx * p.x * iz + cam.cx, cam.fy * p.y * iz + cam.cy, p.z, iz);
       }
-      __syncthreads();
-      for (int i = threadIdx.x; i < cl.nt; i += kBlock) {
-        const uint2 tk = m.ctris[cl.tfirst + i];
+      // the wave's own writes must land before its lanes read them
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (lane < cl.nt) {
+        const uint2 tk = m.ctris[cl.tfirst + lane];
         const float4 p0 = vb[tk.x & 255u], p1 = vb[(tk.x >> 8) & 255u], p2 = vb[(tk.x >> 16) & 255u];
-        if (p0.z <= cam.znear || p1.z <= cam.znear || p2.z <= cam.znear) continue;
+        const bool near = p0.z <= cam.znear || p1.z <= cam.znear || p2.z <= cam.znear;
         const float e0x = p2.x - p1.x, e0y = p2.y - p1.y;
         const float e1x = p0.x - p2.x, e1y = p0.y - p2.y;
         const float e2x = p1.x - p0.x, e2y = p1.y - p0.y;
@@ -382,41 +388,42 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
             2e-6f * fmaxf(fmaxf(fmaxf(fabsf(umin), fabsf(umax)), fmaxf(fabsf(vmin), fabsf(vmax))), 256.0f);
         const float area = e2x * (p2.y - p0.y) - (p2.x - p0.x) * e2y;
         const float amb_area = 2.0f * tau * (fabsf(e1x) + fabsf(e1y) + fabsf(e2x) + fabsf(e2y));
-        if (area > amb_area) continue;  // faces away
         const bool edge_on = area >= -amb_area;
         const float fc0 = ceilf(fmaxf(umin - 0.5f - tau, bx0)), fc1 = floorf(fminf(umax - 0.5f + tau, bx1));
         const float fr0 = ceilf(fmaxf(vmin - 0.5f - tau, by0)), fr1 = floorf(fminf(vmax - 0.5f + tau, by1));
-        if (!(fc0 <= fc1) || !(fr0 <= fr1)) continue;
-        const int c0 = (int)fc0, c1 = (int)fc1, r0 = (int)fr0, r1 = (int)fr1;
-        const uint32_t id = id_base + tk.y;
-        if (COUNT) ++c_setup;
-        const float inv_area = 1.0f / area;
-        const float t0 = tau * (fabsf(e0x) + fabsf(e0y)), t1 = tau * (fabsf(e1x) + fabsf(e1y)),
-                    t2 = tau * (fabsf(e2x) + fabsf(e2y));
-        for (int r = r0; r <= r1; ++r) {
-          const float py = (float)r + 0.5f;
-          for (int col = c0; col <= c1; ++col) {
-            const float px = (float)col + 0.5f;
-            // edge functions; each equals the (negative) area at the opposite vertex
-            const float w0 = e0x * (py - p1.y) - e0y * (px - p1.x);
-            const float w1 = e1x * (py - p2.y) - e1y * (px - p2.x);
-            const float w2 = e2x * (py - p0.y) - e2y * (px - p0.x);
-            if (w0 > t0 || w1 > t1 || w2 > t2) continue;  // clearly outside
-            const int pix = (r - band.y0) * pitch + (col - band.x0);
-            if (edge_on || w0 >= -t0 || w1 >= -t1 || w2 >= -t2) {
-              const int slot = atomicAdd(&lds.counts[0], 1);
-              if (slot < lds.qcap) {
-                lds.queue[slot] = make_uint2((uint32_t)pix, tk.y);
-                continue;
+        // drawn unless behind the near plane, facing away, or with no centre in its box
+        if (!near && !(area > amb_area) && fc0 <= fc1 && fr0 <= fr1) {
+          const int c0 = (int)fc0, c1 = (int)fc1, r0 = (int)fr0, r1 = (int)fr1;
+          const uint32_t id = id_base + tk.y;
+          if (COUNT) ++c_setup;
+          const float inv_area = 1.0f / area;
+          const float t0 = tau * (fabsf(e0x) + fabsf(e0y)), t1 = tau * (fabsf(e1x) + fabsf(e1y)),
+                      t2 = tau * (fabsf(e2x) + fabsf(e2y));
+          for (int r = r0; r <= r1; ++r) {
+            const float py = (float)r + 0.5f;
+            for (int col = c0; col <= c1; ++col) {
+              const float px = (float)col + 0.5f;
+              // edge functions; each equals the (negative) area at the opposite vertex
+              const float w0 = e0x * (py - p1.y) - e0y * (px - p1.x);
+              const float w1 = e1x * (py - p2.y) - e1y * (px - p2.x);
+              const float w2 = e2x * (py - p0.y) - e2y * (px - p0.x);
+              if (w0 > t0 || w1 > t1 || w2 > t2) continue;  // clearly outside
+              const int pix = (r - band.y0) * pitch + (col - band.x0);
+              if (edge_on || w0 >= -t0 || w1 >= -t1 || w2 >= -t2) {
+                const int slot = atomicAdd(&lds.counts[0], 1);
+                if (slot < lds.qcap) {
+                  lds.queue[slot] = make_uint2((uint32_t)pix, tk.y);
+                  continue;
+                }
+                if (edge_on || w0 > 0.0f || w1 > 0.0f || w2 > 0.0f) continue;  // queue full: single precision
               }
-              if (edge_on || w0 > 0.0f || w1 > 0.0f || w2 > 0.0f) continue;  // queue full: single precision
+              // 1/z is affine in screen space: interpolate with barycentrics w_k/area
+              const float invz = (w0 * p0.w + w1 * p1.w + w2 * p2.w) * inv_area;
+              const float z = __builtin_amdgcn_rcpf(invz);
+              if (!(z > 0.0f)) continue;
+              if (COUNT) ++c_frag;
+              atomicMin(&zbuf[pix], pack_key(z, id));
             }
-            // 1/z is affine in screen space: interpolate with barycentrics w_k/area
-            const float invz = (w0 * p0.w + w1 * p1.w + w2 * p2.w) * inv_area;
-            const float z = __builtin_amdgcn_rcpf(invz);
-            if (!(z > 0.0f)) continue;
-            if (COUNT) ++c_frag;
-            atomicMin(&zbuf[pix], pack_key(z, id));
           }
         }
       }

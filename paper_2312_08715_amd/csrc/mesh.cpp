@@ -1,7 +1,7 @@
 // Host-side device layout of a triangle mesh for the rasteriser.
 //
 // The rasteriser walks a mesh cluster by cluster: each cluster holds up to
-// kClusterMax triangles of one orientation class that are close in space,
+// kClusterTris triangles of one orientation class that are close in space,
 // with its own copy of the (deduplicated) vertices they use, a bounding
 // sphere and a cone bounding its face normals.  Per hypothesis a cluster is
 // skipped as a whole when its cone and sphere show that every triangle in it
@@ -241,7 +241,7 @@ MeshLayout build_mesh_layout(const float* verts, int V, const int* tris, int T) 
       size_t j = i;
       for (; j < ids.size(); ++j) {
         const int t = ids[j];
-        if ((order_key[t] >> 32) != cls_dir || c.nt == kClusterMax) break;
+        if ((order_key[t] >> 32) != cls_dir || c.nt == kClusterTris) break;
         int fresh = 0;
         for (int k = 0; k < 3; ++k) {
           const int p = pid[tris[3 * t + k]];
@@ -249,7 +249,7 @@ MeshLayout build_mesh_layout(const float* verts, int V, const int* tris, int T) 
           for (int m = 0; m < k; ++m) seen = seen || pid[tris[3 * t + m]] == p;
           fresh += seen ? 0 : 1;
         }
-        if (c.nv + fresh > kClusterMax) break;
+        if (c.nv + fresh > kClusterVerts) break;
         uint32_t packed = 0;
         for (int k = 0; k < 3; ++k) {
           const int p = pid[tris[3 * t + k]];
