@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/b3d.h"
+#include "b3d.h"
 #include "b3d_launch.hpp"
 #include "b3d_mesh_layout.hpp"
 
