@@ -129,17 +129,28 @@ __device__ __forceinline__ bool project_box(const Pose& P, const float* lo, cons
   return ok;
 }
 
+// Range of x/z over a sphere (centre c, radius r) in front of the camera:
+// the planes x = k z through the camera that touch the sphere have
+// (c_x - k c_z)^2 = r^2 (1 + k^2), i.e.
+// k = (c_x c_z -+ r sqrt(c_x^2 + c_z^2 - r^2)) / (c_z^2 - r^2).
+__device__ __forceinline__ void sphere_slopes(float cx, float cz, float r, float& k0, float& k1) {
+  const float den = cz * cz - r * r;
+  const float root = r * sqrtf(fmaxf(cx * cx + cz * cz - r * r, 0.0f));
+  k0 = (cx * cz - root) / den;
+  k1 = (cx * cz + root) / den;
+}
+
 // Conservative pixel rectangle of the object under pose P: the projection of
-// the mesh's posed bounding box intersected with that of the camera-aligned
-// box around its bounding sphere, widened by one pixel, clipped to the
-// image.  The whole image when neither box lies in front of the near plane.
+// the mesh's posed bounding box intersected with the exact projection bounds
+// of its bounding sphere (slightly enlarged against rounding), widened by one
+// pixel, clipped to the image.  The whole image when neither bound applies
+// (the box reaches the near plane and the sphere reaches the camera plane).
 __device__ __forceinline__ Rect object_rect(const MeshDev& m, const Pose& P, const Cam& cam) {
-  float a[4], s[4];
+  float a[4], b[4];
   const bool aok = project_box(P, m.lo, m.hi, true, cam, a);
   const float3 c = xform(P, m.sphere[0], m.sphere[1], m.sphere[2]);
-  const float rad = m.sphere[3];
-  const float slo[3] = {c.x - rad, c.y - rad, c.z - rad}, shi[3] = {c.x + rad, c.y + rad, c.z + rad};
-  const bool sok = project_box(P, slo, shi, false, cam, s);
+  const float rad = m.sphere[3] * 1.0001f + 1e-6f;
+  const bool sok = c.z - rad > cam.znear;
   Rect r;
   if (!aok && !sok) {
     r.x0 = 0;
@@ -148,14 +159,22 @@ __device__ __forceinline__ Rect object_rect(const MeshDev& m, const Pose& P, con
     r.y1 = cam.H;
     return r;
   }
-  float b[4];
-  if (aok && sok) {
-    b[0] = fmaxf(a[0], s[0]);
-    b[1] = fminf(a[1], s[1]);
-    b[2] = fmaxf(a[2], s[2]);
-    b[3] = fminf(a[3], s[3]);
+  if (sok) {
+    float k0, k1;
+    sphere_slopes(c.x, c.z, rad, k0, k1);
+    b[0] = cam.fx * k0 + cam.cx - 0.01f;
+    b[1] = cam.fx * k1 + cam.cx + 0.01f;
+    sphere_slopes(c.y, c.z, rad, k0, k1);
+    b[2] = cam.fy * k0 + cam.cy - 0.01f;
+    b[3] = cam.fy * k1 + cam.cy + 0.01f;
+    if (aok) {
+      b[0] = fmaxf(a[0], b[0]);
+      b[1] = fminf(a[1], b[1]);
+      b[2] = fmaxf(a[2], b[2]);
+      b[3] = fminf(a[3], b[3]);
+    }
   } else {
-    for (int k = 0; k < 4; ++k) b[k] = aok ? a[k] : s[k];
+    for (int k = 0; k < 4; ++k) b[k] = a[k];
   }
   // pixel centres c + 1/2 in [umin, umax], widened by one pixel each side
   const float fx0 = fmaxf(ceilf(b[0] - 0.5f) - 1.0f, 0.0f);
