@@ -35,6 +35,128 @@ size_t fused_lds_bytes(const SceneDev& s) {
   return kRasterLdsBytes + sizeof(unsigned long long) * (size_t)s.zcap + sizeof(float) * (64 + s.cam.W + s.cam.H);
 }
 
+// Window sums for observed point (ox, oy, oz) at pixel (r, c) over the LDS
+// depth rectangle L (pitch lw): S = sum_j exp(-D_ij/(2 sigma^2)) and
+// T = sum_j exp(-D_ij/(2 sigma^2)) D_ij over the rendered points of the
+// window.  Window positions outside L lie outside the image and are skipped.
+// HH > 0: the window half-width known at compile time (each row unrolled and
+// branch-free, with clamped addresses and predicated terms); HH = 0: any h.
+template <int HH, bool GRAD, bool COUNT>
+__device__ __forceinline__ void window_sums(const unsigned long long* __restrict__ zbuf, const Rect& L, int lw,
+                                            const float* __restrict__ dxt, const float* __restrict__ dyt, int r,
+                                            int c, int h, float ox, float oy, float oz, float c2, float& S, float& T,
+                                            unsigned& pairs) {
+  S = 0.0f;
+  T = 0.0f;
+  if (HH > 0) {
+    constexpr int n = 2 * HH + 1;
+    int cc[n];
+    bool cv[n];
+    float dxs[n];
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      const int cj = c - HH + k;
+      cv[k] = cj >= L.x0 && cj < L.x1;
+      cc[k] = min(max(cj, L.x0), L.x1 - 1);
+      dxs[k] = dxt[cc[k]];
+      cc[k] -= L.x0;
+    }
+#pragma unroll 1
+    for (int j = 0; j < n; ++j) {
+      const int rj = r - HH + j;
+      const bool rv = rj >= L.y0 && rj < L.y1;
+      const int rc = min(max(rj, L.y0), L.y1 - 1);
+      const float dy = dyt[rc];
+      const unsigned long long* zr = zbuf + (rc - L.y0) * lw;
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        const unsigned long long key = zr[cc[k]];
+        const bool ok = rv && cv[k] && key != kEmptyKey;
+        const float z = key_depth(key);
+        const float ex = ox - z * dxs[k], ey = oy - z * dy, ez = oz - z;
+        const float D = ex * ex + ey * ey + ez * ez;
+        const float e = ok ? f_exp2(-D * c2) : 0.0f;
+        S += e;
+        if (GRAD) T += e * D;
+        if (COUNT) pairs += ok ? 1u : 0u;
+      }
+    }
+  } else {
+    const int r0 = max(r - h, L.y0), r1 = min(r + h, L.y1 - 1);
+    const int c0 = max(c - h, L.x0), c1 = min(c + h, L.x1 - 1);
+    for (int rj = r0; rj <= r1; ++rj) {
+      const float dy = dyt[rj];
+      const unsigned long long* zr = zbuf + (rj - L.y0) * lw - L.x0;
+      for (int cj = c0; cj <= c1; ++cj) {
+        const unsigned long long key = zr[cj];
+        if (key == kEmptyKey) continue;
+        const float z = key_depth(key);
+        const float ex = ox - z * dxt[cj], ey = oy - z * dy, ez = oz - z;
+        const float D = ex * ex + ey * ey + ez * ez;
+        const float e = f_exp2(-D * c2);
+        S += e;
+        if (GRAD) T += e * D;
+        if (COUNT) ++pairs;
+      }
+    }
+  }
+}
+
+// d logL / d z_j of an object pixel (r, c) with point q = z (dx, dy, 1):
+// sum over observed i in its window of w_i exp(-D_ij/(2 sigma^2)) (q~_i - q).d,
+// with w_i = b/L_i from the LDS buffer of observed rows [wa, ...) and region
+// columns (0 for invalid observed pixels).  Returns the sum before the
+// 1/sigma^2 factor.  HH as for window_sums.
+template <int HH>
+__device__ __forceinline__ float window_grad(const float* __restrict__ wbuf, int wa, int wb, const Rect& region,
+                                             const float* __restrict__ obs, int W, int r, int c, int h, float qx,
+                                             float qy, float qz, float dx, float dy, float c2) {
+  const int rw = region.w();
+  float g = 0.0f;
+  if (HH > 0) {
+    constexpr int n = 2 * HH + 1;
+    int cc[n];
+    bool cv[n];
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      const int ci = c - HH + k;
+      cv[k] = ci >= region.x0 && ci < region.x1;
+      cc[k] = min(max(ci, region.x0), region.x1 - 1);
+    }
+#pragma unroll 1
+    for (int j = 0; j < n; ++j) {
+      const int ri = r - HH + j;
+      const bool rv = ri >= wa && ri < wb;
+      const int rc = min(max(ri, wa), wb - 1);
+      const float* wr = wbuf + (rc - wa) * rw - region.x0;
+      const float* orow = obs + 3 * (size_t)rc * W;
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        const float wv = (rv && cv[k]) ? wr[cc[k]] : 0.0f;
+        const float* q = orow + 3 * cc[k];
+        const float ex = q[0] - qx, ey = q[1] - qy, ez = q[2] - qz;
+        const float e = f_exp2(-(ex * ex + ey * ey + ez * ez) * c2);
+        g += wv * e * (ex * dx + ey * dy + ez);
+      }
+    }
+  } else {
+    const int r0 = max(r - h, wa), r1 = min(r + h, wb - 1);
+    const int c0 = max(c - h, region.x0), c1 = min(c + h, region.x1 - 1);
+    for (int ri = r0; ri <= r1; ++ri) {
+      const float* wr = wbuf + (ri - wa) * rw - region.x0;
+      for (int ci = c0; ci <= c1; ++ci) {
+        const float wv = wr[ci];
+        if (wv == 0.0f) continue;
+        const float* q = obs + 3 * ((size_t)ri * W + ci);
+        const float ex = q[0] - qx, ey = q[1] - qy, ez = q[2] - qz;
+        const float e = f_exp2(-(ex * ex + ey * ey + ez * ez) * c2);
+        g += wv * e * (ex * dx + ey * dy + ez);
+      }
+    }
+  }
+  return g;
+}
+
 // One hypothesis: pose16 (16 floats), writes *logL_out and, when GRAD,
 // grad_out[0..8).  Must be called by the whole block; `smem` is at least
 // fused_lds_bytes(s).
@@ -93,24 +215,19 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
         const float ox = q[0], oy = q[1], oz = q[2];
         float wv = 0.0f;
         if (oz > 0.0f) {
-          float S = 0.0f, T = 0.0f;
-          const int r0 = max(r - h, 0), r1 = min(r + h, H - 1);
-          const int c0 = max(c - h, 0), c1 = min(c + h, W - 1);
-          for (int rj = r0; rj <= r1; ++rj) {
-            const float dy = dyt[rj];
-            const unsigned long long* zr = zbuf + (rj - L.y0) * lw - L.x0;
-            for (int cj = c0; cj <= c1; ++cj) {
-              const unsigned long long key = zr[cj];
-              if (key == kEmptyKey) continue;
-              const float z = key_depth(key);
-              const float ex = ox - z * dxt[cj], ey = oy - z * dy, ez = oz - z;
-              const float D = ex * ex + ey * ey + ez * ez;
-              const float e = f_exp2(-D * sc.c2);
-              S += e;
-              if (GRAD) T += e * D;
-              if (COUNT && r >= a && r < b) ++c_pair;
-            }
+          float S, T;
+          unsigned pairs = 0;
+          switch (h) {
+            case 1:
+              window_sums<1, GRAD, COUNT>(zbuf, L, lw, dxt, dyt, r, c, h, ox, oy, oz, sc.c2, S, T, pairs);
+              break;
+            case 2:
+              window_sums<2, GRAD, COUNT>(zbuf, L, lw, dxt, dyt, r, c, h, ox, oy, oz, sc.c2, S, T, pairs);
+              break;
+            default:
+              window_sums<0, GRAD, COUNT>(zbuf, L, lw, dxt, dyt, r, c, h, ox, oy, oz, sc.c2, S, T, pairs);
           }
+          if (COUNT && r >= a && r < b) c_pair += pairs;
           const float Li = sc.a + sc.bn * S;
           if (r >= a && r < b) {
             if (COUNT && S > 0.0f) ++c_obs;
@@ -141,19 +258,16 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
           const float z = key_depth(key);
           const float dx = dxt[c], dy = dyt[r];
           const float qx = z * dx, qy = z * dy, qz = z;
-          float g = 0.0f;
-          const int r0 = max(r - h, 0), r1 = min(r + h, H - 1);
-          const int c0 = max(c - h, 0), c1 = min(c + h, W - 1);
-          for (int ri = r0; ri <= r1; ++ri) {
-            const float* wr = wbuf + (ri - wa) * rw - region.x0;
-            for (int ci = c0; ci <= c1; ++ci) {
-              const float wv = wr[ci];
-              if (wv == 0.0f) continue;
-              const float* q = s.obs + 3 * ((size_t)ri * W + ci);
-              const float ex = q[0] - qx, ey = q[1] - qy, ez = q[2] - qz;
-              const float e = f_exp2(-(ex * ex + ey * ey + ez * ez) * sc.c2);
-              g += wv * e * (ex * dx + ey * dy + ez);
-            }
+          float g;
+          switch (h) {
+            case 1:
+              g = window_grad<1>(wbuf, wa, wb, region, s.obs, W, r, c, h, qx, qy, qz, dx, dy, sc.c2);
+              break;
+            case 2:
+              g = window_grad<2>(wbuf, wa, wb, region, s.obs, W, r, c, h, qx, qy, qz, dx, dy, sc.c2);
+              break;
+            default:
+              g = window_grad<0>(wbuf, wa, wb, region, s.obs, W, r, c, h, qx, qy, qz, dx, dy, sc.c2);
           }
           g *= sc.inv_s2;
           const float4 no = s.mesh.normals[id];
