@@ -75,9 +75,11 @@ __device__ __forceinline__ void window_sums(const unsigned long long* __restrict
         const float z = key_depth(key);
         const float ex = ox - z * dxs[k], ey = oy - z * dy, ez = oz - z;
         const float D = ex * ex + ey * ey + ez * ez;
-        const float e = ok ? f_exp2(-D * c2) : 0.0f;
+        // an empty slot reads a NaN depth: mask the distance as well as the term
+        const float Dm = ok ? D : 0.0f;
+        const float e = ok ? f_exp2(-Dm * c2) : 0.0f;
         S += e;
-        if (GRAD) T += e * D;
+        if (GRAD) T += e * Dm;
         if (COUNT) pairs += ok ? 1u : 0u;
       }
     }
