@@ -287,11 +287,11 @@ b3d_status b3d_render_batch(const b3d_mesh* mesh, const float* poses, int32_t N,
   return B3D_OK;
 }
 
-static int score_cap(int W, int h, int planes, int halo_rows) {
+static int score_cap(int W, int h, int planes, int halo_rows, int want) {
   // floats of LDS for staged rows: at least one output row plus halo
   const int need = planes * W * (1 + halo_rows * h);
-  const int want = 16384 - 64;
-  return need > want ? -1 : want;
+  if (need > 16384 - 64) return -1;
+  return std::max(need, want);
 }
 
 b3d_status b3d_score(const float* observed, const float* rendered, int32_t N, int32_t H, int32_t W,
@@ -301,7 +301,7 @@ b3d_status b3d_score(const float* observed, const float* rendered, int32_t N, in
   if (b3d_status s = make_consts(p, H, W, &sc)) return s;
   if (N == 0) return B3D_OK;
   if (!observed || !rendered || !logL_out) return fail(B3D_EINVAL, "score: NULL pointer");
-  const int cap = score_cap(W, sc.h, 3, 2);
+  const int cap = score_cap(W, sc.h, 3, 2, 10240 - 64);  // four workgroups per CU
   if (cap < 0) return fail(B3D_ESHAPE, "score: image too wide for the LDS row buffer");
   B3D_CHECK_HIP(launch_score(observed, rendered, N, H, W, sc, logL_out, cap, (hipStream_t)stream), "score");
   return B3D_OK;
@@ -317,7 +317,7 @@ b3d_status b3d_score_backward(const float* observed, const float* rendered, int3
   if (N == 0) return B3D_OK;
   if (!observed || !rendered) return fail(B3D_EINVAL, "score_backward: NULL pointer");
   if (!d_rendered && !d_sigma && !d_pout) return B3D_OK;
-  const int cap = score_cap(W, sc.h, 4, 4);
+  const int cap = score_cap(W, sc.h, 4, 4, 16384 - 64);
   if (cap < 0) return fail(B3D_ESHAPE, "score_backward: image too wide for the LDS row buffer");
   B3D_CHECK_HIP(launch_score_backward(observed, rendered, N, H, W, sc, dlogL, d_rendered, d_sigma, d_pout, cap,
                                       (hipStream_t)stream),

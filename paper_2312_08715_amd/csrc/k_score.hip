@@ -10,39 +10,101 @@ namespace b3d {
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float fast_ln(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
 
-// Stage rows [y0, y1) of a point image into LDS as three planes.
+// Stage rows [y0, y1) of a point image into LDS as three planes, with 16-byte
+// loads for the aligned middle of the span.
+__device__ __forceinline__ void put_plane(float* sx, float* sy, float* sz, int f, float v) {
+  const int p = f / 3, comp = f - 3 * p;
+  (comp == 0 ? sx : (comp == 1 ? sy : sz))[p] = v;
+}
+
 __device__ __forceinline__ void stage_rows(const float* __restrict__ img, int W, int y0, int y1, float* sx, float* sy,
                                            float* sz) {
   const int nf = (y1 - y0) * W * 3;
   const float* src = img + (size_t)y0 * W * 3;
-  for (int f = threadIdx.x; f < nf; f += kBlock) {
-    const float v = src[f];
-    const int p = f / 3, comp = f - 3 * p;
-    (comp == 0 ? sx : (comp == 1 ? sy : sz))[p] = v;
+  const int head = (int)(((16 - ((uintptr_t)src & 15)) & 15) / 4);
+  const int h0 = min(head, nf);
+  for (int f = threadIdx.x; f < h0; f += kBlock) put_plane(sx, sy, sz, f, src[f]);
+  const int nv = (nf - h0) / 4;
+  const float4* v4 = reinterpret_cast<const float4*>(src + h0);
+  for (int i = threadIdx.x; i < nv; i += kBlock) {
+    const float4 v = v4[i];
+    const int f = h0 + 4 * i;
+    put_plane(sx, sy, sz, f, v.x);
+    put_plane(sx, sy, sz, f + 1, v.y);
+    put_plane(sx, sy, sz, f + 2, v.z);
+    put_plane(sx, sy, sz, f + 3, v.w);
   }
+  for (int f = h0 + 4 * nv + threadIdx.x; f < nf; f += kBlock) put_plane(sx, sy, sz, f, src[f]);
 }
 
 // Window sums S = sum_j exp2(-D c2) and T = sum_j exp2(-D c2) D of the
-// observed point (ox, oy, oz) at pixel (r, c) over staged rows starting at y0.
-template <bool WANT_T>
+// observed point (ox, oy, oz) at pixel (r, c) over staged rows starting at y0
+// (rows outside [0, H) and columns outside [0, W) do not exist).  HH > 0:
+// half-width known at compile time (rows rolled, columns unrolled,
+// predicated); HH = 0: any h.
+template <int HH, bool WANT_T>
 __device__ __forceinline__ void window_sums(const ScoreConsts& sc, int H, int W, int r, int c, float ox, float oy,
                                             float oz, const float* sx, const float* sy, const float* sz, int y0,
                                             float& S, float& T) {
   S = 0.0f;
   T = 0.0f;
-  const int r0 = max(r - sc.h, 0), r1 = min(r + sc.h, H - 1);
-  const int c0 = max(c - sc.h, 0), c1 = min(c + sc.h, W - 1);
-  for (int rj = r0; rj <= r1; ++rj) {
-    const int base = (rj - y0) * W;
-    for (int cj = c0; cj <= c1; ++cj) {
-      const float qz = sz[base + cj];
-      if (!(qz > 0.0f)) continue;
-      const float ex = ox - sx[base + cj], ey = oy - sy[base + cj], ez = oz - qz;
-      const float D = ex * ex + ey * ey + ez * ez;
-      const float e = fast_exp2(-D * sc.c2);
-      S += e;
-      if (WANT_T) T += e * D;
+  if (HH > 0) {
+    constexpr int n = 2 * HH + 1;
+    int cc[n];
+    bool cv[n];
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      const int cj = c - HH + k;
+      cv[k] = cj >= 0 && cj < W;
+      cc[k] = min(max(cj, 0), W - 1);
     }
+#pragma unroll 1
+    for (int j = 0; j < n; ++j) {
+      const int rj = r - HH + j;
+      if (rj < 0 || rj >= H) continue;
+      const int base = (rj - y0) * W;
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        const float qz = sz[base + cc[k]];
+        const bool ok = cv[k] && qz > 0.0f;
+        const float ex = ox - sx[base + cc[k]], ey = oy - sy[base + cc[k]], ez = oz - qz;
+        const float D = ok ? ex * ex + ey * ey + ez * ez : 0.0f;
+        const float e = ok ? fast_exp2(-D * sc.c2) : 0.0f;
+        S += e;
+        if (WANT_T) T += e * D;
+      }
+    }
+  } else {
+    const int r0 = max(r - sc.h, 0), r1 = min(r + sc.h, H - 1);
+    const int c0 = max(c - sc.h, 0), c1 = min(c + sc.h, W - 1);
+    for (int rj = r0; rj <= r1; ++rj) {
+      const int base = (rj - y0) * W;
+      for (int cj = c0; cj <= c1; ++cj) {
+        const float qz = sz[base + cj];
+        if (!(qz > 0.0f)) continue;
+        const float ex = ox - sx[base + cj], ey = oy - sy[base + cj], ez = oz - qz;
+        const float D = ex * ex + ey * ey + ez * ez;
+        const float e = fast_exp2(-D * sc.c2);
+        S += e;
+        if (WANT_T) T += e * D;
+      }
+    }
+  }
+}
+
+template <bool WANT_T>
+__device__ __forceinline__ void window_sums_h(const ScoreConsts& sc, int H, int W, int r, int c, float ox, float oy,
+                                              float oz, const float* sx, const float* sy, const float* sz, int y0,
+                                              float& S, float& T) {
+  switch (sc.h) {
+    case 1:
+      window_sums<1, WANT_T>(sc, H, W, r, c, ox, oy, oz, sx, sy, sz, y0, S, T);
+      break;
+    case 2:
+      window_sums<2, WANT_T>(sc, H, W, r, c, ox, oy, oz, sx, sy, sz, y0, S, T);
+      break;
+    default:
+      window_sums<0, WANT_T>(sc, H, W, r, c, ox, oy, oz, sx, sy, sz, y0, S, T);
   }
 }
 
@@ -71,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_score(const float* __restrict__ obs,
       const float oz = q[2];
       if (!(oz > 0.0f)) continue;
       float S, T;
-      window_sums<false>(sc, H, W, r, c, q[0], q[1], oz, sx, sy, sz, y0, S, T);
+      window_sums_h<false>(sc, H, W, r, c, q[0], q[1], oz, sx, sy, sz, y0, S, T);
       acc[0] += fast_ln(sc.a + sc.bn * S);
     }
     __syncthreads();
@@ -126,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_score_backward(const float* __restri
       float w = 0.0f;
       if (oz > 0.0f) {
         float S, T;
-        window_sums<true>(sc, H, W, r, c, q[0], q[1], oz, sx, sy, sz, y0, S, T);
+        window_sums_h<true>(sc, H, W, r, c, q[0], q[1], oz, sx, sy, sz, y0, S, T);
         const float L = sc.a + sc.bn * S;
         w = sc.bn / L;
         if (r >= a && r < b) {
