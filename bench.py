@@ -78,6 +78,170 @@ def build_inputs(b3d, torch):
     return wl, K, obs
 
 
+def gpu_depth(b3d, torch, objs, cam):
+    """Composite depth [H,W] (numpy) of (verts, tris, pose) objects rendered by the library."""
+    K = b3d.intrinsics_of(cam)
+    z = None
+    for v, t, P in objs:
+        m = b3d.Mesh(v, t)
+        xyz, _ = b3d.render_batch(m, torch.as_tensor(np.asarray(P, np.float32)[None], device="cuda"), K, False)
+        zk = xyz[0, ..., 2].cpu().numpy().astype(np.float64)
+        z = zk if z is None else np.where((zk > 0) & ((z == 0) | (zk < z)), zk, z)
+    return z
+
+
+def noisy_observation(b3d, torch, depth, noise, cam):
+    z = np.where(depth > 0, depth + noise["gauss"], 0.0)
+    z = np.where(noise["outlier_mask"], noise["outlier_depth"], z)
+    return b3d.unproject(torch.as_tensor(z, dtype=torch.float32, device="cuda"), b3d.intrinsics_of(cam))
+
+
+def rot_err_deg(Ra, Rb):
+    c = (np.trace(Ra @ Rb.T) - 1.0) / 2.0
+    return float(np.degrees(np.arccos(np.clip(c, -1.0, 1.0))))
+
+
+def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3):
+    """Many scenes (1-8 objects of 500-8000 voxels, three image sizes, 1k-20k
+    hypotheses each) in one persistent launch, forward + adjoint, against the
+    same scenes one launch at a time."""
+    from workloads import Camera, observation_noise, pose_matrix, random_scene_batch, shoemake_rotations, voxel_blob, \
+        voxel_mesh
+
+    rng = np.random.default_rng(seed)
+    items, keep = [], []
+    for i, sh in enumerate(random_scene_batch(rng, n_scenes)):
+        H, W = sh["H"], sh["W"]
+        cam = Camera(W * 0.9375, W * 0.9375, W / 2.0, H / 2.0, H, W)
+        objs = []
+        for k, nv in enumerate(sh["voxels"]):
+            v, t = voxel_mesh(voxel_blob(nv, rng))
+            pos = (0.0, 0.0, 0.8) if k == 0 else (rng.uniform(-0.2, 0.2), rng.uniform(-0.15, 0.15),
+                                                  rng.uniform(0.8, 1.2))
+            objs.append((v, t, pose_matrix(shoemake_rotations(1, rng)[0], pos)))
+        obs = noisy_observation(b3d, torch, gpu_depth(b3d, torch, objs, cam),
+                                observation_noise(H, W, rng, 0.002, 0.03), cam)
+        meshes = [b3d.Mesh(v, t) for v, t, _ in objs]
+        scene = b3d.Scene(meshes[0], b3d.intrinsics_of(cam), p)
+        if len(objs) > 1:
+            scene.set_background(meshes[1:], np.stack([P for _, _, P in objs[1:]]))
+        scene.set_observed(obs)
+        nz = max(1, int(round(sh["N"] / 1000.0)))
+        grid = b3d.make_grid(objs[0][2], (0.02, 0.02, 0.02), (10, 10, nz), n_rot=10, rot_max_angle=np.deg2rad(10.0))
+        items.append((scene, b3d.enumerate_grid(grid, seed=3003 + i)))
+        keep += [meshes, obs]
+    total = sum(int(P.shape[0]) for _, P in items)
+    batch = b3d.Batch(items, grad=True)
+    batch.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        batch.run()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    for sc, P in items:
+        b3d.render_score(sc, P, grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for sc, P in items:
+            b3d.render_score(sc, P, grad=True)
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / reps
+    return {"scenes": n_scenes, "hypotheses": total, "value": total / t_batch, "ms": t_batch * 1e3,
+            "one_at_a_time": {"value": total / t_seq, "ms": t_seq * 1e3}, "unit": "hypotheses/s",
+            "note": "forward + adjoint; one persistent launch vs one launch per scene"}
+
+
+def bench_tracking(b3d, torch, p, n_frames=200):
+    """Three objects on smooth SE(3) paths, 160x120, 4% outliers; per frame and
+    object 10,000 hypotheses (+-2 cm, 5 deg) and 10 Adam steps, one HIP graph
+    per frame."""
+    from workloads import tracking_sequence
+
+    meshes, paths, cam, noise = tracking_sequence(seed=1004, n_frames=n_frames)
+    M = paths.shape[1]
+    frames = []
+    for f in range(n_frames):
+        objs = [(v, t, paths[f, k]) for k, (v, t) in enumerate(meshes)]
+        frames.append(noisy_observation(b3d, torch, gpu_depth(b3d, torch, objs, cam), noise[f], cam))
+    ms = [b3d.Mesh(v, t) for v, t in meshes]
+    grid = b3d.make_grid(np.eye(4), (0.02, 0.02, 0.02), (10, 10, 10), n_rot=10, rot_max_angle=np.deg2rad(5.0))
+    tr = b3d.Tracker(ms, b3d.intrinsics_of(cam), p, grid, paths[0], n_refine=10, lr_t=1e-3, lr_r=5e-3)
+    est = torch.empty((n_frames, M, 4, 4), dtype=torch.float32, device="cuda")
+    est[0] = torch.as_tensor(paths[0], dtype=torch.float32)
+    tr.frame(frames[1])  # captures the frame graph
+    est[1] = tr.poses()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in range(2, n_frames):
+        tr.frame(frames[f])
+        est[f] = tr.poses()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    E = est.cpu().numpy().astype(np.float64)
+    pos = np.linalg.norm(E[1:, :, :3, 3] - paths[1:, :, :3, 3], axis=2) * 100.0
+    rot = np.array([[rot_err_deg(E[f, k, :3, :3], paths[f, k, :3, :3]) for k in range(M)] for f in range(1, n_frames)])
+    return {"frames_per_s": (n_frames - 2) / dt, "frames": n_frames, "objects": M,
+            "hypotheses_per_frame": int(M * 10000), "position_error_cm": {"mean": float(pos.mean()),
+                                                                           "max": float(pos.max())},
+            "orientation_error_deg": {"mean": float(rot.mean()), "max": float(rot.max())}}
+
+
+def bench_table_c2f(b3d, torch, p):
+    """Four objects on a table at 320x240: per object three coarse-to-fine
+    stages of 10,000 hypotheses for 16 particles, then 20 Adam steps on the
+    survivors with the adjoint."""
+    from workloads import shoemake_rotations, table_scene
+
+    meshes, poses, table, cam, noise, Tcw = table_scene()
+    objs = [(v, t, P) for (v, t), P in zip(meshes, poses)] + [table]
+    obs = noisy_observation(b3d, torch, gpu_depth(b3d, torch, objs, cam), noise, cam)
+    ms = [b3d.Mesh(v, t) for v, t, _ in objs]
+    K = b3d.intrinsics_of(cam)
+    rng = np.random.default_rng(2002)
+    stages = [((0.08, 0.08, 0.08), 30.0), ((0.02, 0.02, 0.02), 10.0), ((0.005, 0.005, 0.005), 3.0)]
+    sched = b3d.make_schedule([b3d.make_grid(np.eye(4), h, (10, 10, 10), n_rot=10, rot_max_angle=np.deg2rad(a))
+                               for h, a in stages])
+    out, total_h, total_t = [], 0, 0.0
+    for k in range(len(meshes)):
+        scene = b3d.Scene(ms[k], K, p)
+        others = [j for j in range(len(objs)) if j != k]
+        scene.set_background([ms[j] for j in others], np.stack([objs[j][2] for j in others]))
+        scene.set_observed(obs)
+        truth = poses[k]
+        # start 3 cm and 15 degrees away from the truth (a detection's error)
+        w = rng.normal(size=3)
+        w *= np.deg2rad(15.0) / np.linalg.norm(w)
+        Kx = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]]) / np.linalg.norm(w)
+        th = np.linalg.norm(w)
+        dR = np.eye(3) + np.sin(th) * Kx + (1 - np.cos(th)) * Kx @ Kx
+        dt = rng.normal(size=3)
+        dt *= 0.03 / np.linalg.norm(dt)
+        start = truth.copy()
+        start[:3, :3] = dR @ truth[:3, :3]
+        start[:3, 3] += dt
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P, logq, idx = b3d.c2f_step(scene, start, sched, 16, 4002 + k)
+        state = torch.zeros((16, 12), dtype=torch.float32, device="cuda")
+        for it in range(1, 21):
+            L, G = b3d.render_score(scene, P, grad=True)
+            b3d.adam_pose_step(P, G, state, it, 1e-3, 1e-2)
+        L = b3d.render_score(scene, P)
+        torch.cuda.synchronize()
+        dtm = time.perf_counter() - t0
+        best = P[int(torch.argmax(L))].cpu().numpy().astype(np.float64)
+        n_h = 10000 + 2 * 16 * 10000 + 21 * 16
+        total_h += n_h
+        total_t += dtm
+        out.append({"object": k, "triangles": int(meshes[k][1].shape[0]), "ms": dtm * 1e3,
+                    "position_error_cm": float(np.linalg.norm(best[:3, 3] - truth[:3, 3]) * 100),
+                    "orientation_error_deg": rot_err_deg(best[:3, :3], truth[:3, :3])})
+    return {"hypotheses_per_s": total_h / total_t, "objects": out,
+            "note": "3 stages x 10,000 hypotheses (16 particles from stage 2), then 20 Adam steps on 16 poses"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +251,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fused-only", action="store_true", help="skip the split-path comparison")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batch, tracking and table workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -170,6 +335,14 @@ def main():
     work = counted_work(b3d, scene, P)
     ops = lane_ops(work, adjoint=True)
     achieved = ops / t_kernel / 1e12
+    extras = {}
+    if not args.no_extras:
+        for name, fn in (("batch_64_scenes", lambda: bench_batch(b3d, torch, p)),
+                         ("tracking_200_frames", lambda: bench_tracking(b3d, torch, p)),
+                         ("table_c2f_adam", lambda: bench_table_c2f(b3d, torch, p))):
+            t0 = time.perf_counter()
+            extras[name] = fn()
+            print(f"# {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     cpu, plain_counts = None, None
     if not args.no_cpu_baseline:
         cpu, plain_counts = cpu_baseline(wl, obs.cpu().numpy().astype(np.float64), args.cpu_seconds)
@@ -202,6 +375,7 @@ def main():
         "plain_split_fwd_adjoint": {"value": N / t_split_adj, "ms_per_step": t_split_adj * 1e3},
         "cpu_baseline": cpu,
     }
+    line.update(extras)
     print(json.dumps(line), flush=True)
 
 

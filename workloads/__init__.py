@@ -25,6 +25,8 @@ from .scenes import (  # noqa: F401
     shoemake_rotations,
     smooth_trajectory,
     tracking_sequence,
+    table_scene,
+    look_at,
     tiny_scene,
     voxel_blob,
     voxel_mesh,

@@ -375,3 +375,49 @@ def tracking_sequence(seed: int = 1004, n_frames: int = 200, n_obj: int = 3, vox
         paths.append(smooth_trajectory(rng, n_frames, start))
     noise = [observation_noise(H, W, rng, 0.002, outlier_frac) for _ in range(n_frames)]
     return meshes, np.stack(paths, 1), cam, noise
+
+
+def look_at(eye: Sequence[float], target: Sequence[float] = (0.0, 0.0, 0.0),
+            up: Sequence[float] = (0.0, 0.0, 1.0)) -> np.ndarray:
+    """World-to-camera transform of a camera at `eye` looking at `target`
+    with `up` pointing up in the image (+z forward, +x right, +y down)."""
+    eye, target, up = (np.asarray(x, dtype=np.float64) for x in (eye, target, up))
+    z = target - eye
+    z /= np.linalg.norm(z)
+    x = np.cross(z, up)
+    x /= np.linalg.norm(x)
+    y = np.cross(z, x)
+    R = np.stack([x, y, z])
+    return pose_matrix(R, -R @ eye)
+
+
+def table_scene(seed: int = 1002, voxels=(800, 1500, 3000, 6000), W: int = 320, H: int = 240, f: float = 300.0,
+                distance: float = 0.8, elevation_deg: float = 45.0):
+    """Objects resting on a 1 m x 1 m table (world z = 0) seen by a camera
+    that looks at the world origin with +z up, at a seeded azimuth.
+    Returns meshes, object poses (camera frame), the table (verts, tris,
+    pose), the camera, observation noise draws and the camera-from-world pose."""
+    rng = np.random.default_rng(seed)
+    cam = Camera(f, f, W / 2.0, H / 2.0, H, W)
+    az = rng.uniform(0, 2 * np.pi)
+    el = np.deg2rad(elevation_deg)
+    eye = distance * np.array([np.cos(el) * np.cos(az), np.cos(el) * np.sin(az), np.sin(el)])
+    Tcw = look_at(eye)
+    meshes, poses = [], []
+    slots = [(-0.15, -0.12), (0.14, -0.1), (-0.1, 0.15), (0.15, 0.14)]
+    for k, n in enumerate(voxels):
+        c = voxel_blob(n, rng)
+        v, t = voxel_mesh(c)
+        meshes.append((v, t))
+        yaw = rng.uniform(0, 2 * np.pi)
+        cy, sy = np.cos(yaw), np.sin(yaw)
+        Rw = np.array([[cy, -sy, 0.0], [sy, cy, 0.0], [0.0, 0.0, 1.0]])
+        lift = -v[:, 2].min()  # rest on the table
+        x, y = slots[k % len(slots)]
+        Tw = pose_matrix(Rw, (x + rng.uniform(-0.02, 0.02), y + rng.uniform(-0.02, 0.02), lift))
+        poses.append(Tcw @ Tw)
+    tv = np.array([[-0.5, -0.5, 0.0], [0.5, -0.5, 0.0], [0.5, 0.5, 0.0], [-0.5, 0.5, 0.0]])
+    tt = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)  # normal +z, towards the camera
+    table = (tv, tt, Tcw.copy())
+    noise = observation_noise(H, W, rng, 0.002, 0.03)
+    return meshes, poses, table, cam, noise, Tcw
