@@ -44,32 +44,48 @@ def build(force: bool = False) -> str:
     return _LIB_PATH
 
 
+def load(path: str):
+    """Load an oracle shared library from `path` and declare its signatures."""
+    L = ctypes.CDLL(path)
+    _declare(L)
+    return L
+
+
+def use_library(L) -> None:
+    """Route every oracle call through the already-loaded library L (None =
+    the default build).  Used by the tests that plant mistakes in a copy."""
+    global _lib
+    _lib = L
+
+
 def lib():
     global _lib
     if _lib is None:
         build()
-        L = ctypes.CDLL(_LIB_PATH)
-        D, I, LL = ctypes.c_double, ctypes.c_int, ctypes.c_longlong
-        pd, pi, pl = ctypes.POINTER(D), ctypes.POINTER(I), ctypes.POINTER(LL)
-        pu = ctypes.POINTER(ctypes.c_uint32)
-        L.orc_render.argtypes = [pd, I, pi, I, I, pd, I, pd, I, I, pd, pi, pl]
-        L.orc_render_frozen.argtypes = [pd, I, pi, I, I, pd, I, pd, I, I, pi, pd]
-        L.orc_unproject.argtypes = [pd, I, pd, I, I, pd]
-        L.orc_score.argtypes = [pd, pd, I, I, I, D, D, D, D, I, pd, pd, pl]
-        L.orc_score_grad.argtypes = [pd, pd, I, I, I, D, D, D, D, I, pd, pd, pd, pd]
-        L.orc_render_grad.argtypes = [pd, I, pi, I, I, pd, I, pd, I, I, pi, pd, pd, pd]
-        L.orc_philox4x32_10.argtypes = [pu, pu, pu]
-        L.orc_uniform.argtypes = [ctypes.c_uint64] + [ctypes.c_uint32] * 4 + [I]
-        L.orc_uniform.restype = D
-        L.orc_sample.argtypes = [pd, I, I, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, pd, pi, pd]
-        L.orc_perturbation.argtypes = [ctypes.c_uint64, ctypes.c_uint32, I, D, pd]
-        L.orc_enumerate.argtypes = [pd, pd, pi, I, pd, I, D, ctypes.c_uint64, ctypes.c_uint32, pd]
-        L.orc_num_threads.restype = I
-        for name in ("orc_render", "orc_render_frozen", "orc_unproject", "orc_score", "orc_score_grad",
-                     "orc_render_grad", "orc_sample", "orc_enumerate"):
-            getattr(L, name).restype = I
-        _lib = L
+        _lib = load(_LIB_PATH)
     return _lib
+
+
+def _declare(L):
+    D, I, LL = ctypes.c_double, ctypes.c_int, ctypes.c_longlong
+    pd, pi, pl = ctypes.POINTER(D), ctypes.POINTER(I), ctypes.POINTER(LL)
+    pu = ctypes.POINTER(ctypes.c_uint32)
+    L.orc_render.argtypes = [pd, I, pi, I, I, pd, I, pd, I, I, pd, pi, pl]
+    L.orc_render_frozen.argtypes = [pd, I, pi, I, I, pd, I, pd, I, I, pi, pd]
+    L.orc_unproject.argtypes = [pd, I, pd, I, I, pd]
+    L.orc_score.argtypes = [pd, pd, I, I, I, D, D, D, D, I, pd, pd, pl]
+    L.orc_score_grad.argtypes = [pd, pd, I, I, I, D, D, D, D, I, pd, pd, pd, pd]
+    L.orc_render_grad.argtypes = [pd, I, pi, I, I, pd, I, pd, I, I, pi, pd, pd, pd]
+    L.orc_philox4x32_10.argtypes = [pu, pu, pu]
+    L.orc_uniform.argtypes = [ctypes.c_uint64] + [ctypes.c_uint32] * 4 + [I]
+    L.orc_uniform.restype = D
+    L.orc_sample.argtypes = [pd, I, I, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, pd, pi, pd]
+    L.orc_perturbation.argtypes = [ctypes.c_uint64, ctypes.c_uint32, I, D, pd]
+    L.orc_enumerate.argtypes = [pd, pd, pi, I, pd, I, D, ctypes.c_uint64, ctypes.c_uint32, pd]
+    L.orc_num_threads.restype = I
+    for name in ("orc_render", "orc_render_frozen", "orc_unproject", "orc_score", "orc_score_grad",
+                 "orc_render_grad", "orc_sample", "orc_enumerate"):
+        getattr(L, name).restype = I
 
 
 def num_threads() -> int:
