@@ -190,6 +190,20 @@ b3d_status b3d_scene_set_observed(b3d_scene* scene, const float* observed, void*
 b3d_status b3d_render_score(const b3d_scene* scene, const float* poses, int32_t N, float* logL_out, float* grad_out,
                             void* stream);
 
+/* Tile-shape tuning of the fused kernel for this scene: times
+ * b3d_render_score (with the adjoint when `grad`) on the given hypotheses for
+ * each candidate size of the LDS depth buffer (the sizes that leave room for
+ * 2..6 resident workgroups per CU, down to the smallest that still holds one
+ * row band), keeps the fastest in the scene and returns its depth-buffer
+ * capacity (keys) in *zcap_out (may be NULL).  Synchronises the device.
+ * poses: device float[N][16], a representative sample (N >= 1). */
+b3d_status b3d_scene_autotune(b3d_scene* scene, const float* poses, int32_t N, int32_t grad, int32_t* zcap_out,
+                              void* stream);
+/* Set the depth-buffer capacity directly (e.g. from a cached tuning result);
+ * zcap <= 0 restores the default.  Fails with B3D_ESHAPE when it does not fit
+ * the LDS or cannot hold one band of rows. */
+b3d_status b3d_scene_set_tile(b3d_scene* scene, int32_t zcap);
+
 /* b3d_render_score with the adjoint, from an instrumented build of the same
  * kernel that also adds the launch's work items to work (device uint64[8],
  * accumulated, zero it first): [0] vertices transformed, [1] triangles

@@ -84,6 +84,8 @@ _SIGNATURES = {
     "b3d_scene_set_background": ([_P, _P, _P, _I32, _P], ctypes.c_int),
     "b3d_scene_set_observed": ([_P, _P, _P], ctypes.c_int),
     "b3d_render_score": ([_P, _P, _I32, _P, _P, _P], ctypes.c_int),
+    "b3d_scene_autotune": ([_P, _P, _I32, _I32, ctypes.POINTER(_I32), _P], ctypes.c_int),
+    "b3d_scene_set_tile": ([_P, _I32], ctypes.c_int),
     "b3d_render_score_work": ([_P, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "b3d_batch_create": ([ctypes.POINTER(BatchItem), _I32, ctypes.POINTER(_P)], ctypes.c_int),
     "b3d_batch_run": ([_P, _P], ctypes.c_int),
@@ -272,6 +274,35 @@ class Scene:
     def set_observed(self, observed: torch.Tensor) -> None:
         self._obs = observed  # the scene reads it by reference
         _call("b3d_scene_set_observed", self._h, _ptr(observed, torch.float32), _stream())
+
+    def autotune(self, poses: torch.Tensor, grad: bool = True, cache: Optional[str] = None) -> int:
+        """Choose the fused kernel's depth-buffer size for this scene by timing
+        the candidates on `poses`; with `cache` (a JSON file), reuse the choice
+        recorded for the same shape class (image size, window, mesh size)."""
+        import json
+
+        key = f"{self.K.H}x{self.K.W}/w{self.params.window}/T{self.mesh.T}/g{int(bool(grad))}"
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                _call("b3d_scene_set_tile", self._h, int(table[key]))
+                return int(table[key])
+        z = _I32()
+        _call("b3d_scene_autotune", self._h, _ptr(poses, torch.float32), int(poses.shape[0]), int(bool(grad)),
+              ctypes.byref(z), _stream())
+        if cache:
+            table = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    table = json.load(f)
+            table[key] = int(z.value)
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+        return int(z.value)
+
+    def set_tile(self, zcap: int) -> None:
+        _call("b3d_scene_set_tile", self._h, int(zcap))
 
     def close(self):
         if getattr(self, "_h", None):

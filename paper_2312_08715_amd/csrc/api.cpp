@@ -105,6 +105,23 @@ b3d_status make_consts(const b3d_score_params* p, int H, int W, ScoreConsts* sc)
   return B3D_OK;
 }
 
+int default_zcap(const SceneDev& d, int blocks_per_cu) {
+  SceneDev t = d;
+  t.zcap = 0;
+  const size_t share = (160 * 1024) / (size_t)blocks_per_cu;
+  const size_t rest = fused_lds_bytes(t);
+  return (int)((share > rest ? share - rest : 0) / sizeof(unsigned long long));
+}
+
+int min_zcap(const SceneDev& d) { return (4 * d.sc.h + 2) * d.cam.W; }
+
+int max_zcap(const SceneDev& d) {
+  SceneDev t = d;
+  t.zcap = 0;
+  const size_t rest = fused_lds_bytes(t);
+  return (int)((kLdsMax > rest ? kLdsMax - rest : 0) / sizeof(unsigned long long));
+}
+
 }  // namespace
 
 struct b3d_mesh {
@@ -354,10 +371,7 @@ b3d_status b3d_scene_create(const b3d_mesh* mesh, const b3d_intrinsics* K, const
   // window weights live in the rasteriser's scratch once the depth buffer is done
   S->dev.wcap = (int)(kRasterLdsBytes / sizeof(float));
   // depth keys: as many as leave room for four workgroups per CU (160 KB of LDS)
-  S->dev.zcap = 0;
-  const size_t share = 40 * 1024;
-  const size_t rest = fused_lds_bytes(S->dev);
-  S->dev.zcap = std::max((int)((share > rest ? share - rest : 0) / sizeof(unsigned long long)), (4 * h + 2) * W);
+  S->dev.zcap = std::max(default_zcap(S->dev, 4), min_zcap(S->dev));
   if ((2 * h + 1) * W > S->dev.wcap || fused_lds_bytes(S->dev) > kLdsMax) {
     delete S;
     return fail(B3D_ESHAPE, "scene_create: image width %d too large for the fused kernel's LDS budget", W);
@@ -515,6 +529,65 @@ b3d_status b3d_batch_destroy(b3d_batch* b) {
   (void)hipFree(b->items);
   (void)hipFree(b->counter);
   delete b;
+  return B3D_OK;
+}
+
+b3d_status b3d_scene_set_tile(b3d_scene* S, int32_t zcap) {
+  if (!S) return fail(B3D_EINVAL, "scene_set_tile: NULL scene");
+  SceneDev t = S->dev;
+  t.zcap = zcap <= 0 ? std::max(default_zcap(S->dev, 4), min_zcap(S->dev)) : zcap;
+  if (t.zcap < min_zcap(S->dev) || fused_lds_bytes(t) > kLdsMax)
+    return fail(B3D_ESHAPE, "scene_set_tile: %d keys outside [%d, LDS limit]", zcap, min_zcap(S->dev));
+  S->dev.zcap = t.zcap;
+  return B3D_OK;
+}
+
+b3d_status b3d_scene_autotune(b3d_scene* S, const float* poses, int32_t N, int32_t grad, int32_t* zcap_out,
+                              void* stream) {
+  if (!S || !poses) return fail(B3D_EINVAL, "scene_autotune: NULL pointer");
+  if (!S->observed) return fail(B3D_EINVAL, "scene_autotune: call b3d_scene_set_observed first");
+  if (N < 1) return fail(B3D_ESHAPE, "scene_autotune: need N >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  float* out = nullptr;
+  if (hipMalloc((void**)&out, sizeof(float) * 9 * (size_t)N) != hipSuccess)
+    return fail(B3D_ENOMEM, "scene_autotune: scratch allocation failed");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const int keep = S->dev.zcap;
+  int best = keep;
+  float best_ms = 3.0e38f;
+  std::vector<int> cands;
+  for (int b = 2; b <= 6; ++b) {
+    const int z = std::min(default_zcap(S->dev, b), max_zcap(S->dev));
+    if (cands.empty() || cands.back() != z) cands.push_back(z);
+  }
+  if (cands.back() != min_zcap(S->dev)) cands.push_back(min_zcap(S->dev));
+  b3d_status status = B3D_OK;
+  for (int z : cands) {
+    SceneDev t = S->dev;
+    t.zcap = z;
+    if (z < min_zcap(S->dev) || fused_lds_bytes(t) > kLdsMax) continue;
+    float ms = 0.0f;
+    for (int rep = 0; rep < 3 && status == B3D_OK; ++rep) {
+      if (hipEventRecord(e0, st) != hipSuccess ||
+          launch_render_score(t, poses, N, out, grad ? out + N : nullptr, st) != hipSuccess ||
+          hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        status = fail(B3D_EHIP, "scene_autotune: timing launch failed");
+    }
+    if (status != B3D_OK) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = z;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  if (status != B3D_OK) return status;
+  S->dev.zcap = best;
+  if (zcap_out) *zcap_out = best;
   return B3D_OK;
 }
 

@@ -166,6 +166,34 @@ def test_fused_render_score_matches_oracle_and_split_path(b3d, k):
     assert np.array_equal(Lf2, Lf.astype(np.float32))
 
 
+def test_autotuned_tile_keeps_results_and_cache_round_trips(b3d, tmp_path):
+    wl, obs, P = workload(1)
+    sel = np.arange(0, P.shape[0], 25)
+    say(f"autotune: config 1, {len(sel)} hypotheses")
+    scene, mesh, o = _scene(b3d, wl, obs)
+    Pd = dev(P[sel])
+    L0, G0 = b3d.render_score(scene, Pd, grad=True)
+    cache = str(tmp_path / "tiles.json")
+    z = scene.autotune(Pd, grad=True, cache=cache)
+    say(f"  chosen depth-buffer capacity {z} keys")
+    L1, G1 = b3d.render_score(scene, Pd, grad=True)
+    _, l1, _, _ = _oracle_logL(wl, obs, P[sel])
+    assert np.max(np.abs(L1.cpu().numpy() - L0.cpu().numpy()) / l1) <= 1e-5
+    g0, g1 = G0.cpu().numpy(), G1.cpu().numpy()
+    assert np.all(np.linalg.norm(g1 - g0, axis=1) <= 1e-4 * np.linalg.norm(g0, axis=1) + 1e-6)
+    # a second scene of the same shape class takes the cached choice without timing
+    scene2, _, _ = _scene(b3d, wl, obs, mesh=mesh)
+    assert scene2.autotune(Pd, grad=True, cache=cache) == z
+    # capacities outside the LDS budget or below one band are refused; 0 restores the default
+    with pytest.raises(b3d.B3DError):
+        scene2.set_tile(1)
+    with pytest.raises(b3d.B3DError):
+        scene2.set_tile(1 << 20)
+    scene2.set_tile(0)
+    L2 = b3d.render_score(scene2, Pd).cpu().numpy()
+    assert np.max(np.abs(L2 - L0.cpu().numpy()) / l1) <= 1e-5
+
+
 def test_score_backward_matches_oracle(b3d):
     wl, obs, P = workload(0)
     sel = np.arange(0, 256, 8)
