@@ -186,7 +186,9 @@ b3d_status b3d_scene_set_observed(b3d_scene* scene, const float* observed, void*
  * grad_out: device float[N][8] or NULL; when given it receives
  *   (d logL_n/d dt [3], d logL_n/d dw [3], d logL_n/d sigma, d logL_n/d p_out)
  * with visibility held fixed (the adjoint of b3d_score_backward followed by
- * b3d_render_backward).  Stream-ordered. */
+ * b3d_render_backward).  Results are bitwise repeatable and do not depend
+ * on the tile size chosen by b3d_scene_autotune / b3d_scene_set_tile.
+ * Stream-ordered. */
 b3d_status b3d_render_score(const b3d_scene* scene, const float* poses, int32_t N, float* logL_out, float* grad_out,
                             void* stream);
 

@@ -159,6 +159,11 @@ __device__ __forceinline__ float window_grad(const float* __restrict__ wbuf, int
   return g;
 }
 
+// First local index k >= 0 with (base + k) mod kBlock == t.
+__device__ __forceinline__ int first_of(unsigned t, int base) {
+  return ((int)t - base % kBlock + kBlock) % kBlock;
+}
+
 // One hypothesis: pose16 (16 floats), writes *logL_out and, when GRAD,
 // grad_out[0..8).  Must be called by the whole block; `smem` is at least
 // fused_lds_bytes(s).
@@ -211,7 +216,10 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
       const int wa = GRAD ? max(a - h, region.y0) : a;
       const int wb = GRAD ? min(b + h, region.y1) : b;
       const int nw = (wb - wa) * rw;
-      for (int k = threadIdx.x; k < nw; k += kBlock) {
+      // pixel g of the region (row-major from its corner) always goes to
+      // thread g mod kBlock, so every thread adds its terms in the same order
+      // however the rows are banded: results do not depend on the band height
+      for (int k = first_of(threadIdx.x, (wa - region.y0) * rw); k < nw; k += kBlock) {
         const int r = wa + k / rw, c = region.x0 + (k - (k / rw) * rw);
         const float* q = s.obs + 3 * ((size_t)r * W + c);
         const float ox = q[0], oy = q[1], oz = q[2];
@@ -250,7 +258,7 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
         const int ga = max(a, obj.y0), gb = min(b, obj.y1);
         const int ow = obj.w();
         const int ng = max(gb - ga, 0) * ow;
-        for (int k = threadIdx.x; k < ng; k += kBlock) {
+        for (int k = first_of(threadIdx.x, (ga - obj.y0) * ow); k < ng; k += kBlock) {
           const int r = ga + k / ow, c = obj.x0 + (k - (k / ow) * ow);
           const unsigned long long key = zbuf[(r - L.y0) * lw + (c - L.x0)];
           if (key == kEmptyKey) continue;
