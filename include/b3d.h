@@ -314,6 +314,31 @@ b3d_status b3d_c2f_step(const b3d_scene* scene, const float* center, const b3d_s
 
 /* ---- gradient refinement and tracking ---------------------------------- */
 
+/* Retraction onto the pose manifold, the update convention of the adjoint
+ * (Sec. III-B's pose grid composed as t = t_c + dt, R = dR R_c, with dR the
+ * rotation exponential): out[n] = (exp([w_n]x) R_b, t_b + dt_n) for
+ * xi[n] = (dt_n, w_n), where b = n when n_base == N and b = 0 when
+ * n_base == 1.  base: device float[n_base][16]; xi: device float[N][6];
+ * out: device float[N][16] (may not alias base).  Stream-ordered. */
+b3d_status b3d_pose_retract(const float* base, int32_t n_base, const float* xi, int32_t N, float* out, void* stream);
+
+/* Adjoint of b3d_pose_retract composed with b3d_render_score's gradient:
+ * grad[n] = b3d_render_score's grad_out at the retracted pose n, dlogL[n]
+ * the incoming adjoint (device float[N], or NULL for all ones).
+ * dxi[n] = dlogL[n] (g_t, J(w_n)^T g_w) with J the left Jacobian of the
+ * rotation exponential.  dsp (device float[2] or NULL) receives
+ * (sum_n dlogL[n] grad[n][6], sum_n dlogL[n] grad[n][7]): the gradients with
+ * respect to a sigma and a p_out shared by all N hypotheses, summed in a
+ * fixed order.  Stream-ordered. */
+b3d_status b3d_pose_retract_backward(const float* xi, const float* grad, const float* dlogL, int32_t N, float* dxi,
+                                     float* dsp, void* stream);
+
+/* Change the likelihood parameters of a scene (sigma, p_out, outlier volume,
+ * normaliser; the window size must stay the same, else B3D_ESHAPE) and, when
+ * an observed image is set, recompute its background terms.  Stream-ordered
+ * with respect to later calls on the same stream. */
+b3d_status b3d_scene_set_params(b3d_scene* scene, const b3d_score_params* p, void* stream);
+
 /* Adam ascent on logL over each pose's tangent (the refinement that follows
  * enumeration): with g = grad[n*gstride + 0..6) (d logL/d(dt, dw), e.g. from
  * b3d_render_score), m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,

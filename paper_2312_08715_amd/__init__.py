@@ -90,6 +90,9 @@ _SIGNATURES = {
     "b3d_batch_create": ([ctypes.POINTER(BatchItem), _I32, ctypes.POINTER(_P)], ctypes.c_int),
     "b3d_batch_run": ([_P, _P], ctypes.c_int),
     "b3d_batch_destroy": ([_P], ctypes.c_int),
+    "b3d_pose_retract": ([_P, _I32, _P, _I32, _P, _P], ctypes.c_int),
+    "b3d_pose_retract_backward": ([_P, _P, _P, _I32, _P, _P, _P], ctypes.c_int),
+    "b3d_scene_set_params": ([_P, ctypes.POINTER(ScoreParams), _P], ctypes.c_int),
     "b3d_adam_pose_step": ([_P, _P, _I32, _P, _I32, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                             ctypes.c_float, ctypes.c_float, _P], ctypes.c_int),
     "b3d_tracker_create": ([_P, _I32, ctypes.POINTER(Intrinsics), ctypes.POINTER(ScoreParams),
@@ -271,6 +274,11 @@ class Scene:
         self._keep = list(meshes)
         _call("b3d_scene_set_background", self._h, arr, P.ctypes.data, n, _stream())
 
+    def set_params(self, p: ScoreParams) -> None:
+        """New sigma / p_out / V / normaliser (same window); background terms are recomputed."""
+        _call("b3d_scene_set_params", self._h, ctypes.byref(p), _stream())
+        self.params = p
+
     def set_observed(self, observed: torch.Tensor) -> None:
         self._obs = observed  # the scene reads it by reference
         _call("b3d_scene_set_observed", self._h, _ptr(observed, torch.float32), _stream())
@@ -326,6 +334,57 @@ def render_score(scene: Scene, poses: torch.Tensor, grad: bool = False):
 
 
 WORK_ITEMS = ("vertices", "triangles", "setup", "fragments", "pairs", "observed", "adjoint_pixels", "exact_tests")
+
+
+def pose_retract(base: torch.Tensor, xi: torch.Tensor) -> torch.Tensor:
+    """Poses [N,4,4] = (exp([w]x) R_b, t_b + dt) for xi [N,6] = (dt, w); base [N,4,4] or [1,4,4]/[4,4]."""
+    N = xi.shape[0]
+    b = base.reshape(-1, 16)
+    out = torch.empty((N, 4, 4), dtype=torch.float32, device=xi.device)
+    _call("b3d_pose_retract", _ptr(b, torch.float32), int(b.shape[0]), _ptr(xi, torch.float32), N,
+          _ptr(out, torch.float32), _stream())
+    return out
+
+
+def pose_retract_backward(xi: torch.Tensor, grad: torch.Tensor, dlogL: Optional[torch.Tensor] = None):
+    """(dxi [N,6], dsp [2]) from render_score's grad [N,8] at the retracted poses: see b3d_pose_retract_backward."""
+    N = xi.shape[0]
+    dxi = torch.empty((N, 6), dtype=torch.float32, device=xi.device)
+    dsp = torch.empty(2, dtype=torch.float32, device=xi.device)
+    _call("b3d_pose_retract_backward", _ptr(xi, torch.float32), _ptr(grad, torch.float32),
+          None if dlogL is None else _ptr(dlogL, torch.float32), N, _ptr(dxi, torch.float32),
+          _ptr(dsp, torch.float32), _stream())
+    return dxi, dsp
+
+
+class B3DScore(torch.autograd.Function):
+    """logL [N] of the poses retracted from base_poses by xi [N,6] = (dt, dw),
+    differentiable in xi, sigma and p_out (visibility held fixed).
+
+    forward(xi, base_poses, sigma, p_out, scene) -> logL;
+    backward(dlogL) -> (dxi, None, dsigma, dp_out, None).
+    sigma and p_out (floats or 0-d tensors) replace the scene's values when
+    they differ; the window, V and normaliser stay the scene's."""
+
+    @staticmethod
+    def forward(ctx, xi, base_poses, sigma, p_out, scene):
+        sg, po = float(sigma), float(p_out)
+        pr = scene.params
+        if sg != pr.sigma or po != pr.p_out:
+            scene.set_params(ScoreParams(sg, po, pr.outlier_volume, pr.norm_M, pr.window))
+        xi_c = xi.detach().contiguous()
+        poses = pose_retract(base_poses.detach().contiguous(), xi_c)
+        logL, grad = render_score(scene, poses, grad=True)
+        ctx.save_for_backward(xi_c, grad)
+        ctx.sp_dev = tuple(v.device if torch.is_tensor(v) else None for v in (sigma, p_out))
+        return logL
+
+    @staticmethod
+    def backward(ctx, dlogL):
+        xi, grad = ctx.saved_tensors
+        dxi, dsp = pose_retract_backward(xi, grad, dlogL.contiguous())
+        ds, dp = (None if d is None else dsp[k].to(d) for k, d in enumerate(ctx.sp_dev))
+        return dxi, None, ds, dp, None
 
 
 def render_score_work(scene: Scene, poses: torch.Tensor) -> dict:

@@ -447,6 +447,38 @@ b3d_status b3d_scene_set_observed(b3d_scene* S, const float* observed, void* str
   return B3D_OK;
 }
 
+b3d_status b3d_scene_set_params(b3d_scene* S, const b3d_score_params* p, void* stream) {
+  if (!S || !p) return fail(B3D_EINVAL, "scene_set_params: NULL pointer");
+  ScoreConsts sc;
+  if (b3d_status s = make_consts(p, S->K.H, S->K.W, &sc)) return s;
+  if (sc.h != S->dev.sc.h) return fail(B3D_ESHAPE, "scene_set_params: the window size cannot change");
+  S->params = *p;
+  S->dev.sc = sc;
+  if (S->observed)
+    B3D_CHECK_HIP(launch_background_terms(S->dev, S->terms, (hipStream_t)stream), "scene_set_params");
+  return B3D_OK;
+}
+
+b3d_status b3d_pose_retract(const float* base, int32_t n_base, const float* xi, int32_t N, float* out, void* stream) {
+  if (N < 0) return fail(B3D_ESHAPE, "pose_retract: N < 0");
+  if (N == 0) return B3D_OK;
+  if (!base || !xi || !out) return fail(B3D_EINVAL, "pose_retract: NULL pointer");
+  if (n_base != 1 && n_base != N) return fail(B3D_ESHAPE, "pose_retract: n_base must be 1 or N");
+  if (out == base) return fail(B3D_EINVAL, "pose_retract: out aliases base");
+  B3D_CHECK_HIP(launch_pose_retract(base, n_base, xi, N, out, (hipStream_t)stream), "pose_retract");
+  return B3D_OK;
+}
+
+b3d_status b3d_pose_retract_backward(const float* xi, const float* grad, const float* dlogL, int32_t N, float* dxi,
+                                     float* dsp, void* stream) {
+  if (N < 0) return fail(B3D_ESHAPE, "pose_retract_backward: N < 0");
+  if (N == 0) return B3D_OK;
+  if (!xi || !grad || !dxi) return fail(B3D_EINVAL, "pose_retract_backward: NULL pointer");
+  B3D_CHECK_HIP(launch_pose_retract_backward(xi, grad, dlogL, N, dxi, dsp, (hipStream_t)stream),
+                "pose_retract_backward");
+  return B3D_OK;
+}
+
 b3d_status b3d_render_score(const b3d_scene* S, const float* poses, int32_t N, float* logL_out, float* grad_out,
                             void* stream) {
   if (!S) return fail(B3D_EINVAL, "render_score: NULL scene");

@@ -194,6 +194,50 @@ def test_autotuned_tile_keeps_results_and_cache_round_trips(b3d, tmp_path):
     assert torch.equal(b3d.render_score(scene2, Pd), L0)
 
 
+def test_autograd_score_through_the_retraction_matches_oracle(b3d):
+    from oracle.refine import retract, retract_grad
+
+    wl, obs, P = workload(0)
+    sel = np.arange(0, P.shape[0], 16)
+    say(f"autograd B3DScore: config 0, {len(sel)} hypotheses")
+    scene, mesh, o = _scene(b3d, wl, obs)
+    rng = np.random.default_rng(77)
+    xi = f32(rng.normal(size=(len(sel), 6)) * np.array([0.005] * 3 + [0.05] * 3))
+    base = P[sel]
+    s = wl.score
+    sigma = torch.tensor(s.sigma * 1.25, dtype=torch.float32, requires_grad=True)
+    p_out = torch.tensor(s.p_out, dtype=torch.float32, requires_grad=True)
+    xi_t = dev(xi).requires_grad_(True)
+    logL = b3d.B3DScore.apply(xi_t, dev(base), sigma, p_out, scene)
+    dl = f32(rng.normal(1.0, 0.3, len(sel)))
+    logL.backward(dev(dl))
+    # oracle: retract in FP64 from the same FP32 inputs, score and adjoints there
+    sg, po = float(sigma.detach()), float(p_out.detach())
+    Pr = retract(base, xi)
+    Pg = b3d.pose_retract(dev(base), dev(xi)).cpu().numpy()
+    assert np.max(np.abs(Pg - Pr)) <= 1e-6
+    od, oi = oracle.render([(wl.verts, wl.tris, Pr)], wl.camera)
+    rend = oracle.unproject(od, wl.camera)
+    L64, l1 = oracle.score(obs, rend, sg, po, s.outlier_volume, s.window)
+    dr, ds, dp = oracle.score_grad(obs, rend, sg, po, s.outlier_volume, s.window)
+    gp = oracle.render_grad(wl.verts, wl.tris, Pr, wl.camera, oi, od, dr)
+    assert np.max(np.abs(logL.detach().cpu().numpy() - L64) / l1) <= LOGL_RTOL
+    want = retract_grad(xi, gp, dl)
+    got = xi_t.grad.cpu().numpy()
+    xyz, tri = b3d.render_batch(mesh, dev(Pg), b3d.intrinsics_of(wl.camera))
+    clean = clean_hypotheses(xyz[..., 2].cpu().numpy(), tri.cpu().numpy(), od, oi)
+    assert clean.mean() >= 0.9
+    for n in np.nonzero(clean)[0]:
+        assert np.linalg.norm(got[n] - want[n]) <= 1e-3 * np.linalg.norm(want[n]) + 1e-6, (n, got[n], want[n])
+    if clean.all():
+        assert abs(float(sigma.grad) - np.sum(dl * ds)) <= 1e-3 * np.sum(np.abs(dl * ds)) + 1e-3
+        assert abs(float(p_out.grad) - np.sum(dl * dp)) <= 1e-4 * np.sum(np.abs(dl * dp)) + 1e-3
+    # the scene took the new sigma; the window cannot change
+    assert scene.params.sigma == np.float32(s.sigma * 1.25)
+    with pytest.raises(b3d.B3DError):
+        scene.set_params(b3d.score_params(s.sigma, s.p_out, s.outlier_volume, s.window + 2))
+
+
 def test_score_backward_matches_oracle(b3d):
     wl, obs, P = workload(0)
     sel = np.arange(0, 256, 8)

@@ -6,7 +6,7 @@ rotations orthonormal."""
 import numpy as np
 from scipy.spatial.transform import Rotation
 
-from oracle.refine import adam_pose_step, rotvec_exp
+from oracle.refine import adam_pose_step, left_jacobian, retract, retract_grad, rotvec_exp
 from workloads import random_poses
 
 
@@ -29,3 +29,46 @@ def test_rotation_exponential_matches_scipy_and_stays_orthonormal():
         R = rotvec_exp(w)
         np.testing.assert_allclose(R, Rotation.from_rotvec(w).as_matrix(), atol=1e-14)
         np.testing.assert_allclose(R @ R.T, np.eye(3), atol=1e-14)
+
+
+def _smooth_f(P, a, B):
+    """A smooth function of a pose: a . t + trace(B R)."""
+    return float(a @ P[:3, 3] + np.trace(B @ P[:3, :3]))
+
+
+def test_retract_grad_matches_finite_differences_through_the_retraction():
+    rng = np.random.default_rng(41)
+    a, B = rng.normal(size=3), rng.normal(size=(3, 3))
+    base = np.eye(4)
+    base[:3, :3] = rotvec_exp(rng.normal(size=3))
+    base[:3, 3] = rng.normal(size=3)
+    for scale in (0.0, 0.3, 2.5):
+        xi = rng.normal(size=(1, 6)) * scale
+        P = retract(base, xi)[0]
+        # tangent gradient at the retracted pose: perturb by exp([d]x) R, t + d
+        g = np.zeros(6)
+        e = 1e-6
+        for k in range(6):
+            d = np.zeros(6)
+            d[k] = e
+            fp = _smooth_f(retract(P, d[None])[0], a, B)
+            fm = _smooth_f(retract(P, -d[None])[0], a, B)
+            g[k] = (fp - fm) / (2 * e)
+        want = np.zeros(6)
+        for k in range(6):
+            d = np.zeros(6)
+            d[k] = e
+            want[k] = (_smooth_f(retract(base, xi + d)[0], a, B) - _smooth_f(retract(base, xi - d)[0], a, B)) / (2 * e)
+        got = retract_grad(xi, g[None], np.array([1.0]))[0]
+        np.testing.assert_allclose(got, want, rtol=1e-6, atol=1e-7)
+        np.testing.assert_allclose(retract_grad(xi, g[None], np.array([-2.0]))[0], -2.0 * want, rtol=1e-6, atol=2e-7)
+
+
+def test_left_jacobian_closed_forms():
+    assert np.array_equal(left_jacobian(np.zeros(3)), np.eye(3))
+    rng = np.random.default_rng(42)
+    w = rng.normal(size=3)
+    # J(w) w = w, and J(w) of a half turn about z in closed form
+    np.testing.assert_allclose(left_jacobian(w) @ w, w, rtol=1e-12)
+    Jz = left_jacobian(np.array([0.0, 0.0, np.pi]))
+    np.testing.assert_allclose(Jz, [[0, -2 / np.pi, 0], [2 / np.pi, 0, 0], [0, 0, 1]], atol=1e-12)
