@@ -386,7 +386,8 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
       for (int v = lane; v < cl.nv; v += 64) {
         const float4 o = m.cverts[cl.vfirst + v];
         const float3 p = xform(P, o.x, o.y, o.z);
-        const float iz = 1.0f / p.z;
+        // hardware reciprocal (1 ulp): far inside the edge margin tau below
+        const float iz = __builtin_amdgcn_rcpf(p.z);
         vb[v] = make_float4(cam.fx * p.x * iz + cam.cx, cam.fy * p.y * iz + cam.cy, p.z, iz);
       }
       // the wave's own writes must land before its lanes read them
@@ -415,12 +416,21 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
           const int c0 = (int)fc0, c1 = (int)fc1, r0 = (int)fr0, r1 = (int)fr1;
           const uint32_t id = id_base + tk.y;
           if (COUNT) ++c_setup;
-          const float inv_area = 1.0f / area;
+          const float inv_area = __builtin_amdgcn_rcpf(area);
           const float t0 = tau * (fabsf(e0x) + fabsf(e0y)), t1 = tau * (fabsf(e1x) + fabsf(e1y)),
                       t2 = tau * (fabsf(e2x) + fabsf(e2y));
-          for (int r = r0; r <= r1; ++r) {
-            const float py = (float)r + 0.5f;
-            for (int col = c0; col <= c1; ++col) {
+          // one flat walk over the box's centres: a wave then iterates max(rows x cols)
+          // times over its lanes, not max(rows) x max(cols)
+          const int n_cent = (c1 - c0 + 1) * (r1 - r0 + 1);
+          int rn = r0, cn = c0;
+          for (int k = 0; k < n_cent; ++k) {
+            const int r = rn, col = cn;
+            if (++cn > c1) {
+              cn = c0;
+              ++rn;
+            }
+            {
+              const float py = (float)r + 0.5f;
               const float px = (float)col + 0.5f;
               // edge functions; each equals the (negative) area at the opposite vertex
               const float w0 = e0x * (py - p1.y) - e0y * (px - p1.x);

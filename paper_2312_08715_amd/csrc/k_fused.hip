@@ -344,7 +344,10 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchItemDev* __restrict
     __syncthreads();
     if (threadIdx.x == 0) work = (long long)atomicAdd(counter, 1ull);
     __syncthreads();
-    const long long w = work;
+    // the same value in every lane: keep it (and the item it selects) scalar
+    const unsigned long long wr = (unsigned long long)work;
+    const long long w = (long long)(((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(wr >> 32)) << 32) |
+                                    (unsigned)__builtin_amdgcn_readfirstlane((unsigned)wr));
     if (w >= total) break;
     int lo = 0, hi = S;
     while (hi - lo > 1) {
