@@ -113,7 +113,8 @@ int default_zcap(const SceneDev& d, int blocks_per_cu) {
   return (int)((share > rest ? share - rest : 0) / sizeof(unsigned long long));
 }
 
-int min_zcap(const SceneDev& d) { return (4 * d.sc.h + 2) * d.cam.W; }
+// two rows of the widest depth buffer (image width plus 2h each side)
+int min_zcap(const SceneDev& d) { return (4 * d.sc.h + 2) * (d.cam.W + 4 * d.sc.h); }
 
 int max_zcap(const SceneDev& d) {
   SceneDev t = d;
@@ -368,6 +369,17 @@ b3d_status b3d_scene_create(const b3d_mesh* mesh, const b3d_intrinsics* K, const
   S->dev.cam = make_cam(K);
   S->dev.sc = sc;
   const int h = sc.h, W = K->W;
+  {
+    // the fused kernel's empty depth slots rely on rays with |x/z|, |y/z| <= 1e3
+    // over the image and 2h pixels beyond it
+    const double rx = std::max(std::fabs((-2.0 * h + 0.5 - K->cx) / K->fx), std::fabs((W + 2.0 * h - 0.5 - K->cx) / K->fx));
+    const double ry =
+        std::max(std::fabs((-2.0 * h + 0.5 - K->cy) / K->fy), std::fabs((K->H + 2.0 * h - 0.5 - K->cy) / K->fy));
+    if (!(rx <= 1e3 && ry <= 1e3)) {
+      delete S;
+      return fail(B3D_ESHAPE, "scene_create: field of view too wide (|x/z| or |y/z| above 1e3 at the image edge)");
+    }
+  }
   // window weights live in the rasteriser's scratch once the depth buffer is done
   S->dev.wcap = (int)(kRasterLdsBytes / sizeof(float));
   // depth keys: as many as leave room for four workgroups per CU (160 KB of LDS)
