@@ -331,8 +331,12 @@ __global__ __launch_bounds__(kBlock) void k_render_score(SceneDev s, const float
 // Items are numbered scene by scene in the order the host chose (longest
 // first), so the expensive scenes start early and the cheap ones fill the
 // tail.  Every block exits once the counter passes the total.
+// The scene's pointers come from memory here, not from kernel arguments, so
+// the compiler addresses through them with 64-bit per-lane (flat) addresses
+// and would need about 180 VGPRs; the bound keeps four workgroups per CU (as
+// for k_render_score) at the price of a few spills outside the inner loops.
 template <bool GRAD>
-__global__ __launch_bounds__(kBlock) void k_batch(const BatchItemDev* __restrict__ items, int S, long long total,
+__global__ __launch_bounds__(kBlock, 4) void k_batch(const BatchItemDev* __restrict__ items, int S, long long total,
                                                   unsigned long long* __restrict__ counter) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ long long work;
