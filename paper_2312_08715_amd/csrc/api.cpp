@@ -824,9 +824,9 @@ struct b3d_tracker {
 
 static b3d_status tracker_record(b3d_tracker* T, hipStream_t st) {
   const b3d_track_params& tp = T->tp;
-  GridDev g;
-  int64_t n;
-  (void)make_grid(&tp.grid, &g, &n);
+  GridDev g[B3D_MAX_STAGES];
+  int64_t ns[B3D_MAX_STAGES];
+  for (int s = 0; s < tp.n_stages; ++s) (void)make_grid(&tp.stages[s], &g[s], &ns[s]);
   for (int o = 0; o < T->M; ++o) {
     b3d_scene* S = T->scenes[o];
     const size_t HW = (size_t)S->K.H * S->K.W;
@@ -843,9 +843,11 @@ static b3d_status tracker_record(b3d_tracker* T, hipStream_t st) {
       }
     }
     B3D_CHECK_HIP(launch_background_terms(S->dev, S->terms, st), "tracker");
-    B3D_CHECK_HIP(launch_enumerate(g, T->poses + 16 * o, 1, 0u, 0u, 0u, T->hyp, st), "tracker");
-    B3D_CHECK_HIP(launch_render_score(S->dev, T->hyp, (int)T->N, T->logL, nullptr, st), "tracker");
-    B3D_CHECK_HIP(launch_argmax_pose(T->logL, T->hyp, (int)T->N, T->poses + 16 * o, st), "tracker");
+    for (int s = 0; s < tp.n_stages; ++s) {
+      B3D_CHECK_HIP(launch_enumerate(g[s], T->poses + 16 * o, 1, 0u, 0u, (uint32_t)s, T->hyp, st), "tracker");
+      B3D_CHECK_HIP(launch_render_score(S->dev, T->hyp, (int)ns[s], T->logL, nullptr, st), "tracker");
+      B3D_CHECK_HIP(launch_argmax_pose(T->logL, T->hyp, (int)ns[s], T->poses + 16 * o, st), "tracker");
+    }
     B3D_CHECK_HIP(launch_fill_f32(T->state, 12, 0.0f, st), "tracker");
     for (int it = 1; it <= tp.n_refine; ++it) {
       B3D_CHECK_HIP(launch_render_score(S->dev, T->poses + 16 * o, 1, T->logL, T->grad, st), "tracker");
@@ -867,10 +869,16 @@ b3d_status b3d_tracker_create(const b3d_mesh* const* meshes, int32_t M, const b3
   if (b3d_status s = check_intrinsics(K)) return s;
   ScoreConsts sc;
   if (b3d_status s = make_consts(p, K->H, K->W, &sc)) return s;
-  GridDev g;
-  int64_t n;
-  if (b3d_status s = make_grid(&tp->grid, &g, &n)) return s;
-  if (n > (1 << 24)) return fail(B3D_ESHAPE, "tracker_create: grid too large");
+  if (tp->n_stages < 1 || tp->n_stages > B3D_MAX_STAGES)
+    return fail(B3D_ESHAPE, "tracker_create: n_stages must be in 1..%d", B3D_MAX_STAGES);
+  int64_t n = 0;
+  for (int s = 0; s < tp->n_stages; ++s) {
+    GridDev g;
+    int64_t ns;
+    if (b3d_status st = make_grid(&tp->stages[s], &g, &ns)) return st;
+    if (ns > (1 << 24)) return fail(B3D_ESHAPE, "tracker_create: grid of stage %d too large", s);
+    n = std::max(n, ns);
+  }
   if (tp->n_refine < 0 || tp->n_refine > 1000) return fail(B3D_EINVAL, "tracker_create: n_refine in 0..1000");
   if (!(tp->beta1 >= 0 && tp->beta1 < 1) || !(tp->beta2 >= 0 && tp->beta2 < 1) || !(tp->eps > 0))
     return fail(B3D_EINVAL, "tracker_create: bad Adam parameters");
