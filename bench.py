@@ -155,8 +155,9 @@ def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3):
 
 def bench_tracking(b3d, torch, p, n_frames=200):
     """Three objects on smooth SE(3) paths, 160x120, 4% outliers; per frame and
-    object 10,000 hypotheses (+-2 cm, 5 deg) and 10 Adam steps, one HIP graph
-    per frame."""
+    object two stages of hypotheses (10,000 over +-3 cm x 10 rotations within
+    8 deg, then 2,500 over +-7.5 mm x 20 rotations within 3 deg around the best)
+    and 10 Adam steps, one HIP graph per frame."""
     from workloads import tracking_sequence
 
     meshes, paths, cam, noise = tracking_sequence(seed=1004, n_frames=n_frames)
@@ -166,8 +167,9 @@ def bench_tracking(b3d, torch, p, n_frames=200):
         objs = [(v, t, paths[f, k]) for k, (v, t) in enumerate(meshes)]
         frames.append(noisy_observation(b3d, torch, gpu_depth(b3d, torch, objs, cam), noise[f], cam))
     ms = [b3d.Mesh(v, t) for v, t in meshes]
-    grid = b3d.make_grid(np.eye(4), (0.02, 0.02, 0.02), (10, 10, 10), n_rot=10, rot_max_angle=np.deg2rad(5.0))
-    tr = b3d.Tracker(ms, b3d.intrinsics_of(cam), p, grid, paths[0], n_refine=10, lr_t=1e-3, lr_r=5e-3)
+    stages = [b3d.make_grid(np.eye(4), (0.03, 0.03, 0.03), (10, 10, 10), n_rot=10, rot_max_angle=np.deg2rad(8.0)),
+              b3d.make_grid(np.eye(4), (0.0075, 0.0075, 0.0075), (5, 5, 5), n_rot=20, rot_max_angle=np.deg2rad(3.0))]
+    tr = b3d.Tracker(ms, b3d.intrinsics_of(cam), p, stages, paths[0], n_refine=10, lr_t=1e-3, lr_r=1e-2)
     est = torch.empty((n_frames, M, 4, 4), dtype=torch.float32, device="cuda")
     est[0] = torch.as_tensor(paths[0], dtype=torch.float32)
     tr.frame(frames[1])  # captures the frame graph
@@ -183,7 +185,7 @@ def bench_tracking(b3d, torch, p, n_frames=200):
     pos = np.linalg.norm(E[1:, :, :3, 3] - paths[1:, :, :3, 3], axis=2) * 100.0
     rot = np.array([[rot_err_deg(E[f, k, :3, :3], paths[f, k, :3, :3]) for k in range(M)] for f in range(1, n_frames)])
     return {"frames_per_s": (n_frames - 2) / dt, "frames": n_frames, "objects": M,
-            "hypotheses_per_frame": int(M * 10000), "position_error_cm": {"mean": float(pos.mean()),
+            "hypotheses_per_frame": int(M * 12500), "position_error_cm": {"mean": float(pos.mean()),
                                                                            "max": float(pos.max())},
             "orientation_error_deg": {"mean": float(rot.mean()), "max": float(rot.max())}}
 

@@ -350,10 +350,12 @@ b3d_status b3d_scene_set_params(b3d_scene* scene, const b3d_score_params* p, voi
 b3d_status b3d_adam_pose_step(float* poses, const float* grad, int32_t gstride, float* state, int32_t N, int32_t iter,
                               float lr_t, float lr_r, float beta1, float beta2, float eps, void* stream);
 
-/* Per-frame tracking settings: hypotheses around the previous estimate, then
- * n_refine Adam steps on the best one. */
+/* Per-frame tracking settings: n_stages grids of hypotheses, stage s centred
+ * on the best hypothesis of stage s-1 (stage 0 on the previous estimate; the
+ * grids' centers are ignored), then n_refine Adam steps on the best one. */
 typedef struct b3d_track_params {
-  b3d_grid grid; /* center ignored */
+  int32_t n_stages; /* 1..B3D_MAX_STAGES */
+  b3d_grid stages[B3D_MAX_STAGES];
   int32_t n_refine;
   float lr_t, lr_r, beta1, beta2, eps;
 } b3d_track_params;
@@ -363,8 +365,9 @@ typedef struct b3d_tracker b3d_tracker;
 /* Track M rigid objects through a sequence of observed images.  Each frame,
  * object by object: the other objects, at their latest estimates, are drawn
  * as static background; the grid of hypotheses around the object's previous
- * estimate is scored with the fused kernel; the best hypothesis is refined
- * by n_refine Adam steps on the adjoint.  The whole frame is captured once
+ * estimate is scored with the fused kernel, stage by stage around the best
+ * of the previous stage; the best hypothesis is refined by n_refine Adam
+ * steps on the adjoint.  The whole frame is captured once
  * into a HIP graph and replayed for every later frame, so a frame costs one
  * copy and one graph launch.  meshes: host array of M handles (they must
  * outlive the tracker); init_poses: host float[M][16].  1 <= M <= 16.

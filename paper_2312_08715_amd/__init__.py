@@ -50,8 +50,9 @@ class BatchItem(ctypes.Structure):
 
 
 class TrackParams(ctypes.Structure):
-    _fields_ = [("grid", Grid), ("n_refine", ctypes.c_int32), ("lr_t", ctypes.c_float), ("lr_r", ctypes.c_float),
-                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+    _fields_ = [("n_stages", ctypes.c_int32), ("stages", Grid * B3D_MAX_STAGES), ("n_refine", ctypes.c_int32),
+                ("lr_t", ctypes.c_float), ("lr_r", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
 
 
 class Schedule(ctypes.Structure):
@@ -529,14 +530,20 @@ def adam_pose_step(poses: torch.Tensor, grad: torch.Tensor, state: torch.Tensor,
 class Tracker:
     """Graph-captured multi-object tracker (b3d_tracker_*)."""
 
-    def __init__(self, meshes: Sequence[Mesh], K: Intrinsics, p: ScoreParams, grid: Grid, init_poses,
+    def __init__(self, meshes: Sequence[Mesh], K: Intrinsics, p: ScoreParams, grid, init_poses,
                  n_refine: int = 10, lr_t: float = 1e-3, lr_r: float = 1e-2, beta1: float = 0.9,
                  beta2: float = 0.999, eps: float = 1e-8):
+        """grid: one Grid, or a sequence of Grids searched stage by stage each frame."""
         self.meshes = list(meshes)
         M = len(self.meshes)
         arr = (_P * M)(*[m.handle for m in self.meshes])
         P0 = np.ascontiguousarray(np.asarray(init_poses, dtype=np.float32).reshape(M, 16))
-        tp = TrackParams(grid, int(n_refine), float(lr_t), float(lr_r), float(beta1), float(beta2), float(eps))
+        grids = [grid] if isinstance(grid, Grid) else list(grid)
+        if not 1 <= len(grids) <= B3D_MAX_STAGES:
+            raise B3DError(f"tracker: 1..{B3D_MAX_STAGES} stages")
+        st = (Grid * B3D_MAX_STAGES)(*grids)
+        tp = TrackParams(len(grids), st, int(n_refine), float(lr_t), float(lr_r), float(beta1), float(beta2),
+                         float(eps))
         h = _P()
         _call("b3d_tracker_create", arr, M, ctypes.byref(K), ctypes.byref(p), ctypes.byref(tp), P0.ctypes.data,
               ctypes.byref(h))

@@ -113,7 +113,8 @@ int default_zcap(const SceneDev& d, int blocks_per_cu) {
   return (int)((share > rest ? share - rest : 0) / sizeof(unsigned long long));
 }
 
-int min_zcap(const SceneDev& d) { return (4 * d.sc.h + 2) * d.cam.W; }
+// two rows of the widest depth buffer (image width plus 2h each side)
+int min_zcap(const SceneDev& d) { return (4 * d.sc.h + 2) * (d.cam.W + 4 * d.sc.h); }
 
 int max_zcap(const SceneDev& d) {
   SceneDev t = d;
@@ -368,6 +369,17 @@ b3d_status b3d_scene_create(const b3d_mesh* mesh, const b3d_intrinsics* K, const
   S->dev.cam = make_cam(K);
   S->dev.sc = sc;
   const int h = sc.h, W = K->W;
+  {
+    // the fused kernel's empty depth slots rely on rays with |x/z|, |y/z| <= 1e3
+    // over the image and 2h pixels beyond it
+    const double rx = std::max(std::fabs((-2.0 * h + 0.5 - K->cx) / K->fx), std::fabs((W + 2.0 * h - 0.5 - K->cx) / K->fx));
+    const double ry =
+        std::max(std::fabs((-2.0 * h + 0.5 - K->cy) / K->fy), std::fabs((K->H + 2.0 * h - 0.5 - K->cy) / K->fy));
+    if (!(rx <= 1e3 && ry <= 1e3)) {
+      delete S;
+      return fail(B3D_ESHAPE, "scene_create: field of view too wide (|x/z| or |y/z| above 1e3 at the image edge)");
+    }
+  }
   // window weights live in the rasteriser's scratch once the depth buffer is done
   S->dev.wcap = (int)(kRasterLdsBytes / sizeof(float));
   // depth keys: as many as leave room for four workgroups per CU (160 KB of LDS)
@@ -812,9 +824,9 @@ struct b3d_tracker {
 
 static b3d_status tracker_record(b3d_tracker* T, hipStream_t st) {
   const b3d_track_params& tp = T->tp;
-  GridDev g;
-  int64_t n;
-  (void)make_grid(&tp.grid, &g, &n);
+  GridDev g[B3D_MAX_STAGES];
+  int64_t ns[B3D_MAX_STAGES];
+  for (int s = 0; s < tp.n_stages; ++s) (void)make_grid(&tp.stages[s], &g[s], &ns[s]);
   for (int o = 0; o < T->M; ++o) {
     b3d_scene* S = T->scenes[o];
     const size_t HW = (size_t)S->K.H * S->K.W;
@@ -831,9 +843,11 @@ static b3d_status tracker_record(b3d_tracker* T, hipStream_t st) {
       }
     }
     B3D_CHECK_HIP(launch_background_terms(S->dev, S->terms, st), "tracker");
-    B3D_CHECK_HIP(launch_enumerate(g, T->poses + 16 * o, 1, 0u, 0u, 0u, T->hyp, st), "tracker");
-    B3D_CHECK_HIP(launch_render_score(S->dev, T->hyp, (int)T->N, T->logL, nullptr, st), "tracker");
-    B3D_CHECK_HIP(launch_argmax_pose(T->logL, T->hyp, (int)T->N, T->poses + 16 * o, st), "tracker");
+    for (int s = 0; s < tp.n_stages; ++s) {
+      B3D_CHECK_HIP(launch_enumerate(g[s], T->poses + 16 * o, 1, 0u, 0u, (uint32_t)s, T->hyp, st), "tracker");
+      B3D_CHECK_HIP(launch_render_score(S->dev, T->hyp, (int)ns[s], T->logL, nullptr, st), "tracker");
+      B3D_CHECK_HIP(launch_argmax_pose(T->logL, T->hyp, (int)ns[s], T->poses + 16 * o, st), "tracker");
+    }
     B3D_CHECK_HIP(launch_fill_f32(T->state, 12, 0.0f, st), "tracker");
     for (int it = 1; it <= tp.n_refine; ++it) {
       B3D_CHECK_HIP(launch_render_score(S->dev, T->poses + 16 * o, 1, T->logL, T->grad, st), "tracker");
@@ -855,10 +869,16 @@ b3d_status b3d_tracker_create(const b3d_mesh* const* meshes, int32_t M, const b3
   if (b3d_status s = check_intrinsics(K)) return s;
   ScoreConsts sc;
   if (b3d_status s = make_consts(p, K->H, K->W, &sc)) return s;
-  GridDev g;
-  int64_t n;
-  if (b3d_status s = make_grid(&tp->grid, &g, &n)) return s;
-  if (n > (1 << 24)) return fail(B3D_ESHAPE, "tracker_create: grid too large");
+  if (tp->n_stages < 1 || tp->n_stages > B3D_MAX_STAGES)
+    return fail(B3D_ESHAPE, "tracker_create: n_stages must be in 1..%d", B3D_MAX_STAGES);
+  int64_t n = 0;
+  for (int s = 0; s < tp->n_stages; ++s) {
+    GridDev g;
+    int64_t ns;
+    if (b3d_status st = make_grid(&tp->stages[s], &g, &ns)) return st;
+    if (ns > (1 << 24)) return fail(B3D_ESHAPE, "tracker_create: grid of stage %d too large", s);
+    n = std::max(n, ns);
+  }
   if (tp->n_refine < 0 || tp->n_refine > 1000) return fail(B3D_EINVAL, "tracker_create: n_refine in 0..1000");
   if (!(tp->beta1 >= 0 && tp->beta1 < 1) || !(tp->beta2 >= 0 && tp->beta2 < 1) || !(tp->eps > 0))
     return fail(B3D_EINVAL, "tracker_create: bad Adam parameters");

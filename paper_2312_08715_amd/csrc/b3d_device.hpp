@@ -12,7 +12,12 @@ constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kWaves = kBlock / 64;
 constexpr int kClusterTris = 64;     // max triangles per cluster (one per lane of a wave)
 constexpr int kClusterVerts = 128;   // max vertices per cluster
-constexpr unsigned long long kEmptyKey = ~0ull;
+// The key of a pixel with no surface: depth 1e15 m (bits 0x58635FA9), id all
+// ones.  It compares above every surface nearer than that, and its depth is
+// finite, so a window term against an empty slot evaluates to exactly 0
+// (exp of minus a huge distance) without a test, provided rays stay within
+// |x/z|, |y/z| <= 1e3 (checked when a scene is created).
+constexpr unsigned long long kEmptyKey = (0x58635FA9ull << 32) | 0xFFFFFFFFull;
 
 // Pinhole camera and image size.
 struct Cam {
@@ -92,6 +97,15 @@ struct Rect {
   __device__ __forceinline__ int h() const { return y1 - y0; }
   __device__ __forceinline__ bool empty() const { return x1 <= x0 || y1 <= y0; }
 };
+
+__device__ __forceinline__ Rect grow(const Rect& r, int m) {
+  Rect o;
+  o.x0 = r.x0 - m;
+  o.x1 = r.x1 + m;
+  o.y0 = r.y0 - m;
+  o.y1 = r.y1 + m;
+  return o;
+}
 
 __device__ __forceinline__ Rect grow_clip(const Rect& r, int m, int W, int H) {
   Rect o;
@@ -326,8 +340,9 @@ __device__ __forceinline__ RasterLds carve_raster_lds(unsigned char* p) {
 // of the adjoint, centres decided by the exact test.
 enum { kCntVert = 0, kCntTri, kCntSetup, kCntFrag, kCntPair, kCntObs, kCntAdj, kCntExact, kCntN };
 
-// Rasterise the mesh under pose P into an LDS key buffer that covers the
-// image rectangle `band` (row pitch band.w()).  Triangle ids written are
+// Rasterise the mesh under pose P into the pixels of the image rectangle
+// `band` of an LDS key buffer that covers the rectangle `buf` (row pitch
+// buf.w(); band inside buf).  Triangle ids written are
 // id_base + the caller's triangle index.  Clusters are tested for drawing,
 // kBlock at a time, and the drawable ones compacted into a list; the four
 // waves then take clusters from the list independently: a wave transforms
@@ -340,10 +355,10 @@ enum { kCntVert = 0, kCntTri, kCntSetup, kCntFrag, kCntPair, kCntObs, kCntAdj, k
 // block; ends after a barrier with the buffer complete.
 template <bool COUNT = false>
 __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, const Cam& cam, uint32_t id_base,
-                                            const Rect& band, unsigned long long* zbuf, const RasterLds& lds,
-                                            unsigned* cnt = nullptr) {
+                                            const Rect& band, const Rect& buf, unsigned long long* zbuf,
+                                            const RasterLds& lds, unsigned* cnt = nullptr) {
   unsigned c_vert = 0, c_tri = 0, c_setup = 0, c_frag = 0, c_exact = 0;
-  const int pitch = band.w();
+  const int pitch = buf.w();
   const float bx0 = (float)band.x0, bx1 = (float)(band.x1 - 1);
   const float by0 = (float)band.y0, by1 = (float)(band.y1 - 1);
   if (threadIdx.x == 0) lds.counts[0] = 0;
@@ -437,7 +452,7 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
               const float w1 = e1x * (py - p2.y) - e1y * (px - p2.x);
               const float w2 = e2x * (py - p0.y) - e2y * (px - p0.x);
               if (w0 > t0 || w1 > t1 || w2 > t2) continue;  // clearly outside
-              const int pix = (r - band.y0) * pitch + (col - band.x0);
+              const int pix = (r - buf.y0) * pitch + (col - buf.x0);
               if (edge_on || w0 >= -t0 || w1 >= -t1 || w2 >= -t2) {
                 const int slot = atomicAdd(&lds.counts[0], 1);
                 if (slot < lds.qcap) {
@@ -463,7 +478,7 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
   const int nq = min(lds.counts[0], lds.qcap);
   for (int k = threadIdx.x; k < nq; k += kBlock) {
     const uint2 e = lds.queue[k];
-    const int r = band.y0 + (int)e.x / pitch, col = band.x0 + (int)e.x % pitch;
+    const int r = buf.y0 + (int)e.x / pitch, col = buf.x0 + (int)e.x % pitch;
     if (COUNT) ++c_exact;
     if (!covered_exact(m, P, cam, e.y, r, col)) continue;
     const float z = plane_depth(m, P, cam, e.y, r, col);

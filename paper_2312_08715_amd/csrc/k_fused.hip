@@ -30,17 +30,20 @@ __device__ __forceinline__ double rect_sum(const double* sat, int W, const Rect&
 }
 
 // LDS: rasteriser scratch (reused for the window weights once the depth
-// buffer is complete) | depth keys [zcap] | reduction [64] | ray tables [W], [H].
+// buffer is complete) | depth keys [zcap] | reduction [64] | ray tables of
+// columns [-2h, W + 2h) and rows [-2h, H + 2h).
 size_t fused_lds_bytes(const SceneDev& s) {
-  return kRasterLdsBytes + sizeof(unsigned long long) * (size_t)s.zcap + sizeof(float) * (64 + s.cam.W + s.cam.H);
+  return kRasterLdsBytes + sizeof(unsigned long long) * (size_t)s.zcap +
+         sizeof(float) * (64 + s.cam.W + s.cam.H + 8 * s.sc.h);
 }
 
 // Window sums for observed point (ox, oy, oz) at pixel (r, c) over the LDS
-// depth rectangle L (pitch lw): S = sum_j exp(-D_ij/(2 sigma^2)) and
+// depth rectangle L (pitch lw), which holds the whole window (positions
+// outside the image are empty slots): S = sum_j exp(-D_ij/(2 sigma^2)) and
 // T = sum_j exp(-D_ij/(2 sigma^2)) D_ij over the rendered points of the
-// window.  Window positions outside L lie outside the image and are skipped.
-// HH > 0: the window half-width known at compile time (each row unrolled and
-// branch-free, with clamped addresses and predicated terms); HH = 0: any h.
+// window.  HH > 0: the window half-width known at compile time, each row
+// unrolled and branch-free: an empty slot's far depth makes its term exactly
+// 0.  HH = 0: any h, empty slots skipped.
 template <int HH, bool GRAD, bool COUNT>
 __device__ __forceinline__ void window_sums(const unsigned long long* __restrict__ zbuf, const Rect& L, int lw,
                                             const float* __restrict__ dxt, const float* __restrict__ dyt, int r,
@@ -50,37 +53,23 @@ __device__ __forceinline__ void window_sums(const unsigned long long* __restrict
   T = 0.0f;
   if (HH > 0) {
     constexpr int n = 2 * HH + 1;
-    int cc[n];
-    bool cv[n];
     float dxs[n];
 #pragma unroll
-    for (int k = 0; k < n; ++k) {
-      const int cj = c - HH + k;
-      cv[k] = cj >= L.x0 && cj < L.x1;
-      cc[k] = min(max(cj, L.x0), L.x1 - 1);
-      dxs[k] = dxt[cc[k]];
-      cc[k] -= L.x0;
-    }
+    for (int k = 0; k < n; ++k) dxs[k] = dxt[c - HH + k];
+    const unsigned long long* zr = zbuf + (r - HH - L.y0) * lw + (c - HH - L.x0);
 #pragma unroll 1
-    for (int j = 0; j < n; ++j) {
-      const int rj = r - HH + j;
-      const bool rv = rj >= L.y0 && rj < L.y1;
-      const int rc = min(max(rj, L.y0), L.y1 - 1);
-      const float dy = dyt[rc];
-      const unsigned long long* zr = zbuf + (rc - L.y0) * lw;
+    for (int j = 0; j < n; ++j, zr += lw) {
+      const float dy = dyt[r - HH + j];
 #pragma unroll
       for (int k = 0; k < n; ++k) {
-        const unsigned long long key = zr[cc[k]];
-        const bool ok = rv && cv[k] && key != kEmptyKey;
+        const unsigned long long key = zr[k];
         const float z = key_depth(key);
         const float ex = ox - z * dxs[k], ey = oy - z * dy, ez = oz - z;
         const float D = ex * ex + ey * ey + ez * ez;
-        // an empty slot reads a NaN depth: mask the distance as well as the term
-        const float Dm = ok ? D : 0.0f;
-        const float e = ok ? f_exp2(-Dm * c2) : 0.0f;
+        const float e = f_exp2(-D * c2);
         S += e;
-        if (GRAD) T += e * Dm;
-        if (COUNT) pairs += ok ? 1u : 0u;
+        if (GRAD) T += e * D;
+        if (COUNT) pairs += key != kEmptyKey ? 1u : 0u;
       }
     }
   } else {
@@ -176,15 +165,16 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
   float* wbuf = reinterpret_cast<float*>(smem);  // after rasterisation
   unsigned long long* zbuf = reinterpret_cast<unsigned long long*>(smem + kRasterLdsBytes);
   float* red = reinterpret_cast<float*>(zbuf + s.zcap);
-  float* dxt = red + 64;
-  float* dyt = dxt + s.cam.W;
 
   const Cam& cam = s.cam;
   const ScoreConsts& sc = s.sc;
   const int H = cam.H, W = cam.W, h = sc.h;
+  // ray tables indexed by column in [-2h, W + 2h) and row in [-2h, H + 2h)
+  float* dxt = red + 64 + 2 * h;
+  float* dyt = dxt + W + 4 * h;
   const Pose P = load_pose(pose16);
-  for (int i = threadIdx.x; i < W; i += kBlock) dxt[i] = ray_x(cam, i);
-  for (int i = threadIdx.x; i < H; i += kBlock) dyt[i] = ray_y(cam, i);
+  for (int i = (int)threadIdx.x - 2 * h; i < W + 2 * h; i += kBlock) dxt[i] = ray_x(cam, i);
+  for (int i = (int)threadIdx.x - 2 * h; i < H + 2 * h; i += kBlock) dyt[i] = ray_y(cam, i);
 
   const Rect obj = object_rect(s.mesh, P, cam);
   // observed pixels whose window can see the object (none when nothing is drawn)
@@ -193,7 +183,9 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
   // acc: l, d(dt) x3, d(dw) x3, d sigma, d p_out
   float acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (!obj.empty()) {
-    const Rect lds = grow_clip(obj, 2 * h, W, H);
+    // the depth buffer spans the object rectangle grown by 2h, past the image
+    // edges if need be (those slots stay empty), so every window is inside it
+    const Rect lds = grow(obj, 2 * h);
     const int lw = lds.w(), rw = region.w();
     int band = s.zcap / lw - 4 * h;
     if (GRAD) band = min(band, s.wcap / rw - 2 * h);
@@ -201,15 +193,17 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
     for (int a = region.y0; a < region.y1; a += band) {
       const int b = min(a + band, region.y1);
       Rect L = lds;
-      L.y0 = max(a - 2 * h, 0);
-      L.y1 = min(b + 2 * h, H);
+      L.y0 = a - 2 * h;
+      L.y1 = b + 2 * h;
+      const Rect D = grow_clip(L, 0, W, H);
       const int nk = L.h() * lw;
       for (int k = threadIdx.x; k < nk; k += kBlock) {
         const int r = L.y0 + k / lw, c = L.x0 + (k - (k / lw) * lw);
-        zbuf[k] = s.bg ? s.bg[(size_t)r * W + c] : kEmptyKey;
+        const bool in = r >= 0 && r < H && c >= 0 && c < W;
+        zbuf[k] = (in && s.bg) ? s.bg[(size_t)r * W + c] : kEmptyKey;
       }
       __syncthreads();
-      raster_mesh<COUNT>(s.mesh, P, cam, 0u, L, zbuf, rl, cnt);
+      raster_mesh<COUNT>(s.mesh, P, cam, 0u, D, L, zbuf, rl, cnt);
       refine_depths(s.mesh, P, cam, 0u, L, zbuf);
 
       // likelihood over observed rows [wa, wb); rows [a, b) are this band's own
@@ -239,15 +233,17 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
           }
           if (COUNT && r >= a && r < b) c_pair += pairs;
           const float Li = sc.a + sc.bn * S;
+          const float iL = __builtin_amdgcn_rcpf(Li);  // 1 / L_i, hardware reciprocal (1 ulp)
+          const float bL = sc.bn * iL;
           if (r >= a && r < b) {
             if (COUNT && S > 0.0f) ++c_obs;
             acc[0] += f_ln(Li);
             if (GRAD) {
-              acc[7] += (sc.bn / Li) * (T * sc.inv_s3 - 3.0f * S * sc.inv_s);
-              acc[8] += (sc.invV - sc.normM * S) / Li;
+              acc[7] += bL * (T * sc.inv_s3 - 3.0f * S * sc.inv_s);
+              acc[8] += (sc.invV - sc.normM * S) * iL;
             }
           }
-          wv = sc.bn / Li;
+          wv = bL;
         }
         if (GRAD) wbuf[k] = wv;
       }
@@ -335,8 +331,12 @@ __global__ __launch_bounds__(kBlock) void k_render_score(SceneDev s, const float
 // Items are numbered scene by scene in the order the host chose (longest
 // first), so the expensive scenes start early and the cheap ones fill the
 // tail.  Every block exits once the counter passes the total.
+// The scene's pointers come from memory here, not from kernel arguments, so
+// the compiler addresses through them with 64-bit per-lane (flat) addresses
+// and would need about 180 VGPRs; the bound keeps four workgroups per CU (as
+// for k_render_score) at the price of a few spills outside the inner loops.
 template <bool GRAD>
-__global__ __launch_bounds__(kBlock) void k_batch(const BatchItemDev* __restrict__ items, int S, long long total,
+__global__ __launch_bounds__(kBlock, 4) void k_batch(const BatchItemDev* __restrict__ items, int S, long long total,
                                                   unsigned long long* __restrict__ counter) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ long long work;

@@ -561,7 +561,8 @@ def test_tracker_graph_replays_match_eager_frames_and_follow_the_objects(b3d):
     ms = [b3d.Mesh(v, t) for v, t in meshes]
     K = b3d.intrinsics_of(cam)
     p = b3d.score_params(0.003, 0.01, 1.0, 5)
-    grid = b3d.make_grid(np.eye(4), (0.02, 0.02, 0.02), (6, 6, 6), n_rot=8, rot_max_angle=np.deg2rad(5.0))
+    grid = [b3d.make_grid(np.eye(4), (0.02, 0.02, 0.02), (6, 6, 6), n_rot=8, rot_max_angle=np.deg2rad(5.0)),
+            b3d.make_grid(np.eye(4), (0.005, 0.005, 0.005), (3, 3, 3), n_rot=8, rot_max_angle=np.deg2rad(2.0))]
     init = f32(paths[0])
     tg = b3d.Tracker(ms, K, p, grid, init, n_refine=5)
     te = b3d.Tracker(ms, K, p, grid, init, n_refine=5)
