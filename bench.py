@@ -40,6 +40,31 @@ METRIC = "pose hypotheses scored/s (render+logL) at 160x120, 24k tris; fwd+adjoi
 COST = {"vert": 17, "tri": 12, "front": 27, "frag": 10, "pair": 12, "obs": 6, "adj_pair": 10, "adj_rpix": 30}
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # FP32 lane-ops/s, non-packed: 39.3 T
 
+# HBM bytes of one fused forward+adjoint launch on this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch) scaled by
+# what the same counters read for a plain 256 MiB device copy (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0).  Valid only for the kernel sources with this digest:
+# after any change to them the figure is reported as null until re-measured.
+TRAFFIC = {"sources_sha256": None, "fetch_KiB": None, "write_KiB": None, "fetch_scale": 2.0, "write_scale": 1.0}
+KERNEL_SOURCES = ["k_fused.hip", "b3d_device.hpp", "b3d_launch.hpp"]
+
+
+def kernel_sources_digest() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2312_08715_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    t = TRAFFIC
+    if t["sources_sha256"] is None or t["sources_sha256"] != kernel_sources_digest():
+        return None
+    return (t["fetch_KiB"] * t["fetch_scale"] + t["write_KiB"] * t["write_scale"]) * 1024.0
+
 
 def lane_ops(c, adjoint=True):
     f = (COST["vert"] * c["vert"] + COST["tri"] * c["tri"] + COST["front"] * c["front"] + COST["frag"] * c["frag"]
@@ -367,7 +392,7 @@ def main():
                    "samples_per_step": args.samples},
         "roofline": {"bound": "alu", "kernel": "k_render_score<true>", "achieved": achieved,
                      "peak": VALU_PEAK_TOPS, "unit": "TOP/s (FP32 lane-ops)", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": None, "kernel_ms": t_kernel * 1e3,
+                     "traffic": measured_traffic(), "kernel_ms": t_kernel * 1e3,
                      "ops_per_hypothesis": ops / N,
                      "work_per_hypothesis": {k: v / N for k, v in work.items()},
                      "plain_method_ops_per_hypothesis": (lane_ops(plain_counts) if plain_counts else None)},
