@@ -279,6 +279,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fused-only", action="store_true", help="skip the split-path comparison")
     ap.add_argument("--no-extras", action="store_true", help="skip the batch, tracking and table workloads")
+    ap.add_argument("--only", choices=["batch", "tracking", "table"],
+                    help="run just one of the extra workloads and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -295,6 +297,10 @@ def main():
     wl, K, obs = build_inputs(b3d, torch)
     s = wl.score
     p = b3d.score_params(s.sigma, s.p_out, s.outlier_volume, s.window)
+    if args.only:
+        fn = {"batch": bench_batch, "tracking": bench_tracking, "table": bench_table_c2f}[args.only]
+        print(json.dumps({args.only: fn(b3d, torch, p)}), flush=True)
+        return
     mesh = b3d.Mesh(wl.verts, wl.tris)
     scene = b3d.Scene(mesh, K, p)
     scene.set_observed(obs)
