@@ -80,23 +80,14 @@ def counted_work(b3d, scene, P):
             "pair": w["pairs"], "obs": w["observed"], "rpix": w["adjoint_pixels"], "exact": w["exact_tests"]}
 
 
-def build_inputs(b3d, torch):
-    """Workload inputs, built on the GPU with the library itself."""
+def build_inputs(b3d, torch, k=1):
+    """Workload inputs (config k: 0 small, 1 paper scale), built on the GPU with the library itself."""
     from workloads import assemble_observed_depth, make_config
 
-    K = None
-
     def render_depth(objs, cam):
-        Kc = b3d.intrinsics_of(cam)
-        z = None
-        for k, (v, t, P) in enumerate(objs):
-            m = b3d.Mesh(v, t)
-            xyz, _ = b3d.render_batch(m, torch.as_tensor(np.asarray(P, np.float32)[None], device="cuda"), Kc, False)
-            zk = xyz[0, ..., 2].cpu().numpy().astype(np.float64)
-            z = zk if z is None else np.where((zk > 0) & ((z == 0) | (zk < z)), zk, z)
-        return z
+        return gpu_depth(b3d, torch, objs, cam)
 
-    wl = make_config(1, render=render_depth)
+    wl = make_config(k, render=render_depth)
     K = b3d.intrinsics_of(wl.camera)
     depth = assemble_observed_depth(render_depth, wl)
     obs = b3d.unproject(torch.as_tensor(depth, dtype=torch.float32, device="cuda"), K)
@@ -124,6 +115,32 @@ def noisy_observation(b3d, torch, depth, noise, cam):
 def rot_err_deg(Ra, Rb):
     c = (np.trace(Ra @ Rb.T) - 1.0) / 2.0
     return float(np.degrees(np.arccos(np.clip(c, -1.0, 1.0))))
+
+
+def bench_small(b3d, torch, steps, warmup):
+    """The small configuration (500 voxels = 6,000 triangles, 64x48, 256
+    hypotheses, 3x3 window): fused forward + adjoint, median of per-launch HIP
+    event times.  At 256 hypotheses one launch fills a quarter of the chip's
+    workgroup slots, so this measures latency more than throughput."""
+    wl, K, obs = build_inputs(b3d, torch, 0)
+    s = wl.score
+    scene = b3d.Scene(b3d.Mesh(wl.verts, wl.tris), K, b3d.score_params(s.sigma, s.p_out, s.outlier_volume, s.window))
+    scene.set_observed(obs)
+    grid, _ = b3d.grid_of(wl.grid)
+    P = b3d.enumerate_grid(grid, seed=wl.seeds["hyp"])
+    stream = torch.cuda.current_stream()
+    ts = []
+    for i in range(warmup + steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b3d.render_score(scene, P, grad=True)
+        e1.record(stream)
+        e1.synchronize()
+        if i >= warmup:
+            ts.append(e0.elapsed_time(e1) / 1e3)
+    t = float(np.median(ts))
+    return {"hypotheses": int(P.shape[0]), "value": P.shape[0] / t, "ms": t * 1e3, "unit": "hypotheses/s",
+            "note": "fused forward + adjoint, 64x48, 6k triangles, median of HIP event times per launch"}
 
 
 def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3):
@@ -340,6 +357,7 @@ def main():
     t_step = timed(lambda: step(timed_kernel=True), args.steps, args.warmup)
     kev_t = [a.elapsed_time(b) for a, b in kev[args.warmup:]]
     t_kernel = float(np.mean(kev_t)) / 1e3
+    t_kernel_median = float(np.median(kev_t)) / 1e3
     # forward only
     t_fwd = timed(lambda: step(grad=False), args.steps, args.warmup)
 
@@ -370,6 +388,7 @@ def main():
     achieved = ops / t_kernel / 1e12
     extras = {}
     if not args.no_extras:
+        extras["small_config"] = bench_small(b3d, torch, args.steps, args.warmup)
         for name, fn in (("batch_64_scenes", lambda: bench_batch(b3d, torch, p)),
                          ("tracking_200_frames", lambda: bench_tracking(b3d, torch, p)),
                          ("table_c2f_adam", lambda: bench_table_c2f(b3d, torch, p))):
@@ -399,6 +418,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_render_score<true>", "achieved": achieved,
                      "peak": VALU_PEAK_TOPS, "unit": "TOP/s (FP32 lane-ops)", "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": measured_traffic(), "kernel_ms": t_kernel * 1e3,
+                     "kernel_ms_median": t_kernel_median * 1e3,
                      "ops_per_hypothesis": ops / N,
                      "work_per_hypothesis": {k: v / N for k, v in work.items()},
                      "plain_method_ops_per_hypothesis": (lane_ops(plain_counts) if plain_counts else None)},
