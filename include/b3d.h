@@ -201,6 +201,9 @@ b3d_status b3d_render_score(const b3d_scene* scene, const float* poses, int32_t 
  * poses: device float[N][16], a representative sample (N >= 1). */
 b3d_status b3d_scene_autotune(b3d_scene* scene, const float* poses, int32_t N, int32_t grad, int32_t* zcap_out,
                               void* stream);
+/* The depth-buffer capacities (keys) b3d_scene_set_tile accepts for this
+ * scene, and the current one.  Any pointer may be NULL. */
+b3d_status b3d_scene_tile_limits(const b3d_scene* scene, int32_t* min_keys, int32_t* max_keys, int32_t* current);
 /* Set the depth-buffer capacity directly (e.g. from a cached tuning result);
  * zcap <= 0 restores the default.  Fails with B3D_ESHAPE when it does not fit
  * the LDS or cannot hold one band of rows. */

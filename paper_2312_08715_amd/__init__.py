@@ -87,6 +87,7 @@ _SIGNATURES = {
     "b3d_render_score": ([_P, _P, _I32, _P, _P, _P], ctypes.c_int),
     "b3d_scene_autotune": ([_P, _P, _I32, _I32, ctypes.POINTER(_I32), _P], ctypes.c_int),
     "b3d_scene_set_tile": ([_P, _I32], ctypes.c_int),
+    "b3d_scene_tile_limits": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)], ctypes.c_int),
     "b3d_render_score_work": ([_P, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "b3d_batch_create": ([ctypes.POINTER(BatchItem), _I32, ctypes.POINTER(_P)], ctypes.c_int),
     "b3d_batch_run": ([_P, _P], ctypes.c_int),
@@ -312,6 +313,12 @@ class Scene:
 
     def set_tile(self, zcap: int) -> None:
         _call("b3d_scene_set_tile", self._h, int(zcap))
+
+    def tile_limits(self) -> Tuple[int, int, int]:
+        """(smallest, largest, current) depth-buffer capacity in keys."""
+        lo, hi, cur = _I32(), _I32(), _I32()
+        _call("b3d_scene_tile_limits", self._h, ctypes.byref(lo), ctypes.byref(hi), ctypes.byref(cur))
+        return int(lo.value), int(hi.value), int(cur.value)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -576,6 +576,14 @@ b3d_status b3d_batch_destroy(b3d_batch* b) {
   return B3D_OK;
 }
 
+b3d_status b3d_scene_tile_limits(const b3d_scene* S, int32_t* min_keys, int32_t* max_keys, int32_t* current) {
+  if (!S) return fail(B3D_EINVAL, "scene_tile_limits: NULL scene");
+  if (min_keys) *min_keys = min_zcap(S->dev);
+  if (max_keys) *max_keys = max_zcap(S->dev);
+  if (current) *current = S->dev.zcap;
+  return B3D_OK;
+}
+
 b3d_status b3d_scene_set_tile(b3d_scene* S, int32_t zcap) {
   if (!S) return fail(B3D_EINVAL, "scene_set_tile: NULL scene");
   SceneDev t = S->dev;

@@ -179,7 +179,9 @@ def test_autotuned_tile_keeps_results_and_cache_round_trips(b3d, tmp_path):
     # every tile shape gives bitwise the same results
     L1, G1 = b3d.render_score(scene, Pd, grad=True)
     assert torch.equal(L1, L0) and torch.equal(G1, G0)
-    scene.set_tile((4 * (wl.score.window // 2) + 2) * wl.camera.W)  # the smallest: bands of two rows
+    lo, hi, cur = scene.tile_limits()
+    assert lo <= cur <= hi and cur == z
+    scene.set_tile(lo)  # the smallest: bands of two rows
     L3, G3 = b3d.render_score(scene, Pd, grad=True)
     assert torch.equal(L3, L0) and torch.equal(G3, G0)
     # a second scene of the same shape class takes the cached choice without timing
@@ -187,9 +189,9 @@ def test_autotuned_tile_keeps_results_and_cache_round_trips(b3d, tmp_path):
     assert scene2.autotune(Pd, grad=True, cache=cache) == z
     # capacities outside the LDS budget or below one band are refused; 0 restores the default
     with pytest.raises(b3d.B3DError):
-        scene2.set_tile(1)
+        scene2.set_tile(lo - 1)
     with pytest.raises(b3d.B3DError):
-        scene2.set_tile(1 << 20)
+        scene2.set_tile(hi + 1)
     scene2.set_tile(0)
     assert torch.equal(b3d.render_score(scene2, Pd), L0)
 
