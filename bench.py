@@ -383,6 +383,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # the chip's FP32 vector FMA rate, measured by an FMA-loop kernel (lane-ops/s)
+    valu_measured = b3d.probe_fma() / 1e12
     work = counted_work(b3d, scene, P)
     ops = lane_ops(work, adjoint=True)
     achieved = ops / t_kernel / 1e12
@@ -419,6 +421,7 @@ def main():
                      "peak": VALU_PEAK_TOPS, "unit": "TOP/s (FP32 lane-ops)", "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": measured_traffic(), "kernel_ms": t_kernel * 1e3,
                      "kernel_ms_median": t_kernel_median * 1e3,
+                     "peak_measured": valu_measured, "frac_of_measured": achieved / valu_measured,
                      "ops_per_hypothesis": ops / N,
                      "work_per_hypothesis": {k: v / N for k, v in work.items()},
                      "plain_method_ops_per_hypothesis": (lane_ops(plain_counts) if plain_counts else None)},
