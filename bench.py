@@ -268,10 +268,7 @@ def bench_table_c2f(b3d, torch, p):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         P, logq, idx = b3d.c2f_step(scene, start, sched, 16, 4002 + k)
-        state = torch.zeros((16, 12), dtype=torch.float32, device="cuda")
-        for it in range(1, 21):
-            L, G = b3d.render_score(scene, P, grad=True)
-            b3d.adam_pose_step(P, G, state, it, 1e-3, 1e-2)
+        b3d.refine_poses(scene, P, 20, 1e-3, 1e-2)
         L = b3d.render_score(scene, P)
         torch.cuda.synchronize()
         dtm = time.perf_counter() - t0

@@ -317,6 +317,12 @@ b3d_status b3d_c2f_step(const b3d_scene* scene, const float* center, const b3d_s
 
 /* ---- gradient refinement and tracking ---------------------------------- */
 
+/* Peak probe (not part of the method): blocks x 256 lanes each run
+ * iters x 128 dependent-in-8-chains FP32 FMAs (2 flops each); out receives
+ * one float per lane (device float[blocks * 256]).  Time it on `stream` to
+ * measure the chip's FP32 vector FMA rate.  Stream-ordered. */
+b3d_status b3d_probe_fma(float* out, int32_t blocks, int32_t iters, void* stream);
+
 /* Retraction onto the pose manifold, the update convention of the adjoint
  * (Sec. III-B's pose grid composed as t = t_c + dt, R = dR R_c, with dR the
  * rotation exponential): out[n] = (exp([w_n]x) R_b, t_b + dt_n) for
@@ -352,6 +358,14 @@ b3d_status b3d_scene_set_params(b3d_scene* scene, const b3d_score_params* p, voi
  * iter >= 1.  Stream-ordered. */
 b3d_status b3d_adam_pose_step(float* poses, const float* grad, int32_t gstride, float* state, int32_t N, int32_t iter,
                               float lr_t, float lr_r, float beta1, float beta2, float eps, void* stream);
+
+/* Gradient refinement of N poses of a scene: n_refine Adam ascent steps on
+ * logL each (the update of b3d_adam_pose_step from zero moments, driven by
+ * b3d_render_score's adjoint), all steps of one pose in one workgroup.
+ * poses: device float[N][16], updated in place.  Equal to n_refine rounds of
+ * b3d_render_score(grad) + b3d_adam_pose_step.  Stream-ordered. */
+b3d_status b3d_refine_poses(const b3d_scene* scene, float* poses, int32_t N, int32_t n_refine, float lr_t, float lr_r,
+                            float beta1, float beta2, float eps, void* stream);
 
 /* Per-frame tracking settings: n_stages grids of hypotheses, stage s centred
  * on the best hypothesis of stage s-1 (stage 0 on the previous estimate; the

@@ -92,9 +92,12 @@ _SIGNATURES = {
     "b3d_batch_create": ([ctypes.POINTER(BatchItem), _I32, ctypes.POINTER(_P)], ctypes.c_int),
     "b3d_batch_run": ([_P, _P], ctypes.c_int),
     "b3d_batch_destroy": ([_P], ctypes.c_int),
+    "b3d_probe_fma": ([_P, _I32, _I32, _P], ctypes.c_int),
     "b3d_pose_retract": ([_P, _I32, _P, _I32, _P, _P], ctypes.c_int),
     "b3d_pose_retract_backward": ([_P, _P, _P, _I32, _P, _P, _P], ctypes.c_int),
     "b3d_scene_set_params": ([_P, ctypes.POINTER(ScoreParams), _P], ctypes.c_int),
+    "b3d_refine_poses": ([_P, _P, _I32, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                          ctypes.c_float, _P], ctypes.c_int),
     "b3d_adam_pose_step": ([_P, _P, _I32, _P, _I32, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                             ctypes.c_float, ctypes.c_float, _P], ctypes.c_int),
     "b3d_tracker_create": ([_P, _I32, ctypes.POINTER(Intrinsics), ctypes.POINTER(ScoreParams),
@@ -344,6 +347,19 @@ def render_score(scene: Scene, poses: torch.Tensor, grad: bool = False):
 WORK_ITEMS = ("vertices", "triangles", "setup", "fragments", "pairs", "observed", "adjoint_pixels", "exact_tests")
 
 
+def probe_fma(blocks: int = 4096, iters: int = 256) -> float:
+    """Measured FP32 vector FMA rate in lane-FMAs/s (one FMA = 2 flops)."""
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    _call("b3d_probe_fma", _ptr(out), blocks, iters, _stream())  # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    _call("b3d_probe_fma", _ptr(out), blocks, iters, _stream())
+    e1.record(st)
+    e1.synchronize()
+    return blocks * 256.0 * iters * 128.0 / (e0.elapsed_time(e1) / 1e3)
+
+
 def pose_retract(base: torch.Tensor, xi: torch.Tensor) -> torch.Tensor:
     """Poses [N,4,4] = (exp([w]x) R_b, t_b + dt) for xi [N,6] = (dt, w); base [N,4,4] or [1,4,4]/[4,4]."""
     N = xi.shape[0]
@@ -523,6 +539,13 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def refine_poses(scene: Scene, poses: torch.Tensor, n_refine: int, lr_t: float, lr_r: float, beta1: float = 0.9,
+                 beta2: float = 0.999, eps: float = 1e-8) -> None:
+    """In place: n_refine Adam steps on logL for each pose [N,4,4] (one workgroup per pose)."""
+    _call("b3d_refine_poses", scene.handle, _ptr(poses, torch.float32), int(poses.shape[0]), int(n_refine),
+          float(lr_t), float(lr_r), float(beta1), float(beta2), float(eps), _stream())
 
 
 def adam_pose_step(poses: torch.Tensor, grad: torch.Tensor, state: torch.Tensor, it: int, lr_t: float, lr_r: float,

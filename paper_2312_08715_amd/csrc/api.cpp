@@ -471,6 +471,14 @@ b3d_status b3d_scene_set_params(b3d_scene* S, const b3d_score_params* p, void* s
   return B3D_OK;
 }
 
+b3d_status b3d_probe_fma(float* out, int32_t blocks, int32_t iters, void* stream) {
+  if (!out) return fail(B3D_EINVAL, "probe_fma: NULL pointer");
+  if (blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > (1 << 20))
+    return fail(B3D_ESHAPE, "probe_fma: blocks and iters in 1..2^20");
+  B3D_CHECK_HIP(launch_probe_fma(out, blocks, iters, (hipStream_t)stream), "probe_fma");
+  return B3D_OK;
+}
+
 b3d_status b3d_pose_retract(const float* base, int32_t n_base, const float* xi, int32_t N, float* out, void* stream) {
   if (N < 0) return fail(B3D_ESHAPE, "pose_retract: N < 0");
   if (N == 0) return B3D_OK;
@@ -488,6 +496,20 @@ b3d_status b3d_pose_retract_backward(const float* xi, const float* grad, const f
   if (!xi || !grad || !dxi) return fail(B3D_EINVAL, "pose_retract_backward: NULL pointer");
   B3D_CHECK_HIP(launch_pose_retract_backward(xi, grad, dlogL, N, dxi, dsp, (hipStream_t)stream),
                 "pose_retract_backward");
+  return B3D_OK;
+}
+
+b3d_status b3d_refine_poses(const b3d_scene* S, float* poses, int32_t N, int32_t n_refine, float lr_t, float lr_r,
+                            float beta1, float beta2, float eps, void* stream) {
+  if (!S) return fail(B3D_EINVAL, "refine_poses: NULL scene");
+  if (!S->observed) return fail(B3D_EINVAL, "refine_poses: call b3d_scene_set_observed first");
+  if (N < 0 || n_refine < 0 || n_refine > 100000) return fail(B3D_ESHAPE, "refine_poses: N >= 0, n_refine in 0..1e5");
+  if (N == 0 || n_refine == 0) return B3D_OK;
+  if (!poses) return fail(B3D_EINVAL, "refine_poses: NULL pointer");
+  if (!(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return fail(B3D_EINVAL, "refine_poses: bad Adam parameters");
+  B3D_CHECK_HIP(launch_refine_pose(S->dev, poses, N, n_refine, lr_t, lr_r, beta1, beta2, eps, (hipStream_t)stream),
+                "refine_poses");
   return B3D_OK;
 }
 
@@ -822,8 +844,6 @@ struct b3d_tracker {
   float* poses = nullptr;    // [M][16] current estimates
   float* hyp = nullptr;      // [N][16]
   float* logL = nullptr;     // [N]
-  float* grad = nullptr;     // [8]
-  float* state = nullptr;    // [12]
   size_t obs_bytes = 0;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -856,13 +876,10 @@ static b3d_status tracker_record(b3d_tracker* T, hipStream_t st) {
       B3D_CHECK_HIP(launch_render_score(S->dev, T->hyp, (int)ns[s], T->logL, nullptr, st), "tracker");
       B3D_CHECK_HIP(launch_argmax_pose(T->logL, T->hyp, (int)ns[s], T->poses + 16 * o, st), "tracker");
     }
-    B3D_CHECK_HIP(launch_fill_f32(T->state, 12, 0.0f, st), "tracker");
-    for (int it = 1; it <= tp.n_refine; ++it) {
-      B3D_CHECK_HIP(launch_render_score(S->dev, T->poses + 16 * o, 1, T->logL, T->grad, st), "tracker");
-      B3D_CHECK_HIP(launch_adam_pose(T->poses + 16 * o, T->grad, 8, T->state, 1, it, tp.lr_t, tp.lr_r, tp.beta1,
-                                     tp.beta2, tp.eps, st),
+    if (tp.n_refine > 0)
+      B3D_CHECK_HIP(launch_refine_pose(S->dev, T->poses + 16 * o, 1, tp.n_refine, tp.lr_t, tp.lr_r, tp.beta1,
+                                       tp.beta2, tp.eps, st),
                     "tracker");
-    }
   }
   return B3D_OK;
 }
@@ -905,8 +922,6 @@ b3d_status b3d_tracker_create(const b3d_mesh* const* meshes, int32_t M, const b3
     (void)hipFree(T->poses);
     (void)hipFree(T->hyp);
     (void)hipFree(T->logL);
-    (void)hipFree(T->grad);
-    (void)hipFree(T->state);
     if (T->cap) (void)hipStreamDestroy(T->cap);
     delete T;
     return fail(s, "%s", msg);
@@ -914,9 +929,7 @@ b3d_status b3d_tracker_create(const b3d_mesh* const* meshes, int32_t M, const b3
   if (hipMalloc((void**)&T->obs, T->obs_bytes) != hipSuccess ||
       hipMalloc((void**)&T->poses, sizeof(float) * 16 * M) != hipSuccess ||
       hipMalloc((void**)&T->hyp, sizeof(float) * 16 * (size_t)n) != hipSuccess ||
-      hipMalloc((void**)&T->logL, sizeof(float) * (size_t)n) != hipSuccess ||
-      hipMalloc((void**)&T->grad, sizeof(float) * 8) != hipSuccess ||
-      hipMalloc((void**)&T->state, sizeof(float) * 12) != hipSuccess)
+      hipMalloc((void**)&T->logL, sizeof(float) * (size_t)n) != hipSuccess)
     return cleanup(B3D_ENOMEM, "tracker_create: device allocation failed");
   if (hipMemcpy(T->poses, init_poses, sizeof(float) * 16 * M, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(T->obs, 0, T->obs_bytes) != hipSuccess)
@@ -984,8 +997,6 @@ b3d_status b3d_tracker_destroy(b3d_tracker* T) {
   (void)hipFree(T->poses);
   (void)hipFree(T->hyp);
   (void)hipFree(T->logL);
-  (void)hipFree(T->grad);
-  (void)hipFree(T->state);
   if (T->cap) (void)hipStreamDestroy(T->cap);
   delete T;
   return B3D_OK;

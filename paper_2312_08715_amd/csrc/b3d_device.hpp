@@ -496,6 +496,36 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
   __syncthreads();
 }
 
+// One Adam ascent step on logL for pose P (row-major 4x4), on the tangent
+// (dt, dw): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+// s = lr * mhat / (sqrt(vhat) + eps), then t <- t + s[0:3], R <- exp([s[3:6]]x) R.
+__device__ __forceinline__ void adam_update(float* P, const float* g, float* m, float* v, int iter, float lr_t,
+                                            float lr_r, float b1, float b2, float eps) {
+  const float c1 = 1.0f - powf(b1, (float)iter), c2 = 1.0f - powf(b2, (float)iter);
+  float s[6];
+  for (int k = 0; k < 6; ++k) {
+    m[k] = b1 * m[k] + (1.0f - b1) * g[k];
+    v[k] = b2 * v[k] + (1.0f - b2) * g[k] * g[k];
+    const float mh = m[k] / c1, vh = v[k] / c2;
+    s[k] = (k < 3 ? lr_t : lr_r) * mh / (sqrtf(vh) + eps);
+  }
+  for (int k = 0; k < 3; ++k) P[4 * k + 3] += s[k];
+  const float wx = s[3], wy = s[4], wz = s[5];
+  const float th = sqrtf(wx * wx + wy * wy + wz * wz);
+  if (th > 0.0f) {
+    const float kx = wx / th, ky = wy / th, kz = wz / th;
+    const float sn = sinf(th), cs = 1.0f - cosf(th);
+    const float E[9] = {1.0f + cs * (kx * kx - 1.0f), -sn * kz + cs * kx * ky,       sn * ky + cs * kx * kz,
+                        sn * kz + cs * kx * ky,       1.0f + cs * (ky * ky - 1.0f), -sn * kx + cs * ky * kz,
+                        -sn * ky + cs * kx * kz,      sn * kx + cs * ky * kz,       1.0f + cs * (kz * kz - 1.0f)};
+    float R[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) R[3 * i + j] = E[3 * i] * P[j] + E[3 * i + 1] * P[4 + j] + E[3 * i + 2] * P[8 + j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) P[4 * i + j] = R[3 * i + j];
+  }
+}
+
 // Fixed-order sum over the 64 lanes of a wave (butterfly), result in all lanes.
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll

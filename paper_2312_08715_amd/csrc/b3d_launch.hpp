@@ -93,9 +93,12 @@ hipError_t launch_c2f_update(const float* poses, int P, int N, const int* idx, c
                              int accumulate, float* centres, float* logq, int* idx_out, hipStream_t st);
 
 // refinement and tracking
+hipError_t launch_probe_fma(float* out, int blocks, int iters, hipStream_t st);
 hipError_t launch_pose_retract(const float* base, int n_base, const float* xi, int N, float* out, hipStream_t st);
 hipError_t launch_pose_retract_backward(const float* xi, const float* grad, const float* dlogL, int N, float* dxi,
                                         float* dsp, hipStream_t st);
+hipError_t launch_refine_pose(const SceneDev& s, float* poses, int N, int n_refine, float lr_t, float lr_r, float b1,
+                              float b2, float eps, hipStream_t st);
 hipError_t launch_adam_pose(float* poses, const float* grad, int gstride, float* state, int N, int iter, float lr_t,
                             float lr_r, float b1, float b2, float eps, hipStream_t st);
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t st);

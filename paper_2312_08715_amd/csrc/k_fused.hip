@@ -380,6 +380,37 @@ hipError_t launch_batch(const BatchItemDev* items, int S, long long total, unsig
   return hipGetLastError();
 }
 
+// n_refine Adam steps on each of N poses of a scene, one workgroup per pose:
+// the fused render + score + adjoint, then the update, with the pose kept in
+// LDS between steps (the same arithmetic as render_score + adam_pose launched
+// in turn, starting from zero moments).
+__global__ __launch_bounds__(kBlock) void k_refine_pose(SceneDev s, float* __restrict__ poses, int N, int n_refine,
+                                                        float lr_t, float lr_r, float b1, float b2, float eps) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ float P[16];
+  __shared__ float g[8];
+  __shared__ float L;
+  const int n = blockIdx.x;
+  if (n >= N) return;
+  float* pose = poses + 16 * (size_t)n;
+  float m[6] = {0, 0, 0, 0, 0, 0}, v[6] = {0, 0, 0, 0, 0, 0};  // used by thread 0
+  if (threadIdx.x < 16) P[threadIdx.x] = pose[threadIdx.x];
+  __syncthreads();
+  for (int it = 1; it <= n_refine; ++it) {
+    render_score_one<true>(s, P, &L, g, smem);
+    if (threadIdx.x == 0) adam_update(P, g, m, v, it, lr_t, lr_r, b1, b2, eps);
+    __syncthreads();
+  }
+  if (threadIdx.x < 16) pose[threadIdx.x] = P[threadIdx.x];
+}
+
+hipError_t launch_refine_pose(const SceneDev& s, float* poses, int N, int n_refine, float lr_t, float lr_r, float b1,
+                              float b2, float eps, hipStream_t st) {
+  hipLaunchKernelGGL(k_refine_pose, dim3(N), dim3(kBlock), fused_lds_bytes(s), st, s, poses, N, n_refine, lr_t,
+                     lr_r, b1, b2, eps);
+  return hipGetLastError();
+}
+
 // The counting instantiation: same work, plus per-launch totals of the work
 // items in work[kCntN] (64-bit, accumulated).
 __global__ __launch_bounds__(kBlock) void k_render_score_count(SceneDev s, const float* __restrict__ poses, int N,

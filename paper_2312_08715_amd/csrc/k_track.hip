@@ -5,41 +5,14 @@
 
 namespace b3d {
 
-// Adam ascent on logL for each pose n, on the tangent (dt, dw):
-// m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2, s = lr * mhat / (sqrt(vhat) + eps),
-// then t <- t + s[0:3], R <- exp([s[3:6]]x) R.  state [N][12] = (m, v).
+// Adam step for each pose n; state [N][12] = (m, v).
 __global__ void k_adam_pose(float* __restrict__ poses, const float* __restrict__ grad, int gstride,
                             float* __restrict__ state, int N, int iter, float lr_t, float lr_r, float b1, float b2,
                             float eps) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
-  float* P = poses + 16 * (size_t)n;
-  const float* g = grad + (size_t)gstride * n;
   float* m = state + 12 * (size_t)n;
-  float* v = m + 6;
-  const float c1 = 1.0f - powf(b1, (float)iter), c2 = 1.0f - powf(b2, (float)iter);
-  float s[6];
-  for (int k = 0; k < 6; ++k) {
-    m[k] = b1 * m[k] + (1.0f - b1) * g[k];
-    v[k] = b2 * v[k] + (1.0f - b2) * g[k] * g[k];
-    const float mh = m[k] / c1, vh = v[k] / c2;
-    s[k] = (k < 3 ? lr_t : lr_r) * mh / (sqrtf(vh) + eps);
-  }
-  for (int k = 0; k < 3; ++k) P[4 * k + 3] += s[k];
-  const float wx = s[3], wy = s[4], wz = s[5];
-  const float th = sqrtf(wx * wx + wy * wy + wz * wz);
-  if (th > 0.0f) {
-    const float kx = wx / th, ky = wy / th, kz = wz / th;
-    const float sn = sinf(th), cs = 1.0f - cosf(th);
-    const float E[9] = {1.0f + cs * (kx * kx - 1.0f), -sn * kz + cs * kx * ky,       sn * ky + cs * kx * kz,
-                        sn * kz + cs * kx * ky,       1.0f + cs * (ky * ky - 1.0f), -sn * kx + cs * ky * kz,
-                        -sn * ky + cs * kx * kz,      sn * kx + cs * ky * kz,       1.0f + cs * (kz * kz - 1.0f)};
-    float R[9];
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) R[3 * i + j] = E[3 * i] * P[j] + E[3 * i + 1] * P[4 + j] + E[3 * i + 2] * P[8 + j];
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) P[4 * i + j] = R[3 * i + j];
-  }
+  adam_update(poses + 16 * (size_t)n, grad + (size_t)gstride * n, m, m + 6, iter, lr_t, lr_r, b1, b2, eps);
 }
 
 hipError_t launch_adam_pose(float* poses, const float* grad, int gstride, float* state, int N, int iter, float lr_t,

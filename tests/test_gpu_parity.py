@@ -546,6 +546,27 @@ def test_adam_pose_step_matches_oracle(b3d):
     np.testing.assert_allclose(sd.cpu().numpy(), st, rtol=1e-5, atol=1e-3)
 
 
+def test_refine_poses_equals_score_and_adam_launched_in_turn(b3d):
+    wl, obs, P = workload(0)
+    sel = np.arange(0, P.shape[0], 32)
+    say(f"refine_poses: config 0, {len(sel)} poses, 6 steps")
+    scene, mesh, o = _scene(b3d, wl, obs)
+    b1, b2, eps = 0.9, 0.999, 1e-8
+    A = dev(P[sel])
+    b3d.refine_poses(scene, A, 6, 1e-3, 1e-2, b1, b2, eps)
+    B = dev(P[sel])
+    st = torch.zeros((len(sel), 12), dtype=torch.float32, device="cuda")
+    for it in range(1, 7):
+        _, G = b3d.render_score(scene, B, grad=True)
+        b3d.adam_pose_step(B, G, st, it, 1e-3, 1e-2, b1, b2, eps)
+    np.testing.assert_allclose(A.cpu().numpy(), B.cpu().numpy(), rtol=0, atol=1e-6)
+    # the steps moved the poses and raised logL
+    assert not np.allclose(A.cpu().numpy(), P[sel])
+    L0 = b3d.render_score(scene, dev(P[sel])).cpu().numpy()
+    L1 = b3d.render_score(scene, A).cpu().numpy()
+    assert np.median(L1 - L0) > 0
+
+
 def test_tracker_graph_replays_match_eager_frames_and_follow_the_objects(b3d):
     from workloads import assemble_observed_depth, tracking_sequence, Workload, ScoreParams, GridSpec
 
