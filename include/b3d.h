@@ -89,7 +89,7 @@ typedef struct b3d_mesh b3d_mesh;
 b3d_status b3d_mesh_create(const float* verts, int32_t V, const int32_t* tris, int32_t T, b3d_mesh** out);
 /* Free a mesh (synchronises the current device).  NULL is accepted. */
 b3d_status b3d_mesh_destroy(b3d_mesh* mesh);
-/* Vertex count, triangle count and number of vertex clusters the device
+/* Vertex count, triangle count and number of primitive clusters the device
  * layout uses (any pointer may be NULL). */
 b3d_status b3d_mesh_info(const b3d_mesh* mesh, int32_t* V, int32_t* T, int32_t* n_clusters);
 
@@ -98,8 +98,10 @@ b3d_status b3d_mesh_info(const b3d_mesh* mesh, int32_t* V, int32_t* T, int32_t* 
  * triangles always drawn, info[3] = triangles drawn only when the object
  * reaches the near plane (coincident opposite faces of two different closed
  * components, which a camera outside the object never sees), info[4] =
- * triangles with a repeated vertex position (never drawn).  info: host
- * int32[5]. */
+ * triangles with a repeated vertex position (never drawn), info[5] = quads
+ * (pairs of triangles sharing an edge, coplanar and convex, rasterised as one
+ * primitive; the other drawn triangles are single primitives).  info: host
+ * int32[6]. */
 b3d_status b3d_mesh_layout_info(const float* verts, int32_t V, const int32_t* tris, int32_t T, int32_t* info);
 
 /* ---- the split path: point images in device memory ---------------------- */

@@ -208,9 +208,9 @@ def mesh_layout_info(verts, tris) -> dict:
     """Host-only summary of the device layout b3d_mesh_create would build."""
     v = np.ascontiguousarray(verts, dtype=np.float32)
     t = np.ascontiguousarray(tris, dtype=np.int32)
-    info = np.zeros(5, dtype=np.int32)
+    info = np.zeros(6, dtype=np.int32)
     _call("b3d_mesh_layout_info", v.ctypes.data, v.shape[0], t.ctypes.data, t.shape[0], info.ctypes.data)
-    return dict(zip(("clusters", "visible_clusters", "drawn", "hidden_pairs", "dropped"), info.tolist()))
+    return dict(zip(("clusters", "visible_clusters", "drawn", "hidden_pairs", "dropped", "quads"), info.tolist()))
 
 
 def unproject(depth: torch.Tensor, K: Intrinsics) -> torch.Tensor:

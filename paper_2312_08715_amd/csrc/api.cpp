@@ -174,8 +174,8 @@ b3d_status b3d_mesh_create(const float* verts, int32_t V, const int32_t* tris, i
     lay.clusters.back().cone = make_float4(0.0f, 0.0f, 1.0f, 4.0f);
     lay.n_visible = 0;
   }
-  if (lay.cverts.empty()) lay.cverts.push_back(make_float4(0, 0, 0, 0));
-  if (lay.ctris.empty()) lay.ctris.push_back(make_uint2(0, 0));
+  if (lay.pverts.empty()) lay.pverts.assign(4, make_float4(0, 0, 0, 0));
+  if (lay.pids.empty()) lay.pids.push_back(make_uint2(0, kNoTri));
   std::vector<float4> v4((size_t)V), nrm((size_t)T);
   std::vector<int4> t4((size_t)T);
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -216,8 +216,8 @@ b3d_status b3d_mesh_create(const float* verts, int32_t V, const int32_t* tris, i
   };
   void *d_cl, *d_cv, *d_ct, *d_v, *d_t, *d_n;
   bool ok = upload(lay.clusters.data(), std::max<size_t>(1, lay.clusters.size()) * sizeof(ClusterDev), &d_cl) &&
-            upload(lay.cverts.data(), std::max<size_t>(1, lay.cverts.size()) * sizeof(float4), &d_cv) &&
-            upload(lay.ctris.data(), std::max<size_t>(1, lay.ctris.size()) * sizeof(uint2), &d_ct) &&
+            upload(lay.pverts.data(), lay.pverts.size() * sizeof(float4), &d_cv) &&
+            upload(lay.pids.data(), lay.pids.size() * sizeof(uint2), &d_ct) &&
             upload(v4.data(), v4.size() * sizeof(float4), &d_v) && upload(t4.data(), t4.size() * sizeof(int4), &d_t) &&
             upload(nrm.data(), nrm.size() * sizeof(float4), &d_n);
   if (!ok) {
@@ -227,8 +227,8 @@ b3d_status b3d_mesh_create(const float* verts, int32_t V, const int32_t* tris, i
   }
   MeshDev& d = m->dev;
   d.clusters = (const ClusterDev*)d_cl;
-  d.cverts = (const float4*)d_cv;
-  d.ctris = (const uint2*)d_ct;
+  d.pverts = (const float4*)d_cv;
+  d.pids = (const uint2*)d_ct;
   d.n_visible = lay.n_visible;
   d.verts = (const float4*)d_v;
   d.tris = (const int4*)d_t;
@@ -270,6 +270,7 @@ b3d_status b3d_mesh_layout_info(const float* verts, int32_t V, const int32_t* tr
   info[2] = lay.n_drawn;
   info[3] = lay.n_hidden;
   info[4] = lay.n_dropped;
+  info[5] = lay.n_quads;
   return B3D_OK;
 }
 

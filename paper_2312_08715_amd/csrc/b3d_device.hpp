@@ -10,8 +10,8 @@ namespace b3d {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kWaves = kBlock / 64;
-constexpr int kClusterTris = 64;     // max triangles per cluster (one per lane of a wave)
-constexpr int kClusterVerts = 128;   // max vertices per cluster
+constexpr int kClusterPrims = 64;    // max primitives (triangles or quads) per cluster, one per lane of a wave
+constexpr uint32_t kNoTri = 0xFFFFFFFFu;  // second id of a primitive that is a single triangle
 // The key of a pixel with no surface: depth 1e15 m (bits 0x58635FA9), id all
 // ones.  It compares above every surface nearer than that, and its depth is
 // finite, so a window term against an empty slot evaluates to exactly 0
@@ -31,13 +31,14 @@ struct Pose {
   float t[3];
 };
 
-// A group of up to kClusterTris triangles of one orientation class that are
-// close in space, with its own copy of the vertices they use (at most
-// kClusterVerts).  sphere = centre and radius of a ball holding them; cone =
-// unit axis and half-angle (radians) of a cone holding their face normals
-// (half-angle > pi/2 means "no bound").
+// A group of up to kClusterPrims primitives of one orientation class that
+// are close in space: primitives [pfirst, pfirst + np).  A primitive is the
+// triangle (a, b, c) and, when its second id is not kNoTri, the triangle
+// (a, c, d) sharing the edge a-c (a convex planar quad).  sphere = centre and
+// radius of a ball holding them; cone = unit axis and half-angle (radians) of
+// a cone holding their face normals (half-angle > pi/2 means "no bound").
 struct ClusterDev {
-  int vfirst, nv, tfirst, nt;
+  int pfirst, np, pad0, pad1;
   float4 sphere;
   float4 cone;
 };
@@ -45,8 +46,8 @@ struct ClusterDev {
 // Device view of an uploaded mesh.
 struct MeshDev {
   const ClusterDev* clusters;  // [0, n_visible) drawn; [n_visible, n_clusters) only near the near plane
-  const float4* cverts;        // cluster-local vertex copies (object frame)
-  const uint2* ctris;          // (local indices a | b << 8 | c << 16, triangle id)
+  const float4* pverts;        // [primitives][4] object-frame corners a, b, c, d (d = c for a triangle)
+  const uint2* pids;           // [primitives] caller's ids of triangles (a, b, c) and (a, c, d) or kNoTri
   const float4* verts;         // caller's vertices
   const int4* tris;            // caller's triangles (w unused)
   const float4* normals;       // object-frame (v1 - v0) x (v2 - v0)
@@ -311,23 +312,21 @@ __device__ __forceinline__ bool covered_exact(const MeshDev& m, const Pose& P, c
   return !(w0 > 0.0 || w1 > 0.0 || w2 > 0.0);
 }
 
-// LDS scratch of the rasteriser (free again once raster_mesh returns).
+// LDS scratch of the rasteriser (free again once raster_mesh returns; the
+// fused kernel then reuses it for the window weights, which sets its size).
 struct RasterLds {
-  float4* vbuf;  // kWaves * kClusterVerts projected vertices (one buffer per wave)
   uint2* queue;  // (band pixel, triangle id) pairs left for the exact test
   int* list;     // drawable clusters of the current group of kBlock
   int* counts;   // [0] queue fill, [1..kWaves] per-wave drawable counts, [kWaves + 1] next list entry
   int qcap;
 };
 
-constexpr int kQueueCap = 512;
-constexpr size_t kRasterLdsBytes =
-    sizeof(float4) * kWaves * kClusterVerts + sizeof(uint2) * kQueueCap + sizeof(int) * kBlock + sizeof(int) * 16;
+constexpr int kQueueCap = 1536;
+constexpr size_t kRasterLdsBytes = sizeof(uint2) * kQueueCap + sizeof(int) * kBlock + sizeof(int) * 16;
 
 __device__ __forceinline__ RasterLds carve_raster_lds(unsigned char* p) {
   RasterLds r;
-  r.vbuf = reinterpret_cast<float4*>(p);
-  r.queue = reinterpret_cast<uint2*>(r.vbuf + kWaves * kClusterVerts);
+  r.queue = reinterpret_cast<uint2*>(p);
   r.list = reinterpret_cast<int*>(r.queue + kQueueCap);
   r.counts = r.list + kBlock;
   r.qcap = kQueueCap;
@@ -339,6 +338,14 @@ __device__ __forceinline__ RasterLds carve_raster_lds(unsigned char* p) {
 // pixel centres, window pairs, observed pixels that saw a point, object pixels
 // of the adjoint, centres decided by the exact test.
 enum { kCntVert = 0, kCntTri, kCntSetup, kCntFrag, kCntPair, kCntObs, kCntAdj, kCntExact, kCntN };
+
+// Pixel position, depth and 1/depth of an object-frame point under pose P.
+__device__ __forceinline__ float4 project_corner(const Pose& P, const Cam& cam, const float4 o) {
+  const float3 p = xform(P, o.x, o.y, o.z);
+  // hardware reciprocal (1 ulp): far inside the rasteriser's edge margin
+  const float iz = __builtin_amdgcn_rcpf(p.z);
+  return make_float4(cam.fx * p.x * iz + cam.cx, cam.fy * p.y * iz + cam.cy, p.z, iz);
+}
 
 // Rasterise the mesh under pose P into the pixels of the image rectangle
 // `band` of an LDS key buffer that covers the rectangle `buf` (row pitch
@@ -371,7 +378,6 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
   }
   const int n_clusters = straddle ? m.n_clusters : m.n_visible;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  float4* vb = lds.vbuf + wave * kClusterVerts;
   for (int base = 0; base < n_clusters; base += kBlock) {
     // each thread tests one cluster; the drawable ones are compacted into `list`
     const int mine = base + threadIdx.x;
@@ -394,46 +400,75 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
       q = __shfl(q, 0, 64);
       if (q >= total) break;
       const ClusterDev cl = m.clusters[lds.list[q]];
-      if (COUNT && lane == 0) {
-        c_vert += cl.nv;
-        c_tri += cl.nt;
-      }
-      for (int v = lane; v < cl.nv; v += 64) {
-        const float4 o = m.cverts[cl.vfirst + v];
-        const float3 p = xform(P, o.x, o.y, o.z);
-        // hardware reciprocal (1 ulp): far inside the edge margin tau below
-        const float iz = __builtin_amdgcn_rcpf(p.z);
-        vb[v] = make_float4(cam.fx * p.x * iz + cam.cx, cam.fy * p.y * iz + cam.cy, p.z, iz);
-      }
-      // the wave's own writes must land before its lanes read them
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (lane < cl.nt) {
-        const uint2 tk = m.ctris[cl.tfirst + lane];
-        const float4 p0 = vb[tk.x & 255u], p1 = vb[(tk.x >> 8) & 255u], p2 = vb[(tk.x >> 16) & 255u];
-        const bool near = p0.z <= cam.znear || p1.z <= cam.znear || p2.z <= cam.znear;
-        const float e0x = p2.x - p1.x, e0y = p2.y - p1.y;
-        const float e1x = p0.x - p2.x, e1y = p0.y - p2.y;
-        const float e2x = p1.x - p0.x, e2y = p1.y - p0.y;
-        const float umin = fminf(p0.x, fminf(p1.x, p2.x)), umax = fmaxf(p0.x, fmaxf(p1.x, p2.x));
-        const float vmin = fminf(p0.y, fminf(p1.y, p2.y)), vmax = fmaxf(p0.y, fmaxf(p1.y, p2.y));
-        // rounding margin (pixels) for this triangle's projected positions
-        const float tau =
-            2e-6f * fmaxf(fmaxf(fmaxf(fabsf(umin), fabsf(umax)), fmaxf(fabsf(vmin), fabsf(vmax))), 256.0f);
-        const float area = e2x * (p2.y - p0.y) - (p2.x - p0.x) * e2y;
-        const float amb_area = 2.0f * tau * (fabsf(e1x) + fabsf(e1y) + fabsf(e2x) + fabsf(e2y));
-        const bool edge_on = area >= -amb_area;
+      if (lane < cl.np) {
+        const size_t pi = (size_t)cl.pfirst + lane;
+        const uint2 ids = m.pids[pi];
+        const bool quad = ids.y != kNoTri;
+        // corners as (u, v, z, 1/z); triangle 1 = (a, b, c), triangle 2 = (a, c, d)
+        const float4* pv = m.pverts + 4 * pi;
+        const float4 A = project_corner(P, cam, pv[0]), B = project_corner(P, cam, pv[1]);
+        const float4 C = project_corner(P, cam, pv[2]), D = project_corner(P, cam, pv[3]);
+        if (COUNT) {
+          c_vert += 4;
+          c_tri += quad ? 2 : 1;
+        }
+        const float zn = cam.znear;
+        const bool near1 = A.z <= zn || B.z <= zn || C.z <= zn;
+        const bool near2 = A.z <= zn || C.z <= zn || D.z <= zn;
+        // edges of triangle 1 (e_k opposite corner k) and of triangle 2 (f_k); the
+        // diagonal a-c is e1 (c -> a) for triangle 1 and -e1 for triangle 2
+        const float e0x = C.x - B.x, e0y = C.y - B.y;
+        const float e1x = A.x - C.x, e1y = A.y - C.y;
+        const float e2x = B.x - A.x, e2y = B.y - A.y;
+        const float f0x = D.x - C.x, f0y = D.y - C.y;
+        const float f1x = A.x - D.x, f1y = A.y - D.y;
+        // rounding margin (pixels) from the magnitudes of the corners in use
+        float mag = fmaxf(fmaxf(fabsf(A.x), fabsf(A.y)), fmaxf(fabsf(C.x), fabsf(C.y)));
+        const float area1 = e2x * (C.y - A.y) - (C.x - A.x) * e2y;
+        const float area2 = -e1x * (D.y - A.y) + (D.x - A.x) * e1y;
+        // preliminary activity (near plane) decides which corners set the margin
+        const bool use1 = !near1, use2 = quad && !near2;
+        mag = fmaxf(mag, use1 ? fmaxf(fabsf(B.x), fabsf(B.y)) : 0.0f);
+        mag = fmaxf(mag, use2 ? fmaxf(fabsf(D.x), fabsf(D.y)) : 0.0f);
+        const float tau = 2e-6f * fmaxf(mag, 256.0f);
+        const float amb1 = 2.0f * tau * (fabsf(e1x) + fabsf(e1y) + fabsf(e2x) + fabsf(e2y));
+        const float amb2 = 2.0f * tau * (fabsf(f1x) + fabsf(f1y) + fabsf(e1x) + fabsf(e1y));
+        // drawn unless behind the near plane or facing away
+        const bool act1 = use1 && !(area1 > amb1);
+        const bool act2 = use2 && !(area2 > amb2);
+        // box of the active triangles' corners (a and c belong to both)
+        const float bxu = act1 ? B.x : A.x, bxv = act1 ? B.y : A.y;
+        const float dxu = act2 ? D.x : A.x, dxv = act2 ? D.y : A.y;
+        const float umin = fminf(fminf(A.x, C.x), fminf(bxu, dxu)), umax = fmaxf(fmaxf(A.x, C.x), fmaxf(bxu, dxu));
+        const float vmin = fminf(fminf(A.y, C.y), fminf(bxv, dxv)), vmax = fmaxf(fmaxf(A.y, C.y), fmaxf(bxv, dxv));
         const float fc0 = ceilf(fmaxf(umin - 0.5f - tau, bx0)), fc1 = floorf(fminf(umax - 0.5f + tau, bx1));
         const float fr0 = ceilf(fmaxf(vmin - 0.5f - tau, by0)), fr1 = floorf(fminf(vmax - 0.5f + tau, by1));
-        // drawn unless behind the near plane, facing away, or with no centre in its box
-        if (!near && !(area > amb_area) && fc0 <= fc1 && fr0 <= fr1) {
+        if ((act1 || act2) && fc0 <= fc1 && fr0 <= fr1) {
           const int c0 = (int)fc0, c1 = (int)fc1, r0 = (int)fr0, r1 = (int)fr1;
-          const uint32_t id = id_base + tk.y;
-          if (COUNT) ++c_setup;
-          const float inv_area = __builtin_amdgcn_rcpf(area);
+          if (COUNT) c_setup += (act1 ? 1u : 0u) + (act2 ? 1u : 0u);
+          const bool eon1 = area1 >= -amb1, eon2 = area2 >= -amb2;
+          const float ia1 = __builtin_amdgcn_rcpf(area1), ia2 = __builtin_amdgcn_rcpf(area2);
           const float t0 = tau * (fabsf(e0x) + fabsf(e0y)), t1 = tau * (fabsf(e1x) + fabsf(e1y)),
                       t2 = tau * (fabsf(e2x) + fabsf(e2y));
+          const float s0 = tau * (fabsf(f0x) + fabsf(f0y)), s1 = tau * (fabsf(f1x) + fabsf(f1y));
+          // a centre of triangle k: queued for the exact test when within the
+          // margin of an edge (or the triangle is nearly edge-on), else written
+          auto emit = [&](int pix, bool eon, float x0, float x1, float x2, float m0, float m1, float m2, float i0,
+                          float i1, float i2, float ia, uint32_t tid) {
+            if (eon || x0 >= -m0 || x1 >= -m1 || x2 >= -m2) {
+              const int slot = atomicAdd(&lds.counts[0], 1);
+              if (slot < lds.qcap) {
+                lds.queue[slot] = make_uint2((uint32_t)pix, tid);
+                return;
+              }
+              if (eon || x0 > 0.0f || x1 > 0.0f || x2 > 0.0f) return;  // queue full: single precision
+            }
+            // 1/z is affine in screen space: interpolate with barycentrics x_k/area
+            const float z = __builtin_amdgcn_rcpf((x0 * i0 + x1 * i1 + x2 * i2) * ia);
+            if (!(z > 0.0f)) return;
+            if (COUNT) ++c_frag;
+            atomicMin(&zbuf[pix], pack_key(z, id_base + tid));
+          };
           // one flat walk over the box's centres: a wave then iterates max(rows x cols)
           // times over its lanes, not max(rows) x max(cols)
           const int n_cent = (c1 - c0 + 1) * (r1 - r0 + 1);
@@ -444,30 +479,20 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
               cn = c0;
               ++rn;
             }
-            {
-              const float py = (float)r + 0.5f;
-              const float px = (float)col + 0.5f;
-              // edge functions; each equals the (negative) area at the opposite vertex
-              const float w0 = e0x * (py - p1.y) - e0y * (px - p1.x);
-              const float w1 = e1x * (py - p2.y) - e1y * (px - p2.x);
-              const float w2 = e2x * (py - p0.y) - e2y * (px - p0.x);
-              if (w0 > t0 || w1 > t1 || w2 > t2) continue;  // clearly outside
-              const int pix = (r - buf.y0) * pitch + (col - buf.x0);
-              if (edge_on || w0 >= -t0 || w1 >= -t1 || w2 >= -t2) {
-                const int slot = atomicAdd(&lds.counts[0], 1);
-                if (slot < lds.qcap) {
-                  lds.queue[slot] = make_uint2((uint32_t)pix, tk.y);
-                  continue;
-                }
-                if (edge_on || w0 > 0.0f || w1 > 0.0f || w2 > 0.0f) continue;  // queue full: single precision
-              }
-              // 1/z is affine in screen space: interpolate with barycentrics w_k/area
-              const float invz = (w0 * p0.w + w1 * p1.w + w2 * p2.w) * inv_area;
-              const float z = __builtin_amdgcn_rcpf(invz);
-              if (!(z > 0.0f)) continue;
-              if (COUNT) ++c_frag;
-              atomicMin(&zbuf[pix], pack_key(z, id));
-            }
+            const float py = (float)r + 0.5f;
+            const float px = (float)col + 0.5f;
+            // edge functions; each equals the (negative) area at the opposite corner
+            const float w0 = e0x * (py - B.y) - e0y * (px - B.x);
+            const float w1 = e1x * (py - C.y) - e1y * (px - C.x);
+            const float w2 = e2x * (py - A.y) - e2y * (px - A.x);
+            const float v0 = f0x * (py - C.y) - f0y * (px - C.x);
+            const float v1 = f1x * (py - D.y) - f1y * (px - D.x);
+            const bool out1 = !act1 || w0 > t0 || w1 > t1 || w2 > t2;
+            const bool out2 = !act2 || v0 > s0 || v1 > s1 || -w1 > t1;
+            if (out1 && out2) continue;  // clearly outside both
+            const int pix = (r - buf.y0) * pitch + (col - buf.x0);
+            if (!out1) emit(pix, eon1, w0, w1, w2, t0, t1, t2, A.w, B.w, C.w, ia1, ids.x);
+            if (!out2) emit(pix, eon2, v0, v1, -w1, s0, s1, t1, A.w, C.w, D.w, ia2, ids.y);
           }
         }
       }

@@ -1,9 +1,13 @@
 // Host-side device layout of a triangle mesh for the rasteriser.
 //
 // The rasteriser walks a mesh cluster by cluster: each cluster holds up to
-// kClusterTris triangles of one orientation class that are close in space,
-// with its own copy of the (deduplicated) vertices they use, a bounding
-// sphere and a cone bounding its face normals.  Per hypothesis a cluster is
+// kClusterPrims primitives of one orientation class that are close in space,
+// a bounding sphere and a cone bounding its face normals.  A primitive is one
+// triangle or a quad: two triangles (a, b, c) and (a, c, d) that share the
+// edge a-c with opposite directions (consistent winding), lie in one plane
+// and form a convex quadrilateral -- the two halves of a voxel face.  One lane
+// walks the quad's pixel box once for both triangles; each triangle is still
+// tested against its own three edges, and keeps its own id.  Per hypothesis a cluster is
 // skipped as a whole when its cone and sphere show that every triangle in it
 // faces away from the camera, or when its sphere misses the pixels being
 // drawn.  Two sets of triangles that can never be the nearest surface for a
@@ -224,61 +228,127 @@ MeshLayout build_mesh_layout(const float* verts, int V, const int* tris, int T) 
     const uint64_t morton = spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2);
     order_key[t] = ((uint64_t)best << 32) | morton;
   }
-  // 5. clusters: drawn triangles first, then hidden pairs
-  auto emit = [&](std::vector<int>& ids) {
-    std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return order_key[a] < order_key[b]; });
+  // 5. primitives: pair triangles into convex planar quads (within the drawn
+  //    set and within the hidden set), the rest stay single
+  auto pos = [&](int p, int k) { return (double)verts[3 * pos_first[p] + k]; };
+  std::unordered_map<uint64_t, std::vector<int>> by_edge;  // directed position edge -> triangles
+  for (int t = 0; t < T; ++t) {
+    if (cls[t] == 2) continue;
+    for (int k = 0; k < 3; ++k) {
+      const uint32_t i = (uint32_t)pid[tris[3 * t + k]], j = (uint32_t)pid[tris[3 * t + (k + 1) % 3]];
+      by_edge[((uint64_t)i << 32) | j].push_back(t);
+    }
+  }
+  struct Prim {
+    int p[4];       // position ids a, b, c, d (d = c for a single triangle)
+    int id1, id2;   // caller's triangle ids (id2 = -1: single)
+    uint64_t key;
+  };
+  std::vector<int> mate((size_t)T, -1);
+  std::vector<Prim> prims[2];  // 0 drawn, 1 hidden
+  auto convex_quad = [&](int a, int b, int c, int d, const double* n) {
+    // planar convex iff b and d lie on opposite sides of a-c and a and c on opposite sides of b-d
+    auto side = [&](int o, int e, int q) {
+      const double u[3] = {pos(e, 0) - pos(o, 0), pos(e, 1) - pos(o, 1), pos(e, 2) - pos(o, 2)};
+      const double w[3] = {pos(q, 0) - pos(o, 0), pos(q, 1) - pos(o, 1), pos(q, 2) - pos(o, 2)};
+      const double x[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+      return x[0] * n[0] + x[1] * n[1] + x[2] * n[2];
+    };
+    return side(a, c, b) * side(a, c, d) < 0.0 && side(b, d, a) * side(b, d, c) < 0.0;
+  };
+  for (int t = 0; t < T; ++t) {
+    if (cls[t] == 2 || mate[t] >= 0) continue;
+    const int pt[3] = {pid[tris[3 * t]], pid[tris[3 * t + 1]], pid[tris[3 * t + 2]]};
+    int found = -1, fk = 0;
+    // longest edge first: a voxel face's two halves share its diagonal
+    int ord[3] = {0, 1, 2};
+    double len2[3];
+    for (int k = 0; k < 3; ++k) {
+      len2[k] = 0.0;
+      for (int a2 = 0; a2 < 3; ++a2) {
+        const double d = pos(pt[(k + 1) % 3], a2) - pos(pt[k], a2);
+        len2[k] += d * d;
+      }
+    }
+    std::stable_sort(ord, ord + 3, [&](int x, int y) { return len2[x] > len2[y]; });
+    for (int oi = 0; oi < 3 && found < 0; ++oi) {
+      const int k = ord[oi];
+      // the partner holds the edge p_{k+1} -> p_k
+      const uint64_t rev = ((uint64_t)(uint32_t)pt[(k + 1) % 3] << 32) | (uint32_t)pt[k];
+      auto it = by_edge.find(rev);
+      if (it == by_edge.end()) continue;
+      for (int u : it->second) {
+        if (u == t || mate[u] >= 0 || cls[u] != cls[t] || (order_key[u] >> 32) != (order_key[t] >> 32)) continue;
+        const double dn = unit[3 * t] * unit[3 * u] + unit[3 * t + 1] * unit[3 * u + 1] + unit[3 * t + 2] * unit[3 * u + 2];
+        if (!(dn > 1.0 - 1e-9)) continue;
+        int far = -1;
+        for (int m2 = 0; m2 < 3; ++m2) {
+          const int q = pid[tris[3 * u + m2]];
+          if (q != pt[k] && q != pt[(k + 1) % 3]) far = q;
+        }
+        // t = (a, b, c) with the shared edge c -> a: a = p_{k+1}, b = p_{k+2}, c = p_k
+        const int qa = pt[(k + 1) % 3], qb = pt[(k + 2) % 3], qc = pt[k];
+        if (far < 0 || !convex_quad(qa, qb, qc, far, &unit[3 * t])) continue;
+        found = u;
+        fk = k;
+        break;
+      }
+    }
+    Prim pr;
+    if (found >= 0) {
+      mate[t] = found;
+      mate[found] = t;
+      pr.p[0] = pt[(fk + 1) % 3];
+      pr.p[1] = pt[(fk + 2) % 3];
+      pr.p[2] = pt[fk];
+      for (int m2 = 0; m2 < 3; ++m2) {
+        const int q = pid[tris[3 * found + m2]];
+        if (q != pr.p[0] && q != pr.p[2]) pr.p[3] = q;
+      }
+      pr.id1 = t;
+      pr.id2 = found;
+      ++L.n_quads;
+    } else {
+      pr.p[0] = pt[0];
+      pr.p[1] = pt[1];
+      pr.p[2] = pt[2];
+      pr.p[3] = pt[2];
+      pr.id1 = t;
+      pr.id2 = -1;
+    }
+    pr.key = order_key[t];
+    prims[cls[t]].push_back(pr);
+  }
+  // 6. clusters: drawn primitives first, then hidden ones
+  auto emit = [&](std::vector<Prim>& ps) {
+    std::stable_sort(ps.begin(), ps.end(), [](const Prim& x, const Prim& y) { return x.key < y.key; });
     size_t i = 0;
-    std::vector<int> stamp_local;
-    std::unordered_map<int, int> local;
-    while (i < ids.size()) {
+    while (i < ps.size()) {
       ClusterDev c{};
-      c.vfirst = (int)L.cverts.size();
-      c.tfirst = (int)L.ctris.size();
-      local.clear();
-      const uint64_t cls_dir = order_key[ids[i]] >> 32;
+      c.pfirst = (int)L.pids.size();
+      const uint64_t cls_dir = ps[i].key >> 32;
       double axis[3] = {0, 0, 0};
       double blo[3] = {1e300, 1e300, 1e300}, bhi[3] = {-1e300, -1e300, -1e300};
       size_t j = i;
-      for (; j < ids.size(); ++j) {
-        const int t = ids[j];
-        if ((order_key[t] >> 32) != cls_dir || c.nt == kClusterTris) break;
-        int fresh = 0;
-        for (int k = 0; k < 3; ++k) {
-          const int p = pid[tris[3 * t + k]];
-          bool seen = local.count(p) > 0;
-          for (int m = 0; m < k; ++m) seen = seen || pid[tris[3 * t + m]] == p;
-          fresh += seen ? 0 : 1;
-        }
-        if (c.nv + fresh > kClusterVerts) break;
-        uint32_t packed = 0;
-        for (int k = 0; k < 3; ++k) {
-          const int p = pid[tris[3 * t + k]];
-          auto it = local.find(p);
-          int li;
-          if (it == local.end()) {
-            li = c.nv++;
-            local.emplace(p, li);
-            const float* pv = verts + 3 * pos_first[p];
-            L.cverts.push_back(make_float4(pv[0], pv[1], pv[2], 0.0f));
-            for (int a = 0; a < 3; ++a) {
-              blo[a] = std::min(blo[a], (double)pv[a]);
-              bhi[a] = std::max(bhi[a], (double)pv[a]);
-            }
-          } else {
-            li = it->second;
+      for (; j < ps.size() && c.np < kClusterPrims && (ps[j].key >> 32) == cls_dir; ++j) {
+        const Prim& pr = ps[j];
+        for (int k = 0; k < 4; ++k) {
+          L.pverts.push_back(make_float4((float)pos(pr.p[k], 0), (float)pos(pr.p[k], 1), (float)pos(pr.p[k], 2), 0.0f));
+          for (int a2 = 0; a2 < 3; ++a2) {
+            blo[a2] = std::min(blo[a2], pos(pr.p[k], a2));
+            bhi[a2] = std::max(bhi[a2], pos(pr.p[k], a2));
           }
-          packed |= (uint32_t)li << (8 * k);
         }
-        L.ctris.push_back(make_uint2(packed, (uint32_t)t));
-        for (int a = 0; a < 3; ++a) axis[a] += unit[3 * t + a];
-        ++c.nt;
+        L.pids.push_back(make_uint2((uint32_t)pr.id1, pr.id2 < 0 ? kNoTri : (uint32_t)pr.id2));
+        for (int a2 = 0; a2 < 3; ++a2) axis[a2] += unit[3 * pr.id1 + a2] + (pr.id2 >= 0 ? unit[3 * pr.id2 + a2] : 0.0);
+        ++c.np;
       }
       double ctr[3], rad = 0.0;
-      for (int a = 0; a < 3; ++a) ctr[a] = 0.5 * (blo[a] + bhi[a]);
-      for (int v = 0; v < c.nv; ++v) {
-        const float4 p = L.cverts[(size_t)c.vfirst + v];
-        const double d2 = (p.x - ctr[0]) * (p.x - ctr[0]) + (p.y - ctr[1]) * (p.y - ctr[1]) +
-                          (p.z - ctr[2]) * (p.z - ctr[2]);
+      for (int a2 = 0; a2 < 3; ++a2) ctr[a2] = 0.5 * (blo[a2] + bhi[a2]);
+      for (int v = 0; v < 4 * c.np; ++v) {
+        const float4 q = L.pverts[4 * (size_t)c.pfirst + v];
+        const double d2 = (q.x - ctr[0]) * (q.x - ctr[0]) + (q.y - ctr[1]) * (q.y - ctr[1]) +
+                          (q.z - ctr[2]) * (q.z - ctr[2]);
         rad = std::max(rad, std::sqrt(d2));
       }
       c.sphere = make_float4((float)ctr[0], (float)ctr[1], (float)ctr[2], (float)(rad * (1.0 + 1e-5) + 1e-6));
@@ -286,10 +356,13 @@ MeshLayout build_mesh_layout(const float* verts, int V, const int* tris, int T) 
       double cos_a = 1.0;
       bool ok = al > 0;
       for (size_t k = i; k < j && ok; ++k) {
-        const int t = ids[k];
-        const double d = (unit[3 * t] * axis[0] + unit[3 * t + 1] * axis[1] + unit[3 * t + 2] * axis[2]) / al;
-        if (unit[3 * t] == 0 && unit[3 * t + 1] == 0 && unit[3 * t + 2] == 0) ok = false;
-        cos_a = std::min(cos_a, d);
+        for (int h2 = 0; h2 < 2; ++h2) {
+          const int t = h2 == 0 ? ps[k].id1 : ps[k].id2;
+          if (t < 0) continue;
+          if (unit[3 * t] == 0 && unit[3 * t + 1] == 0 && unit[3 * t + 2] == 0) ok = false;
+          const double d = (unit[3 * t] * axis[0] + unit[3 * t + 1] * axis[1] + unit[3 * t + 2] * axis[2]) / al;
+          cos_a = std::min(cos_a, d);
+        }
       }
       // half-angle of the normal cone, widened slightly; > pi/2 disables culling
       const double alpha = ok ? std::acos(std::max(-1.0, std::min(1.0, cos_a))) + 1e-4 : 4.0;
@@ -299,16 +372,13 @@ MeshLayout build_mesh_layout(const float* verts, int V, const int* tris, int T) 
       i = j;
     }
   };
-  std::vector<int> drawn, hidden;
-  for (int t = 0; t < T; ++t) {
-    if (cls[t] == 0) drawn.push_back(t);
-    if (cls[t] == 1) hidden.push_back(t);
-  }
-  emit(drawn);
+  emit(prims[0]);
   L.n_visible = (int)L.clusters.size();
-  emit(hidden);
-  L.n_drawn = (int)drawn.size();
-  L.n_hidden = (int)hidden.size();
+  emit(prims[1]);
+  for (int t = 0; t < T; ++t) {
+    if (cls[t] == 0) ++L.n_drawn;
+    if (cls[t] == 1) ++L.n_hidden;
+  }
   L.n_dropped = T - L.n_drawn - L.n_hidden;
   return L;
 }

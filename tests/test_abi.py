@@ -77,6 +77,8 @@ def test_mesh_layout_sets_aside_only_faces_no_outside_camera_sees(lib):
     v, t = voxel_mesh(np.array([[0.0, 0.0, 0.0], [0.01, 0.0, 0.0]]))
     info = b.mesh_layout_info(v, t)
     assert info["hidden_pairs"] == 4 and info["drawn"] == 20 and info["dropped"] == 0
+    # every face's two halves are paired into a quad: 10 drawn faces, 2 set-aside faces
+    assert info["quads"] == 12
     # a two-sided sheet is one component: both sides stay drawn
     v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], float)
     assert b.mesh_layout_info(v, np.array([[0, 1, 2], [0, 2, 1]]))["hidden_pairs"] == 0
@@ -93,3 +95,6 @@ def test_mesh_layout_sets_aside_only_faces_no_outside_camera_sees(lib):
     occ = {tuple(c) for c in cells}
     shared = sum((tuple(c + d) in occ) for c in cells for d in np.vstack([np.eye(3, dtype=int), -np.eye(3, dtype=int)]))
     assert info["hidden_pairs"] == 2 * shared  # two triangles per touching face, counted from both voxels
+    # all voxel faces pair into quads; at most 64 primitives per cluster
+    assert info["quads"] * 2 == info["drawn"] + info["hidden_pairs"]
+    assert info["clusters"] >= (info["quads"] + 63) // 64
