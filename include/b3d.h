@@ -160,7 +160,11 @@ typedef struct b3d_scene b3d_scene;
 /* A scene: the moving object's mesh, the camera, the likelihood parameters,
  * an optional static background (other objects at fixed poses) and the
  * observed point image.  The scene keeps `mesh` by reference (it must
- * outlive the scene).  Allocates device memory (not stream-ordered). */
+ * outlive the scene).  Allocates device memory (not stream-ordered).
+ * The fused kernel holds at least two image rows (plus 2h pixels each side)
+ * of depth keys in LDS, which limits W to about 480 pixels with a 5x5 window
+ * (B3D_ESHAPE beyond); rays must stay within |x/z|, |y/z| <= 1e3 over the
+ * image and 2h pixels beyond it. */
 b3d_status b3d_scene_create(const b3d_mesh* mesh, const b3d_intrinsics* K, const b3d_score_params* p,
                             b3d_scene** out);
 b3d_status b3d_scene_destroy(b3d_scene* scene);

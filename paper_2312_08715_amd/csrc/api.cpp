@@ -110,7 +110,7 @@ int default_zcap(const SceneDev& d, int blocks_per_cu) {
   t.zcap = 0;
   const size_t share = (160 * 1024) / (size_t)blocks_per_cu;
   const size_t rest = fused_lds_bytes(t);
-  return (int)((share > rest ? share - rest : 0) / sizeof(unsigned long long));
+  return (int)((share > rest ? share - rest : 0) / kFusedBytesPerKey);
 }
 
 // two rows of the widest depth buffer (image width plus 2h each side)
@@ -120,7 +120,7 @@ int max_zcap(const SceneDev& d) {
   SceneDev t = d;
   t.zcap = 0;
   const size_t rest = fused_lds_bytes(t);
-  return (int)((kLdsMax > rest ? kLdsMax - rest : 0) / sizeof(unsigned long long));
+  return (int)((kLdsMax > rest ? kLdsMax - rest : 0) / kFusedBytesPerKey);
 }
 
 }  // namespace

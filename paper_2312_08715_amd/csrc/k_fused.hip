@@ -31,10 +31,45 @@ __device__ __forceinline__ double rect_sum(const double* sat, int W, const Rect&
 
 // LDS: rasteriser scratch (reused for the window weights once the depth
 // buffer is complete) | depth keys [zcap] | reduction [64] | ray tables of
-// columns [-2h, W + 2h) and rows [-2h, H + 2h).
+// columns [-2h, W + 2h) and rows [-2h, H + 2h) | drawn-pixel list [zcap].
 size_t fused_lds_bytes(const SceneDev& s) {
-  return kRasterLdsBytes + sizeof(unsigned long long) * (size_t)s.zcap +
-         sizeof(float) * (64 + s.cam.W + s.cam.H + 8 * s.sc.h);
+  return kRasterLdsBytes + sizeof(float) * (64 + s.cam.W + s.cam.H + 8 * s.sc.h) + kFusedBytesPerKey * (size_t)s.zcap;
+}
+
+// Row-major list of the buffer slots (offsets < nk) that hold a surface of the
+// mesh (triangle id < T); returns its length.  Whole block; `wcnt` holds
+// kWaves ints of LDS.
+__device__ __forceinline__ int list_drawn(const unsigned long long* __restrict__ zbuf, int nk, uint32_t T,
+                                          unsigned short* __restrict__ list, int* wcnt) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int total = 0;
+  for (int base = 0; base < nk; base += kBlock) {
+    const int k = base + (int)threadIdx.x;
+    const bool d = k < nk && key_id(zbuf[k]) < T;
+    const unsigned long long m = __ballot(d);
+    if (lane == 0) wcnt[wave] = __popcll(m);
+    __syncthreads();
+    int off = total, sum = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      off += w < wave ? wcnt[w] : 0;
+      sum += wcnt[w];
+    }
+    if (d) list[off + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned short)k;
+    total += sum;
+    __syncthreads();
+  }
+  return total;
+}
+
+// First index of the sorted list [0, n) whose value is >= v.
+__device__ __forceinline__ int lower_bound_u16(const unsigned short* list, int n, int v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if ((int)list[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
 }
 
 // Window sums for observed point (ox, oy, oz) at pixel (r, c) over the LDS
@@ -127,7 +162,7 @@ __device__ __forceinline__ float window_grad(const float* __restrict__ wbuf, int
         const float* q = orow + 3 * cc[k];
         const float ex = q[0] - qx, ey = q[1] - qy, ez = q[2] - qz;
         const float e = f_exp2(-(ex * ex + ey * ey + ez * ez) * c2);
-        g += wv * e * (ex * dx + ey * dy + ez);
+        g += wv * e * __builtin_fmaf(ex, dx, __builtin_fmaf(ey, dy, ez));
       }
     }
   } else {
@@ -141,7 +176,7 @@ __device__ __forceinline__ float window_grad(const float* __restrict__ wbuf, int
         const float* q = obs + 3 * ((size_t)ri * W + ci);
         const float ex = q[0] - qx, ey = q[1] - qy, ez = q[2] - qz;
         const float e = f_exp2(-(ex * ex + ey * ey + ez * ez) * c2);
-        g += wv * e * (ex * dx + ey * dy + ez);
+        g += wv * e * __builtin_fmaf(ex, dx, __builtin_fmaf(ey, dy, ez));
       }
     }
   }
@@ -172,6 +207,7 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
   // ray tables indexed by column in [-2h, W + 2h) and row in [-2h, H + 2h)
   float* dxt = red + 64 + 2 * h;
   float* dyt = dxt + W + 4 * h;
+  unsigned short* dlist = reinterpret_cast<unsigned short*>(red + 64 + W + H + 8 * h);
   const Pose P = load_pose(pose16);
   for (int i = (int)threadIdx.x - 2 * h; i < W + 2 * h; i += kBlock) dxt[i] = ray_x(cam, i);
   for (int i = (int)threadIdx.x - 2 * h; i < H + 2 * h; i += kBlock) dyt[i] = ray_y(cam, i);
@@ -190,6 +226,7 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
     int band = s.zcap / lw - 4 * h;
     if (GRAD) band = min(band, s.wcap / rw - 2 * h);
     band = max(band, 1);
+    int gcarry = 0;  // drawn pixels of earlier bands' own rows
     for (int a = region.y0; a < region.y1; a += band) {
       const int b = min(a + band, region.y1);
       Rect L = lds;
@@ -204,7 +241,15 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
       }
       __syncthreads();
       raster_mesh<COUNT>(s.mesh, P, cam, 0u, D, L, zbuf, rl, cnt);
-      refine_depths(s.mesh, P, cam, 0u, L, zbuf);
+      // the slots this mesh drew, then their depths on the triangles' planes
+      const int nd = list_drawn(zbuf, nk, (uint32_t)s.mesh.T, dlist, reinterpret_cast<int*>(red));
+      for (int k = threadIdx.x; k < nd; k += kBlock) {
+        const int off = dlist[k];
+        const unsigned long long key = zbuf[off];
+        const int r = L.y0 + off / lw, c = L.x0 + (off - (off / lw) * lw);
+        zbuf[off] = pack_key(plane_depth(s.mesh, P, cam, key_id(key), r, c), key_id(key));
+      }
+      __syncthreads();
 
       // likelihood over observed rows [wa, wb); rows [a, b) are this band's own
       const int wa = GRAD ? max(a - h, region.y0) : a;
@@ -250,16 +295,15 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
 
       if (GRAD) {
         __syncthreads();
-        // object pixels of this band gather d logL / d z_j over their window
-        const int ga = max(a, obj.y0), gb = min(b, obj.y1);
-        const int ow = obj.w();
-        const int ng = max(gb - ga, 0) * ow;
-        for (int k = first_of(threadIdx.x, (ga - obj.y0) * ow); k < ng; k += kBlock) {
-          const int r = ga + k / ow, c = obj.x0 + (k - (k / ow) * ow);
-          const unsigned long long key = zbuf[(r - L.y0) * lw + (c - L.x0)];
-          if (key == kEmptyKey) continue;
+        // the drawn pixels of this band's own rows gather d logL / d z_j over
+        // their window; the i-th of them over all bands (row-major) goes to
+        // thread i mod kBlock, so each thread's order does not depend on banding
+        const int ls = lower_bound_u16(dlist, nd, (a - L.y0) * lw), le = lower_bound_u16(dlist, nd, (b - L.y0) * lw);
+        for (int k = ls + first_of(threadIdx.x, gcarry); k < le; k += kBlock) {
+          const int off = dlist[k];
+          const unsigned long long key = zbuf[off];
           const uint32_t id = key_id(key);
-          if (id >= (uint32_t)s.mesh.T) continue;  // a background surface
+          const int r = L.y0 + off / lw, c = L.x0 + (off - (off / lw) * lw);
           if (COUNT) ++c_adj;
           const float z = key_depth(key);
           const float dx = dxt[c], dy = dyt[r];
@@ -278,7 +322,7 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
           g *= sc.inv_s2;
           const float4 no = s.mesh.normals[id];
           const float3 nn = rotate(P, no.x, no.y, no.z);
-          const float sg = g / (nn.x * dx + nn.y * dy + nn.z);
+          const float sg = g * __builtin_amdgcn_rcpf(nn.x * dx + nn.y * dy + nn.z);
           const float tx = P.t[0] - qx, ty = P.t[1] - qy, tz = P.t[2] - qz;
           acc[1] += sg * nn.x;
           acc[2] += sg * nn.y;
@@ -287,6 +331,7 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
           acc[5] += sg * (nn.z * tx - nn.x * tz);
           acc[6] += sg * (nn.x * ty - nn.y * tx);
         }
+        gcarry += le - ls;
       }
       __syncthreads();
     }
