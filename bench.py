@@ -226,7 +226,12 @@ def bench_tracking(b3d, torch, p, n_frames=200):
     E = est.cpu().numpy().astype(np.float64)
     pos = np.linalg.norm(E[1:, :, :3, 3] - paths[1:, :, :3, 3], axis=2) * 100.0
     rot = np.array([[rot_err_deg(E[f, k, :3, :3], paths[f, k, :3, :3]) for k in range(M)] for f in range(1, n_frames)])
-    return {"frames_per_s": (n_frames - 2) / dt, "frames": n_frames, "objects": M,
+    lost = pos > 5.0
+    per_obj = [{"mean_cm": float(pos[:, k].mean()), "max_cm": float(pos[:, k].max()),
+                "frames_over_5cm": int(lost[:, k].sum()),
+                "first_over_5cm": int(np.argmax(lost[:, k]) + 1) if lost[:, k].any() else None}
+               for k in range(M)]
+    return {"frames_per_s": (n_frames - 2) / dt, "frames": n_frames, "objects": M, "per_object": per_obj,
             "hypotheses_per_frame": int(M * 12500), "position_error_cm": {"mean": float(pos.mean()),
                                                                            "max": float(pos.max())},
             "orientation_error_deg": {"mean": float(rot.mean()), "max": float(rot.max())}}

@@ -486,6 +486,11 @@ def test_edge_cases(b3d):
         Ln = b3d.render_score(scene, dev(Pn)).cpu().numpy()
         L0 = b3d.render_score(scene, dev(P)).cpu().numpy()
         assert np.array_equal(Ln, L0[np.arange(n) % P.shape[0]])
+    # the fused kernel's limits: a very wide image, or rays beyond |x/z| = 1e3, are refused
+    with pytest.raises(b3d.B3DError):
+        b3d.Scene(mesh, b3d.Intrinsics(600.0, 600.0, 1024.0, 60.0, 0.01, 120, 2048), b3d.score_params(0.003, 0.01, 1.0, 5))
+    with pytest.raises(b3d.B3DError):
+        b3d.Scene(mesh, b3d.Intrinsics(0.05, 0.05, 80.0, 60.0, 0.01, 120, 160), b3d.score_params(0.003, 0.01, 1.0, 5))
     # invalid arguments are rejected before any launch
     with pytest.raises(b3d.B3DError):
         b3d.score(o, xyz, b3d.score_params(wl.score.sigma, 0.0, 1.0, 3))
