@@ -120,7 +120,8 @@ int max_zcap(const SceneDev& d) {
   SceneDev t = d;
   t.zcap = 0;
   const size_t rest = fused_lds_bytes(t);
-  return (int)((kLdsMax > rest ? kLdsMax - rest : 0) / kFusedBytesPerKey);
+  // also bounded by the drawn-slot list, which lives in the raster scratch
+  return (int)std::min<size_t>((kLdsMax > rest ? kLdsMax - rest : 0) / kFusedBytesPerKey, kRasterLdsBytes / 2);
 }
 
 }  // namespace
@@ -385,7 +386,9 @@ b3d_status b3d_scene_create(const b3d_mesh* mesh, const b3d_intrinsics* K, const
   S->dev.wcap = (int)(kRasterLdsBytes / sizeof(float));
   // depth keys: as many as leave room for four workgroups per CU (160 KB of LDS)
   S->dev.zcap = std::max(default_zcap(S->dev, 4), min_zcap(S->dev));
-  if ((2 * h + 1) * W > S->dev.wcap || fused_lds_bytes(S->dev) > kLdsMax) {
+  // one band row of window weights must leave a round of the drawn-pixel list
+  if ((2 * h + 1) * W > S->dev.wcap || 4 * (size_t)(2 * h + 1) * W + 2 * kBlock > kRasterLdsBytes ||
+      S->dev.zcap > max_zcap(S->dev) || fused_lds_bytes(S->dev) > kLdsMax) {
     delete S;
     return fail(B3D_ESHAPE, "scene_create: image width %d too large for the fused kernel's LDS budget", W);
   }
@@ -611,7 +614,7 @@ b3d_status b3d_scene_set_tile(b3d_scene* S, int32_t zcap) {
   if (!S) return fail(B3D_EINVAL, "scene_set_tile: NULL scene");
   SceneDev t = S->dev;
   t.zcap = zcap <= 0 ? std::max(default_zcap(S->dev, 4), min_zcap(S->dev)) : zcap;
-  if (t.zcap < min_zcap(S->dev) || fused_lds_bytes(t) > kLdsMax)
+  if (t.zcap < min_zcap(S->dev) || t.zcap > max_zcap(S->dev) || fused_lds_bytes(t) > kLdsMax)
     return fail(B3D_ESHAPE, "scene_set_tile: %d keys outside [%d, LDS limit]", zcap, min_zcap(S->dev));
   S->dev.zcap = t.zcap;
   return B3D_OK;

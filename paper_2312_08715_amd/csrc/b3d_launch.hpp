@@ -56,9 +56,8 @@ struct GridDev {
   const float* rots;  // device [n_rot][9] or nullptr (generated)
 };
 
-// LDS bytes of the fused kernel: fixed part + kFusedBytesPerKey per depth key
-// (the 8-byte key and a 2-byte entry of the drawn-pixel list).
-constexpr size_t kFusedBytesPerKey = 10;
+// LDS bytes of the fused kernel: fixed part + kFusedBytesPerKey per depth key.
+constexpr size_t kFusedBytesPerKey = 8;
 size_t fused_lds_bytes(const SceneDev& s);
 
 hipError_t launch_render_batch(const MeshDev& m, const Cam& cam, const float* poses, int N, float* xyz, int* tri,

@@ -29,47 +29,42 @@ __device__ __forceinline__ double rect_sum(const double* sat, int W, const Rect&
          sat[(size_t)r.y0 * p + r.x0];
 }
 
-// LDS: rasteriser scratch (reused for the window weights once the depth
-// buffer is complete) | depth keys [zcap] | reduction [64] | ray tables of
-// columns [-2h, W + 2h) and rows [-2h, H + 2h) | drawn-pixel list [zcap].
+// LDS: rasteriser scratch (once the depth buffer is complete: the window
+// weights, then the drawn-pixel list) | depth keys [zcap] | reduction [64] |
+// ray tables of columns [-2h, W + 2h) and rows [-2h, H + 2h).
 size_t fused_lds_bytes(const SceneDev& s) {
   return kRasterLdsBytes + sizeof(float) * (64 + s.cam.W + s.cam.H + 8 * s.sc.h) + kFusedBytesPerKey * (size_t)s.zcap;
 }
 
-// Row-major list of the buffer slots (offsets < nk) that hold a surface of the
-// mesh (triangle id < T); returns its length.  Whole block; `wcnt` holds
-// kWaves ints of LDS.
-__device__ __forceinline__ int list_drawn(const unsigned long long* __restrict__ zbuf, int nk, uint32_t T,
-                                          unsigned short* __restrict__ list, int* wcnt) {
+// One round of block-wide stream compaction: the threads whose flag is set
+// append their value to list[n ...] in thread order; returns how many did.
+// Whole block; `wcnt` holds kWaves ints of LDS.
+__device__ __forceinline__ int append_flagged(bool flag, int value, unsigned short* __restrict__ list, int n,
+                                              int* wcnt) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int total = 0;
-  for (int base = 0; base < nk; base += kBlock) {
-    const int k = base + (int)threadIdx.x;
-    const bool d = k < nk && key_id(zbuf[k]) < T;
-    const unsigned long long m = __ballot(d);
-    if (lane == 0) wcnt[wave] = __popcll(m);
-    __syncthreads();
-    int off = total, sum = 0;
-    for (int w = 0; w < kWaves; ++w) {
-      off += w < wave ? wcnt[w] : 0;
-      sum += wcnt[w];
-    }
-    if (d) list[off + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned short)k;
-    total += sum;
-    __syncthreads();
+  const unsigned long long m = __ballot(flag);
+  if (lane == 0) wcnt[wave] = __popcll(m);
+  __syncthreads();
+  int off = n, sum = 0;
+  for (int w = 0; w < kWaves; ++w) {
+    off += w < wave ? wcnt[w] : 0;
+    sum += wcnt[w];
   }
-  return total;
+  if (flag) list[off + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned short)value;
+  __syncthreads();
+  return sum;
 }
 
-// First index of the sorted list [0, n) whose value is >= v.
-__device__ __forceinline__ int lower_bound_u16(const unsigned short* list, int n, int v) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if ((int)list[mid] < v) lo = mid + 1;
-    else hi = mid;
+// Row-major list of the buffer slots [k0, k1) that hold a surface of the mesh
+// (triangle id < T); returns its length.  Whole block.
+__device__ __forceinline__ int list_drawn(const unsigned long long* __restrict__ zbuf, int k0, int k1, uint32_t T,
+                                          unsigned short* __restrict__ list, int* wcnt) {
+  int n = 0;
+  for (int base = k0; base < k1; base += kBlock) {
+    const int k = base + (int)threadIdx.x;
+    n += append_flagged(k < k1 && key_id(zbuf[k]) < T, k, list, n, wcnt);
   }
-  return lo;
+  return n;
 }
 
 // Window sums for observed point (ox, oy, oz) at pixel (r, c) over the LDS
@@ -207,7 +202,6 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
   // ray tables indexed by column in [-2h, W + 2h) and row in [-2h, H + 2h)
   float* dxt = red + 64 + 2 * h;
   float* dyt = dxt + W + 4 * h;
-  unsigned short* dlist = reinterpret_cast<unsigned short*>(red + 64 + W + H + 8 * h);
   const Pose P = load_pose(pose16);
   for (int i = (int)threadIdx.x - 2 * h; i < W + 2 * h; i += kBlock) dxt[i] = ray_x(cam, i);
   for (int i = (int)threadIdx.x - 2 * h; i < H + 2 * h; i += kBlock) dyt[i] = ray_y(cam, i);
@@ -223,8 +217,11 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
     // edges if need be (those slots stay empty), so every window is inside it
     const Rect lds = grow(obj, 2 * h);
     const int lw = lds.w(), rw = region.w();
+    const int ow = obj.w();
     int band = s.zcap / lw - 4 * h;
-    if (GRAD) band = min(band, s.wcap / rw - 2 * h);
+    // the window weights ((band + 2h) x rw floats) leave at least one round
+    // (kBlock entries) of the drawn-pixel list in the scratch
+    if (GRAD) band = min(band, min(s.wcap, (int)(kRasterLdsBytes - 2 * kBlock) / 4) / rw - 2 * h);
     band = max(band, 1);
     int gcarry = 0;  // drawn pixels of earlier bands' own rows
     for (int a = region.y0; a < region.y1; a += band) {
@@ -240,21 +237,25 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
         zbuf[k] = (in && s.bg) ? s.bg[(size_t)r * W + c] : kEmptyKey;
       }
       __syncthreads();
-      raster_mesh<COUNT>(s.mesh, P, cam, 0u, D, L, zbuf, rl, cnt);
-      // the slots this mesh drew, then their depths on the triangles' planes
-      const int nd = list_drawn(zbuf, nk, (uint32_t)s.mesh.T, dlist, reinterpret_cast<int*>(red));
-      for (int k = threadIdx.x; k < nd; k += kBlock) {
-        const int off = dlist[k];
-        const unsigned long long key = zbuf[off];
-        const int r = L.y0 + off / lw, c = L.x0 + (off - (off / lw) * lw);
-        zbuf[off] = pack_key(plane_depth(s.mesh, P, cam, key_id(key), r, c), key_id(key));
-      }
-      __syncthreads();
-
       // likelihood over observed rows [wa, wb); rows [a, b) are this band's own
       const int wa = GRAD ? max(a - h, region.y0) : a;
       const int wb = GRAD ? min(b + h, region.y1) : b;
       const int nw = (wb - wa) * rw;
+      raster_mesh<COUNT>(s.mesh, P, cam, 0u, D, L, zbuf, rl, cnt);
+      {
+        // the slots this mesh drew (listed in the free scratch, which holds more
+        // entries than the buffer has slots), then their depths on the planes
+        unsigned short* rlist = reinterpret_cast<unsigned short*>(smem);
+        const int nr = list_drawn(zbuf, 0, nk, (uint32_t)s.mesh.T, rlist, reinterpret_cast<int*>(red));
+        for (int k = threadIdx.x; k < nr; k += kBlock) {
+          const int off = rlist[k];
+          const unsigned long long key = zbuf[off];
+          const int r = L.y0 + off / lw, c = L.x0 + (off - (off / lw) * lw);
+          zbuf[off] = pack_key(plane_depth(s.mesh, P, cam, key_id(key), r, c), key_id(key));
+        }
+        __syncthreads();
+      }
+
       // pixel g of the region (row-major from its corner) always goes to
       // thread g mod kBlock, so every thread adds its terms in the same order
       // however the rows are banded: results do not depend on the band height
@@ -295,15 +296,9 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
 
       if (GRAD) {
         __syncthreads();
-        // the drawn pixels of this band's own rows gather d logL / d z_j over
-        // their window; the i-th of them over all bands (row-major) goes to
-        // thread i mod kBlock, so each thread's order does not depend on banding
-        const int ls = lower_bound_u16(dlist, nd, (a - L.y0) * lw), le = lower_bound_u16(dlist, nd, (b - L.y0) * lw);
-        for (int k = ls + first_of(threadIdx.x, gcarry); k < le; k += kBlock) {
-          const int off = dlist[k];
-          const unsigned long long key = zbuf[off];
+        // d logL / d z_j of drawn pixel (r, c) over its window, onto (dt, dw)
+        auto gather = [&](int r, int c, unsigned long long key) {
           const uint32_t id = key_id(key);
-          const int r = L.y0 + off / lw, c = L.x0 + (off - (off / lw) * lw);
           if (COUNT) ++c_adj;
           const float z = key_depth(key);
           const float dx = dxt[c], dy = dyt[r];
@@ -330,8 +325,35 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
           acc[4] += sg * (nn.y * tz - nn.z * ty);
           acc[5] += sg * (nn.z * tx - nn.x * tz);
           acc[6] += sg * (nn.x * ty - nn.y * tx);
+        };
+        // the drawn pixels of this band's own rows, listed chunk by chunk in the
+        // scratch after the window weights; the i-th of them over all bands and
+        // chunks (row-major) goes to thread i mod kBlock, so each thread's
+        // order does not depend on banding
+        const int ga = max(a, obj.y0), gb = min(b, obj.y1);
+        const int ng = max(gb - ga, 0) * ow;
+        unsigned short* glist = reinterpret_cast<unsigned short*>(smem + 4 * nw);
+        const int gcap = ((int)kRasterLdsBytes - 4 * nw) / 2;
+        for (int pos = 0; pos < ng;) {
+          int n = 0;
+          // compaction rounds while a whole round still fits
+          for (; pos < ng && n + kBlock <= gcap; pos += kBlock) {
+            const int k = pos + (int)threadIdx.x;
+            bool d = false;
+            if (k < ng) {
+              const int r = ga + k / ow, c = obj.x0 + (k - (k / ow) * ow);
+              d = key_id(zbuf[(r - L.y0) * lw + (c - L.x0)]) < (uint32_t)s.mesh.T;
+            }
+            n += append_flagged(d, k, glist, n, reinterpret_cast<int*>(red));
+          }
+          for (int i = first_of(threadIdx.x, gcarry); i < n; i += kBlock) {
+            const int k = glist[i];
+            const int r = ga + k / ow, c = obj.x0 + (k - (k / ow) * ow);
+            gather(r, c, zbuf[(r - L.y0) * lw + (c - L.x0)]);
+          }
+          gcarry += n;
+          __syncthreads();  // the list is rewritten by the next chunk
         }
-        gcarry += le - ls;
       }
       __syncthreads();
     }
