@@ -385,7 +385,7 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
 }
 
 template <bool GRAD>
-__global__ __launch_bounds__(kBlock) void k_render_score(SceneDev s, const float* __restrict__ poses, int N,
+__global__ __launch_bounds__(kBlock, 4) void k_render_score(SceneDev s, const float* __restrict__ poses, int N,
                                                          float* __restrict__ logL, float* __restrict__ grad) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = blockIdx.x;
