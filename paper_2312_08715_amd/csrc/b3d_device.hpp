@@ -281,23 +281,6 @@ __device__ __forceinline__ bool cluster_may_draw(const ClusterDev& c, const Pose
   return true;
 }
 
-// Whether everything a cluster could draw lies behind the surfaces already in
-// the buffer: its nearest depth zmin exceeds (by a rounding margin) the largest
-// stored depth over the pixel centres of its screen box inside the band.
-// Stored depths only decrease, so reading the buffer while other waves still
-// draw into it can only make the answer more cautious.  Boxes of more than
-// 256 centres are not tested.
-__device__ __forceinline__ bool hidden_behind(const unsigned long long* zbuf, int bx0, int by0, int pitch,
-                                                        int c0, int c1, int r0, int r1, float zmin) {
-  if (c0 > c1 || r0 > r1) return true;  // no pixel centre of the band in reach
-  if ((c1 - c0 + 1) * (r1 - r0 + 1) > 256) return false;
-  float far_ = 0.0f;
-  for (int r = r0; r <= r1; ++r) {
-    const unsigned long long* row = zbuf + (r - by0) * pitch - bx0;
-    for (int c = c0; c <= c1; ++c) far_ = fmaxf(far_, key_depth(row[c]));
-  }
-  return zmin * (1.0f - 2e-6f) > far_;
-}
 
 // Coverage of pixel (r, c) by triangle `id` decided in double precision with
 // exactly the operations, in the same order, of the plain definition
@@ -400,29 +383,11 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
   }
   const int n_clusters = straddle ? m.n_clusters : m.n_visible;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // clusters nearer than the object's centre first; then the others, skipping
-  // those hidden behind what the first pass drew
-  const float zobj = xform(P, m.sphere[0], m.sphere[1], m.sphere[2]).z;
-#pragma unroll 1
-  for (int phase = 0; phase < 2; ++phase)
   for (int base = 0; base < n_clusters; base += kBlock) {
-    if (phase == 1 && base == 0) __syncthreads();  // the first pass is complete
     // each thread tests one cluster; the drawable ones are compacted into `list`
     const int mine = base + threadIdx.x;
-    bool draw = false;
-    if (mine < n_clusters) {
-      const ClusterDev cl = m.clusters[mine];
-      if ((xform(P, cl.sphere.x, cl.sphere.y, cl.sphere.z).z > zobj) == (phase == 1)) {
-        float box[4], zmin;
-        draw = cluster_may_draw(cl, P, cam, band, box, &zmin);
-        if (draw && phase == 1 && zmin > 0.0f) {
-          // pixel centres of the band inside the box (widened against rounding)
-          const int c0 = max((int)ceilf(box[0] - 0.51f), band.x0), c1 = min((int)floorf(box[1] - 0.49f), band.x1 - 1);
-          const int r0 = max((int)ceilf(box[2] - 0.51f), band.y0), r1 = min((int)floorf(box[3] - 0.49f), band.y1 - 1);
-          draw = !hidden_behind(zbuf, buf.x0, buf.y0, pitch, c0, c1, r0, r1, zmin);
-        }
-      }
-    }
+    float box[4], zmin;
+    const bool draw = mine < n_clusters && cluster_may_draw(m.clusters[mine], P, cam, band, box, &zmin);
     const unsigned long long mask = __ballot(draw);
     __syncthreads();  // the previous group's list is no longer read
     if (lane == 0) lds.counts[1 + wave] = __popcll(mask);
