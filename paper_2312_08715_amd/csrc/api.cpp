@@ -133,13 +133,11 @@ struct b3d_mesh {
 };
 
 struct b3d_batch {
-  BatchItemDev* items = nullptr;
-  unsigned long long* counter = nullptr;
-  int S = 0;
-  long long total = 0;
+  std::vector<BatchGroupDev> groups;  // scenes in launch order, kBatchGroup per launch
+  std::vector<int> blocks;            // persistent workgroups per launch
+  unsigned long long* counters = nullptr;  // one work counter per launch (256 B apart)
   bool grad = false;
   size_t lds = 0;
-  int blocks = 0;
 };
 
 struct b3d_tracker;
@@ -550,34 +548,32 @@ b3d_status b3d_batch_create(const b3d_batch_item* items, int32_t S, b3d_batch** 
   }
   if (lds > kLdsMax) return fail(B3D_ESHAPE, "batch_create: LDS budget exceeded");
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-  std::vector<BatchItemDev> host((size_t)S);
-  long long first = 0;
-  for (int k = 0; k < S; ++k) {
-    const b3d_batch_item& it = items[order[k]];
-    BatchItemDev& d = host[k];
-    d.s = it.scene->dev;
-    d.poses = it.poses;
-    d.logL = it.logL_out;
-    d.grad = it.grad_out;
-    d.first = first;
-    d.N = it.N;
-    first += it.N;
-  }
   int dev = 0, cus = 0, occ = 0;
   B3D_CHECK_HIP(hipGetDevice(&dev), "batch_create");
   B3D_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "batch_create");
   B3D_CHECK_HIP(batch_occupancy(grad, lds, &occ), "batch_create");
   b3d_batch* b = new b3d_batch();
-  b->S = S;
-  b->total = first;
   b->grad = grad;
   b->lds = lds;
-  b->blocks = (int)std::max<long long>(1, std::min<long long>((long long)cus * std::max(occ, 1), first));
-  if (hipMalloc((void**)&b->items, sizeof(BatchItemDev) * (size_t)S) != hipSuccess ||
-      hipMalloc((void**)&b->counter, 256) != hipSuccess ||
-      hipMemcpy(b->items, host.data(), sizeof(BatchItemDev) * (size_t)S, hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(b->items);
-    (void)hipFree(b->counter);
+  for (int k0 = 0; k0 < S; k0 += kBatchGroup) {
+    BatchGroupDev g{};
+    g.S = std::min(kBatchGroup, S - k0);
+    long long first = 0;
+    for (int j = 0; j < g.S; ++j) {
+      const b3d_batch_item& it = items[order[k0 + j]];
+      g.s[j] = it.scene->dev;
+      g.poses[j] = it.poses;
+      g.logL[j] = it.logL_out;
+      g.grad[j] = it.grad_out;
+      g.first[j] = first;
+      first += it.N;
+    }
+    g.first[g.S] = first;
+    if (first == 0) continue;
+    b->groups.push_back(g);
+    b->blocks.push_back((int)std::max<long long>(1, std::min<long long>((long long)cus * std::max(occ, 1), first)));
+  }
+  if (!b->groups.empty() && hipMalloc((void**)&b->counters, 256 * b->groups.size()) != hipSuccess) {
     delete b;
     return fail(B3D_ENOMEM, "batch_create: device allocation failed");
   }
@@ -587,17 +583,16 @@ b3d_status b3d_batch_create(const b3d_batch_item* items, int32_t S, b3d_batch** 
 
 b3d_status b3d_batch_run(const b3d_batch* b, void* stream) {
   if (!b) return fail(B3D_EINVAL, "batch_run: NULL batch");
-  if (b->total == 0) return B3D_OK;
-  B3D_CHECK_HIP(launch_batch(b->items, b->S, b->total, b->counter, b->grad, b->lds, b->blocks, (hipStream_t)stream),
-                "batch_run");
+  for (size_t k = 0; k < b->groups.size(); ++k)
+    B3D_CHECK_HIP(launch_batch(b->groups[k], b->counters + 32 * k, b->grad, b->lds, b->blocks[k], (hipStream_t)stream),
+                  "batch_run");
   return B3D_OK;
 }
 
 b3d_status b3d_batch_destroy(b3d_batch* b) {
   if (!b) return B3D_OK;
   (void)hipDeviceSynchronize();
-  (void)hipFree(b->items);
-  (void)hipFree(b->counter);
+  (void)hipFree(b->counters);
   delete b;
   return B3D_OK;
 }

@@ -35,15 +35,21 @@ struct SceneDev {
   int zcap, wcap;                  // LDS capacities: depth keys, window weights (wcap <= kRasterLdsBytes / 4)
 };
 
-// One scene of a multi-scene batch: its hypotheses are work items
-// [first, first + N) of the flattened list.
-struct BatchItemDev {
-  SceneDev s;
-  const float* poses;
-  float* logL;
-  float* grad;
-  long long first, N;
+// A group of up to kBatchGroup scenes of a multi-scene batch, passed to the
+// kernel by value: pointers that arrive as kernel arguments are known to be
+// global memory, so the compiler addresses through them with a scalar base
+// (pointers read from a device array would be generic, flat-addressed).
+// Scene k's hypotheses are work items [first[k], first[k + 1]).
+constexpr int kBatchGroup = 8;
+struct BatchGroupDev {
+  SceneDev s[kBatchGroup];
+  const float* poses[kBatchGroup];
+  float* logL[kBatchGroup];
+  float* grad[kBatchGroup];
+  long long first[kBatchGroup + 1];
+  int S;
 };
+static_assert(sizeof(BatchGroupDev) <= 4000, "a batch group must fit the kernel-argument segment");
 
 // Generic grid description for the hypothesis expander.
 struct GridDev {
@@ -75,8 +81,8 @@ hipError_t launch_render_score_count(const SceneDev& s, const float* poses, int 
                                      unsigned long long* work, hipStream_t st);
 
 hipError_t batch_occupancy(bool grad, size_t lds, int* blocks_per_cu);
-hipError_t launch_batch(const BatchItemDev* items, int S, long long total, unsigned long long* counter, bool grad,
-                        size_t lds, int blocks, hipStream_t st);
+hipError_t launch_batch(const BatchGroupDev& g, unsigned long long* counter, bool grad, size_t lds, int blocks,
+                        hipStream_t st);
 
 // scene preparation
 hipError_t launch_fill_keys(unsigned long long* keys, size_t n, hipStream_t st);

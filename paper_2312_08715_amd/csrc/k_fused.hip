@@ -393,38 +393,29 @@ __global__ __launch_bounds__(kBlock, 4) void k_render_score(SceneDev s, const fl
   render_score_one<GRAD>(s, poses + 16 * (size_t)n, logL + n, GRAD ? grad + 8 * (size_t)n : nullptr, smem);
 }
 
-// Many scenes in one persistent launch: every block pulls the next
-// (scene, hypothesis) item from a device counter until the list is drained.
-// Items are numbered scene by scene in the order the host chose (longest
-// first), so the expensive scenes start early and the cheap ones fill the
-// tail.  Every block exits once the counter passes the total.
-// The scene's pointers come from memory here, not from kernel arguments, so
-// the compiler addresses through them with 64-bit per-lane (flat) addresses
-// and would need about 180 VGPRs; the bound keeps four workgroups per CU (as
-// for k_render_score) at the price of a few spills outside the inner loops.
+// A group of scenes in one persistent launch: every block pulls the next
+// (scene, hypothesis) item from a device counter until the group is drained.
+// Items are numbered scene by scene in the order the host chose (costliest
+// hypotheses first), so the expensive scenes start early and the cheap ones
+// fill the tail.  Every block exits once the counter passes the group's total.
 template <bool GRAD>
-__global__ __launch_bounds__(kBlock, 4) void k_batch(const BatchItemDev* __restrict__ items, int S, long long total,
-                                                  unsigned long long* __restrict__ counter) {
+__global__ __launch_bounds__(kBlock, 4) void k_batch(const BatchGroupDev G, unsigned long long* __restrict__ counter) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ long long work;
+  const long long total = G.first[G.S];
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) work = (long long)atomicAdd(counter, 1ull);
     __syncthreads();
-    // the same value in every lane: keep it (and the item it selects) scalar
+    // the same value in every lane: keep it (and the scene it selects) scalar
     const unsigned long long wr = (unsigned long long)work;
     const long long w = (long long)(((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(wr >> 32)) << 32) |
                                     (unsigned)__builtin_amdgcn_readfirstlane((unsigned)wr));
     if (w >= total) break;
-    int lo = 0, hi = S;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (items[mid].first <= w) lo = mid;
-      else hi = mid;
-    }
-    const BatchItemDev& it = items[lo];
-    const long long n = w - it.first;
-    render_score_one<GRAD>(it.s, it.poses + 16 * n, it.logL + n, GRAD ? it.grad + 8 * n : nullptr, smem);
+    int k = 0;
+    for (int j = 1; j < G.S; ++j) k = G.first[j] <= w ? j : k;
+    const long long n = w - G.first[k];
+    render_score_one<GRAD>(G.s[k], G.poses[k] + 16 * n, G.logL[k] + n, GRAD ? G.grad[k] + 8 * n : nullptr, smem);
   }
 }
 
@@ -437,13 +428,13 @@ hipError_t batch_occupancy(bool grad, size_t lds, int* blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch<false>, kBlock, lds);
 }
 
-hipError_t launch_batch(const BatchItemDev* items, int S, long long total, unsigned long long* counter, bool grad,
-                        size_t lds, int blocks, hipStream_t st) {
+hipError_t launch_batch(const BatchGroupDev& g, unsigned long long* counter, bool grad, size_t lds, int blocks,
+                        hipStream_t st) {
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
   if (grad)
-    hipLaunchKernelGGL(k_batch<true>, dim3(blocks), dim3(kBlock), lds, st, items, S, total, counter);
+    hipLaunchKernelGGL(k_batch<true>, dim3(blocks), dim3(kBlock), lds, st, g, counter);
   else
-    hipLaunchKernelGGL(k_batch<false>, dim3(blocks), dim3(kBlock), lds, st, items, S, total, counter);
+    hipLaunchKernelGGL(k_batch<false>, dim3(blocks), dim3(kBlock), lds, st, g, counter);
   return hipGetLastError();
 }
 
