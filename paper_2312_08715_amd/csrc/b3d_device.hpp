@@ -476,47 +476,29 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
             atomicMin(&zbuf[pix], pack_key(z, id_base + tid));
           };
           // one flat walk over the box's centres: a wave then iterates max(rows x cols)
-          // times over its lanes, not max(rows) x max(cols).  Edge functions (each
-          // the negative area at the opposite corner) are evaluated directly at the
-          // first centre and then stepped: -e_y per column, e_x + e_y (c1 - c0) per
-          // row.  Up to 16 steps the accumulated rounding stays below 1/16 of the
-          // margin tau; larger boxes evaluate every centre directly.
+          // times over its lanes, not max(rows) x max(cols)
           const int n_cent = (c1 - c0 + 1) * (r1 - r0 + 1);
-          const bool step = n_cent <= 16;
-          const float span = (float)(c1 - c0);
           int rn = r0, cn = c0;
-          float w0, w1, w2, v0, v1;
-          auto direct = [&](int r, int col) {
-            const float py = (float)r + 0.5f, px = (float)col + 0.5f;
-            w0 = e0x * (py - B.y) - e0y * (px - B.x);
-            w1 = e1x * (py - C.y) - e1y * (px - C.x);
-            w2 = e2x * (py - A.y) - e2y * (px - A.x);
-            v0 = f0x * (py - C.y) - f0y * (px - C.x);
-            v1 = f1x * (py - D.y) - f1y * (px - D.x);
-          };
-          direct(r0, c0);
           for (int k = 0; k < n_cent; ++k) {
-            const bool out1 = !act1 || w0 > t0 || w1 > t1 || w2 > t2;
-            const bool out2 = !act2 || v0 > s0 || v1 > s1 || -w1 > t1;
-            if (!(out1 && out2)) {  // not clearly outside both
-              const int pix = (rn - buf.y0) * pitch + (cn - buf.x0);
-              if (!out1) emit(pix, eon1, w0, w1, w2, t0, t1, t2, A.w, B.w, C.w, ia1, ids.x);
-              if (!out2) emit(pix, eon2, v0, v1, -w1, s0, s1, t1, A.w, C.w, D.w, ia2, ids.y);
-            }
-            const bool wrap = ++cn > c1;
-            if (wrap) {
+            const int r = rn, col = cn;
+            if (++cn > c1) {
               cn = c0;
               ++rn;
             }
-            if (step) {
-              w0 += wrap ? e0x + e0y * span : -e0y;
-              w1 += wrap ? e1x + e1y * span : -e1y;
-              w2 += wrap ? e2x + e2y * span : -e2y;
-              v0 += wrap ? f0x + f0y * span : -f0y;
-              v1 += wrap ? f1x + f1y * span : -f1y;
-            } else {
-              direct(rn, cn);
-            }
+            const float py = (float)r + 0.5f;
+            const float px = (float)col + 0.5f;
+            // edge functions; each equals the (negative) area at the opposite corner
+            const float w0 = e0x * (py - B.y) - e0y * (px - B.x);
+            const float w1 = e1x * (py - C.y) - e1y * (px - C.x);
+            const float w2 = e2x * (py - A.y) - e2y * (px - A.x);
+            const float v0 = f0x * (py - C.y) - f0y * (px - C.x);
+            const float v1 = f1x * (py - D.y) - f1y * (px - D.x);
+            const bool out1 = !act1 || w0 > t0 || w1 > t1 || w2 > t2;
+            const bool out2 = !act2 || v0 > s0 || v1 > s1 || -w1 > t1;
+            if (out1 && out2) continue;  // clearly outside both
+            const int pix = (r - buf.y0) * pitch + (col - buf.x0);
+            if (!out1) emit(pix, eon1, w0, w1, w2, t0, t1, t2, A.w, B.w, C.w, ia1, ids.x);
+            if (!out2) emit(pix, eon2, v0, v1, -w1, s0, s1, t1, A.w, C.w, D.w, ia2, ids.y);
           }
         }
       }
