@@ -475,6 +475,16 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
             if (COUNT) ++c_frag;
             atomicMin(&zbuf[pix], pack_key(z, id_base + tid));
           };
+          // edge functions (each the negative area at the opposite corner) at the
+          // box's first centre; at a centre dr rows and dc columns further they
+          // are w + e_x dr - e_y dc with exact small integers dr, dc: two FMAs
+          // each, and the rounding stays far below the margin for any box size
+          const float py0 = (float)r0 + 0.5f, px0 = (float)c0 + 0.5f;
+          const float w0b = e0x * (py0 - B.y) - e0y * (px0 - B.x);
+          const float w1b = e1x * (py0 - C.y) - e1y * (px0 - C.x);
+          const float w2b = e2x * (py0 - A.y) - e2y * (px0 - A.x);
+          const float v0b = f0x * (py0 - C.y) - f0y * (px0 - C.x);
+          const float v1b = f1x * (py0 - D.y) - f1y * (px0 - D.x);
           // one flat walk over the box's centres: a wave then iterates max(rows x cols)
           // times over its lanes, not max(rows) x max(cols)
           const int n_cent = (c1 - c0 + 1) * (r1 - r0 + 1);
@@ -485,14 +495,12 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
               cn = c0;
               ++rn;
             }
-            const float py = (float)r + 0.5f;
-            const float px = (float)col + 0.5f;
-            // edge functions; each equals the (negative) area at the opposite corner
-            const float w0 = e0x * (py - B.y) - e0y * (px - B.x);
-            const float w1 = e1x * (py - C.y) - e1y * (px - C.x);
-            const float w2 = e2x * (py - A.y) - e2y * (px - A.x);
-            const float v0 = f0x * (py - C.y) - f0y * (px - C.x);
-            const float v1 = f1x * (py - D.y) - f1y * (px - D.x);
+            const float dr = (float)(r - r0), dc = (float)(col - c0);
+            const float w0 = __builtin_fmaf(-e0y, dc, __builtin_fmaf(e0x, dr, w0b));
+            const float w1 = __builtin_fmaf(-e1y, dc, __builtin_fmaf(e1x, dr, w1b));
+            const float w2 = __builtin_fmaf(-e2y, dc, __builtin_fmaf(e2x, dr, w2b));
+            const float v0 = __builtin_fmaf(-f0y, dc, __builtin_fmaf(f0x, dr, v0b));
+            const float v1 = __builtin_fmaf(-f1y, dc, __builtin_fmaf(f1x, dr, v1b));
             const bool out1 = !act1 || w0 > t0 || w1 > t1 || w2 > t2;
             const bool out2 = !act2 || v0 > s0 || v1 > s1 || -w1 > t1;
             if (out1 && out2) continue;  // clearly outside both
