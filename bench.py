@@ -143,6 +143,29 @@ def bench_small(b3d, torch, steps, warmup):
             "note": "fused forward + adjoint, 64x48, 6k triangles, median of HIP event times per launch"}
 
 
+def bench_throughput_vs_n(b3d, torch, scene, P, ns=(625, 1250, 2500, 5000, 10000, 20000), reps=10):
+    """Fused forward + adjoint at several batch sizes of the same workload (the
+    5000 paper-scale hypotheses tiled or cut): one GPU's share when the
+    hypotheses of a stage are split across g GPUs is N = 5000 / g."""
+    stream = torch.cuda.current_stream()
+    out = []
+    for n in ns:
+        Pn = P.repeat((n + P.shape[0] - 1) // P.shape[0], 1, 1)[:n].contiguous()
+        for _ in range(2):
+            b3d.render_score(scene, Pn, grad=True)
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            b3d.render_score(scene, Pn, grad=True)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        t = float(np.median(ts))
+        out.append({"N": n, "ms": t * 1e3, "hypotheses_per_s": n / t})
+    return out
+
+
 def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3):
     """Many scenes (1-8 objects of 500-8000 voxels, three image sizes, 1k-20k
     hypotheses each) in one persistent launch, forward + adjoint, against the
@@ -407,6 +430,7 @@ def main():
     extras = {}
     if not args.no_extras:
         extras["small_config"] = bench_small(b3d, torch, args.steps, args.warmup)
+        extras["throughput_vs_n"] = bench_throughput_vs_n(b3d, torch, scene, P)
         for name, fn in (("batch_64_scenes", lambda: bench_batch(b3d, torch, p)),
                          ("tracking_200_frames", lambda: bench_tracking(b3d, torch, p)),
                          ("table_c2f_adam", lambda: bench_table_c2f(b3d, torch, p))):
