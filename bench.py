@@ -166,6 +166,27 @@ def bench_throughput_vs_n(b3d, torch, scene, P, ns=(625, 1250, 2500, 5000, 10000
     return out
 
 
+def bench_noise_grid(b3d, torch, scene, P, A=4, B=4, sigma_max=0.01, reps=10):
+    """Hierarchical likelihood: logL of every hypothesis under a 4 x 4 grid of
+    (sigma, p_out) midpoints and the marginal over it, forward only."""
+    sig, po = b3d.noise_grid_midpoints(sigma_max, A, B)
+    scene.set_noise_grid(sig, po)
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        b3d.render_score_marginal(scene, P, grid=True)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b3d.render_score_marginal(scene, P, grid=True)
+        e1.record(stream)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    t = float(np.median(ts))
+    return {"grid": f"{A}x{B}", "value": P.shape[0] / t, "ms": t * 1e3, "unit": "hypotheses/s",
+            "note": "fused render + windowed likelihood under every grid point + marginal, one launch"}
+
+
 def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3):
     """Many scenes (1-8 objects of 500-8000 voxels, three image sizes, 1k-20k
     hypotheses each) in one persistent launch, forward + adjoint, against the
@@ -431,6 +452,7 @@ def main():
     if not args.no_extras:
         extras["small_config"] = bench_small(b3d, torch, args.steps, args.warmup)
         extras["throughput_vs_n"] = bench_throughput_vs_n(b3d, torch, scene, P)
+        extras["noise_grid_4x4"] = bench_noise_grid(b3d, torch, scene, P)
         for name, fn in (("batch_64_scenes", lambda: bench_batch(b3d, torch, p)),
                          ("tracking_200_frames", lambda: bench_tracking(b3d, torch, p)),
                          ("table_c2f_adam", lambda: bench_table_c2f(b3d, torch, p))):

@@ -198,6 +198,29 @@ b3d_status b3d_scene_set_observed(b3d_scene* scene, const float* observed, void*
 b3d_status b3d_render_score(const b3d_scene* scene, const float* poses, int32_t N, float* logL_out, float* grad_out,
                             void* stream);
 
+/* Hierarchical likelihood (Alg. 1's priors p_out ~ U(0, 1) and
+ * sigma ~ U(0, sigma_max) on the noise parameters of eq. (1), and the
+ * marginal over them used to compare hypotheses under unknown noise, Sec.
+ * IV hierarchical Bayesian inference).  Sets a grid of A standard deviations
+ * (host float[A], > 0) x B outlier probabilities (host float[B], in (0, 1]),
+ * grid point k = a * B + b, with log quadrature weights log_w (host
+ * float[A*B]; NULL: equal weights 1/(A*B), the midpoint rule for the uniform
+ * priors when the values are cell centres).  The grid keeps the scene's
+ * outlier volume, normaliser and window at the time of the call.
+ * 1 <= A <= 8, A*B <= 16 (B3D_ESHAPE beyond).  Allocates device memory; when
+ * an observed image is set, recomputes the background terms of every grid
+ * point (stream-ordered), as b3d_scene_set_observed does from then on. */
+b3d_status b3d_scene_set_noise_grid(b3d_scene* scene, const float* sigma, int32_t A, const float* p_out, int32_t B,
+                                    const float* log_w, void* stream);
+
+/* For each of N hypotheses: logL under every grid point (logL_grid, device
+ * float[N][A*B], or NULL) and the log marginal
+ * log sum_k w_k exp(logL_k) (logL_marg, device float[N]).  The same render
+ * and windowed score as b3d_render_score, each pair's distance computed once
+ * for all deviations.  Bitwise repeatable.  Stream-ordered. */
+b3d_status b3d_render_score_marginal(const b3d_scene* scene, const float* poses, int32_t N, float* logL_grid,
+                                     float* logL_marg, void* stream);
+
 /* Tile-shape tuning of the fused kernel for this scene: times
  * b3d_render_score (with the adjoint when `grad`) on the given hypotheses for
  * each candidate size of the LDS depth buffer (the sizes that leave room for

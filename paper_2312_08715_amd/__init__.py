@@ -87,6 +87,8 @@ _SIGNATURES = {
     "b3d_render_score": ([_P, _P, _I32, _P, _P, _P], ctypes.c_int),
     "b3d_scene_autotune": ([_P, _P, _I32, _I32, ctypes.POINTER(_I32), _P], ctypes.c_int),
     "b3d_scene_set_tile": ([_P, _I32], ctypes.c_int),
+    "b3d_scene_set_noise_grid": ([_P, _P, _I32, _P, _I32, _P, _P], ctypes.c_int),
+    "b3d_render_score_marginal": ([_P, _P, _I32, _P, _P, _P], ctypes.c_int),
     "b3d_scene_tile_limits": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)], ctypes.c_int),
     "b3d_render_score_work": ([_P, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "b3d_batch_create": ([ctypes.POINTER(BatchItem), _I32, ctypes.POINTER(_P)], ctypes.c_int),
@@ -314,6 +316,16 @@ class Scene:
                 json.dump(table, f, indent=1, sort_keys=True)
         return int(z.value)
 
+    def set_noise_grid(self, sigmas, p_outs, log_w=None) -> None:
+        """Noise grid of the hierarchical likelihood: sigmas [A] x p_outs [B]
+        (grid point a * B + b) with log weights [A, B] (None: equal)."""
+        sg = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float32).ravel())
+        po = np.ascontiguousarray(np.asarray(p_outs, dtype=np.float32).ravel())
+        lw = None if log_w is None else np.ascontiguousarray(np.asarray(log_w, dtype=np.float32).ravel())
+        _call("b3d_scene_set_noise_grid", self._h, sg.ctypes.data, sg.size, po.ctypes.data, po.size,
+              None if lw is None else lw.ctypes.data, _stream())
+        self.noise_grid = (sg.size, po.size)
+
     def set_tile(self, zcap: int) -> None:
         _call("b3d_scene_set_tile", self._h, int(zcap))
 
@@ -409,6 +421,24 @@ class B3DScore(torch.autograd.Function):
         dxi, dsp = pose_retract_backward(xi, grad, dlogL.contiguous())
         ds, dp = (None if d is None else dsp[k].to(d) for k, d in enumerate(ctx.sp_dev))
         return dxi, None, ds, dp, None
+
+
+def noise_grid_midpoints(sigma_max: float, A: int, B: int):
+    """Cell centres of A equal cells of (0, sigma_max] and B of (0, 1]: with
+    equal weights, the midpoint rule for the uniform priors on sigma and p_out."""
+    sig = sigma_max * (np.arange(A) + 0.5) / A
+    po = (np.arange(B) + 0.5) / B
+    return sig, po
+
+
+def render_score_marginal(scene: Scene, poses: torch.Tensor, grid: bool = False):
+    """log marginal over the scene's noise grid [N] (and logL per grid point [N, A, B] when grid)."""
+    A, B = scene.noise_grid
+    N = poses.shape[0]
+    marg = torch.empty(N, dtype=torch.float32, device=poses.device)
+    g = torch.empty((N, A, B), dtype=torch.float32, device=poses.device) if grid else None
+    _call("b3d_render_score_marginal", scene.handle, _ptr(poses, torch.float32), N, _ptr(g), _ptr(marg), _stream())
+    return (marg, g) if grid else marg
 
 
 def render_score_work(scene: Scene, poses: torch.Tensor) -> dict:

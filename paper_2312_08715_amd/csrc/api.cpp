@@ -152,7 +152,24 @@ struct b3d_scene {
   double* sat = nullptr;             // [3][(H+1)(W+1)]
   bool has_bg = false;
   bool observed = false;
+  // hierarchical likelihood: noise grid and its background summed-area tables
+  NoiseGridDev grid{};
+  std::vector<b3d_score_params> grid_params;  // per grid point
+  double* grid_sat = nullptr;                // [A*B][3][(H+1)(W+1)]
 };
+
+// Background-only per-pixel terms of every noise-grid point, as summed-area
+// tables (stream-ordered; the scene's own terms buffer is reused).
+static b3d_status grid_background(b3d_scene* S, hipStream_t st) {
+  const size_t SP = (size_t)(S->K.H + 1) * (S->K.W + 1);
+  for (size_t k = 0; k < S->grid_params.size(); ++k) {
+    SceneDev t = S->dev;
+    if (b3d_status s = make_consts(&S->grid_params[k], S->K.H, S->K.W, &t.sc)) return s;
+    t.sat = S->grid_sat + 3 * SP * k;
+    B3D_CHECK_HIP(launch_background_terms(t, S->terms, st), "noise grid");
+  }
+  return B3D_OK;
+}
 
 extern "C" {
 
@@ -412,6 +429,7 @@ b3d_status b3d_scene_destroy(b3d_scene* S) {
   (void)hipFree(S->terms);
   (void)hipFree(S->sat);
   (void)hipFree(S->bg);
+  (void)hipFree(S->grid_sat);
   delete S;
   return B3D_OK;
 }
@@ -457,6 +475,7 @@ b3d_status b3d_scene_set_observed(b3d_scene* S, const float* observed, void* str
   if (!S || !observed) return fail(B3D_EINVAL, "scene_set_observed: NULL pointer");
   S->dev.obs = observed;
   B3D_CHECK_HIP(launch_background_terms(S->dev, S->terms, (hipStream_t)stream), "scene_set_observed");
+  if (b3d_status s = grid_background(S, (hipStream_t)stream)) return s;
   S->observed = true;
   return B3D_OK;
 }
@@ -512,6 +531,64 @@ b3d_status b3d_refine_poses(const b3d_scene* S, float* poses, int32_t N, int32_t
     return fail(B3D_EINVAL, "refine_poses: bad Adam parameters");
   B3D_CHECK_HIP(launch_refine_pose(S->dev, poses, N, n_refine, lr_t, lr_r, beta1, beta2, eps, (hipStream_t)stream),
                 "refine_poses");
+  return B3D_OK;
+}
+
+b3d_status b3d_scene_set_noise_grid(b3d_scene* S, const float* sigma, int32_t A, const float* p_out, int32_t B,
+                                    const float* log_w, void* stream) {
+  if (!S || !sigma || !p_out) return fail(B3D_EINVAL, "scene_set_noise_grid: NULL pointer");
+  if (A < 1 || A > kMaxSigma || B < 1 || A * B > kMaxNoise)
+    return fail(B3D_ESHAPE, "scene_set_noise_grid: need 1 <= A <= %d, B >= 1, A*B <= %d", kMaxSigma, kMaxNoise);
+  NoiseGridDev g{};
+  g.A = A;
+  g.B = B;
+  std::vector<b3d_score_params> ps;
+  for (int ia = 0; ia < A; ++ia)
+    for (int ib = 0; ib < B; ++ib) {
+      b3d_score_params p = S->params;
+      p.sigma = sigma[ia];
+      p.p_out = p_out[ib];
+      ScoreConsts sc;
+      if (b3d_status s = make_consts(&p, S->K.H, S->K.W, &sc)) return s;
+      const int k = ia * B + ib;
+      g.c2[ia] = sc.c2;
+      g.normM[ia] = sc.normM;
+      g.ka[k] = ia;
+      g.pa[k] = sc.a;
+      g.pomp[k] = (float)(1.0 - (double)p.p_out);
+      const float lw = log_w ? log_w[k] : (float)(-std::log((double)A * B));
+      if (!std::isfinite(lw)) return fail(B3D_EINVAL, "scene_set_noise_grid: non-finite log weight %d", k);
+      g.logw[k] = lw;
+      ps.push_back(p);
+    }
+  const size_t SP = (size_t)(S->K.H + 1) * (S->K.W + 1);
+  double* sat = nullptr;
+  if (hipMalloc((void**)&sat, sizeof(double) * 3 * SP * ps.size()) != hipSuccess)
+    return fail(B3D_ENOMEM, "scene_set_noise_grid: device allocation failed");
+  if (S->grid_sat) {
+    (void)hipDeviceSynchronize();  // launches in flight may still read the old tables
+    (void)hipFree(S->grid_sat);    // freed after the new allocation, so a failure keeps the old grid
+  }
+  S->grid_sat = sat;
+  g.sat = sat;
+  g.sat_stride = (long long)(3 * SP);
+  S->grid = g;
+  S->grid_params = ps;
+  if (S->observed)
+    if (b3d_status s = grid_background(S, (hipStream_t)stream)) return s;
+  return B3D_OK;
+}
+
+b3d_status b3d_render_score_marginal(const b3d_scene* S, const float* poses, int32_t N, float* logL_grid,
+                                     float* logL_marg, void* stream) {
+  if (!S) return fail(B3D_EINVAL, "render_score_marginal: NULL scene");
+  if (S->grid_params.empty()) return fail(B3D_EINVAL, "render_score_marginal: call b3d_scene_set_noise_grid first");
+  if (!S->observed) return fail(B3D_EINVAL, "render_score_marginal: call b3d_scene_set_observed first");
+  if (N < 0) return fail(B3D_ESHAPE, "render_score_marginal: N < 0");
+  if (N == 0) return B3D_OK;
+  if (!poses || !logL_marg) return fail(B3D_EINVAL, "render_score_marginal: NULL pointer");
+  B3D_CHECK_HIP(launch_render_score_grid(S->dev, S->grid, poses, N, logL_grid, logL_marg, (hipStream_t)stream),
+                "render_score_marginal");
   return B3D_OK;
 }
 

@@ -35,6 +35,29 @@ struct SceneDev {
   int zcap, wcap;                  // LDS capacities: depth keys, window weights (wcap <= kRasterLdsBytes / 4)
 };
 
+// A grid of noise parameters for the hierarchical likelihood: A standard
+// deviations x B outlier probabilities, grid point k = a * B + b (at most
+// kMaxNoise points, at most kMaxSigma deviations).  Per deviation: the
+// exponent scale and the inlier normaliser; per grid point: its deviation's
+// index, p_out / V, 1 - p_out and the log quadrature weight; and the
+// summed-area tables of the background-only per-pixel terms (table 0 of
+// each stride-spaced group of three, as the scene's own).
+constexpr int kMaxNoise = 16;
+constexpr int kMaxSigma = 8;
+struct NoiseGridDev {
+  int A, B;
+  float c2[kMaxSigma];     // log2(e) / (2 sigma_a^2)
+  float normM[kMaxSigma];  // (2 pi sigma_a^2)^(-3/2) / M
+  int ka[kMaxNoise];       // deviation index of grid point k
+  float pa[kMaxNoise];     // p_out / V
+  float pomp[kMaxNoise];   // 1 - p_out
+  float logw[kMaxNoise];
+  const double* sat;
+  long long sat_stride;    // doubles between consecutive grid points' tables
+};
+hipError_t launch_render_score_grid(const SceneDev& s, const NoiseGridDev& g, const float* poses, int N,
+                                    float* logL_grid, float* logL_marg, hipStream_t st);
+
 // A group of up to kBatchGroup scenes of a multi-scene batch, passed to the
 // kernel by value: pointers that arrive as kernel arguments are known to be
 // global memory, so the compiler addresses through them with a scalar base

@@ -183,6 +183,36 @@ __device__ __forceinline__ int first_of(unsigned t, int base) {
   return ((int)t - base % kBlock + kBlock) % kBlock;
 }
 
+// The depth buffer of one band: the LDS rectangle L (pitch L.w(), rows and
+// columns possibly beyond the image, which stay empty) initialised from the
+// background keys, the mesh rasterised into its image part, then the depth of
+// every slot the mesh drew recomputed on its triangle's plane.  Whole block.
+template <bool COUNT>
+__device__ __forceinline__ void raster_band(const SceneDev& s, const Pose& P, const Rect& L,
+                                            unsigned long long* zbuf, unsigned char* smem, float* red, unsigned* cnt) {
+  const Cam& cam = s.cam;
+  const int H = cam.H, W = cam.W, lw = L.w();
+  const int nk = L.h() * lw;
+  for (int k = threadIdx.x; k < nk; k += kBlock) {
+    const int r = L.y0 + k / lw, c = L.x0 + (k - (k / lw) * lw);
+    const bool in = r >= 0 && r < H && c >= 0 && c < W;
+    zbuf[k] = (in && s.bg) ? s.bg[(size_t)r * W + c] : kEmptyKey;
+  }
+  __syncthreads();
+  raster_mesh<COUNT>(s.mesh, P, cam, 0u, grow_clip(L, 0, W, H), L, zbuf, carve_raster_lds(smem), cnt);
+  // the slots this mesh drew (listed in the free scratch, which holds more
+  // entries than the buffer has slots), then their depths on the planes
+  unsigned short* rlist = reinterpret_cast<unsigned short*>(smem);
+  const int nr = list_drawn(zbuf, 0, nk, (uint32_t)s.mesh.T, rlist, reinterpret_cast<int*>(red));
+  for (int k = threadIdx.x; k < nr; k += kBlock) {
+    const int off = rlist[k];
+    const unsigned long long key = zbuf[off];
+    const int r = L.y0 + off / lw, c = L.x0 + (off - (off / lw) * lw);
+    zbuf[off] = pack_key(plane_depth(s.mesh, P, cam, key_id(key), r, c), key_id(key));
+  }
+  __syncthreads();
+}
+
 // One hypothesis: pose16 (16 floats), writes *logL_out and, when GRAD,
 // grad_out[0..8).  Must be called by the whole block; `smem` is at least
 // fused_lds_bytes(s).
@@ -191,7 +221,6 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
                                                  float* __restrict__ logL_out, float* __restrict__ grad_out,
                                                  unsigned char* smem, unsigned* cnt = nullptr) {
   unsigned c_pair = 0, c_obs = 0, c_adj = 0;
-  const RasterLds rl = carve_raster_lds(smem);
   float* wbuf = reinterpret_cast<float*>(smem);  // after rasterisation
   unsigned long long* zbuf = reinterpret_cast<unsigned long long*>(smem + kRasterLdsBytes);
   float* red = reinterpret_cast<float*>(zbuf + s.zcap);
@@ -229,32 +258,11 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
       Rect L = lds;
       L.y0 = a - 2 * h;
       L.y1 = b + 2 * h;
-      const Rect D = grow_clip(L, 0, W, H);
-      const int nk = L.h() * lw;
-      for (int k = threadIdx.x; k < nk; k += kBlock) {
-        const int r = L.y0 + k / lw, c = L.x0 + (k - (k / lw) * lw);
-        const bool in = r >= 0 && r < H && c >= 0 && c < W;
-        zbuf[k] = (in && s.bg) ? s.bg[(size_t)r * W + c] : kEmptyKey;
-      }
-      __syncthreads();
+      raster_band<COUNT>(s, P, L, zbuf, smem, red, cnt);
       // likelihood over observed rows [wa, wb); rows [a, b) are this band's own
       const int wa = GRAD ? max(a - h, region.y0) : a;
       const int wb = GRAD ? min(b + h, region.y1) : b;
       const int nw = (wb - wa) * rw;
-      raster_mesh<COUNT>(s.mesh, P, cam, 0u, D, L, zbuf, rl, cnt);
-      {
-        // the slots this mesh drew (listed in the free scratch, which holds more
-        // entries than the buffer has slots), then their depths on the planes
-        unsigned short* rlist = reinterpret_cast<unsigned short*>(smem);
-        const int nr = list_drawn(zbuf, 0, nk, (uint32_t)s.mesh.T, rlist, reinterpret_cast<int*>(red));
-        for (int k = threadIdx.x; k < nr; k += kBlock) {
-          const int off = rlist[k];
-          const unsigned long long key = zbuf[off];
-          const int r = L.y0 + off / lw, c = L.x0 + (off - (off / lw) * lw);
-          zbuf[off] = pack_key(plane_depth(s.mesh, P, cam, key_id(key), r, c), key_id(key));
-        }
-        __syncthreads();
-      }
 
       // pixel g of the region (row-major from its corner) always goes to
       // thread g mod kBlock, so every thread adds its terms in the same order
@@ -466,6 +474,156 @@ hipError_t launch_refine_pose(const SceneDev& s, float* poses, int N, int n_refi
                               float b2, float eps, hipStream_t st) {
   hipLaunchKernelGGL(k_refine_pose, dim3(N), dim3(kBlock), fused_lds_bytes(s), st, s, poses, N, n_refine, lr_t,
                      lr_r, b1, b2, eps);
+  return hipGetLastError();
+}
+
+// Window sums under each deviation of a noise grid: S[a] = sum_j
+// exp(-D_ij c2[a]) over the rendered points of the window of observed point
+// (ox, oy, oz) at pixel (r, c) (as window_sums, with each distance computed
+// once).
+template <int HH>
+__device__ __forceinline__ void window_sums_grid(const unsigned long long* __restrict__ zbuf, const Rect& L, int lw,
+                                                 const float* __restrict__ dxt, const float* __restrict__ dyt, int r,
+                                                 int c, int h, float ox, float oy, float oz, const NoiseGridDev& g,
+                                                 float (&S)[kMaxSigma]) {
+#pragma unroll
+  for (int a = 0; a < kMaxSigma; ++a) S[a] = 0.0f;
+  auto add = [&](float D) {
+#pragma unroll
+    for (int a = 0; a < kMaxSigma; ++a)
+      if (a < g.A) S[a] += f_exp2(-D * g.c2[a]);
+  };
+  if (HH > 0) {
+    constexpr int n = 2 * HH + 1;
+    float dxs[n];
+#pragma unroll
+    for (int k = 0; k < n; ++k) dxs[k] = dxt[c - HH + k];
+    const unsigned long long* zr = zbuf + (r - HH - L.y0) * lw + (c - HH - L.x0);
+#pragma unroll 1
+    for (int j = 0; j < n; ++j, zr += lw) {
+      const float dy = dyt[r - HH + j];
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        const float z = key_depth(zr[k]);
+        const float ex = ox - z * dxs[k], ey = oy - z * dy, ez = oz - z;
+        add(ex * ex + ey * ey + ez * ez);
+      }
+    }
+  } else {
+    const int r0 = max(r - h, L.y0), r1 = min(r + h, L.y1 - 1);
+    const int c0 = max(c - h, L.x0), c1 = min(c + h, L.x1 - 1);
+    for (int rj = r0; rj <= r1; ++rj) {
+      const float dy = dyt[rj];
+      const unsigned long long* zr = zbuf + (rj - L.y0) * lw - L.x0;
+      for (int cj = c0; cj <= c1; ++cj) {
+        const unsigned long long key = zr[cj];
+        if (key == kEmptyKey) continue;
+        const float z = key_depth(key);
+        const float ex = ox - z * dxt[cj], ey = oy - z * dy, ez = oz - z;
+        add(ex * ex + ey * ey + ez * ez);
+      }
+    }
+  }
+}
+
+// logL of one hypothesis under every point of the noise grid (grid_out[k],
+// k = a * B + b) and their weighted log-sum-exp (*marg_out).  The same
+// render and windows as render_score_one; each observed pixel's window
+// distances are computed once and exponentiated per deviation.  Whole block.
+__device__ __forceinline__ void render_score_grid_one(const SceneDev& s, const NoiseGridDev& g,
+                                                      const float* __restrict__ pose16, float* __restrict__ grid_out,
+                                                      float* __restrict__ marg_out, unsigned char* smem) {
+  unsigned long long* zbuf = reinterpret_cast<unsigned long long*>(smem + kRasterLdsBytes);
+  float* red = reinterpret_cast<float*>(zbuf + s.zcap);
+  float* sbuf = reinterpret_cast<float*>(smem);  // per thread: S[a] normM[a] (raster scratch, free by then)
+  const Cam& cam = s.cam;
+  const int H = cam.H, W = cam.W, h = s.sc.h;
+  float* dxt = red + 64 + 2 * h;
+  float* dyt = dxt + W + 4 * h;
+  const Pose P = load_pose(pose16);
+  for (int i = (int)threadIdx.x - 2 * h; i < W + 2 * h; i += kBlock) dxt[i] = ray_x(cam, i);
+  for (int i = (int)threadIdx.x - 2 * h; i < H + 2 * h; i += kBlock) dyt[i] = ray_y(cam, i);
+  const Rect obj = object_rect(s.mesh, P, cam);
+  Rect region = grow_clip(obj, h, W, H);
+  if (obj.empty()) region.x1 = region.x0;
+  const int nk_grid = g.A * g.B;
+  float acc[kMaxNoise];
+#pragma unroll
+  for (int k = 0; k < kMaxNoise; ++k) acc[k] = 0.0f;
+  if (!obj.empty()) {
+    const Rect lds = grow(obj, 2 * h);
+    const int lw = lds.w(), rw = region.w();
+    const int band = max(s.zcap / lw - 4 * h, 1);
+    for (int a = region.y0; a < region.y1; a += band) {
+      const int b = min(a + band, region.y1);
+      Rect L = lds;
+      L.y0 = a - 2 * h;
+      L.y1 = b + 2 * h;
+      raster_band<false>(s, P, L, zbuf, smem, red, nullptr);
+      const int nw = (b - a) * rw;
+      // observed pixel g of the region always goes to thread g mod kBlock
+      for (int k = first_of(threadIdx.x, (a - region.y0) * rw); k < nw; k += kBlock) {
+        const int r = a + k / rw, c = region.x0 + (k - (k / rw) * rw);
+        const float* q = s.obs + 3 * ((size_t)r * W + c);
+        const float ox = q[0], oy = q[1], oz = q[2];
+        if (!(oz > 0.0f)) continue;
+        float S[kMaxSigma];
+        switch (h) {
+          case 1:
+            window_sums_grid<1>(zbuf, L, lw, dxt, dyt, r, c, h, ox, oy, oz, g, S);
+            break;
+          case 2:
+            window_sums_grid<2>(zbuf, L, lw, dxt, dyt, r, c, h, ox, oy, oz, g, S);
+            break;
+          default:
+            window_sums_grid<0>(zbuf, L, lw, dxt, dyt, r, c, h, ox, oy, oz, g, S);
+        }
+#pragma unroll
+        for (int ai = 0; ai < kMaxSigma; ++ai)
+          if (ai < g.A) sbuf[ai * kBlock + threadIdx.x] = S[ai] * g.normM[ai];
+#pragma unroll
+        for (int kk = 0; kk < kMaxNoise; ++kk)
+          if (kk < nk_grid) acc[kk] += f_ln(g.pa[kk] + g.pomp[kk] * sbuf[g.ka[kk] * kBlock + threadIdx.x]);
+      }
+      __syncthreads();
+    }
+  }
+  block_sum<kMaxNoise>(acc, red);
+  if (threadIdx.x == 0) {
+    Rect all;
+    all.x0 = 0;
+    all.x1 = W;
+    all.y0 = 0;
+    all.y1 = H;
+    double v[kMaxNoise], m = -1e300;
+    for (int k = 0; k < nk_grid; ++k) {
+      const double* sat = g.sat + g.sat_stride * k;
+      v[k] = (double)acc[k] + rect_sum(sat, W, all) - rect_sum(sat, W, region);
+      grid_out[k] = (float)v[k];
+      m = fmax(m, v[k] + (double)g.logw[k]);
+    }
+    double t = 0.0;
+    for (int k = 0; k < nk_grid; ++k) t += exp(v[k] + (double)g.logw[k] - m);
+    *marg_out = (float)(m + log(t));
+  }
+}
+
+__global__ __launch_bounds__(kBlock, 4) void k_render_score_grid(SceneDev s, NoiseGridDev g,
+                                                                 const float* __restrict__ poses, int N,
+                                                                 float* __restrict__ logL_grid,
+                                                                 float* __restrict__ logL_marg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = blockIdx.x;
+  if (n >= N) return;
+  float dummy[kMaxNoise];
+  float* gout = logL_grid ? logL_grid + (size_t)g.A * g.B * n : dummy;
+  render_score_grid_one(s, g, poses + 16 * (size_t)n, gout, logL_marg + n, smem);
+}
+
+hipError_t launch_render_score_grid(const SceneDev& s, const NoiseGridDev& g, const float* poses, int N,
+                                    float* logL_grid, float* logL_marg, hipStream_t st) {
+  hipLaunchKernelGGL(k_render_score_grid, dim3(N), dim3(kBlock), fused_lds_bytes(s), st, s, g, poses, N, logL_grid,
+                     logL_marg);
   return hipGetLastError();
 }
 

@@ -454,6 +454,76 @@ def test_static_background_scene_matches_oracle(b3d):
         assert np.linalg.norm(G[n, :6] - gp[n]) <= 1e-3 * np.linalg.norm(gp[n]) + 1e-6
 
 
+def _grid_compare(b3d, scene, P, obs, rend64, clean, sig, po, V, window):
+    """GPU noise-grid logL and marginal vs the oracle's on FP64 renders."""
+    from oracle.noise import score_grid
+
+    sig32, po32 = f32(sig), f32(po)
+    scene.set_noise_grid(sig32, po32)
+    marg, Lg = b3d.render_score_marginal(scene, dev(P), grid=True)
+    marg, Lg = marg.cpu().numpy().astype(np.float64), Lg.cpu().numpy().astype(np.float64)
+    L64, marg64 = score_grid(obs, rend64, sig32, po32, V=V, window=window)
+    l1 = np.stack([np.stack([oracle.score(obs, rend64, float(s), float(p), V, window)[1] for p in po32], -1)
+                   for s in sig32], -2)
+    err = np.abs(Lg - L64) / l1
+    say(f"  noise grid {len(sig)}x{len(po)}: max rel-L1 err per point (clean) {err[clean].max():.3g}")
+    assert err[clean].max() <= LOGL_RTOL
+    assert np.all(np.abs(marg - marg64)[clean] <= LOGL_RTOL * l1.max(axis=(1, 2))[clean])
+    # bitwise repeatable, and the marginal is the weighted log-sum-exp of the grid values
+    assert np.array_equal(b3d.render_score_marginal(scene, dev(P)).cpu().numpy(), marg.astype(np.float32))
+    lse = np.log(np.exp(Lg.reshape(len(P), -1) - Lg.max(axis=(1, 2))[:, None]).sum(1) / Lg[0].size) + Lg.max(axis=(1, 2))
+    assert np.allclose(marg, lse, rtol=0, atol=1e-3 + 1e-6 * np.abs(lse))
+
+
+def test_noise_grid_marginal_matches_oracle(b3d):
+    wl, obs, P = workload(0)
+    say(f"noise grid parity: config 0, {P.shape[0]} hypotheses")
+    scene, mesh, o = _scene(b3d, wl, obs)
+    xyz, tri = b3d.render_batch(mesh, dev(P), b3d.intrinsics_of(wl.camera))
+    L64, l1, oid, od = _oracle_logL(wl, obs, P)
+    clean = clean_hypotheses(xyz[..., 2].cpu().numpy(), tri.cpu().numpy(), od, oid)
+    assert clean.mean() >= 0.9
+    sig, po = b3d.noise_grid_midpoints(0.012, 3, 3)
+    s = wl.score
+    _grid_compare(b3d, scene, P, obs, oracle.unproject(od, wl.camera), clean, sig, po, s.outlier_volume, s.window)
+    # a grid of one point is the plain score
+    scene.set_noise_grid([s.sigma], [s.p_out], log_w=[[0.0]])
+    m1 = b3d.render_score_marginal(scene, dev(P)).cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(m1 - b3d.render_score(scene, dev(P)).cpu().numpy()) / l1) <= 1e-5
+    # limits of the grid are refused
+    with pytest.raises(b3d.B3DError):
+        scene.set_noise_grid(np.full(9, 0.005), [0.1])
+    with pytest.raises(b3d.B3DError):
+        scene.set_noise_grid([0.005, 0.006, 0.007], np.full(6, 0.1))
+
+
+def test_noise_grid_with_static_background_matches_oracle(b3d):
+    rng = np.random.default_rng(13)
+    va, ta = voxel_mesh(voxel_blob(300, rng, radius=0.06))
+    vb, tb = voxel_mesh(voxel_blob(200, rng, radius=0.05))
+    va, vb = f32(va), f32(vb)
+    cam = Camera(150.0, 150.0, 80.0, 60.0, 120, 160)
+    Pb = f32(random_poses(rng, 1, 0.75, 0.0)[0])
+    Pb[:3, 3] = [0.05, 0.02, 0.75]
+    truth = f32(random_poses(rng, 1, 0.8, 0.0)[0])
+    truth[:3, 3] = [-0.02, 0.0, 0.8]
+    d, _ = oracle.render([(va, ta, truth), (vb, tb, Pb)], cam)
+    obs = f32(oracle.unproject(d[0] + 0.002 * rng.standard_normal(d[0].shape) * (d[0] > 0), cam))
+    P = f32(random_poses(rng, 48, 0.8, 0.04))
+    say("noise grid with background: 2 objects, 48 hypotheses")
+    ma, mb = b3d.Mesh(va, ta), b3d.Mesh(vb, tb)
+    K = b3d.intrinsics_of(cam)
+    scene = b3d.Scene(ma, K, b3d.score_params(0.003, 0.01, 1.0, 5))
+    scene.set_background([mb], Pb[None])
+    scene.set_observed(dev(obs))
+    xa, ta_ = b3d.render_batch(ma, dev(P), K)
+    oda, oia = oracle.render([(va, ta, P)], cam)
+    clean = clean_hypotheses(xa[..., 2].cpu().numpy(), ta_.cpu().numpy(), oda, oia)
+    od, oi = oracle.render([(va, ta, P), (vb, tb, Pb)], cam)
+    sig, po = b3d.noise_grid_midpoints(0.01, 4, 4)
+    _grid_compare(b3d, scene, P, obs, oracle.unproject(od, cam), clean, sig, po, 1.0, 5)
+
+
 def test_edge_cases(b3d):
     wl, obs, P = workload(0)
     mesh = b3d.Mesh(wl.verts, wl.tris)
