@@ -45,7 +45,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # FP32 lane-ops/s, non-packed: 39.
 # what the same counters read for a plain 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0).  Valid only for the kernel sources with this digest:
 # after any change to them the figure is reported as null until re-measured.
-TRAFFIC = {"sources_sha256": "e3236ebedf7cf4737e919b3c7134f95e9960150236d4fcfea4fdb00b0c162cf6", "fetch_KiB": 6359.54, "write_KiB": 312.5, "fetch_scale": 2.0, "write_scale": 1.0}
+TRAFFIC = {"sources_sha256": "0dd2e881e11c6a1d60fb003d0f400fc327a268e3250400d36d05b5ebdf948799", "fetch_KiB": 6363.69, "write_KiB": 312.5, "fetch_scale": 2.0, "write_scale": 1.0}
 KERNEL_SOURCES = ["k_fused.hip", "b3d_device.hpp", "b3d_launch.hpp"]
 
 
@@ -183,7 +183,16 @@ def bench_noise_grid(b3d, torch, scene, P, A=4, B=4, sigma_max=0.01, reps=10):
         e1.synchronize()
         ts.append(e0.elapsed_time(e1) / 1e3)
     t = float(np.median(ts))
+    # counted work of the same render and windows; each pair adds a scale and an
+    # exponential per extra deviation, each observed pixel a logarithm per grid point
+    c = counted_work(b3d, scene, P)
+    ops = (lane_ops(c, adjoint=False) + 3 * (A - 1) * c["pair"]
+           + (COST["obs"] * (A * B - 1) + A) * c["obs"])
+    achieved = ops / t / 1e12
     return {"grid": f"{A}x{B}", "value": P.shape[0] / t, "ms": t * 1e3, "unit": "hypotheses/s",
+            "roofline": {"bound": "alu", "kernel": "k_render_score_grid", "achieved": achieved,
+                         "peak": VALU_PEAK_TOPS, "unit": "TOP/s (FP32 lane-ops)", "frac": achieved / VALU_PEAK_TOPS,
+                         "ops_per_hypothesis": ops / P.shape[0]},
             "note": "fused render + windowed likelihood under every grid point + marginal, one launch"}
 
 
@@ -356,7 +365,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fused-only", action="store_true", help="skip the split-path comparison")
     ap.add_argument("--no-extras", action="store_true", help="skip the batch, tracking and table workloads")
-    ap.add_argument("--only", choices=["batch", "tracking", "table"],
+    ap.add_argument("--only", choices=["batch", "tracking", "table", "noise_grid"],
                     help="run just one of the extra workloads and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (reference for HBM byte counters)")
@@ -374,7 +383,7 @@ def main():
     wl, K, obs = build_inputs(b3d, torch)
     s = wl.score
     p = b3d.score_params(s.sigma, s.p_out, s.outlier_volume, s.window)
-    if args.only:
+    if args.only and args.only != "noise_grid":
         fn = {"batch": bench_batch, "tracking": bench_tracking, "table": bench_table_c2f}[args.only]
         print(json.dumps({args.only: fn(b3d, torch, p)}), flush=True)
         return
@@ -382,6 +391,10 @@ def main():
     scene = b3d.Scene(mesh, K, p)
     scene.set_observed(obs)
     grid, rots = b3d.grid_of(wl.grid)
+    if args.only == "noise_grid":
+        P = b3d.enumerate_grid(grid, seed=wl.seeds["sampler"])
+        print(json.dumps({args.only: bench_noise_grid(b3d, torch, scene, P)}), flush=True)
+        return
     N = b3d.grid_size(grid)
     seed = wl.seeds["sampler"]
     stream = torch.cuda.current_stream()

@@ -497,6 +497,33 @@ def test_noise_grid_marginal_matches_oracle(b3d):
         scene.set_noise_grid([0.005, 0.006, 0.007], np.full(6, 0.1))
 
 
+def test_noise_grid_at_paper_scale_matches_oracle_on_sampled_hypotheses(b3d):
+    # the launch the bench times: 4 x 4 grid over all 5000 hypotheses
+    wl, obs, P = workload(1)
+    say(f"noise grid parity: config 1, N={P.shape[0]}, 4x4 grid, every 25th hypothesis checked")
+    scene, mesh, o = _scene(b3d, wl, obs)
+    sig, po = b3d.noise_grid_midpoints(0.01, 4, 4)
+    scene.set_noise_grid(f32(sig), f32(po))
+    marg, Lg = b3d.render_score_marginal(scene, dev(P), grid=True)
+    sel = np.arange(0, P.shape[0], 25)
+    sub, _, _ = _scene(b3d, wl, obs, mesh=mesh)
+    xyz, tri = b3d.render_batch(mesh, dev(P[sel]), b3d.intrinsics_of(wl.camera))
+    _, _, oid, od = _oracle_logL(wl, obs, P[sel])
+    clean = clean_hypotheses(xyz[..., 2].cpu().numpy(), tri.cpu().numpy(), od, oid)
+    assert clean.mean() >= 0.9
+    s = wl.score
+    _grid_compare(b3d, sub, P[sel], obs, oracle.unproject(od, wl.camera), clean, sig, po, s.outlier_volume, s.window)
+    # the full launch agrees with the launch over the sample, bit for bit
+    m_sub, L_sub = b3d.render_score_marginal(sub, dev(P[sel]), grid=True)
+    assert torch.equal(marg[torch.as_tensor(sel, device="cuda")], m_sub)
+    assert torch.equal(Lg[torch.as_tensor(sel, device="cuda")], L_sub)
+    # and bands of two rows give the same bits as the default depth-buffer tile
+    lo, _, _ = sub.tile_limits()
+    sub.set_tile(lo)
+    m_lo, L_lo = b3d.render_score_marginal(sub, dev(P[sel]), grid=True)
+    assert torch.equal(m_lo, m_sub) and torch.equal(L_lo, L_sub)
+
+
 def test_noise_grid_with_static_background_matches_oracle(b3d):
     rng = np.random.default_rng(13)
     va, ta = voxel_mesh(voxel_blob(300, rng, radius=0.06))
