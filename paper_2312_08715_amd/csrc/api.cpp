@@ -12,13 +12,12 @@
 #include <string>
 #include <vector>
 
-#include "b3d.h"
-#include "b3d_launch.hpp"
+#include "api_internal.hpp"
 #include "b3d_mesh_layout.hpp"
 
 using namespace b3d;
 
-namespace {
+namespace b3d_api {
 
 thread_local std::string g_err;
 
@@ -35,15 +34,6 @@ b3d_status fail(b3d_status s, const char* fmt, ...) {
 b3d_status hip_fail(hipError_t e, const char* where) {
   return fail(B3D_EHIP, "%s: %s", where, hipGetErrorString(e));
 }
-
-#define B3D_CHECK_HIP(expr, where)             \
-  do {                                         \
-    hipError_t e_ = (expr);                    \
-    if (e_ != hipSuccess) return hip_fail(e_, where); \
-  } while (0)
-
-constexpr int kMaxImage = 4096;
-constexpr size_t kLdsMax = 65536;
 
 bool finite_all(const float* p, size_t n) {
   for (size_t i = 0; i < n; ++i)
@@ -124,13 +114,9 @@ int max_zcap(const SceneDev& d) {
   return (int)std::min<size_t>((kLdsMax > rest ? kLdsMax - rest : 0) / kFusedBytesPerKey, kRasterLdsBytes / 2);
 }
 
-}  // namespace
+}  // namespace b3d_api
 
-struct b3d_mesh {
-  int V = 0, T = 0, n_clusters = 0, n_drawn = 0, n_hidden = 0, n_dropped = 0;
-  MeshDev dev{};
-  std::vector<void*> allocs;
-};
+using namespace b3d_api;
 
 struct b3d_batch {
   std::vector<BatchGroupDev> groups;  // scenes in launch order, kBatchGroup per launch
@@ -142,21 +128,6 @@ struct b3d_batch {
 
 struct b3d_tracker;
 
-struct b3d_scene {
-  const b3d_mesh* mesh = nullptr;
-  b3d_intrinsics K{};
-  b3d_score_params params{};
-  SceneDev dev{};
-  unsigned long long* bg = nullptr;  // background keys [H][W]
-  double* terms = nullptr;           // [3][H][W]
-  double* sat = nullptr;             // [3][(H+1)(W+1)]
-  bool has_bg = false;
-  bool observed = false;
-  // hierarchical likelihood: noise grid and its background summed-area tables
-  NoiseGridDev grid{};
-  std::vector<b3d_score_params> grid_params;  // per grid point
-  double* grid_sat = nullptr;                // [A*B][3][(H+1)(W+1)]
-};
 
 // Background-only per-pixel terms of every noise-grid point, as summed-area
 // tables (stream-ordered; the scene's own terms buffer is reused).
@@ -587,7 +558,7 @@ b3d_status b3d_render_score_marginal(const b3d_scene* S, const float* poses, int
   if (N < 0) return fail(B3D_ESHAPE, "render_score_marginal: N < 0");
   if (N == 0) return B3D_OK;
   if (!poses || !logL_marg) return fail(B3D_EINVAL, "render_score_marginal: NULL pointer");
-  B3D_CHECK_HIP(launch_render_score_grid(S->dev, S->grid, poses, N, logL_grid, logL_marg, (hipStream_t)stream),
+  B3D_CHECK_HIP(launch_render_score_grid(S->dev, S->grid, poses, N, logL_grid, logL_marg, 0, (hipStream_t)stream),
                 "render_score_marginal");
   return B3D_OK;
 }

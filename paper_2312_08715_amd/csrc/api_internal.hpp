@@ -1,0 +1,65 @@
+// Declarations shared by the translation units of the C ABI (not part of
+// the public interface): error reporting, validation helpers and the opaque
+// handle types.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "b3d.h"
+#include "b3d_launch.hpp"
+
+namespace b3d_api {
+
+using namespace b3d;
+
+extern thread_local std::string g_err;
+
+// Record a formatted message for b3d_last_error and return s.
+b3d_status fail(b3d_status s, const char* fmt, ...);
+b3d_status hip_fail(hipError_t e, const char* where);
+
+constexpr int kMaxImage = 4096;
+constexpr size_t kLdsMax = 65536;
+
+bool finite_all(const float* p, size_t n);
+b3d_status check_intrinsics(const b3d_intrinsics* K);
+Cam make_cam(const b3d_intrinsics* K);
+// Likelihood constants of eq. (1) for an H x W image (validates p).
+b3d_status make_consts(const b3d_score_params* p, int H, int W, ScoreConsts* sc);
+int default_zcap(const SceneDev& d, int blocks_per_cu);
+int min_zcap(const SceneDev& d);
+int max_zcap(const SceneDev& d);
+
+}  // namespace b3d_api
+
+#define B3D_CHECK_HIP(expr, where)                                   \
+  do {                                                               \
+    hipError_t e_ = (expr);                                          \
+    if (e_ != hipSuccess) return b3d_api::hip_fail(e_, where);       \
+  } while (0)
+
+struct b3d_mesh {
+  int V = 0, T = 0, n_clusters = 0, n_drawn = 0, n_hidden = 0, n_dropped = 0;
+  b3d::MeshDev dev{};
+  std::vector<void*> allocs;
+};
+
+struct b3d_scene {
+  const b3d_mesh* mesh = nullptr;
+  b3d_intrinsics K{};
+  b3d_score_params params{};
+  b3d::SceneDev dev{};
+  unsigned long long* bg = nullptr;  // background keys [H][W]
+  double* terms = nullptr;           // [3][H][W]
+  double* sat = nullptr;             // [3][(H+1)(W+1)]
+  bool has_bg = false;
+  bool observed = false;
+  // hierarchical likelihood: noise grid and its background summed-area tables
+  b3d::NoiseGridDev grid{};
+  std::vector<b3d_score_params> grid_params;  // per grid point
+  double* grid_sat = nullptr;                // [A*B][3][(H+1)(W+1)]
+};
+

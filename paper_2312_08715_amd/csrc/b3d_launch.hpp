@@ -55,8 +55,10 @@ struct NoiseGridDev {
   const double* sat;
   long long sat_stride;    // doubles between consecutive grid points' tables
 };
+// full = 1: every observed pixel of the image is scored in the kernel (the
+// grid's tables are not read).
 hipError_t launch_render_score_grid(const SceneDev& s, const NoiseGridDev& g, const float* poses, int N,
-                                    float* logL_grid, float* logL_marg, hipStream_t st);
+                                    float* logL_grid, float* logL_marg, int full, hipStream_t st);
 
 // A group of up to kBatchGroup scenes of a multi-scene batch, passed to the
 // kernel by value: pointers that arrive as kernel arguments are known to be

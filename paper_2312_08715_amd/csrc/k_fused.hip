@@ -529,10 +529,13 @@ __device__ __forceinline__ void window_sums_grid(const unsigned long long* __res
 // logL of one hypothesis under every point of the noise grid (grid_out[k],
 // k = a * B + b) and their weighted log-sum-exp (*marg_out).  The same
 // render and windows as render_score_one; each observed pixel's window
-// distances are computed once and exponentiated per deviation.  Whole block.
+// distances are computed once and exponentiated per deviation.  full = 1
+// walks every observed pixel of the image in bands of full-width rows
+// instead of the object's region plus the background tables (no table is
+// read).  Whole block.
 __device__ __forceinline__ void render_score_grid_one(const SceneDev& s, const NoiseGridDev& g,
                                                       const float* __restrict__ pose16, float* __restrict__ grid_out,
-                                                      float* __restrict__ marg_out, unsigned char* smem) {
+                                                      float* __restrict__ marg_out, unsigned char* smem, int full) {
   unsigned long long* zbuf = reinterpret_cast<unsigned long long*>(smem + kRasterLdsBytes);
   float* red = reinterpret_cast<float*>(zbuf + s.zcap);
   float* sbuf = reinterpret_cast<float*>(smem);  // per thread: S[a] normM[a] (raster scratch, free by then)
@@ -543,7 +546,12 @@ __device__ __forceinline__ void render_score_grid_one(const SceneDev& s, const N
   const Pose P = load_pose(pose16);
   for (int i = (int)threadIdx.x - 2 * h; i < W + 2 * h; i += kBlock) dxt[i] = ray_x(cam, i);
   for (int i = (int)threadIdx.x - 2 * h; i < H + 2 * h; i += kBlock) dyt[i] = ray_y(cam, i);
-  const Rect obj = object_rect(s.mesh, P, cam);
+  Rect all;
+  all.x0 = 0;
+  all.x1 = W;
+  all.y0 = 0;
+  all.y1 = H;
+  const Rect obj = full ? all : object_rect(s.mesh, P, cam);
   Rect region = grow_clip(obj, h, W, H);
   if (obj.empty()) region.x1 = region.x0;
   const int nk_grid = g.A * g.B;
@@ -551,7 +559,7 @@ __device__ __forceinline__ void render_score_grid_one(const SceneDev& s, const N
 #pragma unroll
   for (int k = 0; k < kMaxNoise; ++k) acc[k] = 0.0f;
   if (!obj.empty()) {
-    const Rect lds = grow(obj, 2 * h);
+    const Rect lds = grow(full ? all : obj, 2 * h);
     const int lw = lds.w(), rw = region.w();
     const int band = max(s.zcap / lw - 4 * h, 1);
     for (int a = region.y0; a < region.y1; a += band) {
@@ -590,15 +598,13 @@ __device__ __forceinline__ void render_score_grid_one(const SceneDev& s, const N
   }
   block_sum<kMaxNoise>(acc, red);
   if (threadIdx.x == 0) {
-    Rect all;
-    all.x0 = 0;
-    all.x1 = W;
-    all.y0 = 0;
-    all.y1 = H;
     double v[kMaxNoise], m = -1e300;
     for (int k = 0; k < nk_grid; ++k) {
-      const double* sat = g.sat + g.sat_stride * k;
-      v[k] = (double)acc[k] + rect_sum(sat, W, all) - rect_sum(sat, W, region);
+      v[k] = (double)acc[k];
+      if (!full) {
+        const double* sat = g.sat + g.sat_stride * k;
+        v[k] += rect_sum(sat, W, all) - rect_sum(sat, W, region);
+      }
       grid_out[k] = (float)v[k];
       m = fmax(m, v[k] + (double)g.logw[k]);
     }
@@ -611,19 +617,19 @@ __device__ __forceinline__ void render_score_grid_one(const SceneDev& s, const N
 __global__ __launch_bounds__(kBlock, 4) void k_render_score_grid(SceneDev s, NoiseGridDev g,
                                                                  const float* __restrict__ poses, int N,
                                                                  float* __restrict__ logL_grid,
-                                                                 float* __restrict__ logL_marg) {
+                                                                 float* __restrict__ logL_marg, int full) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = blockIdx.x;
   if (n >= N) return;
   float dummy[kMaxNoise];
   float* gout = logL_grid ? logL_grid + (size_t)g.A * g.B * n : dummy;
-  render_score_grid_one(s, g, poses + 16 * (size_t)n, gout, logL_marg + n, smem);
+  render_score_grid_one(s, g, poses + 16 * (size_t)n, gout, logL_marg + n, smem, full);
 }
 
 hipError_t launch_render_score_grid(const SceneDev& s, const NoiseGridDev& g, const float* poses, int N,
-                                    float* logL_grid, float* logL_marg, hipStream_t st) {
+                                    float* logL_grid, float* logL_marg, int full, hipStream_t st) {
   hipLaunchKernelGGL(k_render_score_grid, dim3(N), dim3(kBlock), fused_lds_bytes(s), st, s, g, poses, N, logL_grid,
-                     logL_marg);
+                     logL_marg, full);
   return hipGetLastError();
 }
 
