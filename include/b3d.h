@@ -433,6 +433,116 @@ b3d_status b3d_tracker_frame_eager(b3d_tracker* tr, const float* observed, void*
 b3d_status b3d_tracker_poses(const b3d_tracker* tr, float* poses_out, void* stream);
 b3d_status b3d_tracker_destroy(b3d_tracker* tr);
 
+/* ---- table scenes: contact placement and SMC over the objects ---------- */
+
+/* The table, root of the scene graph (Alg. 1): pose maps the table frame to
+ * the camera frame (row-major); the table top is the plane z = 0 of that
+ * frame, +z up, a width x height rectangle (width along x) centred on the
+ * frame's origin. */
+typedef struct b3d_table {
+  float pose[16];
+  float width, height;
+} b3d_table;
+
+/* Object poses from contact placements (Alg. 1's type, contact face and
+ * relative pose; Sec. III-A (i)).  Object k of type place[k][0] rests on face
+ * c = place[k][1] of the axis-aligned bounding box of its vertices in its
+ * own frame (c = 0..5: -x, +x, -y, +y, -z, +z): R_c turns the face's outward
+ * normal to -z and d_c puts the face on z = 0 with the face's centre on the
+ * origin; then
+ *   pose = table.pose * [Rz(dth) R_c | Rz(dth) d_c + (dx, dy, 0)]
+ * with (dx, dy, dth) = dphi[k].  types: host array of n_types mesh handles;
+ * place: device int32[N][2]; dphi: device float[N][3]; poses_out: device
+ * float[N][16].  The kernel clamps a type or face outside its range to the
+ * nearest valid one (no error is reported).  Stream-ordered. */
+b3d_status b3d_contact_poses(const b3d_mesh* const* types, int32_t n_types, const b3d_table* table,
+                             const int32_t* place, const float* dphi, int32_t N, float* poses_out, void* stream);
+
+#define B3D_MAX_SMC_OBJECTS 8
+#define B3D_MAX_TYPES 16
+
+/* Sequential Monte Carlo over the objects of a table scene (Sec. III-B,
+ * eq. (2)-(3)).  Stage i places object i in every particle:
+ *  1. coarse-to-fine search over cells of (type, face, dx, dy, dth): stage 0
+ *     splits every (type, face) placement box -- dx, dy over the table less
+ *     the face's footprint, dth over [0, 2 pi) -- into counts[0] cells
+ *     (ix * ny + iy) * nth + ith, stage t splits the chosen cell into
+ *     counts[t]; every cell is scored by the fused kernel at its centre, with
+ *     the fixed content and the particle's earlier objects as background and
+ *     the particle's current noise, and one is drawn by softmax (b3d_sample,
+ *     stage word (i << 8) | t, draw = particle); a uniform point of the final
+ *     cell (Philox4x32-10 counter (m, i, 0, 2), words 0..2) is the placement;
+ *  2. the noise: A x B equal cells of (0, sigma_max] x (0, 1) scored at their
+ *     midpoints over the whole image, one drawn (stage word (i << 8) | 0x40),
+ *     a uniform point of it taken (counter (m, i, 1, 2), words 0, 1);
+ *  3. log q = sum of the draws' log probabilities - log(final cell volume)
+ *     - log(noise cell area); log p_i = logL of the scene at the new noise
+ *     + the objects' log priors (1/|O| 1/6 1/((W_t - w)(H_t - h)) 1/(2 pi)
+ *     each) - log sigma_max; log W += log p_i - log p_{i-1} - log q, plus
+ *     -log sigma_max from stage 2 on (the noise prior as the density of the
+ *     noise values that the stage replaces);
+ *  4. when the effective sample size is below ess_threshold * M, multinomial
+ *     resampling by Gumbel-max over the log weights (stage word
+ *     (i << 8) | 0x80, draw = particle) and every log weight set to the log
+ *     mean weight. */
+typedef struct b3d_smc_params {
+  int32_t n_particles;               /* M, 1..1024 */
+  int32_t n_objects;                 /* objects to place, 1..B3D_MAX_SMC_OBJECTS */
+  int32_t n_stages;                  /* coarse-to-fine stages per object, 1..B3D_MAX_STAGES */
+  int32_t counts[B3D_MAX_STAGES][3]; /* cells per axis (dx, dy, dth) of each stage's split */
+  float sigma_max;                   /* the prior sigma ~ U(0, sigma_max) */
+  int32_t noise_A, noise_B;          /* noise cells along sigma and p_out: A <= 8, A * B <= 16 */
+  float sigma0, p_out0;              /* noise used while placing the first object */
+  float ess_threshold;               /* resample when ESS < ess_threshold * M (0: never, > 1: always) */
+  float outlier_volume;              /* V of eq. (1) */
+  int32_t window;                    /* odd window side */
+  float norm_M;                      /* eq. (1)'s normaliser; 0 for H * W */
+  uint64_t seed;
+} b3d_smc_params;
+
+typedef struct b3d_smc b3d_smc;
+
+/* types: host array of n_types (1..B3D_MAX_TYPES) mesh handles, the object
+ * library; fixed, fixed_poses (host float[n_fixed][16]): content drawn in
+ * every hypothesis's background (the table's own mesh, for instance).  Mesh
+ * handles must outlive the sampler.  Every face footprint must be smaller
+ * than the table (B3D_ESHAPE).  Allocates device memory (not
+ * stream-ordered). */
+b3d_status b3d_smc_create(const b3d_mesh* const* types, int32_t n_types, const b3d_mesh* const* fixed,
+                          const float* fixed_poses, int32_t n_fixed, const b3d_table* table, const b3d_intrinsics* K,
+                          const b3d_smc_params* p, b3d_smc** out);
+/* Start over on an observed image (device float[H][W][3], read by pointer
+ * until the next reset): no objects, log weights 0, noise (sigma0, p_out0).
+ * Stream-ordered. */
+b3d_status b3d_smc_reset(b3d_smc* smc, const float* observed, void* stream);
+/* One SMC stage: place the next object in every particle.  B3D_ESHAPE once
+ * n_objects are placed.  Synchronises `stream` a few times (the host reads
+ * the particles' noise and chosen types to set up the next launches). */
+b3d_status b3d_smc_step(b3d_smc* smc, void* stream);
+
+/* Where b3d_smc_read copies the particles and the last stage's diagnostics
+ * (device buffers; NULL skips a field).  M = n_particles, n = n_objects. */
+typedef struct b3d_smc_view {
+  int32_t* place;     /* [M][n][2] type, face of the objects placed so far */
+  float* dphi;        /* [M][n][3] */
+  float* poses;       /* [M][n][16] camera-frame poses */
+  float* noise;       /* [M][2] sigma, p_out */
+  double* logW;       /* [M] */
+  double* logp;       /* [M] log target at the particle */
+  float* logL;        /* [M] logL of the particle's scene at its noise */
+  /* the last stage, per proposal (before resampling) */
+  int32_t* choice;    /* [n_stages][M] cell drawn at each coarse-to-fine stage */
+  double* logq;       /* [M] */
+  double* logW_pre;   /* [M] */
+  float* noise_grid;  /* [M][A * B] logL at the noise cells' midpoints */
+  int32_t* ancestors; /* [M] particle each survivor copies (identity without resampling) */
+  double* ess;        /* [1] */
+} b3d_smc_view;
+
+/* n_placed (host, may be NULL): objects placed so far.  Stream-ordered. */
+b3d_status b3d_smc_read(const b3d_smc* smc, const b3d_smc_view* view, int32_t* n_placed, void* stream);
+b3d_status b3d_smc_destroy(b3d_smc* smc);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,6 +59,23 @@ class Schedule(ctypes.Structure):
     _fields_ = [("n_stages", ctypes.c_int32), ("stages", Grid * B3D_MAX_STAGES)]
 
 
+class Table(ctypes.Structure):
+    _fields_ = [("pose", ctypes.c_float * 16), ("width", ctypes.c_float), ("height", ctypes.c_float)]
+
+
+class SMCParams(ctypes.Structure):
+    _fields_ = [("n_particles", ctypes.c_int32), ("n_objects", ctypes.c_int32), ("n_stages", ctypes.c_int32),
+                ("counts", (ctypes.c_int32 * 3) * B3D_MAX_STAGES), ("sigma_max", ctypes.c_float),
+                ("noise_A", ctypes.c_int32), ("noise_B", ctypes.c_int32), ("sigma0", ctypes.c_float),
+                ("p_out0", ctypes.c_float), ("ess_threshold", ctypes.c_float), ("outlier_volume", ctypes.c_float),
+                ("window", ctypes.c_int32), ("norm_M", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+class SMCView(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("place", "dphi", "poses", "noise", "logW", "logp", "logL", "choice",
+                                               "logq", "logW_pre", "noise_grid", "ancestors", "ess")]
+
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -114,6 +131,13 @@ _SIGNATURES = {
     "b3d_c2f_workspace_size": ([ctypes.POINTER(Schedule), _I32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "b3d_c2f_step": ([_P, _P, ctypes.POINTER(Schedule), _I32, _U64, _P, ctypes.c_size_t, _P, _P, _P, _P],
                      ctypes.c_int),
+    "b3d_contact_poses": ([_P, _I32, ctypes.POINTER(Table), _P, _P, _I32, _P, _P], ctypes.c_int),
+    "b3d_smc_create": ([_P, _I32, _P, _P, _I32, ctypes.POINTER(Table), ctypes.POINTER(Intrinsics),
+                        ctypes.POINTER(SMCParams), ctypes.POINTER(_P)], ctypes.c_int),
+    "b3d_smc_reset": ([_P, _P, _P], ctypes.c_int),
+    "b3d_smc_step": ([_P, _P], ctypes.c_int),
+    "b3d_smc_read": ([_P, ctypes.POINTER(SMCView), ctypes.POINTER(_I32), _P], ctypes.c_int),
+    "b3d_smc_destroy": ([_P], ctypes.c_int),
 }
 
 
@@ -622,6 +646,97 @@ class Tracker:
     def close(self):
         if getattr(self, "_h", None):
             load_library().b3d_tracker_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def table(pose, width: float, height: float) -> Table:
+    """The table: pose maps its frame (top at z = 0, +z up) to the camera."""
+    return Table((ctypes.c_float * 16)(*np.asarray(pose, dtype=np.float32).reshape(16).tolist()), float(width),
+                 float(height))
+
+
+def contact_poses(types: Sequence[Mesh], tbl: Table, place: torch.Tensor, dphi: torch.Tensor) -> torch.Tensor:
+    """Camera-frame poses [N,4,4] of objects resting on the table: place [N,2]
+    (type, face) int32, dphi [N,3] (dx, dy, dtheta)."""
+    N = place.shape[0]
+    arr = (_P * len(types))(*[m.handle for m in types])
+    out = torch.empty((N, 4, 4), dtype=torch.float32, device=place.device)
+    _call("b3d_contact_poses", arr, len(types), ctypes.byref(tbl), _ptr(place, torch.int32), _ptr(dphi, torch.float32),
+          N, _ptr(out), _stream())
+    return out
+
+
+def smc_params(n_particles, n_objects, counts, sigma_max, noise_A, noise_B, sigma0, p_out0, ess_threshold,
+               outlier_volume=1.0, window=5, norm_M=0.0, seed=0) -> SMCParams:
+    if not 1 <= len(counts) <= B3D_MAX_STAGES:
+        raise B3DError(f"smc: 1..{B3D_MAX_STAGES} stages")
+    c = ((ctypes.c_int32 * 3) * B3D_MAX_STAGES)()
+    for t, x in enumerate(counts):
+        for k in range(3):
+            c[t][k] = int(x[k])
+    return SMCParams(int(n_particles), int(n_objects), len(counts), c, float(sigma_max), int(noise_A), int(noise_B),
+                     float(sigma0), float(p_out0), float(ess_threshold), float(outlier_volume), int(window),
+                     float(norm_M), int(seed))
+
+
+class SMC:
+    """Sequential Monte Carlo over the objects of a table scene (b3d_smc_*)."""
+
+    def __init__(self, types: Sequence[Mesh], tbl: Table, K: Intrinsics, p: SMCParams,
+                 fixed: Sequence[Mesh] = (), fixed_poses=None):
+        self.types = list(types)
+        self.fixed = list(fixed)
+        self.p = p
+        arr = (_P * len(self.types))(*[m.handle for m in self.types])
+        fx = (_P * max(1, len(self.fixed)))(*[m.handle for m in self.fixed])
+        fp = np.ascontiguousarray(np.asarray(fixed_poses if fixed_poses is not None else np.zeros((0, 16)),
+                                             dtype=np.float32).reshape(-1, 16))
+        h = _P()
+        _call("b3d_smc_create", arr, len(self.types), fx, fp.ctypes.data if len(self.fixed) else None,
+              len(self.fixed), ctypes.byref(tbl), ctypes.byref(K), ctypes.byref(p), ctypes.byref(h))
+        self._h = h
+        self._observed = None
+
+    def reset(self, observed: torch.Tensor) -> None:
+        self._observed = observed  # read by pointer until the next reset
+        _call("b3d_smc_reset", self._h, _ptr(observed, torch.float32), _stream())
+
+    def step(self) -> None:
+        _call("b3d_smc_step", self._h, _stream())
+
+    def read(self) -> dict:
+        M, n, T = self.p.n_particles, self.p.n_objects, self.p.n_stages
+        AB = self.p.noise_A * self.p.noise_B
+        d = "cuda"
+        out = dict(place=torch.empty((M, n, 2), dtype=torch.int32, device=d),
+                   dphi=torch.empty((M, n, 3), dtype=torch.float32, device=d),
+                   poses=torch.empty((M, n, 4, 4), dtype=torch.float32, device=d),
+                   noise=torch.empty((M, 2), dtype=torch.float32, device=d),
+                   logW=torch.empty(M, dtype=torch.float64, device=d),
+                   logp=torch.empty(M, dtype=torch.float64, device=d),
+                   logL=torch.empty(M, dtype=torch.float32, device=d),
+                   choice=torch.empty((T, M), dtype=torch.int32, device=d),
+                   logq=torch.empty(M, dtype=torch.float64, device=d),
+                   logW_pre=torch.empty(M, dtype=torch.float64, device=d),
+                   noise_grid=torch.empty((M, AB), dtype=torch.float32, device=d),
+                   ancestors=torch.empty(M, dtype=torch.int32, device=d),
+                   ess=torch.empty(1, dtype=torch.float64, device=d))
+        v = SMCView(*[_ptr(out[k]) for k, _ in SMCView._fields_])
+        k = _I32()
+        _call("b3d_smc_read", self._h, ctypes.byref(v), ctypes.byref(k), _stream())
+        torch.cuda.current_stream().synchronize()
+        out["placed"] = int(k.value)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().b3d_smc_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -17,7 +17,7 @@ LIB_DIR = os.path.join(HERE, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "libb3d.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["api.cpp", "mesh.cpp", "k_render.hip", "k_score.hip", "k_fused.hip", "k_sample.hip", "k_track.hip", "k_probe.hip"]
+SOURCES = ["api.cpp", "mesh.cpp", "smc.cpp", "k_render.hip", "k_score.hip", "k_fused.hip", "k_sample.hip", "k_track.hip", "k_probe.hip"]
 
 HIPCC_FLAGS = [
     "-O3",

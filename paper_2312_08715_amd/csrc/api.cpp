@@ -114,16 +114,42 @@ int max_zcap(const SceneDev& d) {
   return (int)std::min<size_t>((kLdsMax > rest ? kLdsMax - rest : 0) / kFusedBytesPerKey, kRasterLdsBytes / 2);
 }
 
+b3d_status make_noise_grid(const b3d_score_params& base, int H, int W, const float* sigma, int A, const float* p_out,
+                           int B, const float* log_w, NoiseGridDev* g, std::vector<b3d_score_params>* per_point) {
+  if (A < 1 || A > kMaxSigma || B < 1 || A * B > kMaxNoise)
+    return fail(B3D_ESHAPE, "noise grid: need 1 <= A <= %d, B >= 1, A*B <= %d", kMaxSigma, kMaxNoise);
+  *g = NoiseGridDev{};
+  g->A = A;
+  g->B = B;
+  per_point->clear();
+  for (int ia = 0; ia < A; ++ia)
+    for (int ib = 0; ib < B; ++ib) {
+      b3d_score_params p = base;
+      p.sigma = sigma[ia];
+      p.p_out = p_out[ib];
+      ScoreConsts sc;
+      if (b3d_status s = make_consts(&p, H, W, &sc)) return s;
+      const int k = ia * B + ib;
+      g->c2[ia] = sc.c2;
+      g->normM[ia] = sc.normM;
+      g->ka[k] = ia;
+      g->pa[k] = sc.a;
+      g->pomp[k] = (float)(1.0 - (double)p.p_out);
+      const float lw = log_w ? log_w[k] : (float)(-std::log((double)A * B));
+      if (!std::isfinite(lw)) return fail(B3D_EINVAL, "noise grid: non-finite log weight %d", k);
+      g->logw[k] = lw;
+      per_point->push_back(p);
+    }
+  return B3D_OK;
+}
+
 }  // namespace b3d_api
 
 using namespace b3d_api;
 
 struct b3d_batch {
-  std::vector<BatchGroupDev> groups;  // scenes in launch order, kBatchGroup per launch
-  std::vector<int> blocks;            // persistent workgroups per launch
+  BatchPlan plan;
   unsigned long long* counters = nullptr;  // one work counter per launch (256 B apart)
-  bool grad = false;
-  size_t lds = 0;
 };
 
 struct b3d_tracker;
@@ -194,6 +220,10 @@ b3d_status b3d_mesh_create(const float* verts, int32_t V, const int32_t* tris, i
 
   b3d_mesh* m = new b3d_mesh();
   m->V = V;
+  for (int k = 0; k < 3; ++k) {
+    m->box_lo[k] = (float)lo[k];
+    m->box_hi[k] = (float)hi[k];
+  }
   m->T = T;
   m->n_clusters = lay.n_visible == 0 && lay.n_hidden == 0 ? 0 : (int)lay.clusters.size();
   auto upload = [&](const void* src, size_t bytes, void** dst) -> bool {
@@ -508,30 +538,9 @@ b3d_status b3d_refine_poses(const b3d_scene* S, float* poses, int32_t N, int32_t
 b3d_status b3d_scene_set_noise_grid(b3d_scene* S, const float* sigma, int32_t A, const float* p_out, int32_t B,
                                     const float* log_w, void* stream) {
   if (!S || !sigma || !p_out) return fail(B3D_EINVAL, "scene_set_noise_grid: NULL pointer");
-  if (A < 1 || A > kMaxSigma || B < 1 || A * B > kMaxNoise)
-    return fail(B3D_ESHAPE, "scene_set_noise_grid: need 1 <= A <= %d, B >= 1, A*B <= %d", kMaxSigma, kMaxNoise);
   NoiseGridDev g{};
-  g.A = A;
-  g.B = B;
   std::vector<b3d_score_params> ps;
-  for (int ia = 0; ia < A; ++ia)
-    for (int ib = 0; ib < B; ++ib) {
-      b3d_score_params p = S->params;
-      p.sigma = sigma[ia];
-      p.p_out = p_out[ib];
-      ScoreConsts sc;
-      if (b3d_status s = make_consts(&p, S->K.H, S->K.W, &sc)) return s;
-      const int k = ia * B + ib;
-      g.c2[ia] = sc.c2;
-      g.normM[ia] = sc.normM;
-      g.ka[k] = ia;
-      g.pa[k] = sc.a;
-      g.pomp[k] = (float)(1.0 - (double)p.p_out);
-      const float lw = log_w ? log_w[k] : (float)(-std::log((double)A * B));
-      if (!std::isfinite(lw)) return fail(B3D_EINVAL, "scene_set_noise_grid: non-finite log weight %d", k);
-      g.logw[k] = lw;
-      ps.push_back(p);
-    }
+  if (b3d_status s = make_noise_grid(S->params, S->K.H, S->K.W, sigma, A, p_out, B, log_w, &g, &ps)) return s;
   const size_t SP = (size_t)(S->K.H + 1) * (S->K.W + 1);
   double* sat = nullptr;
   if (hipMalloc((void**)&sat, sizeof(double) * 3 * SP * ps.size()) != hipSuccess)
@@ -574,13 +583,67 @@ b3d_status b3d_render_score(const b3d_scene* S, const float* poses, int32_t N, f
   return B3D_OK;
 }
 
+}  // extern "C"
+
+namespace b3d_api {
+
+b3d_status plan_batch(const std::vector<BatchItemDev>& items, bool grad, BatchPlan* plan) {
+  const int S = (int)items.size();
+  std::vector<int> order((size_t)S);
+  std::vector<double> cost((size_t)S);
+  size_t lds = 0;
+  for (int i = 0; i < S; ++i) {
+    order[i] = i;
+    const SceneDev& d = items[i].s;
+    cost[i] = (double)d.mesh.T + 0.25 * (double)d.cam.H * d.cam.W;
+    lds = std::max(lds, fused_lds_bytes(d));
+  }
+  if (lds > kLdsMax) return fail(B3D_ESHAPE, "batch: LDS budget exceeded");
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  int dev = 0, cus = 0, occ = 0;
+  B3D_CHECK_HIP(hipGetDevice(&dev), "batch");
+  B3D_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "batch");
+  B3D_CHECK_HIP(batch_occupancy(grad, lds, &occ), "batch");
+  plan->grad = grad;
+  plan->lds = lds;
+  plan->groups.clear();
+  plan->blocks.clear();
+  for (int k0 = 0; k0 < S; k0 += kBatchGroup) {
+    BatchGroupDev g{};
+    g.S = std::min(kBatchGroup, S - k0);
+    long long first = 0;
+    for (int j = 0; j < g.S; ++j) {
+      const BatchItemDev& it = items[order[k0 + j]];
+      g.s[j] = it.s;
+      g.poses[j] = it.poses;
+      g.logL[j] = it.logL;
+      g.grad[j] = it.grad;
+      g.first[j] = first;
+      first += it.N;
+    }
+    g.first[g.S] = first;
+    if (first == 0) continue;
+    plan->groups.push_back(g);
+    plan->blocks.push_back((int)std::max<long long>(1, std::min<long long>((long long)cus * std::max(occ, 1), first)));
+  }
+  return B3D_OK;
+}
+
+b3d_status run_batch(const BatchPlan& plan, unsigned long long* counters, hipStream_t st) {
+  for (size_t k = 0; k < plan.groups.size(); ++k)
+    B3D_CHECK_HIP(launch_batch(plan.groups[k], counters + 32 * k, plan.grad, plan.lds, plan.blocks[k], st), "batch");
+  return B3D_OK;
+}
+
+}  // namespace b3d_api
+
+extern "C" {
+
 b3d_status b3d_batch_create(const b3d_batch_item* items, int32_t S, b3d_batch** out) {
   if (!items || !out) return fail(B3D_EINVAL, "batch_create: NULL pointer");
   if (S < 1) return fail(B3D_ESHAPE, "batch_create: need at least one item");
   const bool grad = items[0].grad_out != nullptr;
-  std::vector<int> order((size_t)S);
-  std::vector<double> cost((size_t)S);
-  size_t lds = 0;
+  std::vector<BatchItemDev> its((size_t)S);
   for (int i = 0; i < S; ++i) {
     const b3d_batch_item& it = items[i];
     if (!it.scene) return fail(B3D_EINVAL, "batch_create: item %d has no scene", i);
@@ -589,39 +652,14 @@ b3d_status b3d_batch_create(const b3d_batch_item* items, int32_t S, b3d_batch** 
     if (it.N > 0 && (!it.poses || !it.logL_out)) return fail(B3D_EINVAL, "batch_create: item %d: NULL buffer", i);
     if ((it.grad_out != nullptr) != grad)
       return fail(B3D_ENOTSUP, "batch_create: grad_out must be given for all items or for none");
-    order[i] = i;
-    const SceneDev& d = it.scene->dev;
-    cost[i] = (double)d.mesh.T + 0.25 * (double)d.cam.H * d.cam.W;
-    lds = std::max(lds, fused_lds_bytes(d));
+    its[i] = BatchItemDev{it.scene->dev, it.poses, it.N, it.logL_out, it.grad_out};
   }
-  if (lds > kLdsMax) return fail(B3D_ESHAPE, "batch_create: LDS budget exceeded");
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-  int dev = 0, cus = 0, occ = 0;
-  B3D_CHECK_HIP(hipGetDevice(&dev), "batch_create");
-  B3D_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "batch_create");
-  B3D_CHECK_HIP(batch_occupancy(grad, lds, &occ), "batch_create");
   b3d_batch* b = new b3d_batch();
-  b->grad = grad;
-  b->lds = lds;
-  for (int k0 = 0; k0 < S; k0 += kBatchGroup) {
-    BatchGroupDev g{};
-    g.S = std::min(kBatchGroup, S - k0);
-    long long first = 0;
-    for (int j = 0; j < g.S; ++j) {
-      const b3d_batch_item& it = items[order[k0 + j]];
-      g.s[j] = it.scene->dev;
-      g.poses[j] = it.poses;
-      g.logL[j] = it.logL_out;
-      g.grad[j] = it.grad_out;
-      g.first[j] = first;
-      first += it.N;
-    }
-    g.first[g.S] = first;
-    if (first == 0) continue;
-    b->groups.push_back(g);
-    b->blocks.push_back((int)std::max<long long>(1, std::min<long long>((long long)cus * std::max(occ, 1), first)));
+  if (b3d_status s = plan_batch(its, grad, &b->plan)) {
+    delete b;
+    return s;
   }
-  if (!b->groups.empty() && hipMalloc((void**)&b->counters, 256 * b->groups.size()) != hipSuccess) {
+  if (!b->plan.groups.empty() && hipMalloc((void**)&b->counters, 256 * b->plan.groups.size()) != hipSuccess) {
     delete b;
     return fail(B3D_ENOMEM, "batch_create: device allocation failed");
   }
@@ -631,10 +669,7 @@ b3d_status b3d_batch_create(const b3d_batch_item* items, int32_t S, b3d_batch** 
 
 b3d_status b3d_batch_run(const b3d_batch* b, void* stream) {
   if (!b) return fail(B3D_EINVAL, "batch_run: NULL batch");
-  for (size_t k = 0; k < b->groups.size(); ++k)
-    B3D_CHECK_HIP(launch_batch(b->groups[k], b->counters + 32 * k, b->grad, b->lds, b->blocks[k], (hipStream_t)stream),
-                  "batch_run");
-  return B3D_OK;
+  return run_batch(b->plan, b->counters, (hipStream_t)stream);
 }
 
 b3d_status b3d_batch_destroy(b3d_batch* b) {

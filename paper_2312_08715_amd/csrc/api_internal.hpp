@@ -33,6 +33,30 @@ int default_zcap(const SceneDev& d, int blocks_per_cu);
 int min_zcap(const SceneDev& d);
 int max_zcap(const SceneDev& d);
 
+// Noise-grid constants for sigma[A] x p_out[B] (other parameters from base);
+// log_w: A*B log weights or nullptr for equal weights.  sat is left unset.
+b3d_status make_noise_grid(const b3d_score_params& base, int H, int W, const float* sigma, int A, const float* p_out,
+                           int B, const float* log_w, NoiseGridDev* g, std::vector<b3d_score_params>* per_point);
+
+// One scene's share of a multi-scene launch, and the launch plan: scenes
+// ordered by estimated cost, kBatchGroup per persistent launch.
+struct BatchItemDev {
+  SceneDev s;
+  const float* poses;
+  int N;
+  float* logL;
+  float* grad;
+};
+struct BatchPlan {
+  std::vector<BatchGroupDev> groups;
+  std::vector<int> blocks;  // persistent workgroups per launch
+  bool grad = false;
+  size_t lds = 0;
+};
+b3d_status plan_batch(const std::vector<BatchItemDev>& items, bool grad, BatchPlan* plan);
+// counters: device, 256 B per group.
+b3d_status run_batch(const BatchPlan& plan, unsigned long long* counters, hipStream_t st);
+
 }  // namespace b3d_api
 
 #define B3D_CHECK_HIP(expr, where)                                   \
@@ -43,6 +67,7 @@ int max_zcap(const SceneDev& d);
 
 struct b3d_mesh {
   int V = 0, T = 0, n_clusters = 0, n_drawn = 0, n_hidden = 0, n_dropped = 0;
+  float box_lo[3] = {0, 0, 0}, box_hi[3] = {0, 0, 0};  // exact bounds of the vertices (object frame)
   b3d::MeshDev dev{};
   std::vector<void*> allocs;
 };

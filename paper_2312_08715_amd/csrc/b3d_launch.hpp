@@ -60,6 +60,76 @@ struct NoiseGridDev {
 hipError_t launch_render_score_grid(const SceneDev& s, const NoiseGridDev& g, const float* poses, int N,
                                     float* logL_grid, float* logL_marg, int full, hipStream_t st);
 
+// Table-contact placement (see b3d_contact_poses): the resting frame of face
+// c of a type's bounding box and the log prior density of a placement on it.
+struct FaceDev {
+  float R[9];     // object frame -> resting frame (entries 0, +-1)
+  float d[3];     // puts the face on z = 0 with its centre on the origin
+  float w, h;     // footprint extents along x and y
+  double lprior;  // log(1/|O| 1/6 1/((W_t - w)(H_t - h)) 1/(2 pi))
+};
+struct ContactDev {
+  float T[16];           // table frame -> camera
+  const FaceDev* faces;  // device [n_types][6]
+  int n_types;
+};
+// A cell of the placement partition: type, face and the box [lo, hi) of
+// (dx, dy, dth).
+struct CellDev {
+  int type, face;
+  float lo[3], hi[3];
+};
+// Particle state of the SMC sampler (device arrays, M particles, n slots).
+struct PartDev {
+  int* place;      // [M][n][2]
+  float* dphi;     // [M][n][3]
+  float* poses;    // [M][n][16]
+  float* noise;    // [M][2]
+  float* logL;     // [M]
+  double* logp;    // [M]
+  double* lprior;  // [M]
+  double* logW;    // [M]
+};
+// Proposals of one SMC stage, before resampling.
+struct StageDev {
+  const CellDev* cells;     // [M] final cells (type, face)
+  const float* dphi;        // [M][3]
+  const float* poses;       // [M][16]
+  const float* noise;       // [M][2]
+  const float* logL;        // [M]
+  const double* logq;       // [M]
+  double* logp;             // [M] written by the reweight
+  double* lprior;           // [M] written by the reweight
+  double* logW_pre;         // [M] written by the reweight
+};
+
+hipError_t launch_contact_poses(const ContactDev& C, const int* place, const float* dphi, int N, float* poses,
+                                hipStream_t st);
+// Poses of the centres of every cell's split into nx x ny x nt cells:
+// poses[(p * n + j) * 16], n = nx ny nt.
+hipError_t launch_contact_enumerate(const ContactDev& C, const CellDev* cells, int P, int nx, int ny, int nt,
+                                    float* poses, hipStream_t st);
+// Move each particle into its drawn cell.  roots != nullptr: stage 0, draw
+// n = r * n_split + j picks split cell j of roots[r]; else split cell idx of
+// cells[m].  clogq = logw (stage 0) or += logw.
+hipError_t launch_contact_choose(const CellDev* roots, int nx, int ny, int nt, const int* idx, const float* logw, int M,
+                                 CellDev* cells, double* clogq, int* choice, hipStream_t st);
+// A uniform point of each final cell: placement, pose and log q so far.
+hipError_t launch_contact_draw(const ContactDev& C, const CellDev* cells, int M, uint32_t key0, uint32_t key1,
+                               uint32_t i, const double* clogq, float* dphi, float* poses, double* logq,
+                               hipStream_t st);
+// A uniform point of each particle's drawn noise cell; logq += its log density.
+hipError_t launch_noise_draw(const int* nidx, const float* nlogw, int M, int A, int B, float sigma_max,
+                             uint32_t key0, uint32_t key1, uint32_t i, float* noise, double* logq, hipStream_t st);
+// log p_i, the log prior sum and the pre-resampling log weights (one block);
+// lw_shift = logW_pre - max, as floats for the resampling draws.
+hipError_t launch_smc_reweight(const ContactDev& C, int M, int i, double log_sigma_max, const PartDev& in,
+                               const StageDev& sd, float* lw_shift, hipStream_t st);
+// Effective sample size, the resampling decision, and the next state (one
+// block): survivors copy in[src]'s first k objects and the stage's proposal.
+hipError_t launch_smc_resample(int M, int n_slots, int k, float threshold, const PartDev& in, const StageDev& sd,
+                               const int* drawn, PartDev out, int* ancestors, double* ess, hipStream_t st);
+
 // A group of up to kBatchGroup scenes of a multi-scene batch, passed to the
 // kernel by value: pointers that arrive as kernel arguments are known to be
 // global memory, so the compiler addresses through them with a scalar base

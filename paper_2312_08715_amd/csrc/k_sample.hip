@@ -205,4 +205,246 @@ hipError_t launch_c2f_update(const float* poses, int P, int N, const int* idx, c
   return hipGetLastError();
 }
 
+// ---- table-contact placement and the SMC sampler's per-particle steps ----
+
+// Camera-frame pose of an object resting on face f, turned by th about the
+// table normal and moved by (dx, dy): T [Rz(th) R | Rz(th) d + (dx, dy, 0)].
+__device__ void contact_pose(const ContactDev& C, const FaceDev& f, float dx, float dy, float th,
+                             float* __restrict__ out) {
+  float s, c;
+  sincosf(th, &s, &c);
+  float Rt[9], tt[3];
+  for (int j = 0; j < 3; ++j) {
+    Rt[j] = c * f.R[j] - s * f.R[3 + j];
+    Rt[3 + j] = s * f.R[j] + c * f.R[3 + j];
+    Rt[6 + j] = f.R[6 + j];
+  }
+  tt[0] = c * f.d[0] - s * f.d[1] + dx;
+  tt[1] = s * f.d[0] + c * f.d[1] + dy;
+  tt[2] = f.d[2];
+  for (int r = 0; r < 3; ++r) {
+    const float* T = C.T + 4 * r;
+    for (int j = 0; j < 3; ++j) out[4 * r + j] = T[0] * Rt[j] + T[1] * Rt[3 + j] + T[2] * Rt[6 + j];
+    out[4 * r + 3] = T[0] * tt[0] + T[1] * tt[1] + T[2] * tt[2] + T[3];
+  }
+  out[12] = 0.0f;
+  out[13] = 0.0f;
+  out[14] = 0.0f;
+  out[15] = 1.0f;
+}
+
+__global__ void k_contact_poses(ContactDev C, const int* __restrict__ place, const float* __restrict__ dphi, int N,
+                                float* __restrict__ poses) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int o = min(max(place[2 * n], 0), C.n_types - 1), c = min(max(place[2 * n + 1], 0), 5);
+  contact_pose(C, C.faces[6 * o + c], dphi[3 * n], dphi[3 * n + 1], dphi[3 * n + 2], poses + 16 * (size_t)n);
+}
+
+hipError_t launch_contact_poses(const ContactDev& C, const int* place, const float* dphi, int N, float* poses,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_contact_poses, dim3((N + 63) / 64), dim3(64), 0, st, C, place, dphi, N, poses);
+  return hipGetLastError();
+}
+
+// Split cell j = (ix ny + iy) nt + it of [lo, hi) into nx x ny x nt cells.
+__device__ __forceinline__ CellDev split_cell(const CellDev& p, int nx, int ny, int nt, int j) {
+  const int i[3] = {j / (ny * nt), (j / nt) % ny, j % nt};
+  const int n[3] = {nx, ny, nt};
+  CellDev q;
+  q.type = p.type;
+  q.face = p.face;
+  for (int k = 0; k < 3; ++k) {
+    const float step = (p.hi[k] - p.lo[k]) / (float)n[k];
+    q.lo[k] = p.lo[k] + (float)i[k] * step;
+    q.hi[k] = p.lo[k] + (float)(i[k] + 1) * step;
+  }
+  return q;
+}
+
+__global__ void k_contact_enumerate(ContactDev C, const CellDev* __restrict__ cells, int P, int nx, int ny, int nt,
+                                    float* __restrict__ poses) {
+  const int n = nx * ny * nt;
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (long long)P * n) return;
+  const int p = (int)(id / n), j = (int)(id - (long long)p * n);
+  const CellDev q = split_cell(cells[p], nx, ny, nt, j);
+  contact_pose(C, C.faces[6 * q.type + q.face], 0.5f * (q.lo[0] + q.hi[0]), 0.5f * (q.lo[1] + q.hi[1]),
+               0.5f * (q.lo[2] + q.hi[2]), poses + 16 * id);
+}
+
+hipError_t launch_contact_enumerate(const ContactDev& C, const CellDev* cells, int P, int nx, int ny, int nt,
+                                    float* poses, hipStream_t st) {
+  const long long n = (long long)P * nx * ny * nt;
+  hipLaunchKernelGGL(k_contact_enumerate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, C, cells, P, nx, ny,
+                     nt, poses);
+  return hipGetLastError();
+}
+
+__global__ void k_contact_choose(const CellDev* __restrict__ roots, int nx, int ny, int nt, const int* __restrict__ idx,
+                                 const float* __restrict__ logw, int M, CellDev* __restrict__ cells,
+                                 double* __restrict__ clogq, int* __restrict__ choice) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const int n = idx[m], ns = nx * ny * nt;
+  const CellDev parent = roots ? roots[n / ns] : cells[m];
+  cells[m] = split_cell(parent, nx, ny, nt, roots ? n % ns : n);
+  clogq[m] = (roots ? 0.0 : clogq[m]) + (double)logw[m];
+  if (choice) choice[m] = n;
+}
+
+hipError_t launch_contact_choose(const CellDev* roots, int nx, int ny, int nt, const int* idx, const float* logw, int M,
+                                 CellDev* cells, double* clogq, int* choice, hipStream_t st) {
+  hipLaunchKernelGGL(k_contact_choose, dim3((M + 63) / 64), dim3(64), 0, st, roots, nx, ny, nt, idx, logw, M, cells,
+                     clogq, choice);
+  return hipGetLastError();
+}
+
+__global__ void k_contact_draw(ContactDev C, const CellDev* __restrict__ cells, int M, uint32_t k0, uint32_t k1,
+                               uint32_t i, const double* __restrict__ clogq, float* __restrict__ dphi,
+                               float* __restrict__ poses, double* __restrict__ logq) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const CellDev q = cells[m];
+  U4 c = {(uint32_t)m, i, 0u, 2u};
+  const U4 o = philox4x32_10(c, k0, k1);
+  const float u[3] = {to_unit(o.x), to_unit(o.y), to_unit(o.z)};
+  float x[3];
+  double vol = 1.0;
+  for (int k = 0; k < 3; ++k) {
+    x[k] = q.lo[k] + u[k] * (q.hi[k] - q.lo[k]);
+    vol *= (double)q.hi[k] - (double)q.lo[k];
+    dphi[3 * m + k] = x[k];
+  }
+  logq[m] = clogq[m] - log(vol);
+  contact_pose(C, C.faces[6 * q.type + q.face], x[0], x[1], x[2], poses + 16 * (size_t)m);
+}
+
+hipError_t launch_contact_draw(const ContactDev& C, const CellDev* cells, int M, uint32_t key0, uint32_t key1,
+                               uint32_t i, const double* clogq, float* dphi, float* poses, double* logq,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_contact_draw, dim3((M + 63) / 64), dim3(64), 0, st, C, cells, M, key0, key1, i, clogq, dphi,
+                     poses, logq);
+  return hipGetLastError();
+}
+
+__global__ void k_noise_draw(const int* __restrict__ nidx, const float* __restrict__ nlogw, int M, int A, int B,
+                             float sigma_max, uint32_t k0, uint32_t k1, uint32_t i, float* __restrict__ noise,
+                             double* __restrict__ logq) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const int k = nidx[m], a = k / B, b = k - (k / B) * B;
+  U4 c = {(uint32_t)m, i, 1u, 2u};
+  const U4 o = philox4x32_10(c, k0, k1);
+  noise[2 * m] = sigma_max * ((float)a + to_unit(o.x)) / (float)A;
+  noise[2 * m + 1] = ((float)b + to_unit(o.y)) / (float)B;
+  logq[m] += (double)nlogw[m] - log((double)sigma_max / ((double)A * B));
+}
+
+hipError_t launch_noise_draw(const int* nidx, const float* nlogw, int M, int A, int B, float sigma_max,
+                             uint32_t key0, uint32_t key1, uint32_t i, float* noise, double* logq, hipStream_t st) {
+  hipLaunchKernelGGL(k_noise_draw, dim3((M + 63) / 64), dim3(64), 0, st, nidx, nlogw, M, A, B, sigma_max, key0, key1,
+                     i, noise, logq);
+  return hipGetLastError();
+}
+
+// Fixed-order block reductions of doubles (whole block, kBlock threads).
+__device__ double block_max_d(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double block_sum_d(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_smc_reweight(ContactDev C, int M, int i, double log_smax, PartDev in,
+                                                         StageDev sd, float* __restrict__ lw_shift) {
+  __shared__ double red[kBlock];
+  double mx = -INFINITY;
+  for (int m = threadIdx.x; m < M; m += kBlock) {
+    const CellDev q = sd.cells[m];
+    const double lpr = in.lprior[m] + C.faces[6 * q.type + q.face].lprior;
+    const double lp = (double)sd.logL[m] + lpr - log_smax;
+    const double back = i > 1 ? -log_smax : 0.0;
+    const double lw = in.logW[m] + lp - in.logp[m] - sd.logq[m] + back;
+    sd.lprior[m] = lpr;
+    sd.logp[m] = lp;
+    sd.logW_pre[m] = lw;
+    mx = fmax(mx, lw);
+  }
+  mx = block_max_d(mx, red);
+  for (int m = threadIdx.x; m < M; m += kBlock) lw_shift[m] = (float)(sd.logW_pre[m] - mx);
+}
+
+hipError_t launch_smc_reweight(const ContactDev& C, int M, int i, double log_sigma_max, const PartDev& in,
+                               const StageDev& sd, float* lw_shift, hipStream_t st) {
+  hipLaunchKernelGGL(k_smc_reweight, dim3(1), dim3(kBlock), 0, st, C, M, i, log_sigma_max, in, sd, lw_shift);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_smc_resample(int M, int n, int k, float threshold, PartDev in,
+                                                         StageDev sd, const int* __restrict__ drawn, PartDev out,
+                                                         int* __restrict__ ancestors, double* __restrict__ ess) {
+  __shared__ double red[kBlock];
+  double mx = -INFINITY;
+  for (int m = threadIdx.x; m < M; m += kBlock) mx = fmax(mx, sd.logW_pre[m]);
+  mx = block_max_d(mx, red);
+  double s1 = 0.0, s2 = 0.0;
+  for (int m = threadIdx.x; m < M; m += kBlock) {
+    const double e = exp(sd.logW_pre[m] - mx);
+    s1 += e;
+    s2 += e * e;
+  }
+  s1 = block_sum_d(s1, red);
+  s2 = block_sum_d(s2, red);
+  const double e_ss = s1 * s1 / s2;
+  const bool resample = e_ss < (double)threshold * M;
+  const double mean_lw = mx + log(s1) - log((double)M);
+  for (int m = threadIdx.x; m < M; m += kBlock) {
+    const int src = resample ? drawn[m] : m;
+    ancestors[m] = src;
+    for (int j = 0; j < k; ++j) {
+      const size_t a = (size_t)src * n + j, b = (size_t)m * n + j;
+      for (int e = 0; e < 2; ++e) out.place[2 * b + e] = in.place[2 * a + e];
+      for (int e = 0; e < 3; ++e) out.dphi[3 * b + e] = in.dphi[3 * a + e];
+      for (int e = 0; e < 16; ++e) out.poses[16 * b + e] = in.poses[16 * a + e];
+    }
+    const size_t b = (size_t)m * n + k;
+    out.place[2 * b] = sd.cells[src].type;
+    out.place[2 * b + 1] = sd.cells[src].face;
+    for (int e = 0; e < 3; ++e) out.dphi[3 * b + e] = sd.dphi[3 * src + e];
+    for (int e = 0; e < 16; ++e) out.poses[16 * b + e] = sd.poses[16 * (size_t)src + e];
+    out.noise[2 * m] = sd.noise[2 * src];
+    out.noise[2 * m + 1] = sd.noise[2 * src + 1];
+    out.logL[m] = sd.logL[src];
+    out.logp[m] = sd.logp[src];
+    out.lprior[m] = sd.lprior[src];
+    out.logW[m] = resample ? mean_lw : sd.logW_pre[m];
+  }
+  if (threadIdx.x == 0) *ess = e_ss;
+}
+
+hipError_t launch_smc_resample(int M, int n_slots, int k, float threshold, const PartDev& in, const StageDev& sd,
+                               const int* drawn, PartDev out, int* ancestors, double* ess, hipStream_t st) {
+  hipLaunchKernelGGL(k_smc_resample, dim3(1), dim3(kBlock), 0, st, M, n_slots, k, threshold, in, sd, drawn, out,
+                     ancestors, ess);
+  return hipGetLastError();
+}
+
 }  // namespace b3d

@@ -1,0 +1,214 @@
+"""SMC over the objects of a table scene and the contact placement: the HIP
+library against the oracle (oracle/smc.py), stage by stage.
+
+The library's state after stage i-1 is fed to the oracle, which runs stage i
+from it with its FP64 renderer and likelihood; the discrete choices must
+agree except for rare near-ties, and for the particles whose choices agree
+the placements, noise, proposal densities and weights must agree to the
+stated tolerances.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.smc import Particles, SMCParams, Table, contact_pose, faces_of, log_prior, smc_stage
+from workloads import table_scene
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def b3d():
+    import paper_2312_08715_amd as b
+
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    b.load_library()
+    return b
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+_scene_cache = {}
+
+
+def small_table_scene():
+    """Two voxel objects on a 1 m x 1 m table at 64x48, observed with 2 mm
+    depth noise and 3% outliers (float32 inputs, widened for the oracle)."""
+    if "s" not in _scene_cache:
+        meshes, poses, table, cam, noise, Tcw = table_scene(seed=77, voxels=(90, 140), W=64, H=48, f=55.0,
+                                                            distance=0.7)
+        meshes = [(f32(v), t) for v, t in meshes]
+        tv, tt, tT = table
+        objs = [(v, t, f32(P)) for (v, t), P in zip(meshes, poses)] + [(f32(tv), tt, f32(tT))]
+        d, _ = oracle.render(objs, cam)
+        z = np.where(d[0] > 0, d[0] + noise["gauss"], 0.0)
+        z = np.where(noise["outlier_mask"], noise["outlier_depth"], z)
+        obs = f32(oracle.unproject(z, cam))
+        _scene_cache["s"] = (meshes, [f32(P) for P in poses], (f32(tv), tt, f32(tT)), cam, obs)
+    return _scene_cache["s"]
+
+
+def gpu_setup(b3d, meshes, table, cam, **kw):
+    tv, tt, tT = table
+    types = [b3d.Mesh(v, t) for v, t in meshes]
+    tmesh = b3d.Mesh(tv, tt)
+    tbl = b3d.table(tT, 1.0, 1.0)
+    args = dict(n_particles=4, n_objects=2, counts=((2, 2, 4), (2, 2, 2), (2, 2, 2)), sigma_max=0.01, noise_A=3,
+                noise_B=2, sigma0=0.008, p_out0=0.5, ess_threshold=0.0, outlier_volume=1.0, window=5, seed=1234)
+    args.update(kw)
+    p = b3d.smc_params(**args)
+    smc = b3d.SMC(types, tbl, b3d.intrinsics_of(cam), p, fixed=[tmesh], fixed_poses=tT[None])
+    return smc, types, tmesh, args
+
+
+def oracle_params(args):
+    return SMCParams(counts=args["counts"], sigma_max=args["sigma_max"], A=args["noise_A"], B=args["noise_B"],
+                     sigma0=args["sigma0"], p0=args["p_out0"], ess_threshold=args["ess_threshold"],
+                     seed=args["seed"])
+
+
+def state_of(r, k):
+    """The library's particles after k objects, as the oracle's state."""
+    return Particles(place=r["place"][:, :k].cpu().numpy().astype(np.int32),
+                     dphi=r["dphi"][:, :k].cpu().numpy().astype(np.float64),
+                     poses=r["poses"][:, :k].cpu().numpy().astype(np.float64),
+                     noise=r["noise"].cpu().numpy().astype(np.float64),
+                     logW=r["logW"].cpu().numpy(), logp=r["logp"].cpu().numpy(),
+                     lprior=np.zeros(r["logW"].shape[0]), logL=r["logL"].cpu().numpy().astype(np.float64))
+
+
+def test_contact_poses_match_oracle(b3d):
+    rng = np.random.default_rng(8)
+    meshes, _, table, cam, _ = small_table_scene()
+    types = [b3d.Mesh(v, t) for v, t in meshes]
+    tT = table[2]
+    N = 300
+    place = np.stack([rng.integers(0, 2, N), rng.integers(0, 6, N)], 1).astype(np.int32)
+    dphi = f32(np.stack([rng.uniform(-0.4, 0.4, N), rng.uniform(-0.4, 0.4, N), rng.uniform(0, 2 * np.pi, N)], 1))
+    P = b3d.contact_poses(types, b3d.table(tT, 1.0, 1.0), dev(place, torch.int32), dev(dphi)).cpu().numpy()
+    faces = [faces_of(v) for v, _ in meshes]
+    T = Table(tT, 1.0, 1.0)
+    want = np.stack([contact_pose(T, faces[o][c], *x) for (o, c), x in zip(place, dphi)])
+    err = np.abs(P - want).max()
+    say(f"contact poses: max |dP| {err:.3g}")
+    assert err <= 2e-5
+
+
+def test_flat_likelihood_gives_equal_weights(b3d):
+    # no valid observed pixel: logL = 0 for every hypothesis, so the proposal
+    # is the prior and every log weight is 0 (eq. (2), then eq. (3))
+    meshes, _, table, cam, obs = small_table_scene()
+    smc, *_ = gpu_setup(b3d, meshes, table, cam, n_particles=8, ess_threshold=0.5)
+    empty = torch.zeros((cam.H, cam.W, 3), dtype=torch.float32, device="cuda")
+    smc.reset(empty)
+    for i in (1, 2):
+        smc.step()
+        r = smc.read()
+        lw = r["logW"].cpu().numpy()
+        say(f"  flat likelihood, stage {i}: max |logW| {np.abs(lw).max():.3g}, ESS {r['ess'].item():.3f}")
+        assert np.abs(lw).max() <= 1e-4
+        assert abs(r["ess"].item() - 8) <= 1e-6
+        assert np.array_equal(r["ancestors"].cpu().numpy(), np.arange(8))
+
+
+def test_smc_stages_match_oracle(b3d):
+    meshes, truth, table, cam, obs = small_table_scene()
+    smc, types, tmesh, args = gpu_setup(b3d, meshes, table, cam)
+    tv, tt, tT = table
+    fixed = [(tv, tt, tT)]
+    loglik = oracle.smc.scene_loglik(obs, cam, meshes, fixed, 1.0, 5)
+    faces = [faces_of(v) for v, _ in meshes]
+    T = Table(tT, 1.0, 1.0)
+    op = oracle_params(args)
+    smc.reset(dev(obs))
+    r = smc.read()
+    M = args["n_particles"]
+    agree_all = 0
+    for i in (1, 2):
+        st = state_of(r, i - 1)
+        # the oracle's log prior sum for the particles' earlier objects
+        st.lprior = np.array([sum(log_prior(len(faces), T, faces[o][c]) for o, c in st.place[m]) for m in range(M)])
+        new, diag = smc_stage(st, i, loglik, faces, T, op)
+        smc.step()
+        r = smc.read()
+        ch = r["choice"].cpu().numpy()
+        same = np.all(ch == diag["choice"], axis=0) & (r["place"][:, i - 1].cpu().numpy() == diag["place"]).all(1)
+        say(f"stage {i}: particles whose cells all agree: {same.sum()}/{M}")
+        agree_all += same.sum()
+        if not same.any():
+            continue
+        g_dphi = r["dphi"][:, i - 1].cpu().numpy()
+        g_pose = r["poses"][:, i - 1].cpu().numpy()
+        assert np.abs(g_dphi[same] - diag["dphi"][same]).max() <= 2e-5
+        assert np.abs(g_pose[same] - diag["poses"][same]).max() <= 5e-5
+        # noise grid at the proposed placement: eq. (1) over the whole image
+        gg = r["noise_grid"].cpu().numpy().astype(np.float64)
+        og = diag["noise_grid"]
+        rel = np.abs(gg - og) / (np.abs(og) + 1.0)
+        say(f"  noise grid: max rel err (agreeing particles) {rel[same].max():.3g}")
+        assert np.median(rel[same]) <= 1e-4 and rel[same].max() <= 2e-3
+        nsame = same & np.all(np.isclose(r["noise"].cpu().numpy(), diag["noise"], rtol=1e-5, atol=1e-7), axis=1)
+        say(f"  noise draws agree: {nsame.sum()}/{same.sum()}")
+        assert nsame.sum() >= max(1, same.sum() - 1)
+        # log q: the draws' log probabilities, the cell volume and the noise cell area
+        gq = r["logq"].cpu().numpy()
+        assert np.all(np.abs(gq - diag["logq"])[nsame] <= 1e-3 + 1e-4 * np.abs(diag["logq"][nsame]))
+        # logL at the new noise, against the oracle's at the library's own placement
+        gl = r["logL"].cpu().numpy().astype(np.float64)
+        for m in np.nonzero(nsame)[0]:
+            objs = [(int(o), Pq) for (o, c), Pq in zip(r["place"][m, :i].cpu().numpy(),
+                                                        r["poses"][m, :i].cpu().numpy().astype(np.float64))]
+            o_new, P_new = objs[-1]
+            d, _ = oracle.render([(meshes[o_new][0], meshes[o_new][1], P_new)] + fixed +
+                                 [(meshes[o][0], meshes[o][1], Pq) for o, Pq in objs[:-1]], cam)
+            s, p_ = r["noise"][m].cpu().numpy().astype(np.float64)
+            L64, l1 = oracle.score(obs, oracle.unproject(d, cam), float(s), float(p_), 1.0, 5)
+            assert abs(gl[m] - L64[0]) <= 1e-4 * l1[0] + 1e-2, (m, gl[m], L64[0], l1[0])
+        # eq. (2)/(3) on the library's own logL and log q (exact arithmetic check)
+        lpr = np.array([log_prior(len(faces), T, faces[o][c]) for o, c in r["place"][:, i - 1].cpu().numpy()])
+        logp = gl + st.lprior + lpr - np.log(args["sigma_max"])
+        back = 0.0 if i == 1 else -np.log(args["sigma_max"])
+        want = st.logW + logp - st.logp - gq + back
+        assert np.allclose(r["logW_pre"].cpu().numpy(), want, rtol=1e-12, atol=1e-6)
+        assert np.allclose(r["logW"].cpu().numpy(), want, rtol=1e-12, atol=1e-6)  # no resampling here
+        assert np.allclose(r["logp"].cpu().numpy(), logp, rtol=1e-12, atol=1e-6)
+    assert agree_all >= 2 * M - 2
+
+
+def test_resampling_copies_ancestors_and_keeps_the_evidence(b3d):
+    meshes, truth, table, cam, obs = small_table_scene()
+    a, *_ = gpu_setup(b3d, meshes, table, cam, n_particles=16, ess_threshold=0.0)
+    b, *_ = gpu_setup(b3d, meshes, table, cam, n_particles=16, ess_threshold=2.0)
+    o = dev(obs)
+    a.reset(o)
+    b.reset(o)
+    a.step()
+    b.step()
+    ra, rb = a.read(), b.read()
+    # the same proposals (the same counters), then b resamples
+    assert torch.equal(ra["logW_pre"], rb["logW_pre"])
+    anc = rb["ancestors"].cpu().numpy()
+    for key in ("place", "dphi", "poses", "noise", "logL", "logp"):
+        assert torch.equal(rb[key], ra[key][torch.as_tensor(anc, device="cuda").long()]), key
+    lw = ra["logW_pre"].cpu().numpy()
+    lse = lw.max() + np.log(np.exp(lw - lw.max()).sum())
+    assert np.allclose(rb["logW"].cpu().numpy(), lse - np.log(16), rtol=0, atol=1e-9)
+    # the ancestors are the oracle's multinomial draws from the same weights
+    _, want, _ = oracle.sample(lw - lw.max(), 16, 1234, stage=(1 << 8) | 0x80, k0=0)
+    say(f"resampling: ancestors equal to the oracle's draws: {(anc == want).mean():.3f}")
+    assert (anc == want).mean() >= 0.9
+    # ESS from the weights
+    e = np.exp(lw - lw.max())
+    assert np.isclose(rb["ess"].item(), e.sum() ** 2 / (e * e).sum(), rtol=1e-9)
