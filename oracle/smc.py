@@ -204,7 +204,7 @@ def smc_stage(state: Particles, i: int, loglik: LogLik, faces: Sequence[Sequence
                     cells.append((o, c, a, b))
                     cents.append(0.5 * (a + b))
         L = np.concatenate([
-            loglik(m, o, np.stack([contact_pose(table, faces[o][c], *cents[n])
+            loglik(m, o, np.stack([contact_pose(table, faces[o][cells[n][1]], *cents[n])
                                    for n in range(len(cells)) if cells[n][0] == o]), objs, sig, po)
             for o in range(n_types)])
         _, idx, lw = sample(L, 1, seed, stage=(i << 8) | 0, k0=m)

@@ -85,6 +85,25 @@ def test_constant_likelihood_makes_every_weight_the_likelihood(thr):
         assert diag["resampled"] == (thr > 1)
 
 
+def test_every_cell_is_scored_at_its_own_face():
+    # a likelihood of the pose alone that strongly prefers the object's +z
+    # axis pointing up the table normal (face 4, -z, resting): every particle
+    # must choose that face, which it can only if each stage-0 cell's pose
+    # rests on that cell's face
+    rng = np.random.default_rng(9)
+    table = random_table(rng)
+    Tinv = np.linalg.inv(table.T)
+    types = [faces_of(box_verts(rng)) for _ in range(2)]
+    params = _params(41)
+
+    def lik(m, o, P, objs, s, p):
+        up = np.einsum("ij,njk->nik", Tinv, P)[:, 2, 2]  # table-frame z of the object's z axis
+        return 60.0 * up
+
+    st, diag = smc_stage(init_particles(12, params), 1, lik, types, table, params)
+    assert np.all(diag["place"][:, 1] == 4)
+
+
 def test_weights_are_unbiased_for_the_evidence():
     # E_q[p_1 / q] = integral of p_1 = Z for a likelihood with a closed-form
     # integral: exp(L) = exp(a dx) (1 + 0.5 cos dth) (1 + sigma/sigma_max) (2 - p_out)
