@@ -196,6 +196,60 @@ def bench_noise_grid(b3d, torch, scene, P, A=4, B=4, sigma_max=0.01, reps=10):
             "note": "fused render + windowed likelihood under every grid point + marginal, one launch"}
 
 
+def bench_smc(b3d, torch, p=None, n_particles=16, reps=2, seed=4242):
+    """SMC over the objects of the four-object table scene at 320x240: the
+    library is the scene's four meshes, every particle places four objects;
+    per object, stage 0 scores 4 types x 6 faces x 512 placement cells, then
+    two splits of 64 cells, then the 4 x 4 noise cells over the whole image."""
+    from workloads import table_scene
+
+    meshes, poses, table, cam, noise, Tcw = table_scene()
+    objs = [(v, t, P) for (v, t), P in zip(meshes, poses)] + [table]
+    obs = noisy_observation(b3d, torch, gpu_depth(b3d, torch, objs, cam), noise, cam)
+    types = [b3d.Mesh(v, t) for v, t in meshes]
+    tv, tt, tT = table
+    tmesh = b3d.Mesh(tv, tt)
+    counts = ((8, 8, 8), (4, 4, 4), (4, 4, 4))
+    n_obj = len(meshes)
+    sp = b3d.smc_params(n_particles=n_particles, n_objects=n_obj, counts=counts, sigma_max=0.02, noise_A=4, noise_B=4,
+                        sigma0=0.015, p_out0=0.5, ess_threshold=0.5, outlier_volume=1.0, window=5, seed=seed)
+    smc = b3d.SMC(types, b3d.table(tT, 1.0, 1.0), b3d.intrinsics_of(cam), sp, fixed=[tmesh],
+                  fixed_poses=np.asarray(tT, np.float32)[None])
+
+    def run():
+        smc.reset(obs)
+        for _ in range(n_obj):
+            smc.step()
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    n0 = int(np.prod(counts[0])) * 6 * len(types)
+    hyp = n_obj * n_particles * (n0 + sum(int(np.prod(c)) for c in counts[1:]))
+    r = smc.read()
+    best = int(torch.argmax(r["logW"]).item())
+    place = r["place"][best].cpu().numpy()
+    est = r["poses"][best].cpu().numpy()
+    found = []
+    for k, ((v, _), P) in enumerate(zip(meshes, poses)):
+        c = 0.5 * (v.min(0) + v.max(0))
+        ct = P[:3, :3] @ c + P[:3, 3]
+        errs = [np.linalg.norm((est[j][:3, :3] @ c + est[j][:3, 3]) - ct) for j in range(n_obj) if place[j, 0] == k]
+        found.append(round(100 * min(errs), 2) if errs else None)
+    return {"particles": n_particles, "objects": n_obj, "types": len(types), "image": f"{cam.W}x{cam.H}",
+            "ms_per_run": t * 1e3, "hypotheses_per_run": hyp, "hypotheses_per_s": hyp / t,
+            "map_particle": {"types": place[:, 0].tolist(), "faces": place[:, 1].tolist(),
+                             "noise": [round(float(x), 5) for x in r["noise"][best].cpu().numpy()],
+                             "centre_error_cm_per_true_object": found},
+            "ess_last": float(r["ess"].item()),
+            "note": "reset + 4 SMC stages; placement cells scored by the batched fused kernel (16 particles x "
+                    f"{n0} cells at stage 0), noise cells over the whole image, eq. (2)/(3) weights, resampling"}
+
+
 def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3):
     """Many scenes (1-8 objects of 500-8000 voxels, three image sizes, 1k-20k
     hypotheses each) in one persistent launch, forward + adjoint, against the
@@ -365,7 +419,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fused-only", action="store_true", help="skip the split-path comparison")
     ap.add_argument("--no-extras", action="store_true", help="skip the batch, tracking and table workloads")
-    ap.add_argument("--only", choices=["batch", "tracking", "table", "noise_grid"],
+    ap.add_argument("--only", choices=["batch", "tracking", "table", "noise_grid", "smc"],
                     help="run just one of the extra workloads and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (reference for HBM byte counters)")
@@ -384,7 +438,7 @@ def main():
     s = wl.score
     p = b3d.score_params(s.sigma, s.p_out, s.outlier_volume, s.window)
     if args.only and args.only != "noise_grid":
-        fn = {"batch": bench_batch, "tracking": bench_tracking, "table": bench_table_c2f}[args.only]
+        fn = {"batch": bench_batch, "tracking": bench_tracking, "table": bench_table_c2f, "smc": bench_smc}[args.only]
         print(json.dumps({args.only: fn(b3d, torch, p)}), flush=True)
         return
     mesh = b3d.Mesh(wl.verts, wl.tris)
@@ -466,7 +520,8 @@ def main():
         extras["small_config"] = bench_small(b3d, torch, args.steps, args.warmup)
         extras["throughput_vs_n"] = bench_throughput_vs_n(b3d, torch, scene, P)
         extras["noise_grid_4x4"] = bench_noise_grid(b3d, torch, scene, P)
-        for name, fn in (("batch_64_scenes", lambda: bench_batch(b3d, torch, p)),
+        for name, fn in (("smc_table_scene", lambda: bench_smc(b3d, torch)),
+                         ("batch_64_scenes", lambda: bench_batch(b3d, torch, p)),
                          ("tracking_200_frames", lambda: bench_tracking(b3d, torch, p)),
                          ("table_c2f_adam", lambda: bench_table_c2f(b3d, torch, p))):
             t0 = time.perf_counter()

@@ -567,7 +567,7 @@ b3d_status b3d_render_score_marginal(const b3d_scene* S, const float* poses, int
   if (N < 0) return fail(B3D_ESHAPE, "render_score_marginal: N < 0");
   if (N == 0) return B3D_OK;
   if (!poses || !logL_marg) return fail(B3D_EINVAL, "render_score_marginal: NULL pointer");
-  B3D_CHECK_HIP(launch_render_score_grid(S->dev, S->grid, poses, N, logL_grid, logL_marg, 0, (hipStream_t)stream),
+  B3D_CHECK_HIP(launch_render_score_grid(S->dev, S->grid, poses, N, logL_grid, logL_marg, (hipStream_t)stream),
                 "render_score_marginal");
   return B3D_OK;
 }

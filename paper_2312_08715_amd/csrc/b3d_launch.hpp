@@ -44,6 +44,9 @@ struct SceneDev {
 // each stride-spaced group of three, as the scene's own).
 constexpr int kMaxNoise = 16;
 constexpr int kMaxSigma = 8;
+// Scenes per multi-scene launch (their descriptors travel as kernel arguments).
+constexpr int kBatchGroup = 8;
+
 struct NoiseGridDev {
   int A, B;
   float c2[kMaxSigma];     // log2(e) / (2 sigma_a^2)
@@ -55,10 +58,28 @@ struct NoiseGridDev {
   const double* sat;
   long long sat_stride;    // doubles between consecutive grid points' tables
 };
-// full = 1: every observed pixel of the image is scored in the kernel (the
-// grid's tables are not read).
 hipError_t launch_render_score_grid(const SceneDev& s, const NoiseGridDev& g, const float* poses, int N,
-                                    float* logL_grid, float* logL_marg, int full, hipStream_t st);
+                                    float* logL_grid, float* logL_marg, hipStream_t st);
+
+// Whole-image scores of one pose per scene, for up to kBatchGroup scenes
+// (one camera size, one LDS size: the first scene's), each under the group's
+// noise grid or under its own (sigma, p_out) at noise[j].
+struct RowsGroupDev {
+  SceneDev s[kBatchGroup];
+  const float* pose[kBatchGroup];   // device float[16]
+  const float* noise[kBatchGroup];  // device float[2] or nullptr
+  NoiseGridDev grid;
+  double inv_V, M_norm;             // for the per-scene noise
+  int first;                        // index of scene 0 in the partial-sum rows
+  int S;
+};
+static_assert(sizeof(RowsGroupDev) <= 4000, "a rows group must fit the kernel-argument segment");
+// Bands of R full-width rows per block: partial[(scene n_bands + band) kMaxNoise + k].
+hipError_t launch_score_rows_grid(const RowsGroupDev& G, int R, int n_bands, float* partial, hipStream_t st);
+// Band sums per (scene, grid point) in band order (double), logL to
+// grid_out[scene nk + k], and the weighted log-sum-exp to marg_out (or none).
+hipError_t launch_reduce_rows_grid(const float* partial, int P, int n_bands, int nk, const NoiseGridDev& g,
+                                   float* grid_out, float* marg_out, hipStream_t st);
 
 // Table-contact placement (see b3d_contact_poses): the resting frame of face
 // c of a type's bounding box and the log prior density of a placement on it.
@@ -135,7 +156,6 @@ hipError_t launch_smc_resample(int M, int n_slots, int k, float threshold, const
 // global memory, so the compiler addresses through them with a scalar base
 // (pointers read from a device array would be generic, flat-addressed).
 // Scene k's hypotheses are work items [first[k], first[k + 1]).
-constexpr int kBatchGroup = 8;
 struct BatchGroupDev {
   SceneDev s[kBatchGroup];
   const float* poses[kBatchGroup];

@@ -529,13 +529,14 @@ __device__ __forceinline__ void window_sums_grid(const unsigned long long* __res
 // logL of one hypothesis under every point of the noise grid (grid_out[k],
 // k = a * B + b) and their weighted log-sum-exp (*marg_out).  The same
 // render and windows as render_score_one; each observed pixel's window
-// distances are computed once and exponentiated per deviation.  full = 1
-// walks every observed pixel of the image in bands of full-width rows
-// instead of the object's region plus the background tables (no table is
-// read).  Whole block.
+// distances are computed once and exponentiated per deviation.  With
+// row0 >= 0 the block instead scores the full-width image rows [row0, row1)
+// (their pixels only, no background table) and grid_out[k] receives the
+// block's sum for grid point k; marg_out is not written.  Whole block.
 __device__ __forceinline__ void render_score_grid_one(const SceneDev& s, const NoiseGridDev& g,
                                                       const float* __restrict__ pose16, float* __restrict__ grid_out,
-                                                      float* __restrict__ marg_out, unsigned char* smem, int full) {
+                                                      float* __restrict__ marg_out, unsigned char* smem, int row0,
+                                                      int row1) {
   unsigned long long* zbuf = reinterpret_cast<unsigned long long*>(smem + kRasterLdsBytes);
   float* red = reinterpret_cast<float*>(zbuf + s.zcap);
   float* sbuf = reinterpret_cast<float*>(smem);  // per thread: S[a] normM[a] (raster scratch, free by then)
@@ -546,20 +547,27 @@ __device__ __forceinline__ void render_score_grid_one(const SceneDev& s, const N
   const Pose P = load_pose(pose16);
   for (int i = (int)threadIdx.x - 2 * h; i < W + 2 * h; i += kBlock) dxt[i] = ray_x(cam, i);
   for (int i = (int)threadIdx.x - 2 * h; i < H + 2 * h; i += kBlock) dyt[i] = ray_y(cam, i);
+  const bool rows = row0 >= 0;
   Rect all;
   all.x0 = 0;
   all.x1 = W;
   all.y0 = 0;
   all.y1 = H;
-  const Rect obj = full ? all : object_rect(s.mesh, P, cam);
-  Rect region = grow_clip(obj, h, W, H);
+  Rect obj = all;
+  if (rows) {
+    obj.y0 = row0;
+    obj.y1 = row1;
+  } else {
+    obj = object_rect(s.mesh, P, cam);
+  }
+  Rect region = rows ? obj : grow_clip(obj, h, W, H);
   if (obj.empty()) region.x1 = region.x0;
   const int nk_grid = g.A * g.B;
   float acc[kMaxNoise];
 #pragma unroll
   for (int k = 0; k < kMaxNoise; ++k) acc[k] = 0.0f;
   if (!obj.empty()) {
-    const Rect lds = grow(full ? all : obj, 2 * h);
+    const Rect lds = grow(obj, 2 * h);
     const int lw = lds.w(), rw = region.w();
     const int band = max(s.zcap / lw - 4 * h, 1);
     for (int a = region.y0; a < region.y1; a += band) {
@@ -598,13 +606,14 @@ __device__ __forceinline__ void render_score_grid_one(const SceneDev& s, const N
   }
   block_sum<kMaxNoise>(acc, red);
   if (threadIdx.x == 0) {
+    if (rows) {
+      for (int k = 0; k < nk_grid; ++k) grid_out[k] = acc[k];
+      return;
+    }
     double v[kMaxNoise], m = -1e300;
     for (int k = 0; k < nk_grid; ++k) {
-      v[k] = (double)acc[k];
-      if (!full) {
-        const double* sat = g.sat + g.sat_stride * k;
-        v[k] += rect_sum(sat, W, all) - rect_sum(sat, W, region);
-      }
+      const double* sat = g.sat + g.sat_stride * k;
+      v[k] = (double)acc[k] + rect_sum(sat, W, all) - rect_sum(sat, W, region);
       grid_out[k] = (float)v[k];
       m = fmax(m, v[k] + (double)g.logw[k]);
     }
@@ -617,19 +626,94 @@ __device__ __forceinline__ void render_score_grid_one(const SceneDev& s, const N
 __global__ __launch_bounds__(kBlock, 4) void k_render_score_grid(SceneDev s, NoiseGridDev g,
                                                                  const float* __restrict__ poses, int N,
                                                                  float* __restrict__ logL_grid,
-                                                                 float* __restrict__ logL_marg, int full) {
+                                                                 float* __restrict__ logL_marg) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = blockIdx.x;
   if (n >= N) return;
   float dummy[kMaxNoise];
   float* gout = logL_grid ? logL_grid + (size_t)g.A * g.B * n : dummy;
-  render_score_grid_one(s, g, poses + 16 * (size_t)n, gout, logL_marg + n, smem, full);
+  render_score_grid_one(s, g, poses + 16 * (size_t)n, gout, logL_marg + n, smem, -1, -1);
 }
 
 hipError_t launch_render_score_grid(const SceneDev& s, const NoiseGridDev& g, const float* poses, int N,
-                                    float* logL_grid, float* logL_marg, int full, hipStream_t st) {
+                                    float* logL_grid, float* logL_marg, hipStream_t st) {
   hipLaunchKernelGGL(k_render_score_grid, dim3(N), dim3(kBlock), fused_lds_bytes(s), st, s, g, poses, N, logL_grid,
-                     logL_marg, full);
+                     logL_marg);
+  return hipGetLastError();
+}
+
+// The noise grid of one observation point (sigma, p_out): the constants of
+// eq. (1) as the host computes them, in double then rounded.
+__device__ NoiseGridDev grid_point(float sigma, float p_out, double inv_V, double M) {
+  NoiseGridDev g{};
+  const double s = sigma;
+  g.A = 1;
+  g.B = 1;
+  g.c2[0] = (float)(1.0 / (2.0 * s * s) / 0.69314718055994530942);
+  g.normM[0] = (float)(pow(2.0 * 3.14159265358979323846 * s * s, -1.5) / M);
+  g.ka[0] = 0;
+  g.pa[0] = (float)((double)p_out * inv_V);
+  g.pomp[0] = (float)(1.0 - (double)p_out);
+  g.logw[0] = 0.0f;
+  return g;
+}
+
+// Block (band b, scene j of the group): full-width rows [b R, (b + 1) R) of
+// scene j's image under the group's noise grid, or under the scene's own
+// (sigma, p_out) when G.noise[j] is set; per-point sums to
+// partial[((G.first + j) n_bands + b) kMaxNoise + k].
+__global__ __launch_bounds__(kBlock) void k_score_rows_grid(RowsGroupDev G, int R, int n_bands,
+                                                            float* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.x, j = blockIdx.y;
+  if (j >= G.S) return;
+  const SceneDev& s = G.s[j];
+  const int row0 = b * R;
+  const int row1 = min(s.cam.H, row0 + R);
+  float* out = partial + ((size_t)(G.first + j) * n_bands + b) * kMaxNoise;
+  if (row0 >= row1) {
+    if (threadIdx.x < kMaxNoise) out[threadIdx.x] = 0.0f;
+    return;
+  }
+  if (G.noise[j]) {
+    const NoiseGridDev g = grid_point(G.noise[j][0], G.noise[j][1], G.inv_V, G.M_norm);
+    render_score_grid_one(s, g, G.pose[j], out, nullptr, smem, row0, row1);
+  } else {
+    render_score_grid_one(s, G.grid, G.pose[j], out, nullptr, smem, row0, row1);
+  }
+}
+
+// One thread per (scene, grid point): the band sums in band order, in
+// double; then per scene the log-sum-exp with the grid's log weights.
+__global__ void k_reduce_rows_grid(const float* __restrict__ partial, int P, int n_bands, int nk,
+                                   NoiseGridDev g, float* __restrict__ grid_out, float* __restrict__ marg_out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  double v[kMaxNoise], m = -1e300;
+  for (int k = 0; k < nk; ++k) {
+    double t = 0.0;
+    for (int b = 0; b < n_bands; ++b) t += (double)partial[((size_t)p * n_bands + b) * kMaxNoise + k];
+    v[k] = t;
+    grid_out[(size_t)p * nk + k] = (float)t;
+    m = fmax(m, t + (double)g.logw[k]);
+  }
+  if (marg_out) {
+    double t = 0.0;
+    for (int k = 0; k < nk; ++k) t += exp(v[k] + (double)g.logw[k] - m);
+    marg_out[p] = (float)(m + log(t));
+  }
+}
+
+hipError_t launch_score_rows_grid(const RowsGroupDev& G, int R, int n_bands, float* partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_score_rows_grid, dim3(n_bands, G.S), dim3(kBlock), fused_lds_bytes(G.s[0]), st, G, R, n_bands,
+                     partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_rows_grid(const float* partial, int P, int n_bands, int nk, const NoiseGridDev& g,
+                                   float* grid_out, float* marg_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_rows_grid, dim3((P + 63) / 64), dim3(64), 0, st, partial, P, n_bands, nk, g, grid_out,
+                     marg_out);
   return hipGetLastError();
 }
 

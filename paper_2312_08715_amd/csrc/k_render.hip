@@ -159,10 +159,15 @@ hipError_t launch_fill_keys(unsigned long long* keys, size_t n, hipStream_t st) 
   return hipGetLastError();
 }
 
-// One thread per triangle, whole image, global 64-bit atomicMin: used once
-// per scene to draw the static objects.
+// One thread per (triangle, slice of its rows), whole image, global 64-bit
+// atomicMin: used per scene to draw the static objects.  Slicing the rows
+// keeps a triangle that spans the image (a table top) from serialising on
+// one thread; the minimum does not depend on the order.
+constexpr int kRasterSlices = 32;
+
 __global__ void k_raster_global(MeshDev m, Cam cam, Pose P, uint32_t id_base, unsigned long long* keys) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int slice = blockIdx.y;
   if (i >= m.T) return;
   const int4 tr = m.tris[i];
   float4 pv[3];
@@ -186,7 +191,7 @@ __global__ void k_raster_global(MeshDev m, Cam cam, Pose P, uint32_t id_base, un
   const float e0x = p2.x - p1.x, e0y = p2.y - p1.y;
   const float e1x = p0.x - p2.x, e1y = p0.y - p2.y;
   const float e2x = p1.x - p0.x, e2y = p1.y - p0.y;
-  for (int r = (int)fr0; r <= (int)fr1; ++r) {
+  for (int r = (int)fr0 + slice; r <= (int)fr1; r += kRasterSlices) {
     const float py = (float)r + 0.5f;
     for (int c = (int)fc0; c <= (int)fc1; ++c) {
       const float px = (float)c + 0.5f;
@@ -224,7 +229,8 @@ hipError_t launch_raster_global(const MeshDev& m, const Cam& cam, const float* p
     for (int j = 0; j < 3; ++j) P.r[3 * i + j] = pose16[4 * i + j];
     P.t[i] = pose16[4 * i + 3];
   }
-  hipLaunchKernelGGL(k_raster_global, dim3((m.T + 255) / 256), dim3(256), 0, st, m, cam, P, id_base, keys);
+  hipLaunchKernelGGL(k_raster_global, dim3((m.T + 255) / 256, kRasterSlices), dim3(256), 0, st, m, cam, P, id_base,
+                     keys);
   return hipGetLastError();
 }
 

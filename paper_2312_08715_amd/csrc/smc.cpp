@@ -102,10 +102,49 @@ struct b3d_smc {
   float *hyp = nullptr, *logL_h = nullptr, *logw = nullptr, *nlogw = nullptr, *lw_shift = nullptr;
   float *dphi_new = nullptr, *pose_new = nullptr, *noise_new = nullptr, *logL_new = nullptr, *noise_grid = nullptr;
   float* marg = nullptr;
+  float* partial = nullptr;  // [M][n_bands][kMaxNoise] band sums of the whole-image scores
+  int rows_R = 0, n_bands = 0;
   unsigned long long* counters = nullptr;
   int max_groups = 0;
   std::vector<void*> owned;
 };
+
+// Whole-image logL of each particle's scene with its proposed object at
+// pose_new: under the noise cells' midpoints (into noise_grid) or, with
+// own_noise, under the particle's proposed noise (into logL_new).
+static b3d_status whole_image_scores(b3d_smc* S, hipStream_t st, const std::vector<int>& type_of,
+                                     const std::vector<int>& rep, bool own_noise) {
+  const b3d_smc_params& p = S->p;
+  const int M = p.n_particles;
+  for (int g0 = 0; g0 < M; g0 += kBatchGroup) {
+    RowsGroupDev G{};
+    G.S = std::min(kBatchGroup, M - g0);
+    G.first = g0;
+    G.grid = S->noise_mid;
+    G.inv_V = 1.0 / (double)p.outlier_volume;
+    G.M_norm = p.norm_M > 0 ? (double)p.norm_M : (double)S->K.H * S->K.W;
+    for (int j = 0; j < G.S; ++j) {
+      const int m = g0 + j;
+      SceneDev d = S->scenes[rep[m]]->dev;
+      d.mesh = S->types[type_of[m]]->dev;
+      d.zcap = max_zcap(d);
+      G.s[j] = d;
+      G.pose[j] = S->pose_new + 16 * (size_t)m;
+      G.noise[j] = own_noise ? S->noise_new + 2 * (size_t)m : nullptr;
+    }
+    B3D_CHECK_HIP(launch_score_rows_grid(G, S->rows_R, S->n_bands, S->partial, st), "smc_step");
+  }
+  NoiseGridDev one{};
+  if (own_noise) {
+    one.A = one.B = 1;
+    one.logw[0] = 0.0f;
+  }
+  const NoiseGridDev& g = own_noise ? one : S->noise_mid;
+  B3D_CHECK_HIP(launch_reduce_rows_grid(S->partial, M, S->n_bands, g.A * g.B, g, own_noise ? S->logL_new : S->noise_grid,
+                                        nullptr, st),
+                "smc_step");
+  return B3D_OK;
+}
 
 extern "C" {
 
@@ -248,6 +287,16 @@ b3d_status b3d_smc_create(const b3d_mesh* const* types, int32_t n_types, const b
       (s = dev_alloc(S->owned, &S->logL_new, (size_t)M)) ||
       (s = dev_alloc(S->owned, &S->noise_grid, (size_t)M * A * B)) || (s = dev_alloc(S->owned, &S->marg, (size_t)M)))
     return bail(s);
+  {
+    // whole-image scores in bands of full-width rows, the largest that fit
+    SceneDev d = S->scenes[0]->dev;
+    d.zcap = max_zcap(d);
+    const int h = d.sc.h;
+    S->rows_R = d.zcap / (K->W + 4 * h) - 4 * h;
+    if (S->rows_R < 1) return bail(fail(B3D_ESHAPE, "smc_create: image too wide for whole-image scoring"));
+    S->n_bands = (K->H + S->rows_R - 1) / S->rows_R;
+    if ((s = dev_alloc(S->owned, &S->partial, (size_t)M * S->n_bands * kMaxNoise))) return bail(s);
+  }
   S->max_groups = (M * n_types + kBatchGroup - 1) / kBatchGroup;
   if ((s = dev_alloc(S->owned, &S->counters, 32 * (size_t)S->max_groups))) return bail(s);
   // the root cells (every type and face: dx, dy over the table less the
@@ -326,9 +375,30 @@ b3d_status b3d_smc_step(b3d_smc* S, void* stream) {
                   "smc_step");
   }
   B3D_CHECK_HIP(hipStreamSynchronize(st), "smc_step");
+  // particles with equal noise and equal objects (copies made by resampling,
+  // and all of them before the first object) score every hypothesis alike:
+  // one scene per distinct state, its stage-0 scores copied to the others
+  std::vector<int> rep((size_t)M);
+  for (int m = 0; m < M; ++m) {
+    rep[m] = m;
+    for (int u = 0; u < m; ++u) {
+      if (rep[u] != u) continue;
+      bool same = h_noise[2 * u] == h_noise[2 * m] && h_noise[2 * u + 1] == h_noise[2 * m + 1];
+      for (int j = 0; same && j < k; ++j) {
+        const size_t a = (size_t)u * n + j, b = (size_t)m * n + j;
+        same = h_place[2 * a] == h_place[2 * b] &&
+               std::memcmp(&h_poses[16 * a], &h_poses[16 * b], 16 * sizeof(float)) == 0;
+      }
+      if (same) {
+        rep[m] = u;
+        break;
+      }
+    }
+  }
   std::vector<const b3d_mesh*> bg_mesh;
   std::vector<float> bg_pose;
   for (int m = 0; m < M; ++m) {
+    if (rep[m] != m) continue;
     bg_mesh.assign(S->fixed.begin(), S->fixed.end());
     bg_pose.assign(S->fixed_poses.begin(), S->fixed_poses.end());
     for (int j = 0; j < k; ++j) {
@@ -343,7 +413,7 @@ b3d_status b3d_smc_step(b3d_smc* S, void* stream) {
     if (b3d_status s = b3d_scene_set_observed(sc, S->observed, st)) return s;
   }
   auto scene_of = [&](int m, int o) {
-    SceneDev d = S->scenes[m]->dev;
+    SceneDev d = S->scenes[rep[m]]->dev;
     d.mesh = S->types[o]->dev;
     return d;
   };
@@ -352,12 +422,18 @@ b3d_status b3d_smc_step(b3d_smc* S, void* stream) {
   const int n0 = p.counts[0][0] * p.counts[0][1] * p.counts[0][2], N0 = S->n_stage0;
   std::vector<BatchItemDev> items;
   for (int m = 0; m < M; ++m)
-    for (int o = 0; o < n_types; ++o)
-      items.push_back(BatchItemDev{scene_of(m, o), S->stage0_poses + 16 * (size_t)o * 6 * n0, 6 * n0,
-                                   S->logL_h + (size_t)m * N0 + (size_t)o * 6 * n0, nullptr});
+    if (rep[m] == m)
+      for (int o = 0; o < n_types; ++o)
+        items.push_back(BatchItemDev{scene_of(m, o), S->stage0_poses + 16 * (size_t)o * 6 * n0, 6 * n0,
+                                     S->logL_h + (size_t)m * N0 + (size_t)o * 6 * n0, nullptr});
   BatchPlan plan;
   if (b3d_status s = plan_batch(items, false, &plan)) return s;
   if (b3d_status s = run_batch(plan, S->counters, st)) return s;
+  for (int m = 0; m < M; ++m)
+    if (rep[m] != m)
+      B3D_CHECK_HIP(hipMemcpyAsync(S->logL_h + (size_t)m * N0, S->logL_h + (size_t)rep[m] * N0, sizeof(float) * N0,
+                                   hipMemcpyDeviceToDevice, st),
+                    "smc_step");
   B3D_CHECK_HIP(launch_sample(S->logL_h, M, N0, 1, key0, key1, ((uint32_t)i << 8) | 0u, 0u, nullptr, S->idx, S->logw, st),
                 "smc_step");
   B3D_CHECK_HIP(launch_contact_choose(S->roots, p.counts[0][0], p.counts[0][1], p.counts[0][2], S->idx, S->logw, M,
@@ -390,13 +466,7 @@ b3d_status b3d_smc_step(b3d_smc* S, void* stream) {
                 "smc_step");
 
   // the noise: midpoint-scored cells over the whole image, then a uniform point of the drawn one
-  for (int m = 0; m < M; ++m) {
-    SceneDev d = scene_of(m, type_of[m]);
-    d.zcap = max_zcap(d);
-    B3D_CHECK_HIP(launch_render_score_grid(d, S->noise_mid, S->pose_new + 16 * (size_t)m, 1,
-                                           S->noise_grid + (size_t)m * AB, S->marg + m, 1, st),
-                  "smc_step");
-  }
+  if (b3d_status s = whole_image_scores(S, st, type_of, rep, false)) return s;
   B3D_CHECK_HIP(launch_sample(S->noise_grid, M, AB, 1, key0, key1, ((uint32_t)i << 8) | 0x40u, 0u, nullptr, S->nidx,
                               S->nlogw, st),
                 "smc_step");
@@ -404,19 +474,7 @@ b3d_status b3d_smc_step(b3d_smc* S, void* stream) {
                                   S->noise_new, S->logq, st),
                 "smc_step");
   // logL of each particle's scene at its new noise
-  B3D_CHECK_HIP(hipMemcpyAsync(h_noise.data(), S->noise_new, sizeof(float) * M * 2, hipMemcpyDeviceToHost, st),
-                "smc_step");
-  B3D_CHECK_HIP(hipStreamSynchronize(st), "smc_step");
-  for (int m = 0; m < M; ++m) {
-    b3d_score_params sp{h_noise[2 * m], h_noise[2 * m + 1], p.outlier_volume, p.norm_M, p.window};
-    NoiseGridDev one{};
-    std::vector<b3d_score_params> per;
-    if (b3d_status s = make_noise_grid(sp, S->K.H, S->K.W, &sp.sigma, 1, &sp.p_out, 1, nullptr, &one, &per)) return s;
-    SceneDev d = scene_of(m, type_of[m]);
-    d.zcap = max_zcap(d);
-    B3D_CHECK_HIP(launch_render_score_grid(d, one, S->pose_new + 16 * (size_t)m, 1, S->logL_new + m, S->marg + m, 1, st),
-                  "smc_step");
-  }
+  if (b3d_status s = whole_image_scores(S, st, type_of, rep, true)) return s;
 
   // eq. (2)/(3), then resampling
   StageDev sd{S->cells, S->dphi_new, S->pose_new, S->noise_new, S->logL_new, S->logq, S->logp_new, S->lprior_new,
