@@ -539,8 +539,13 @@ typedef struct b3d_smc_view {
   double* ess;        /* [1] */
 } b3d_smc_view;
 
-/* n_placed (host, may be NULL): objects placed so far.  Stream-ordered. */
-b3d_status b3d_smc_read(const b3d_smc* smc, const b3d_smc_view* view, int32_t* n_placed, void* stream);
+/* n_placed (host, may be NULL): objects placed so far; n_scored (host, may
+ * be NULL): placement hypotheses rendered and scored since the reset
+ * (particles with equal noise and equal objects -- all of them before the
+ * first object, and the copies made by resampling -- share one scoring of
+ * the stage-0 cells).  Unplaced slots read as zeros.  Stream-ordered. */
+b3d_status b3d_smc_read(const b3d_smc* smc, const b3d_smc_view* view, int32_t* n_placed, int64_t* n_scored,
+                        void* stream);
 b3d_status b3d_smc_destroy(b3d_smc* smc);
 
 #ifdef __cplusplus

@@ -136,7 +136,8 @@ _SIGNATURES = {
                         ctypes.POINTER(SMCParams), ctypes.POINTER(_P)], ctypes.c_int),
     "b3d_smc_reset": ([_P, _P, _P], ctypes.c_int),
     "b3d_smc_step": ([_P, _P], ctypes.c_int),
-    "b3d_smc_read": ([_P, ctypes.POINTER(SMCView), ctypes.POINTER(_I32), _P], ctypes.c_int),
+    "b3d_smc_read": ([_P, ctypes.POINTER(SMCView), ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_int64), _P],
+                     ctypes.c_int),
     "b3d_smc_destroy": ([_P], ctypes.c_int),
 }
 
@@ -728,10 +729,11 @@ class SMC:
                    ancestors=torch.empty(M, dtype=torch.int32, device=d),
                    ess=torch.empty(1, dtype=torch.float64, device=d))
         v = SMCView(*[_ptr(out[k]) for k, _ in SMCView._fields_])
-        k = _I32()
-        _call("b3d_smc_read", self._h, ctypes.byref(v), ctypes.byref(k), _stream())
+        k, ns = _I32(), ctypes.c_int64()
+        _call("b3d_smc_read", self._h, ctypes.byref(v), ctypes.byref(k), ctypes.byref(ns), _stream())
         torch.cuda.current_stream().synchronize()
         out["placed"] = int(k.value)
+        out["scored"] = int(ns.value)
         return out
 
     def close(self):

@@ -104,6 +104,7 @@ struct b3d_smc {
   float* marg = nullptr;
   float* partial = nullptr;  // [M][n_bands][kMaxNoise] band sums of the whole-image scores
   int rows_R = 0, n_bands = 0;
+  long long scored = 0;  // hypotheses rendered and scored since the last reset
   unsigned long long* counters = nullptr;
   int max_groups = 0;
   std::vector<void*> owned;
@@ -339,6 +340,14 @@ b3d_status b3d_smc_reset(b3d_smc* S, const float* observed, void* stream) {
     noise[2 * m] = S->p.sigma0;
     noise[2 * m + 1] = S->p.p_out0;
   }
+  const int n = S->p.n_objects;
+  for (int b = 0; b < 2; ++b) {  // slots of objects not yet placed read as zeros
+    const PartDev& z = S->st[b];
+    B3D_CHECK_HIP(hipMemsetAsync(z.place, 0, sizeof(int) * M * n * 2, st), "smc_reset");
+    B3D_CHECK_HIP(hipMemsetAsync(z.dphi, 0, sizeof(float) * M * n * 3, st), "smc_reset");
+    B3D_CHECK_HIP(hipMemsetAsync(z.poses, 0, sizeof(float) * M * n * 16, st), "smc_reset");
+  }
+  S->scored = 0;
   const PartDev& d = S->st[0];
   B3D_CHECK_HIP(hipMemcpyAsync(d.noise, noise.data(), sizeof(float) * noise.size(), hipMemcpyHostToDevice, st),
                 "smc_reset");
@@ -429,6 +438,7 @@ b3d_status b3d_smc_step(b3d_smc* S, void* stream) {
   BatchPlan plan;
   if (b3d_status s = plan_batch(items, false, &plan)) return s;
   if (b3d_status s = run_batch(plan, S->counters, st)) return s;
+  for (const BatchItemDev& it : items) S->scored += it.N;
   for (int m = 0; m < M; ++m)
     if (rep[m] != m)
       B3D_CHECK_HIP(hipMemcpyAsync(S->logL_h + (size_t)m * N0, S->logL_h + (size_t)rep[m] * N0, sizeof(float) * N0,
@@ -454,6 +464,7 @@ b3d_status b3d_smc_step(b3d_smc* S, void* stream) {
                                    S->logL_h + (size_t)m * ns, nullptr});
     if (b3d_status s = plan_batch(items, false, &plan)) return s;
     if (b3d_status s = run_batch(plan, S->counters, st)) return s;
+    S->scored += (long long)M * ns;
     B3D_CHECK_HIP(launch_sample(S->logL_h, M, ns, 1, key0, key1, ((uint32_t)i << 8) | (uint32_t)t, 0u, nullptr, S->idx,
                                 S->logw, st),
                   "smc_step");
@@ -489,7 +500,8 @@ b3d_status b3d_smc_step(b3d_smc* S, void* stream) {
   return B3D_OK;
 }
 
-b3d_status b3d_smc_read(const b3d_smc* S, const b3d_smc_view* v, int32_t* n_placed, void* stream) {
+b3d_status b3d_smc_read(const b3d_smc* S, const b3d_smc_view* v, int32_t* n_placed, int64_t* n_scored,
+                        void* stream) {
   if (!S || !v) return fail(B3D_EINVAL, "smc_read: NULL pointer");
   hipStream_t st = (hipStream_t)stream;
   const int M = S->p.n_particles, n = S->p.n_objects, AB = S->p.noise_A * S->p.noise_B;
@@ -510,6 +522,7 @@ b3d_status b3d_smc_read(const b3d_smc* S, const b3d_smc_view* v, int32_t* n_plac
     if (x != hipSuccess) e = x;
   if (e != hipSuccess) return hip_fail(e, "smc_read");
   if (n_placed) *n_placed = S->placed;
+  if (n_scored) *n_scored = S->scored;
   return B3D_OK;
 }
 
