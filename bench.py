@@ -512,8 +512,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # the chip's FP32 vector FMA rate, measured by an FMA-loop kernel (lane-ops/s)
+    # the chip's peaks, re-measured by microbenchmarks: an FMA loop (lane-ops/s),
+    # an HBM triad and an LDS read loop (bytes/s)
     valu_measured = b3d.probe_fma() / 1e12
+    peaks = {"valu_TOPs": valu_measured, "hbm_GBps": b3d.probe_hbm() / 1e9, "lds_TBps": b3d.probe_lds() / 1e12}
     work = counted_work(b3d, scene, P)
     ops = lane_ops(work, adjoint=True)
     achieved = ops / t_kernel / 1e12
@@ -561,19 +563,48 @@ def main():
         "plain_split": {"value": N / t_split, "ms_per_step": t_split * 1e3,
                         "note": "render_batch -> score, point images in HBM"},
         "plain_split_fwd_adjoint": {"value": N / t_split_adj, "ms_per_step": t_split_adj * 1e3},
+        "peaks_measured": peaks,
         "cpu_baseline": cpu,
     }
     line.update(extras)
     print(json.dumps(line), flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, obs64, seconds):
     """The FP64 oracle (render, score, both adjoints) on hypotheses of the same
-    workload, in chunks, until about `seconds` of CPU time; all host threads."""
+    workload, in chunks, until about `seconds` of CPU time; all host threads,
+    then one thread on a smaller sample."""
     import oracle
 
     s = wl.score
     P = oracle.enumerate_grid(wl.grid, seed=wl.seeds["hyp"])
+
+    def run(limit, max_done):
+        done, t0 = 0, time.perf_counter()
+        while done < min(P.shape[0], max_done) and time.perf_counter() - t0 < limit:
+            Q = P[done:done + 16]
+            d, ids = oracle.render([(wl.verts, wl.tris, Q)], wl.camera)
+            xyz = oracle.unproject(d, wl.camera)
+            oracle.score(obs64, xyz, s.sigma, s.p_out, s.outlier_volume, s.window)
+            dr, ds, dp = oracle.score_grad(obs64, xyz, s.sigma, s.p_out, s.outlier_volume, s.window)
+            oracle.render_grad(wl.verts, wl.tris, Q, wl.camera, ids, d, dr)
+            done += Q.shape[0]
+        return done, time.perf_counter() - t0
+
+    all_threads = oracle.num_threads()
+    oracle.set_threads(1)
+    one_done, one_dt = run(max(2.0, seconds / 5), 1 << 30)
+    oracle.set_threads(all_threads)
     done, t0 = 0, time.perf_counter()
     cnt_sum = np.zeros(oracle.NC)
     chunk = 64
@@ -591,7 +622,10 @@ def cpu_baseline(wl, obs64, seconds):
     counts = {"vert": m[oracle.C_VERT], "tri": m[oracle.C_TRI], "front": m[oracle.C_FRONT], "frag": m[oracle.C_FRAG],
               "pair": m[oracle.C_PAIR], "obs": m[oracle.C_OBS_ACTIVE], "rpix": m[oracle.C_RPIX]}
     return ({"value": done / dt, "unit": "hypotheses/s", "cores": oracle.num_threads(), "kind": "oracle",
-             "sample": f"first {done} of {P.shape[0]} hypotheses, render+score+adjoint in FP64"}, counts)
+             "sample": f"first {done} of {P.shape[0]} hypotheses, render+score+adjoint in FP64",
+             "cpu": cpu_model(), "host_cpus": os.cpu_count(),
+             "single_thread": {"value": one_done / one_dt, "unit": "hypotheses/s",
+                               "sample": f"first {one_done} hypotheses, one thread"}}, counts)
 
 
 if __name__ == "__main__":

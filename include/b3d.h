@@ -352,6 +352,18 @@ b3d_status b3d_c2f_step(const b3d_scene* scene, const float* center, const b3d_s
  * measure the chip's FP32 vector FMA rate.  Stream-ordered. */
 b3d_status b3d_probe_fma(float* out, int32_t blocks, int32_t iters, void* stream);
 
+/* Peak probe (not part of the method): one pass of c = a + 1.5 b over n
+ * floats (n a positive multiple of 4; device buffers, 16-byte aligned): 12 n
+ * bytes of HBM traffic when the buffers exceed the caches.  Time it on
+ * `stream`.  Stream-ordered. */
+b3d_status b3d_probe_hbm(const float* a, const float* b, float* c, int64_t n, void* stream);
+
+/* Peak probe (not part of the method): blocks x 256 lanes each read
+ * iters x 32 16-byte LDS words (conflict-free); out: device float[blocks *
+ * 256].  Time it on `stream` to measure LDS read bandwidth.
+ * Stream-ordered. */
+b3d_status b3d_probe_lds(float* out, int32_t blocks, int32_t iters, void* stream);
+
 /* Retraction onto the pose manifold, the update convention of the adjoint
  * (Sec. III-B's pose grid composed as t = t_c + dt, R = dR R_c, with dR the
  * rotation exponential): out[n] = (exp([w_n]x) R_b, t_b + dt_n) for
@@ -537,6 +549,8 @@ typedef struct b3d_smc_view {
   float* noise_grid;  /* [M][A * B] logL at the noise cells' midpoints */
   int32_t* ancestors; /* [M] particle each survivor copies (identity without resampling) */
   double* ess;        /* [1] */
+  float* type_post;   /* [M][n_types] posterior over the new object's type from the stage-0 cells: the softmax
+                         mass of each type's cells, marginal over face and placement */
 } b3d_smc_view;
 
 /* n_placed (host, may be NULL): objects placed so far; n_scored (host, may

@@ -83,6 +83,8 @@ def _declare(L):
     L.orc_perturbation.argtypes = [ctypes.c_uint64, ctypes.c_uint32, I, D, pd]
     L.orc_enumerate.argtypes = [pd, pd, pi, I, pd, I, D, ctypes.c_uint64, ctypes.c_uint32, pd]
     L.orc_num_threads.restype = I
+    L.orc_set_threads.argtypes = [I]
+    L.orc_set_threads.restype = None
     for name in ("orc_render", "orc_render_frozen", "orc_unproject", "orc_score", "orc_score_grad",
                  "orc_render_grad", "orc_sample", "orc_enumerate"):
         getattr(L, name).restype = I
@@ -90,6 +92,11 @@ def _declare(L):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().orc_set_threads(int(n))
 
 
 def _d(a):

@@ -64,6 +64,9 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads used by the OpenMP loops from now on (n >= 1). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
 static void xform(const double* P, const double* v, double* c) {
   c[0] = P[0] * v[0] + P[1] * v[1] + P[2] * v[2] + P[3];
   c[1] = P[4] * v[0] + P[5] * v[1] + P[6] * v[2] + P[7];

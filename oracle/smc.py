@@ -191,6 +191,7 @@ def smc_stage(state: Particles, i: int, loglik: LogLik, faces: Sequence[Sequence
     logL_new = np.zeros(M)
     noise_grid = np.zeros((M, params.A * params.B))
     noise_choice = np.zeros(M, np.int32)
+    type_post = np.zeros((M, n_types))
     for m in range(M):
         objs = [(int(state.place[m, j, 0]), state.poses[m, j]) for j in range(k)]
         sig, po = state.noise[m]
@@ -207,6 +208,8 @@ def smc_stage(state: Particles, i: int, loglik: LogLik, faces: Sequence[Sequence
             loglik(m, o, np.stack([contact_pose(table, faces[o][cells[n][1]], *cents[n])
                                    for n in range(len(cells)) if cells[n][0] == o]), objs, sig, po)
             for o in range(n_types)])
+        w = np.exp(L - L.max())
+        type_post[m] = w.reshape(n_types, -1).sum(axis=1) / w.sum()  # marginal over face and placement
         _, idx, lw = sample(L, 1, seed, stage=(i << 8) | 0, k0=m)
         choice[0, m] = idx[0]
         o, c, lo, hi = cells[idx[0]]
@@ -261,7 +264,7 @@ def smc_stage(state: Particles, i: int, loglik: LogLik, faces: Sequence[Sequence
         noise=new_noise[src], logW=logW, logp=logp[src], lprior=lprior[src], logL=logL_new[src])
     diag = dict(choice=choice, logq=logq, logL=logL_new, logp=logp, logW_pre=logW_pre, ess=ess, ancestors=src,
                 resampled=resampled, noise_grid=noise_grid, noise_choice=noise_choice, place=new_place,
-                dphi=new_dphi, poses=new_pose, noise=new_noise)
+                dphi=new_dphi, poses=new_pose, noise=new_noise, type_post=type_post)
     return new, diag
 
 

@@ -73,7 +73,8 @@ class SMCParams(ctypes.Structure):
 
 class SMCView(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("place", "dphi", "poses", "noise", "logW", "logp", "logL", "choice",
-                                               "logq", "logW_pre", "noise_grid", "ancestors", "ess")]
+                                               "logq", "logW_pre", "noise_grid", "ancestors", "ess",
+                                               "type_post")]
 
 
 _lib = None
@@ -112,6 +113,8 @@ _SIGNATURES = {
     "b3d_batch_run": ([_P, _P], ctypes.c_int),
     "b3d_batch_destroy": ([_P], ctypes.c_int),
     "b3d_probe_fma": ([_P, _I32, _I32, _P], ctypes.c_int),
+    "b3d_probe_hbm": ([_P, _P, _P, ctypes.c_int64, _P], ctypes.c_int),
+    "b3d_probe_lds": ([_P, _I32, _I32, _P], ctypes.c_int),
     "b3d_pose_retract": ([_P, _I32, _P, _I32, _P, _P], ctypes.c_int),
     "b3d_pose_retract_backward": ([_P, _P, _P, _I32, _P, _P, _P], ctypes.c_int),
     "b3d_scene_set_params": ([_P, ctypes.POINTER(ScoreParams), _P], ctypes.c_int),
@@ -395,6 +398,38 @@ def probe_fma(blocks: int = 4096, iters: int = 256) -> float:
     e1.record(st)
     e1.synchronize()
     return blocks * 256.0 * iters * 128.0 / (e0.elapsed_time(e1) / 1e3)
+
+
+def probe_hbm(n_floats: int = 1 << 28, reps: int = 5) -> float:
+    """Measured HBM bandwidth in bytes/s: median of `reps` triads over three
+    n_floats buffers (3 GiB at the default)."""
+    a = torch.ones(n_floats, dtype=torch.float32, device="cuda")
+    b = torch.ones_like(a)
+    c = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    _call("b3d_probe_hbm", _ptr(a), _ptr(b), _ptr(c), n_floats, _stream())  # warm-up
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        _call("b3d_probe_hbm", _ptr(a), _ptr(b), _ptr(c), n_floats, _stream())
+        e1.record(st)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    return 12.0 * n_floats / float(np.median(ts))
+
+
+def probe_lds(blocks: int = 4096, iters: int = 256) -> float:
+    """Measured LDS read bandwidth in bytes/s over the whole chip."""
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    _call("b3d_probe_lds", _ptr(out), blocks, iters, _stream())  # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    _call("b3d_probe_lds", _ptr(out), blocks, iters, _stream())
+    e1.record(st)
+    e1.synchronize()
+    return blocks * 256.0 * iters * 32.0 * 16.0 / (e0.elapsed_time(e1) / 1e3)
 
 
 def pose_retract(base: torch.Tensor, xi: torch.Tensor) -> torch.Tensor:
@@ -727,7 +762,8 @@ class SMC:
                    logW_pre=torch.empty(M, dtype=torch.float64, device=d),
                    noise_grid=torch.empty((M, AB), dtype=torch.float32, device=d),
                    ancestors=torch.empty(M, dtype=torch.int32, device=d),
-                   ess=torch.empty(1, dtype=torch.float64, device=d))
+                   ess=torch.empty(1, dtype=torch.float64, device=d),
+                   type_post=torch.empty((M, len(self.types)), dtype=torch.float32, device=d))
         v = SMCView(*[_ptr(out[k]) for k, _ in SMCView._fields_])
         k, ns = _I32(), ctypes.c_int64()
         _call("b3d_smc_read", self._h, ctypes.byref(v), ctypes.byref(k), ctypes.byref(ns), _stream())

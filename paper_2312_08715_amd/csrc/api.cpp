@@ -501,6 +501,26 @@ b3d_status b3d_probe_fma(float* out, int32_t blocks, int32_t iters, void* stream
   return B3D_OK;
 }
 
+b3d_status b3d_probe_hbm(const float* a, const float* b, float* c, int64_t n, void* stream) {
+  if (!a || !b || !c) return fail(B3D_EINVAL, "probe_hbm: NULL pointer");
+  if (n < 4 || (n % 4) != 0) return fail(B3D_ESHAPE, "probe_hbm: n must be a positive multiple of 4");
+  if ((((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15) != 0)
+    return fail(B3D_EINVAL, "probe_hbm: buffers must be 16-byte aligned");
+  int dev = 0, cus = 0;
+  B3D_CHECK_HIP(hipGetDevice(&dev), "probe_hbm");
+  B3D_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "probe_hbm");
+  B3D_CHECK_HIP(launch_probe_triad(a, b, c, n / 4, cus * 8, (hipStream_t)stream), "probe_hbm");
+  return B3D_OK;
+}
+
+b3d_status b3d_probe_lds(float* out, int32_t blocks, int32_t iters, void* stream) {
+  if (!out) return fail(B3D_EINVAL, "probe_lds: NULL pointer");
+  if (blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > (1 << 20))
+    return fail(B3D_ESHAPE, "probe_lds: blocks and iters in 1..2^20");
+  B3D_CHECK_HIP(launch_probe_lds(out, blocks, iters, (hipStream_t)stream), "probe_lds");
+  return B3D_OK;
+}
+
 b3d_status b3d_pose_retract(const float* base, int32_t n_base, const float* xi, int32_t N, float* out, void* stream) {
   if (N < 0) return fail(B3D_ESHAPE, "pose_retract: N < 0");
   if (N == 0) return B3D_OK;

@@ -81,6 +81,9 @@ hipError_t launch_score_rows_grid(const RowsGroupDev& G, int R, int n_bands, flo
 hipError_t launch_reduce_rows_grid(const float* partial, int P, int n_bands, int nk, const NoiseGridDev& g,
                                    float* grid_out, float* marg_out, hipStream_t st);
 
+// Object types in an SMC library.
+constexpr int kMaxTypes = 16;
+
 // Table-contact placement (see b3d_contact_poses): the resting frame of face
 // c of a type's bounding box and the log prior density of a placement on it.
 struct FaceDev {
@@ -124,6 +127,9 @@ struct StageDev {
   double* logW_pre;         // [M] written by the reweight
 };
 
+// Posterior over type of each particle's stage-0 cells (one block per particle).
+hipError_t launch_type_posterior(const float* logL, int M, int N, int n_types, int per_type, float* post,
+                                 hipStream_t st);
 hipError_t launch_contact_poses(const ContactDev& C, const int* place, const float* dphi, int N, float* poses,
                                 hipStream_t st);
 // Poses of the centres of every cell's split into nx x ny x nt cells:
@@ -217,6 +223,8 @@ hipError_t launch_c2f_update(const float* poses, int P, int N, const int* idx, c
 
 // refinement and tracking
 hipError_t launch_probe_fma(float* out, int blocks, int iters, hipStream_t st);
+hipError_t launch_probe_triad(const float* a, const float* b, float* c, long long n4, int blocks, hipStream_t st);
+hipError_t launch_probe_lds(float* out, int blocks, int iters, hipStream_t st);
 hipError_t launch_pose_retract(const float* base, int n_base, const float* xi, int N, float* out, hipStream_t st);
 hipError_t launch_pose_retract_backward(const float* xi, const float* grad, const float* dlogL, int N, float* dxi,
                                         float* dsp, hipStream_t st);

@@ -27,4 +27,49 @@ hipError_t launch_probe_fma(float* out, int blocks, int iters, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Peak probe: HBM bandwidth by a triad c = a + s b over float4s, one pass,
+// grid-stride (3 x 16 bytes per element moved).
+__global__ __launch_bounds__(256) void k_probe_triad(const float4* __restrict__ a, const float4* __restrict__ b,
+                                                     float4* __restrict__ c, long long n, float s) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float4 x = a[i], y = b[i];
+    c[i] = make_float4(x.x + s * y.x, x.y + s * y.y, x.z + s * y.z, x.w + s * y.w);
+  }
+}
+
+hipError_t launch_probe_triad(const float* a, const float* b, float* c, long long n4, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_probe_triad, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const float4*>(a),
+                     reinterpret_cast<const float4*>(b), reinterpret_cast<float4*>(c), n4, 1.5f);
+  return hipGetLastError();
+}
+
+// Peak probe: LDS read bandwidth.  Each lane reads 16-byte words of a 32 KB
+// LDS array at addresses that walk the banks without conflicts, iters x 32
+// times; the sum is stored so that nothing is elided.
+__global__ __launch_bounds__(256) void k_probe_lds(float* __restrict__ out, int iters) {
+  __shared__ float4 buf[2048];
+  for (int i = threadIdx.x; i < 2048; i += 256) buf[i] = make_float4((float)i, 1.0f, 2.0f, 3.0f);
+  __syncthreads();
+  float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  int k = threadIdx.x;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+      const float4 v = buf[(k + r * 64) & 2047];
+      acc.x += v.x;
+      acc.y += v.y;
+      acc.z += v.z;
+      acc.w += v.w;
+    }
+    k = (k + 7) & 2047;
+  }
+  out[blockIdx.x * blockDim.x + threadIdx.x] = acc.x + acc.y + acc.z + acc.w;
+}
+
+hipError_t launch_probe_lds(float* out, int blocks, int iters, hipStream_t st) {
+  hipLaunchKernelGGL(k_probe_lds, dim3(blocks), dim3(256), 0, st, out, iters);
+  return hipGetLastError();
+}
+
 }  // namespace b3d

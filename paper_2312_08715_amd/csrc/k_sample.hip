@@ -348,6 +348,49 @@ hipError_t launch_noise_draw(const int* nidx, const float* nlogw, int M, int A, 
   return hipGetLastError();
 }
 
+// Block m: the posterior over type of particle m's stage-0 cells, marginal
+// over face and placement: post[m][o] = sum over type o's cells of
+// exp(logL - LSE), the cells of type o being [o per_type, (o + 1) per_type).
+__global__ __launch_bounds__(kBlock) void k_type_posterior(const float* __restrict__ logL, int N, int n_types,
+                                                           int per_type, float* __restrict__ post) {
+  __shared__ double red[kBlock];
+  const float* L = logL + (size_t)blockIdx.x * N;
+  double mx = -INFINITY;
+  for (int n = threadIdx.x; n < N; n += kBlock) mx = fmax(mx, (double)L[n]);
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  mx = red[0];
+  __syncthreads();
+  __shared__ double typ[kMaxTypes];
+  for (int o = 0; o < n_types; ++o) {
+    double s = 0.0;
+    for (int n = o * per_type + threadIdx.x; n < (o + 1) * per_type; n += kBlock) s += exp((double)L[n] - mx);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) typ[o] = red[0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int o = 0; o < n_types; ++o) tot += typ[o];
+    for (int o = 0; o < n_types; ++o) post[(size_t)blockIdx.x * n_types + o] = (float)(typ[o] / tot);
+  }
+}
+
+hipError_t launch_type_posterior(const float* logL, int M, int N, int n_types, int per_type, float* post,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_type_posterior, dim3(M), dim3(kBlock), 0, st, logL, N, n_types, per_type, post);
+  return hipGetLastError();
+}
+
 // Fixed-order block reductions of doubles (whole block, kBlock threads).
 __device__ double block_max_d(double v, double* red) {
   red[threadIdx.x] = v;

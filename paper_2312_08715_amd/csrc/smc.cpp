@@ -102,6 +102,7 @@ struct b3d_smc {
   float *hyp = nullptr, *logL_h = nullptr, *logw = nullptr, *nlogw = nullptr, *lw_shift = nullptr;
   float *dphi_new = nullptr, *pose_new = nullptr, *noise_new = nullptr, *logL_new = nullptr, *noise_grid = nullptr;
   float* marg = nullptr;
+  float* type_post = nullptr;  // [M][n_types]
   float* partial = nullptr;  // [M][n_bands][kMaxNoise] band sums of the whole-image scores
   int rows_R = 0, n_bands = 0;
   long long scored = 0;  // hypotheses rendered and scored since the last reset
@@ -286,7 +287,8 @@ b3d_status b3d_smc_create(const b3d_mesh* const* types, int32_t n_types, const b
       (s = dev_alloc(S->owned, &S->lw_shift, (size_t)M)) || (s = dev_alloc(S->owned, &S->dphi_new, (size_t)M * 3)) ||
       (s = dev_alloc(S->owned, &S->pose_new, (size_t)M * 16)) || (s = dev_alloc(S->owned, &S->noise_new, (size_t)M * 2)) ||
       (s = dev_alloc(S->owned, &S->logL_new, (size_t)M)) ||
-      (s = dev_alloc(S->owned, &S->noise_grid, (size_t)M * A * B)) || (s = dev_alloc(S->owned, &S->marg, (size_t)M)))
+      (s = dev_alloc(S->owned, &S->noise_grid, (size_t)M * A * B)) || (s = dev_alloc(S->owned, &S->marg, (size_t)M)) ||
+      (s = dev_alloc(S->owned, &S->type_post, (size_t)M * n_types)))
     return bail(s);
   {
     // whole-image scores in bands of full-width rows, the largest that fit
@@ -444,6 +446,7 @@ b3d_status b3d_smc_step(b3d_smc* S, void* stream) {
       B3D_CHECK_HIP(hipMemcpyAsync(S->logL_h + (size_t)m * N0, S->logL_h + (size_t)rep[m] * N0, sizeof(float) * N0,
                                    hipMemcpyDeviceToDevice, st),
                     "smc_step");
+  B3D_CHECK_HIP(launch_type_posterior(S->logL_h, M, N0, n_types, 6 * n0, S->type_post, st), "smc_step");
   B3D_CHECK_HIP(launch_sample(S->logL_h, M, N0, 1, key0, key1, ((uint32_t)i << 8) | 0u, 0u, nullptr, S->idx, S->logw, st),
                 "smc_step");
   B3D_CHECK_HIP(launch_contact_choose(S->roots, p.counts[0][0], p.counts[0][1], p.counts[0][2], S->idx, S->logw, M,
@@ -517,7 +520,8 @@ b3d_status b3d_smc_read(const b3d_smc* S, const b3d_smc_view* v, int32_t* n_plac
       cp(v->logL, d.logL, sizeof(float) * M), cp(v->choice, S->choice, sizeof(int) * S->p.n_stages * M),
       cp(v->logq, S->logq, sizeof(double) * M), cp(v->logW_pre, S->logW_pre, sizeof(double) * M),
       cp(v->noise_grid, S->noise_grid, sizeof(float) * M * AB), cp(v->ancestors, S->anc, sizeof(int) * M),
-      cp(v->ess, S->ess, sizeof(double))};
+      cp(v->ess, S->ess, sizeof(double)),
+      cp(v->type_post, S->type_post, sizeof(float) * M * S->types.size())};
   for (hipError_t x : es)
     if (x != hipSuccess) e = x;
   if (e != hipSuccess) return hip_fail(e, "smc_read");

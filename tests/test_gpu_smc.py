@@ -143,6 +143,11 @@ def test_smc_stages_match_oracle(b3d):
         new, diag = smc_stage(st, i, loglik, faces, T, op)
         smc.step()
         r = smc.read()
+        # the posterior over the new object's type, marginal over face and placement
+        tp = r["type_post"].cpu().numpy().astype(np.float64)
+        say(f"  type posterior: max |dp| {np.abs(tp - diag['type_post']).max():.3g}")
+        assert np.allclose(tp, diag["type_post"], rtol=1e-2, atol=2e-3)
+        assert np.allclose(tp.sum(1), 1.0, atol=1e-5)
         ch = r["choice"].cpu().numpy()
         same = np.all(ch == diag["choice"], axis=0) & (r["place"][:, i - 1].cpu().numpy() == diag["place"]).all(1)
         say(f"stage {i}: particles whose cells all agree: {same.sum()}/{M}")

@@ -104,6 +104,19 @@ def test_every_cell_is_scored_at_its_own_face():
     assert np.all(diag["place"][:, 1] == 4)
 
 
+def test_type_posterior_of_a_type_only_likelihood_is_its_softmax():
+    # every type has the same number of stage-0 cells, so a likelihood that
+    # depends on the type alone gives posterior softmax over the types
+    rng = np.random.default_rng(10)
+    table = random_table(rng)
+    types = [faces_of(box_verts(rng)) for _ in range(3)]
+    a = np.array([0.3, -1.2, 2.0])
+    st, diag = smc_stage(init_particles(3, _params(51)), 1, lambda m, o, P, objs, s, p: np.full(len(P), a[o]),
+                         types, table, _params(51))
+    want = np.exp(a - a.max()) / np.exp(a - a.max()).sum()
+    assert np.allclose(diag["type_post"], want[None], rtol=1e-13, atol=0)
+
+
 def test_weights_are_unbiased_for_the_evidence():
     # E_q[p_1 / q] = integral of p_1 = Z for a likelihood with a closed-form
     # integral: exp(L) = exp(a dx) (1 + 0.5 cos dth) (1 + sigma/sigma_max) (2 - p_out)
