@@ -225,3 +225,89 @@ def test_resampling_copies_ancestors_and_keeps_the_evidence(b3d):
     assert not rb["poses"][:, 1].any()
     n0 = 2 * 6 * 16
     assert rb["scored"] == n0 + 16 * (8 + 8)
+
+
+def test_smc_first_stage_at_bench_scale_matches_oracle(b3d):
+    # the bench's SMC launch configuration: the four-object table scene at
+    # 320x240, library of its four meshes, 16 particles, 8x8x8 stage-0 cells;
+    # checked on the outputs the oracle can recompute: all 12,288 stage-0
+    # scores (through the draws and the type posterior), each particle's noise
+    # grid and logL at its placement, and the weights
+    from oracle.smc import root_box, sub_cell
+
+    meshes, poses, table, cam, noise, Tcw = table_scene()
+    tv, tt, tT = table
+    meshes = [(f32(v), t) for v, t in meshes]
+    fixed = [(f32(tv), tt, f32(tT))]
+    objs = [(v, t, f32(P)) for (v, t), P in zip(meshes, poses)] + fixed
+    d, _ = oracle.render(objs, cam)
+    z = np.where(d[0] > 0, d[0] + noise["gauss"], 0.0)
+    z = np.where(noise["outlier_mask"], noise["outlier_depth"], z)
+    obs = f32(oracle.unproject(z, cam))
+    counts = ((8, 8, 8), (4, 4, 4), (4, 4, 4))
+    smc, types, tmesh, args = gpu_setup(b3d, meshes, (f32(tv), tt, f32(tT)), cam, n_particles=16, n_objects=4,
+                                        counts=counts, sigma_max=0.02, noise_A=4, noise_B=4, sigma0=0.015,
+                                        p_out0=0.5, ess_threshold=0.0, seed=4242)
+    smc.reset(dev(obs))
+    smc.step()
+    r = smc.read()
+    say(f"bench-scale SMC stage 1: {cam.W}x{cam.H}, 16 particles, {r['scored']} hypotheses scored")
+    faces = [faces_of(v) for v, _ in meshes]
+    T = Table(f32(tT), 1.0, 1.0)
+    # the oracle's stage-0 scores (every particle shares them before the first object)
+    cents = []
+    for o in range(4):
+        for c in range(6):
+            lo, hi = root_box(T, faces[o][c])
+            for j in range(512):
+                a, b = sub_cell(lo, hi, counts[0], j)
+                cents.append((o, c, 0.5 * (a + b)))
+    L0, l1_0 = np.zeros(len(cents)), np.zeros(len(cents))
+    for o in range(4):
+        idx = [n for n, (oo, _, _) in enumerate(cents) if oo == o]
+        P = np.stack([contact_pose(T, faces[o][cents[n][1]], *cents[n][2]) for n in idx])
+        for k in range(0, len(idx), 256):
+            dd, _ = oracle.render([(meshes[o][0], meshes[o][1], P[k:k + 256])] + fixed, cam)
+            L, l1 = oracle.score(obs, oracle.unproject(dd, cam), 0.015, 0.5, 1.0, 5)
+            L0[idx[k:k + 256]] = L
+            l1_0[idx[k:k + 256]] = l1
+    w = np.exp(L0 - L0.max())
+    post = w.reshape(4, -1).sum(1) / w.sum()
+    tp = r["type_post"].cpu().numpy().astype(np.float64)
+    say(f"  type posterior {np.round(tp[0], 4).tolist()} (oracle {np.round(post, 4).tolist()})")
+    assert np.allclose(tp, post[None], rtol=1e-2, atol=2e-3)
+    # the draws: equal wherever the oracle's top-two gap of logL + G exceeds 1e-3 of the L1 mass
+    ch = r["choice"].cpu().numpy()[0]
+    agree = 0
+    for m in range(16):
+        g = np.array([-np.log(-np.log(oracle.uniform(4242, n, m, 1 << 8, 0))) for n in range(len(cents))])
+        v = L0 + g
+        top2 = np.sort(v)[-2:]
+        want = int(np.argmax(v))
+        if ch[m] == want:
+            agree += 1
+        else:
+            assert top2[1] - top2[0] <= 1e-3 * l1_0[want], (m, ch[m], want)
+    say(f"  stage-0 draws equal to the oracle's: {agree}/16")
+    # each particle's noise grid and logL at its own placement, and eq. (2)
+    gg = r["noise_grid"].cpu().numpy().astype(np.float64)
+    gl = r["logL"].cpu().numpy().astype(np.float64)
+    place = r["place"][:, 0].cpu().numpy()
+    Pm = r["poses"][:, 0].cpu().numpy().astype(np.float64)
+    nz = r["noise"].cpu().numpy().astype(np.float64)
+    worst = 0.0
+    for m in range(16):
+        o = int(place[m, 0])
+        dd, _ = oracle.render([(meshes[o][0], meshes[o][1], Pm[m])] + fixed, cam)
+        xyz = oracle.unproject(dd, cam)
+        for k, (a, b) in enumerate([(a, b) for a in range(4) for b in range(4)]):
+            L, l1 = oracle.score(obs, xyz, float(np.float32(0.02 * (a + 0.5) / 4)), float(np.float32((b + 0.5) / 4)),
+                                 1.0, 5)
+            worst = max(worst, abs(gg[m, k] - L[0]) / l1[0])
+        L, l1 = oracle.score(obs, xyz, float(nz[m, 0]), float(nz[m, 1]), 1.0, 5)
+        worst = max(worst, abs(gl[m] - L[0]) / l1[0])
+    say(f"  noise grid and logL at the placements: max rel-L1 err {worst:.3g}")
+    assert worst <= 1e-4
+    lpr = np.array([log_prior(4, T, faces[o][c]) for o, c in place])
+    want = gl + lpr - np.log(0.02) - r["logq"].cpu().numpy()
+    assert np.allclose(r["logW_pre"].cpu().numpy(), want, rtol=1e-12, atol=1e-6)
