@@ -196,7 +196,10 @@ def bench_noise_grid(b3d, torch, scene, P, A=4, B=4, sigma_max=0.01, reps=10):
             "note": "fused render + windowed likelihood under every grid point + marginal, one launch"}
 
 
-def bench_smc(b3d, torch, p=None, n_particles=16, reps=2, seed=4242):
+SMC_STAGE_NOISE = ((0.03, 0.3), (0.01, 0.2), (0.004, 0.1))
+
+
+def bench_smc(b3d, torch, p=None, n_particles=16, reps=2, seed=4242, stage_noise=SMC_STAGE_NOISE):
     """SMC over the objects of the four-object table scene at 320x240: the
     library is the scene's four meshes, every particle places four objects;
     per object, stage 0 scores 4 types x 6 faces x 512 placement cells, then
@@ -212,7 +215,8 @@ def bench_smc(b3d, torch, p=None, n_particles=16, reps=2, seed=4242):
     counts = ((8, 8, 8), (4, 4, 4), (4, 4, 4))
     n_obj = len(meshes)
     sp = b3d.smc_params(n_particles=n_particles, n_objects=n_obj, counts=counts, sigma_max=0.02, noise_A=4, noise_B=4,
-                        sigma0=0.015, p_out0=0.5, ess_threshold=0.5, outlier_volume=1.0, window=5, seed=seed)
+                        sigma0=0.015, p_out0=0.5, ess_threshold=0.5, outlier_volume=1.0, window=5, seed=seed,
+                        stage_noise=stage_noise)
     smc = b3d.SMC(types, b3d.table(tT, 1.0, 1.0), b3d.intrinsics_of(cam), sp, fixed=[tmesh],
                   fixed_poses=np.asarray(tT, np.float32)[None])
 
@@ -246,7 +250,7 @@ def bench_smc(b3d, torch, p=None, n_particles=16, reps=2, seed=4242):
             "map_particle": {"types": place[:, 0].tolist(), "faces": place[:, 1].tolist(),
                              "noise": [round(float(x), 5) for x in r["noise"][best].cpu().numpy()],
                              "centre_error_cm_per_true_object": found},
-            "ess_last": float(r["ess"].item()),
+            "ess_last": float(r["ess"].item()), "stage_noise": stage_noise,
             "note": "reset + 4 SMC stages; placement cells scored by the batched fused kernel (16 particles x "
                     f"{n0} cells at stage 0; particles with equal state share one scoring, hence scored < "
                     "particle hypotheses), noise cells over the whole image, eq. (2)/(3) weights, resampling"}

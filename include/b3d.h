@@ -481,7 +481,8 @@ b3d_status b3d_contact_poses(const b3d_mesh* const* types, int32_t n_types, cons
  *     (ix * ny + iy) * nth + ith, stage t splits the chosen cell into
  *     counts[t]; every cell is scored by the fused kernel at its centre, with
  *     the fixed content and the particle's earlier objects as background and
- *     the particle's current noise, and one is drawn by softmax (b3d_sample,
+ *     the stage's noise (stage_sigma[t], stage_p_out[t]) or, where that is
+ *     0, the particle's current noise, and one is drawn by softmax (b3d_sample,
  *     stage word (i << 8) | t, draw = particle); a uniform point of the final
  *     cell (Philox4x32-10 counter (m, i, 0, 2), words 0..2) is the placement;
  *  2. the noise: A x B equal cells of (0, sigma_max] x (0, 1) scored at their
@@ -510,6 +511,10 @@ typedef struct b3d_smc_params {
   int32_t window;                    /* odd window side */
   float norm_M;                      /* eq. (1)'s normaliser; 0 for H * W */
   uint64_t seed;
+  /* the noise at which placement stage t scores its cells (sigma, p_out);
+   * stage_sigma[t] = 0 uses each particle's current estimates */
+  float stage_sigma[B3D_MAX_STAGES];
+  float stage_p_out[B3D_MAX_STAGES];
 } b3d_smc_params;
 
 typedef struct b3d_smc b3d_smc;

@@ -27,9 +27,11 @@ Readings (the paper gives no more detail than the above):
   splits the chosen cell into counts[t]; each cell is scored by the target at
   its centre times the cell's volume (its midpoint estimate of the target's
   mass), and since prior density times cell volume is the same for every cell
-  of a stage the draw uses softmax(logL).  The search uses the particle's
-  current noise estimates (sigma0, p0 for the first object).  A uniform point
-  of the final cell is the proposed dphi.
+  of a stage the draw uses softmax(logL).  Stage t scores at a stated
+  noise (sigma_t, p_t) when one is given (coarse cells want a wide inlier
+  kernel), else at the particle's current estimates (sigma0, p0 for the first
+  object); any such choice keeps q exact.  A uniform point of the final cell
+  is the proposed dphi.
 * The noise is proposed next: A x B equal cells of (0, sigma_max] x (0, 1),
   each scored at its midpoint with the new object at the proposed placement,
   one drawn by softmax, and a uniform point of it taken.
@@ -147,6 +149,7 @@ class SMCParams:
     p0: float
     ess_threshold: float
     seed: int
+    stage_noise: Sequence = None      # per pose stage (sigma, p_out) or None: the particle's noise
 
 
 @dataclass
@@ -194,7 +197,10 @@ def smc_stage(state: Particles, i: int, loglik: LogLik, faces: Sequence[Sequence
     type_post = np.zeros((M, n_types))
     for m in range(M):
         objs = [(int(state.place[m, j, 0]), state.poses[m, j]) for j in range(k)]
-        sig, po = state.noise[m]
+
+        def noise_at(t):
+            sn = params.stage_noise
+            return tuple(sn[t]) if sn is not None and sn[t][0] > 0 else tuple(state.noise[m])
         # pose stage 0: every (type, face) box split into counts[0] cells
         cents, cells = [], []
         for o in range(n_types):
@@ -204,6 +210,7 @@ def smc_stage(state: Particles, i: int, loglik: LogLik, faces: Sequence[Sequence
                     a, b = sub_cell(lo, hi, params.counts[0], j)
                     cells.append((o, c, a, b))
                     cents.append(0.5 * (a + b))
+        sig, po = noise_at(0)
         L = np.concatenate([
             loglik(m, o, np.stack([contact_pose(table, faces[o][cells[n][1]], *cents[n])
                                    for n in range(len(cells)) if cells[n][0] == o]), objs, sig, po)
@@ -219,7 +226,7 @@ def smc_stage(state: Particles, i: int, loglik: LogLik, faces: Sequence[Sequence
             n_t = int(np.prod(params.counts[t]))
             subs = [sub_cell(lo, hi, params.counts[t], j) for j in range(n_t)]
             P = np.stack([contact_pose(table, faces[o][c], *(0.5 * (a + b))) for a, b in subs])
-            L = loglik(m, o, P, objs, sig, po)
+            L = loglik(m, o, P, objs, *noise_at(t))
             _, idx, lw = sample(L, 1, seed, stage=(i << 8) | t, k0=m)
             choice[t, m] = idx[0]
             lo, hi = subs[idx[0]]

@@ -68,7 +68,8 @@ class SMCParams(ctypes.Structure):
                 ("counts", (ctypes.c_int32 * 3) * B3D_MAX_STAGES), ("sigma_max", ctypes.c_float),
                 ("noise_A", ctypes.c_int32), ("noise_B", ctypes.c_int32), ("sigma0", ctypes.c_float),
                 ("p_out0", ctypes.c_float), ("ess_threshold", ctypes.c_float), ("outlier_volume", ctypes.c_float),
-                ("window", ctypes.c_int32), ("norm_M", ctypes.c_float), ("seed", ctypes.c_uint64)]
+                ("window", ctypes.c_int32), ("norm_M", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("stage_sigma", ctypes.c_float * B3D_MAX_STAGES), ("stage_p_out", ctypes.c_float * B3D_MAX_STAGES)]
 
 
 class SMCView(ctypes.Structure):
@@ -709,16 +710,22 @@ def contact_poses(types: Sequence[Mesh], tbl: Table, place: torch.Tensor, dphi: 
 
 
 def smc_params(n_particles, n_objects, counts, sigma_max, noise_A, noise_B, sigma0, p_out0, ess_threshold,
-               outlier_volume=1.0, window=5, norm_M=0.0, seed=0) -> SMCParams:
+               outlier_volume=1.0, window=5, norm_M=0.0, seed=0, stage_noise=None) -> SMCParams:
+    """stage_noise: per placement stage (sigma, p_out) at which its cells are
+    scored, or None (each particle's current noise at every stage)."""
     if not 1 <= len(counts) <= B3D_MAX_STAGES:
         raise B3DError(f"smc: 1..{B3D_MAX_STAGES} stages")
     c = ((ctypes.c_int32 * 3) * B3D_MAX_STAGES)()
     for t, x in enumerate(counts):
         for k in range(3):
             c[t][k] = int(x[k])
+    ss, sp = (ctypes.c_float * B3D_MAX_STAGES)(), (ctypes.c_float * B3D_MAX_STAGES)()
+    if stage_noise is not None:
+        for t, (s, q) in enumerate(stage_noise):
+            ss[t], sp[t] = float(s), float(q)
     return SMCParams(int(n_particles), int(n_objects), len(counts), c, float(sigma_max), int(noise_A), int(noise_B),
                      float(sigma0), float(p_out0), float(ess_threshold), float(outlier_volume), int(window),
-                     float(norm_M), int(seed))
+                     float(norm_M), int(seed), ss, sp)
 
 
 class SMC:

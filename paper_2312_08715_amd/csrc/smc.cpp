@@ -204,6 +204,10 @@ b3d_status b3d_smc_create(const b3d_mesh* const* types, int32_t n_types, const b
     return fail(B3D_EINVAL, "smc_create: bad initial noise");
   if (!(p->ess_threshold >= 0) || !std::isfinite(p->ess_threshold))
     return fail(B3D_EINVAL, "smc_create: bad ess_threshold");
+  for (int t = 0; t < p->n_stages; ++t)
+    if (!(p->stage_sigma[t] >= 0) || !std::isfinite(p->stage_sigma[t]) ||
+        (p->stage_sigma[t] > 0 && !(p->stage_p_out[t] > 0 && p->stage_p_out[t] <= 1)))
+      return fail(B3D_EINVAL, "smc_create: bad noise for stage %d", t);
   if (n_fixed < 0 || n_fixed > 16 || (n_fixed > 0 && (!fixed || !fixed_poses)))
     return fail(B3D_EINVAL, "smc_create: bad fixed content");
   if (n_fixed > 0 && !finite_all(fixed_poses, 16 * (size_t)n_fixed))
@@ -389,12 +393,14 @@ b3d_status b3d_smc_step(b3d_smc* S, void* stream) {
   // particles with equal noise and equal objects (copies made by resampling,
   // and all of them before the first object) score every hypothesis alike:
   // one scene per distinct state, its stage-0 scores copied to the others
+  bool own_noise = false;  // some stage scores at the particles' own noise
+  for (int t = 0; t < p.n_stages; ++t) own_noise = own_noise || !(p.stage_sigma[t] > 0);
   std::vector<int> rep((size_t)M);
   for (int m = 0; m < M; ++m) {
     rep[m] = m;
     for (int u = 0; u < m; ++u) {
       if (rep[u] != u) continue;
-      bool same = h_noise[2 * u] == h_noise[2 * m] && h_noise[2 * u + 1] == h_noise[2 * m + 1];
+      bool same = !own_noise || (h_noise[2 * u] == h_noise[2 * m] && h_noise[2 * u + 1] == h_noise[2 * m + 1]);
       for (int j = 0; same && j < k; ++j) {
         const size_t a = (size_t)u * n + j, b = (size_t)m * n + j;
         same = h_place[2 * a] == h_place[2 * b] &&
@@ -406,6 +412,14 @@ b3d_status b3d_smc_step(b3d_smc* S, void* stream) {
       }
     }
   }
+  // the noise at which stage t scores particle m's cells
+  b3d_score_params sp_buf{};
+  auto stage_noise = [&](int m, int t) -> const b3d_score_params& {
+    sp_buf = b3d_score_params{p.stage_sigma[t] > 0 ? p.stage_sigma[t] : h_noise[2 * m],
+                              p.stage_sigma[t] > 0 ? p.stage_p_out[t] : h_noise[2 * m + 1], p.outlier_volume,
+                              p.norm_M, p.window};
+    return sp_buf;
+  };
   std::vector<const b3d_mesh*> bg_mesh;
   std::vector<float> bg_pose;
   for (int m = 0; m < M; ++m) {
@@ -419,8 +433,7 @@ b3d_status b3d_smc_step(b3d_smc* S, void* stream) {
     }
     b3d_scene* sc = S->scenes[m];
     if (b3d_status s = b3d_scene_set_background(sc, bg_mesh.data(), bg_pose.data(), (int)bg_mesh.size(), st)) return s;
-    b3d_score_params sp{h_noise[2 * m], h_noise[2 * m + 1], p.outlier_volume, p.norm_M, p.window};
-    if (b3d_status s = b3d_scene_set_params(sc, &sp, st)) return s;
+    if (b3d_status s = b3d_scene_set_params(sc, &stage_noise(m, 0), st)) return s;
     if (b3d_status s = b3d_scene_set_observed(sc, S->observed, st)) return s;
   }
   auto scene_of = [&](int m, int o) {
@@ -460,6 +473,11 @@ b3d_status b3d_smc_step(b3d_smc* S, void* stream) {
   for (int m = 0; m < M; ++m) type_of[m] = std::min(std::max(h_cells[m].type, 0), n_types - 1);
   for (int t = 1; t < p.n_stages; ++t) {
     const int nx = p.counts[t][0], ny = p.counts[t][1], nt = p.counts[t][2], ns = nx * ny * nt;
+    const bool change = p.stage_sigma[t] != p.stage_sigma[t - 1] || p.stage_p_out[t] != p.stage_p_out[t - 1];
+    if (change)  // the stage's own noise (the background terms follow)
+      for (int m = 0; m < M; ++m)
+        if (rep[m] == m)
+          if (b3d_status s = b3d_scene_set_params(S->scenes[m], &stage_noise(m, t), st)) return s;
     B3D_CHECK_HIP(launch_contact_enumerate(S->C, S->cells, M, nx, ny, nt, S->hyp, st), "smc_step");
     items.clear();
     for (int m = 0; m < M; ++m)

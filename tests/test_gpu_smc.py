@@ -74,9 +74,11 @@ def gpu_setup(b3d, meshes, table, cam, **kw):
 
 
 def oracle_params(args):
+    sn = args.get("stage_noise")
     return SMCParams(counts=args["counts"], sigma_max=args["sigma_max"], A=args["noise_A"], B=args["noise_B"],
                      sigma0=args["sigma0"], p0=args["p_out0"], ess_threshold=args["ess_threshold"],
-                     seed=args["seed"])
+                     seed=args["seed"],
+                     stage_noise=None if sn is None else [tuple(float(np.float32(x)) for x in s) for s in sn])
 
 
 def state_of(r, k):
@@ -123,9 +125,10 @@ def test_flat_likelihood_gives_equal_weights(b3d):
         assert np.array_equal(r["ancestors"].cpu().numpy(), np.arange(8))
 
 
-def test_smc_stages_match_oracle(b3d):
+@pytest.mark.parametrize("stage_noise", [None, ((0.02, 0.3), (0.008, 0.2), (0.004, 0.1))])
+def test_smc_stages_match_oracle(b3d, stage_noise):
     meshes, truth, table, cam, obs = small_table_scene()
-    smc, types, tmesh, args = gpu_setup(b3d, meshes, table, cam)
+    smc, types, tmesh, args = gpu_setup(b3d, meshes, table, cam, stage_noise=stage_noise)
     tv, tt, tT = table
     fixed = [(tv, tt, tT)]
     loglik = oracle.smc.scene_loglik(obs, cam, meshes, fixed, 1.0, 5)

@@ -117,14 +117,17 @@ def test_type_posterior_of_a_type_only_likelihood_is_its_softmax():
     assert np.allclose(diag["type_post"], want[None], rtol=1e-13, atol=0)
 
 
-def test_weights_are_unbiased_for_the_evidence():
+@pytest.mark.parametrize("stage_noise", [None, ((0.009, 0.6), (0.002, 0.1))])
+def test_weights_are_unbiased_for_the_evidence(stage_noise):
     # E_q[p_1 / q] = integral of p_1 = Z for a likelihood with a closed-form
-    # integral: exp(L) = exp(a dx) (1 + 0.5 cos dth) (1 + sigma/sigma_max) (2 - p_out)
+    # integral: exp(L) = exp(a dx) (1 + 0.5 cos dth) (1 + sigma/sigma_max) (2 - p_out),
+    # whatever noise the placement stages score at
     rng = np.random.default_rng(6)
     table = random_table(rng)
     types = [faces_of(box_verts(rng)) for _ in range(2)]
     a = 8.0
     params = _params(21, counts=((2, 2, 2), (2, 1, 1)))
+    params.stage_noise = stage_noise
     pose_of = {}
 
     # the likelihood reads each pose's placement back: contact_pose is wrapped
