@@ -256,13 +256,16 @@ def bench_smc(b3d, torch, p=None, n_particles=16, reps=2, seed=4242, stage_noise
                     "particle hypotheses), noise cells over the whole image, eq. (2)/(3) weights, resampling"}
 
 
-def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3):
+def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3, tune=True):
     """Many scenes (1-8 objects of 500-8000 voxels, three image sizes, 1k-20k
     hypotheses each) in one persistent launch, forward + adjoint, against the
-    same scenes one launch at a time."""
+    same scenes one launch at a time; depth-buffer tiles from the autotuner."""
+    import tempfile
+
     from workloads import Camera, observation_noise, pose_matrix, random_scene_batch, shoemake_rotations, voxel_blob, \
         voxel_mesh
 
+    tile_cache = os.path.join(tempfile.mkdtemp(prefix="b3d_tiles_"), "tiles.json")
     rng = np.random.default_rng(seed)
     items, keep = [], []
     for i, sh in enumerate(random_scene_batch(rng, n_scenes)):
@@ -283,7 +286,10 @@ def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3):
         scene.set_observed(obs)
         nz = max(1, int(round(sh["N"] / 1000.0)))
         grid = b3d.make_grid(objs[0][2], (0.02, 0.02, 0.02), (10, 10, nz), n_rot=10, rot_max_angle=np.deg2rad(10.0))
-        items.append((scene, b3d.enumerate_grid(grid, seed=3003 + i)))
+        P = b3d.enumerate_grid(grid, seed=3003 + i)
+        if tune:  # the tile of each shape class (image size, window, mesh size), timed once
+            scene.autotune(P[:2048], grad=True, cache=tile_cache)
+        items.append((scene, P))
         keep += [meshes, obs]
     total = sum(int(P.shape[0]) for _, P in items)
     batch = b3d.Batch(items, grad=True)
@@ -305,6 +311,7 @@ def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3):
     t_seq = (time.perf_counter() - t0) / reps
     return {"scenes": n_scenes, "hypotheses": total, "value": total / t_batch, "ms": t_batch * 1e3,
             "one_at_a_time": {"value": total / t_seq, "ms": t_seq * 1e3}, "unit": "hypotheses/s",
+            "tiles": "autotuned per shape class" if tune else "default",
             "note": "forward + adjoint; one persistent launch vs one launch per scene"}
 
 

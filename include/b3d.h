@@ -534,7 +534,10 @@ b3d_status b3d_smc_create(const b3d_mesh* const* types, int32_t n_types, const b
 b3d_status b3d_smc_reset(b3d_smc* smc, const float* observed, void* stream);
 /* One SMC stage: place the next object in every particle.  B3D_ESHAPE once
  * n_objects are placed.  Synchronises `stream` a few times (the host reads
- * the particles' noise and chosen types to set up the next launches). */
+ * the particles' noise and chosen types to set up the next launches).  The
+ * first step of a sampler also times the fused kernel's depth-buffer tile
+ * (b3d_scene_autotune on the largest type's stage-0 cells) for all its
+ * scenes; results do not depend on the tile. */
 b3d_status b3d_smc_step(b3d_smc* smc, void* stream);
 
 /* Where b3d_smc_read copies the particles and the last stage's diagnostics

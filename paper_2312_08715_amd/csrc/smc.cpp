@@ -106,6 +106,7 @@ struct b3d_smc {
   float* partial = nullptr;  // [M][n_bands][kMaxNoise] band sums of the whole-image scores
   int rows_R = 0, n_bands = 0;
   long long scored = 0;  // hypotheses rendered and scored since the last reset
+  int zcap = 0;          // depth-buffer tile of the particles' scenes, tuned on the first step
   unsigned long long* counters = nullptr;
   int max_groups = 0;
   std::vector<void*> owned;
@@ -436,14 +437,29 @@ b3d_status b3d_smc_step(b3d_smc* S, void* stream) {
     if (b3d_status s = b3d_scene_set_params(sc, &stage_noise(m, 0), st)) return s;
     if (b3d_status s = b3d_scene_set_observed(sc, S->observed, st)) return s;
   }
+  // the tile: timed once, on the first step, over the largest type's stage-0 cells
+  const int n0 = p.counts[0][0] * p.counts[0][1] * p.counts[0][2], N0 = S->n_stage0;
+  if (S->zcap == 0) {
+    int big = 0;
+    for (int o = 0; o < n_types; ++o)
+      if (S->types[o]->T > S->types[big]->T) big = o;
+    b3d_scene* sc = S->scenes[rep[0]];
+    SceneDev keep = sc->dev;
+    sc->dev.mesh = S->types[big]->dev;
+    int z = 0;
+    const b3d_status s = b3d_scene_autotune(sc, S->stage0_poses + 16 * (size_t)big * 6 * n0, 6 * n0, 0, &z, st);
+    sc->dev.mesh = keep.mesh;
+    if (s) return s;
+    S->zcap = z;
+  }
   auto scene_of = [&](int m, int o) {
     SceneDev d = S->scenes[rep[m]]->dev;
     d.mesh = S->types[o]->dev;
+    d.zcap = S->zcap;
     return d;
   };
 
   // stage 0: every (type, face) box split, the same hypotheses for every particle
-  const int n0 = p.counts[0][0] * p.counts[0][1] * p.counts[0][2], N0 = S->n_stage0;
   std::vector<BatchItemDev> items;
   for (int m = 0; m < M; ++m)
     if (rep[m] == m)
