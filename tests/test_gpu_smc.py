@@ -314,3 +314,47 @@ def test_smc_first_stage_at_bench_scale_matches_oracle(b3d):
     lpr = np.array([log_prior(4, T, faces[o][c]) for o, c in place])
     want = gl + lpr - np.log(0.02) - r["logq"].cpu().numpy()
     assert np.allclose(r["logW_pre"].cpu().numpy(), want, rtol=1e-12, atol=1e-6)
+
+
+def test_smc_edge_cases_and_errors(b3d):
+    meshes, truth, table, cam, obs = small_table_scene()
+    tv, tt, tT = table
+    types = [b3d.Mesh(v, t) for v, t in meshes[:1]]
+    tmesh = b3d.Mesh(tv, tt)
+    K = b3d.intrinsics_of(cam)
+
+    def make(tbl=None, **kw):
+        args = dict(n_particles=1, n_objects=2, counts=((2, 2, 2),), sigma_max=0.01, noise_A=1, noise_B=1,
+                    sigma0=0.008, p_out0=0.5, ess_threshold=2.0, outlier_volume=1.0, window=5, seed=5)
+        args.update(kw)
+        return b3d.SMC(types, tbl or b3d.table(tT, 1.0, 1.0), K, b3d.smc_params(**args), fixed=[tmesh],
+                       fixed_poses=tT[None])
+
+    # refused set-ups: a table smaller than a footprint, empty splits, a noise grid too large
+    with pytest.raises(b3d.B3DError):
+        make(b3d.table(tT, 0.05, 1.0))
+    with pytest.raises(b3d.B3DError):
+        make(counts=((2, 0, 2),))
+    with pytest.raises(b3d.B3DError):
+        make(noise_A=9)
+    with pytest.raises(b3d.B3DError):
+        make(stage_noise=((-0.01, 0.5),))
+    # one particle, one type, one stage, one noise cell
+    smc = make()
+    with pytest.raises(b3d.B3DError):
+        smc.step()  # no observation yet
+    smc.reset(dev(obs))
+    for i in (1, 2):
+        smc.step()
+        r = smc.read()
+        assert r["placed"] == i
+        for k in ("logW", "logp", "logq", "logL", "noise", "poses"):
+            assert torch.isfinite(r[k]).all(), k
+        assert r["ancestors"].item() == 0 and abs(r["ess"].item() - 1.0) < 1e-12
+        assert 0 < r["noise"][0, 0].item() <= 0.01 and 0 < r["noise"][0, 1].item() < 1
+        assert r["type_post"].cpu().numpy().tolist() == [[1.0]]
+    with pytest.raises(b3d.B3DError):
+        smc.step()  # both objects placed
+    # contact poses of nothing
+    assert b3d.contact_poses(types, b3d.table(tT, 1.0, 1.0), torch.zeros((0, 2), dtype=torch.int32, device="cuda"),
+                             torch.zeros((0, 3), device="cuda")).shape == (0, 4, 4)
