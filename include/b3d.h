@@ -425,7 +425,9 @@ typedef struct b3d_tracker b3d_tracker;
  * as static background; the grid of hypotheses around the object's previous
  * estimate is scored with the fused kernel, stage by stage around the best
  * of the previous stage; the best hypothesis is refined by n_refine Adam
- * steps on the adjoint.  The whole frame is captured once
+ * steps on the adjoint, each step's render, windows and adjoint spread over
+ * row bands of the object's region (one workgroup per eight image rows) and
+ * summed in band order.  The whole frame is captured once
  * into a HIP graph and replayed for every later frame, so a frame costs one
  * copy and one graph launch.  meshes: host array of M handles (they must
  * outlive the tracker); init_poses: host float[M][16].  1 <= M <= 16.

@@ -936,6 +936,9 @@ b3d_status b3d_adam_pose_step(float* poses, const float* grad, int32_t gstride, 
 
 // ---- tracker -------------------------------------------------------------
 
+// Image rows per block of the tracker's refinement steps.
+constexpr int kRefineRows = 8;
+
 struct b3d_tracker {
   int M = 0;
   int64_t N = 0;
@@ -946,6 +949,8 @@ struct b3d_tracker {
   float* poses = nullptr;    // [M][16] current estimates
   float* hyp = nullptr;      // [N][16]
   float* logL = nullptr;     // [N]
+  float* partial = nullptr;  // [ceil(H / kRefineRows)][9] band sums of a refinement step
+  float* adam = nullptr;     // [M][12] Adam moments of the refinement
   size_t obs_bytes = 0;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -979,8 +984,8 @@ static b3d_status tracker_record(b3d_tracker* T, hipStream_t st) {
       B3D_CHECK_HIP(launch_argmax_pose(T->logL, T->hyp, (int)ns[s], T->poses + 16 * o, st), "tracker");
     }
     if (tp.n_refine > 0)
-      B3D_CHECK_HIP(launch_refine_pose(S->dev, T->poses + 16 * o, 1, tp.n_refine, tp.lr_t, tp.lr_r, tp.beta1,
-                                       tp.beta2, tp.eps, st),
+      B3D_CHECK_HIP(launch_refine_banded(S->dev, T->poses + 16 * o, tp.n_refine, tp.lr_t, tp.lr_r, tp.beta1, tp.beta2,
+                                         tp.eps, kRefineRows, T->partial, T->adam + 12 * o, st),
                     "tracker");
   }
   return B3D_OK;
@@ -1024,6 +1029,8 @@ b3d_status b3d_tracker_create(const b3d_mesh* const* meshes, int32_t M, const b3
     (void)hipFree(T->poses);
     (void)hipFree(T->hyp);
     (void)hipFree(T->logL);
+    (void)hipFree(T->partial);
+    (void)hipFree(T->adam);
     if (T->cap) (void)hipStreamDestroy(T->cap);
     delete T;
     return fail(s, "%s", msg);
@@ -1031,7 +1038,9 @@ b3d_status b3d_tracker_create(const b3d_mesh* const* meshes, int32_t M, const b3
   if (hipMalloc((void**)&T->obs, T->obs_bytes) != hipSuccess ||
       hipMalloc((void**)&T->poses, sizeof(float) * 16 * M) != hipSuccess ||
       hipMalloc((void**)&T->hyp, sizeof(float) * 16 * (size_t)n) != hipSuccess ||
-      hipMalloc((void**)&T->logL, sizeof(float) * (size_t)n) != hipSuccess)
+      hipMalloc((void**)&T->logL, sizeof(float) * (size_t)n) != hipSuccess ||
+      hipMalloc((void**)&T->partial, sizeof(float) * 9 * (size_t)((K->H + kRefineRows - 1) / kRefineRows)) != hipSuccess ||
+      hipMalloc((void**)&T->adam, sizeof(float) * 12 * (size_t)M) != hipSuccess)
     return cleanup(B3D_ENOMEM, "tracker_create: device allocation failed");
   if (hipMemcpy(T->poses, init_poses, sizeof(float) * 16 * M, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(T->obs, 0, T->obs_bytes) != hipSuccess)
@@ -1099,6 +1108,8 @@ b3d_status b3d_tracker_destroy(b3d_tracker* T) {
   (void)hipFree(T->poses);
   (void)hipFree(T->hyp);
   (void)hipFree(T->logL);
+  (void)hipFree(T->partial);
+  (void)hipFree(T->adam);
   if (T->cap) (void)hipStreamDestroy(T->cap);
   delete T;
   return B3D_OK;

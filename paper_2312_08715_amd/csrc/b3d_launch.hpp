@@ -230,6 +230,11 @@ hipError_t launch_pose_retract_backward(const float* xi, const float* grad, cons
                                         float* dsp, hipStream_t st);
 hipError_t launch_refine_pose(const SceneDev& s, float* poses, int N, int n_refine, float lr_t, float lr_r, float b1,
                               float b2, float eps, hipStream_t st);
+// n_refine Adam steps of one pose, each over row bands of R image rows (one
+// block per band, ceil(H / R) blocks) then a one-thread reduce + update.
+// partial: device float[ceil(H / R)][9]; state: device float[12] (moments).
+hipError_t launch_refine_banded(const SceneDev& s, float* pose, int n_refine, float lr_t, float lr_r, float b1,
+                                float b2, float eps, int R, float* partial, float* state, hipStream_t st);
 hipError_t launch_adam_pose(float* poses, const float* grad, int gstride, float* state, int N, int iter, float lr_t,
                             float lr_r, float b1, float b2, float eps, hipStream_t st);
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t st);

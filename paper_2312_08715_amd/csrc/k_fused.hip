@@ -219,7 +219,8 @@ __device__ __forceinline__ void raster_band(const SceneDev& s, const Pose& P, co
 template <bool GRAD, bool COUNT = false>
 __device__ __forceinline__ void render_score_one(const SceneDev& s, const float* __restrict__ pose16,
                                                  float* __restrict__ logL_out, float* __restrict__ grad_out,
-                                                 unsigned char* smem, unsigned* cnt = nullptr) {
+                                                 unsigned char* smem, unsigned* cnt = nullptr, int row_lo = -1,
+                                                 int row_hi = -1) {
   unsigned c_pair = 0, c_obs = 0, c_adj = 0;
   float* wbuf = reinterpret_cast<float*>(smem);  // after rasterisation
   unsigned long long* zbuf = reinterpret_cast<unsigned long long*>(smem + kRasterLdsBytes);
@@ -253,8 +254,12 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
     if (GRAD) band = min(band, min(s.wcap, (int)(kRasterLdsBytes - 2 * kBlock) / 4) / rw - 2 * h);
     band = max(band, 1);
     int gcarry = 0;  // drawn pixels of earlier bands' own rows
-    for (int a = region.y0; a < region.y1; a += band) {
-      const int b = min(a + band, region.y1);
+    // with a row range: only the region's rows in [row_lo, row_hi) (the
+    // adjoint's weights still span the whole region's halo rows)
+    const int ya = row_lo >= 0 ? max(region.y0, row_lo) : region.y0;
+    const int yb = row_lo >= 0 ? min(region.y1, row_hi) : region.y1;
+    for (int a = ya; a < yb; a += band) {
+      const int b = min(a + band, yb);
       Rect L = lds;
       L.y0 = a - 2 * h;
       L.y1 = b + 2 * h;
@@ -372,6 +377,14 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
     atomicAdd(&cnt[kCntAdj], c_adj);
   }
   block_sum<9>(acc, red);
+  if (row_lo >= 0) {  // the rows' own terms only, no background outside the region
+    if (threadIdx.x == 0) {
+      *logL_out = acc[0];
+      if (GRAD)
+        for (int k = 0; k < 8; ++k) grad_out[k] = acc[1 + k];
+    }
+    return;
+  }
   if (threadIdx.x == 0) {
     const size_t stride = (size_t)(H + 1) * (W + 1);
     Rect all;
@@ -474,6 +487,52 @@ hipError_t launch_refine_pose(const SceneDev& s, float* poses, int N, int n_refi
                               float b2, float eps, hipStream_t st) {
   hipLaunchKernelGGL(k_refine_pose, dim3(N), dim3(kBlock), fused_lds_bytes(s), st, s, poses, N, n_refine, lr_t,
                      lr_r, b1, b2, eps);
+  return hipGetLastError();
+}
+
+// One Adam step of one pose spread over row bands: block b scores the image
+// rows [b R, (b + 1) R) of the pose's region (render, windows, adjoint) and
+// writes its terms to partial[9 b .. 9 b + 9) (logL, d(dt, dw), d sigma,
+// d p_out, without the background outside the region, which the pose
+// gradient does not involve).
+__global__ __launch_bounds__(kBlock, 4) void k_refine_bands(SceneDev s, const float* __restrict__ pose, int R,
+                                                            float* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.x;
+  render_score_one<true>(s, pose, partial + 9 * b, partial + 9 * b + 1, smem, nullptr, b * R, (b + 1) * R);
+}
+
+// The band sums in band order (double), then the Adam update of the pose;
+// the moments live in state[0..12) (zero at iter 1).  One thread.
+__global__ void k_refine_update(float* __restrict__ pose, const float* __restrict__ partial, int nb,
+                                float* __restrict__ state, int iter, float lr_t, float lr_r, float b1, float b2,
+                                float eps) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  float g[6], m[6], v[6], P[16];
+  for (int k = 0; k < 6; ++k) {
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += (double)partial[9 * b + 1 + k];
+    g[k] = (float)t;
+    m[k] = iter == 1 ? 0.0f : state[k];
+    v[k] = iter == 1 ? 0.0f : state[6 + k];
+  }
+  for (int k = 0; k < 16; ++k) P[k] = pose[k];
+  adam_update(P, g, m, v, iter, lr_t, lr_r, b1, b2, eps);
+  for (int k = 0; k < 16; ++k) pose[k] = P[k];
+  for (int k = 0; k < 6; ++k) {
+    state[k] = m[k];
+    state[6 + k] = v[k];
+  }
+}
+
+hipError_t launch_refine_banded(const SceneDev& s, float* pose, int n_refine, float lr_t, float lr_r, float b1,
+                                float b2, float eps, int R, float* partial, float* state, hipStream_t st) {
+  const int nb = (s.cam.H + R - 1) / R;
+  for (int it = 1; it <= n_refine; ++it) {
+    hipLaunchKernelGGL(k_refine_bands, dim3(nb), dim3(kBlock), fused_lds_bytes(s), st, s, pose, R, partial);
+    hipLaunchKernelGGL(k_refine_update, dim3(1), dim3(64), 0, st, pose, partial, nb, state, it, lr_t, lr_r, b1, b2,
+                       eps);
+  }
   return hipGetLastError();
 }
 
