@@ -703,3 +703,36 @@ def test_tracker_graph_replays_match_eager_frames_and_follow_the_objects(b3d):
         err_r = np.degrees(np.arccos(np.clip((np.trace(dR) - 1) / 2, -1, 1)))
         say(f"  object {k}: position error {err_t * 100:.3f} cm, orientation error {err_r:.3f} deg")
         assert err_t < 0.01 and err_r < 5.0
+
+
+def test_hot_calls_replay_from_a_captured_graph(b3d):
+    # enumerate -> fused render + score + adjoint -> sample, captured once into a
+    # graph and replayed several times with eager work in between: every replay
+    # must equal the eager results bit for bit (the calls launch only on the
+    # caller's stream, allocate nothing and issue no memset)
+    wl, obs, P = workload(1)
+    scene, mesh, o = _scene(b3d, wl, obs)
+    grid, _ = b3d.grid_of(wl.grid)
+    seed = wl.seeds["sampler"]
+    Pe = b3d.enumerate_grid(grid, seed=seed)
+    Le, Ge = b3d.render_score(scene, Pe, grad=True)
+    we, ie, lwe = b3d.sample(Le, 64, seed)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm the allocator on the side stream
+        b3d.render_score(scene, b3d.enumerate_grid(grid, seed=seed), grad=True)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        Pg = b3d.enumerate_grid(grid, seed=seed)
+        Lg, Gg = b3d.render_score(scene, Pg, grad=True)
+        wg, ig, lwg = b3d.sample(Lg, 64, seed)
+    for rep in range(3):
+        Lx = b3d.render_score(scene, Pe[::7].contiguous())  # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        say(f"  graph replay {rep}: logL equal {torch.equal(Lg, Le)}, samples equal {torch.equal(ig, ie)}")
+        assert torch.equal(Pg, Pe) and torch.equal(Lg, Le) and torch.equal(Gg, Ge)
+        assert torch.equal(ig, ie) and torch.equal(lwg, lwe) and torch.equal(wg, we)
+        assert torch.equal(Lx, Le[::7])
