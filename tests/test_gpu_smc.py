@@ -125,10 +125,11 @@ def test_flat_likelihood_gives_equal_weights(b3d):
         assert np.array_equal(r["ancestors"].cpu().numpy(), np.arange(8))
 
 
-@pytest.mark.parametrize("stage_noise", [None, ((0.02, 0.3), (0.008, 0.2), (0.004, 0.1))])
-def test_smc_stages_match_oracle(b3d, stage_noise):
+@pytest.mark.parametrize("stage_noise,thr", [(None, 0.0), (((0.02, 0.3), (0.008, 0.2), (0.004, 0.1)), 0.0),
+                                              (None, 2.0)])
+def test_smc_stages_match_oracle(b3d, stage_noise, thr):
     meshes, truth, table, cam, obs = small_table_scene()
-    smc, types, tmesh, args = gpu_setup(b3d, meshes, table, cam, stage_noise=stage_noise)
+    smc, types, tmesh, args = gpu_setup(b3d, meshes, table, cam, stage_noise=stage_noise, ess_threshold=thr)
     tv, tt, tT = table
     fixed = [(tv, tt, tT)]
     loglik = oracle.smc.scene_loglik(obs, cam, meshes, fixed, 1.0, 5)
@@ -151,31 +152,46 @@ def test_smc_stages_match_oracle(b3d, stage_noise):
         say(f"  type posterior: max |dp| {np.abs(tp - diag['type_post']).max():.3g}")
         assert np.allclose(tp, diag["type_post"], rtol=1e-2, atol=2e-3)
         assert np.allclose(tp.sum(1), 1.0, atol=1e-5)
+        # the state is gathered by ancestor (identity without resampling):
+        # proposal j is seen at a survivor m with ancestors[m] == j
+        anc = r["ancestors"].cpu().numpy()
+        at = np.full(M, -1)
+        for m in range(M):
+            if at[anc[m]] < 0:
+                at[anc[m]] = m
+        seen = at >= 0
+
+        def pre(x):  # per-proposal view of a gathered per-particle array (rows of unseen proposals unused)
+            return x[np.maximum(at, 0)]
+
         ch = r["choice"].cpu().numpy()
-        same = np.all(ch == diag["choice"], axis=0) & (r["place"][:, i - 1].cpu().numpy() == diag["place"]).all(1)
-        say(f"stage {i}: particles whose cells all agree: {same.sum()}/{M}")
-        agree_all += same.sum()
+        same = (np.all(ch == diag["choice"], axis=0) & seen &
+                (pre(r["place"][:, i - 1].cpu().numpy()) == diag["place"]).all(1))
+        say(f"stage {i}: proposals whose cells all agree: {same.sum()}/{M} ({seen.sum()} survive)")
+        agree_all += (np.all(ch == diag["choice"], axis=0)).sum()
         if not same.any():
             continue
-        g_dphi = r["dphi"][:, i - 1].cpu().numpy()
-        g_pose = r["poses"][:, i - 1].cpu().numpy()
+        g_dphi = pre(r["dphi"][:, i - 1].cpu().numpy())
+        g_pose = pre(r["poses"][:, i - 1].cpu().numpy())
         assert np.abs(g_dphi[same] - diag["dphi"][same]).max() <= 2e-5
         assert np.abs(g_pose[same] - diag["poses"][same]).max() <= 5e-5
         # noise grid at the proposed placement: eq. (1) over the whole image
         gg = r["noise_grid"].cpu().numpy().astype(np.float64)
         og = diag["noise_grid"]
         rel = np.abs(gg - og) / (np.abs(og) + 1.0)
-        say(f"  noise grid: max rel err (agreeing particles) {rel[same].max():.3g}")
+        say(f"  noise grid: max rel err (agreeing proposals) {rel[same].max():.3g}")
         assert np.median(rel[same]) <= 1e-4 and rel[same].max() <= 2e-3
-        nsame = same & np.all(np.isclose(r["noise"].cpu().numpy(), diag["noise"], rtol=1e-5, atol=1e-7), axis=1)
+        g_noise = pre(r["noise"].cpu().numpy())
+        nsame = same & np.all(np.isclose(g_noise, diag["noise"], rtol=1e-5, atol=1e-7), axis=1)
         say(f"  noise draws agree: {nsame.sum()}/{same.sum()}")
         assert nsame.sum() >= max(1, same.sum() - 1)
         # log q: the draws' log probabilities, the cell volume and the noise cell area
         gq = r["logq"].cpu().numpy()
         assert np.all(np.abs(gq - diag["logq"])[nsame] <= 1e-3 + 1e-4 * np.abs(diag["logq"][nsame]))
         # logL at the new noise, against the oracle's at the library's own placement
-        gl = r["logL"].cpu().numpy().astype(np.float64)
-        for m in np.nonzero(nsame)[0]:
+        gl = pre(r["logL"].cpu().numpy().astype(np.float64))
+        for jp in np.nonzero(nsame)[0]:
+            m = at[jp]
             objs = [(int(o), Pq) for (o, c), Pq in zip(r["place"][m, :i].cpu().numpy(),
                                                         r["poses"][m, :i].cpu().numpy().astype(np.float64))]
             o_new, P_new = objs[-1]
@@ -183,15 +199,23 @@ def test_smc_stages_match_oracle(b3d, stage_noise):
                                  [(meshes[o][0], meshes[o][1], Pq) for o, Pq in objs[:-1]], cam)
             s, p_ = r["noise"][m].cpu().numpy().astype(np.float64)
             L64, l1 = oracle.score(obs, oracle.unproject(d, cam), float(s), float(p_), 1.0, 5)
-            assert abs(gl[m] - L64[0]) <= 1e-4 * l1[0] + 1e-2, (m, gl[m], L64[0], l1[0])
+            assert abs(gl[jp] - L64[0]) <= 1e-4 * l1[0] + 1e-2, (jp, gl[jp], L64[0], l1[0])
         # eq. (2)/(3) on the library's own logL and log q (exact arithmetic check)
-        lpr = np.array([log_prior(len(faces), T, faces[o][c]) for o, c in r["place"][:, i - 1].cpu().numpy()])
+        lpr = np.array([log_prior(len(faces), T, faces[o][c]) for o, c in pre(r["place"][:, i - 1].cpu().numpy())])
         logp = gl + st.lprior + lpr - np.log(args["sigma_max"])
         back = 0.0 if i == 1 else -np.log(args["sigma_max"])
         want = st.logW + logp - st.logp - gq + back
-        assert np.allclose(r["logW_pre"].cpu().numpy(), want, rtol=1e-12, atol=1e-6)
-        assert np.allclose(r["logW"].cpu().numpy(), want, rtol=1e-12, atol=1e-6)  # no resampling here
-        assert np.allclose(r["logp"].cpu().numpy(), logp, rtol=1e-12, atol=1e-6)
+        lw_pre = r["logW_pre"].cpu().numpy()
+        assert np.allclose(lw_pre[seen], want[seen], rtol=1e-12, atol=1e-6)
+        assert np.allclose(r["logp"].cpu().numpy(), logp[anc], rtol=1e-12, atol=1e-6)
+        if thr > 1:  # resampled: every weight is the mean weight
+            lse = lw_pre.max() + np.log(np.exp(lw_pre - lw_pre.max()).sum())
+            assert np.allclose(r["logW"].cpu().numpy(), lse - np.log(M), rtol=0, atol=1e-9)
+            say(f"  ancestors equal to the oracle's: {(anc == diag['ancestors']).mean():.2f}")
+            assert (anc == diag["ancestors"]).mean() >= 0.75
+        else:
+            assert np.array_equal(anc, np.arange(M))
+            assert np.array_equal(r["logW"].cpu().numpy(), lw_pre)
     assert agree_all >= 2 * M - 2
 
 
