@@ -171,6 +171,8 @@ def init_particles(M: int, params: SMCParams) -> Particles:
 
 
 # loglik(m, o, poses [N,4,4], particle objects [(type, pose)], sigma, p_out) -> logL [N]
+# (m is the particle; particles with equal objects and noise share one
+# evaluation of the stage-0 cells, made with the first of them)
 LogLik = Callable[[int, int, np.ndarray, list, float, float], np.ndarray]
 
 
@@ -195,6 +197,7 @@ def smc_stage(state: Particles, i: int, loglik: LogLik, faces: Sequence[Sequence
     noise_grid = np.zeros((M, params.A * params.B))
     noise_choice = np.zeros(M, np.int32)
     type_post = np.zeros((M, n_types))
+    stage0, stage0_of = {}, []
     for m in range(M):
         objs = [(int(state.place[m, j, 0]), state.poses[m, j]) for j in range(k)]
 
@@ -211,10 +214,15 @@ def smc_stage(state: Particles, i: int, loglik: LogLik, faces: Sequence[Sequence
                     cells.append((o, c, a, b))
                     cents.append(0.5 * (a + b))
         sig, po = noise_at(0)
-        L = np.concatenate([
-            loglik(m, o, np.stack([contact_pose(table, faces[o][cells[n][1]], *cents[n])
-                                   for n in range(len(cells)) if cells[n][0] == o]), objs, sig, po)
-            for o in range(n_types)])
+        # particles with equal objects and noise score the stage-0 cells alike: once
+        key = (float(sig), float(po), tuple((t, Q.tobytes()) for t, Q in objs))
+        if key not in stage0:
+            stage0[key] = np.concatenate([
+                loglik(m, o, np.stack([contact_pose(table, faces[o][cells[n][1]], *cents[n])
+                                       for n in range(len(cells)) if cells[n][0] == o]), objs, sig, po)
+                for o in range(n_types)])
+        L = stage0[key]
+        stage0_of.append(L)
         w = np.exp(L - L.max())
         type_post[m] = w.reshape(n_types, -1).sum(axis=1) / w.sum()  # marginal over face and placement
         _, idx, lw = sample(L, 1, seed, stage=(i << 8) | 0, k0=m)
@@ -271,7 +279,7 @@ def smc_stage(state: Particles, i: int, loglik: LogLik, faces: Sequence[Sequence
         noise=new_noise[src], logW=logW, logp=logp[src], lprior=lprior[src], logL=logL_new[src])
     diag = dict(choice=choice, logq=logq, logL=logL_new, logp=logp, logW_pre=logW_pre, ess=ess, ancestors=src,
                 resampled=resampled, noise_grid=noise_grid, noise_choice=noise_choice, place=new_place,
-                dphi=new_dphi, poses=new_pose, noise=new_noise, type_post=type_post)
+                dphi=new_dphi, poses=new_pose, noise=new_noise, type_post=type_post, stage0_logL=stage0_of)
     return new, diag
 
 
