@@ -640,7 +640,46 @@ def cpu_baseline(wl, obs64, seconds):
              "sample": f"first {done} of {P.shape[0]} hypotheses, render+score+adjoint in FP64",
              "cpu": cpu_model(), "host_cpus": os.cpu_count(),
              "single_thread": {"value": one_done / one_dt, "unit": "hypotheses/s",
-                               "sample": f"first {one_done} hypotheses, one thread"}}, counts)
+                               "sample": f"first {one_done} hypotheses, one thread"},
+             "other_workloads": cpu_other_workloads()}, counts)
+
+
+def cpu_other_workloads():
+    """The oracle (render + score, forward, all threads) on the small
+    configuration (all 256 hypotheses) and on 256 hypotheses of the table
+    scene's first coarse-to-fine stage (320x240, the other objects and the
+    table as background)."""
+    import oracle
+    from workloads import make_config, table_scene
+
+    out = {}
+    wl = make_config(0, render=oracle.render_depth_fn)
+    obs = oracle.observed_xyz(wl)
+    P = oracle.enumerate_grid(wl.grid, seed=wl.seeds["hyp"])
+    s = wl.score
+    t0 = time.perf_counter()
+    d, _ = oracle.render([(wl.verts, wl.tris, P)], wl.camera)
+    oracle.score(obs, oracle.unproject(d, wl.camera), s.sigma, s.p_out, s.outlier_volume, s.window)
+    out["small_config"] = {"value": P.shape[0] / (time.perf_counter() - t0), "unit": "hypotheses/s",
+                           "sample": f"all {P.shape[0]} hypotheses, forward"}
+    meshes, poses, table, cam, noise, Tcw = table_scene()
+    objs = [(v, t, Q) for (v, t), Q in zip(meshes, poses)] + [table]
+    d, _ = oracle.render(objs, cam)
+    z = np.where(d[0] > 0, d[0] + noise["gauss"], 0.0)
+    z = np.where(noise["outlier_mask"], noise["outlier_depth"], z)
+    obs = oracle.unproject(z, cam)
+    rng = np.random.default_rng(2003)
+    k = 3
+    P = np.repeat(np.asarray(poses[k])[None], 256, axis=0)
+    P[:, :3, 3] += rng.uniform(-0.08, 0.08, size=(256, 3))
+    bg = [o for j, o in enumerate(objs) if j != k]
+    t0 = time.perf_counter()
+    d, _ = oracle.render([(meshes[k][0], meshes[k][1], P)] + bg, cam)
+    oracle.score(obs, oracle.unproject(d, cam), 0.003, 0.01, 1.0, 5)
+    out["table_scene_stage1"] = {"value": 256 / (time.perf_counter() - t0), "unit": "hypotheses/s",
+                                 "sample": "256 hypotheses of the 6000-voxel object within +-8 cm, 320x240, "
+                                           "forward with the other objects and the table as background"}
+    return out
 
 
 if __name__ == "__main__":
