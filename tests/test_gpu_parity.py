@@ -703,6 +703,20 @@ def test_tracker_graph_replays_match_eager_frames_and_follow_the_objects(b3d):
         err_r = np.degrees(np.arccos(np.clip((np.trace(dR) - 1) / 2, -1, 1)))
         say(f"  object {k}: position error {err_t * 100:.3f} cm, orientation error {err_r:.3f} deg")
         assert err_t < 0.01 and err_r < 5.0
+    # checkpoint and resume: a frame's state is the objects' poses (the
+    # refinement's moments start from zero every frame), so a tracker created
+    # from poses saved after frame 2 continues bit for bit like the original
+    tc = b3d.Tracker(ms, K, p, grid, init, n_refine=5)
+    for f in range(1, 3):
+        tc.frame(frames[f])
+    saved = tc.poses().cpu().numpy()
+    tr = b3d.Tracker(ms, K, p, grid, saved, n_refine=5)
+    for f in range(3, F):
+        tc.frame(frames[f])
+        tr.frame(frames[f])
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(tc.poses().cpu().numpy(), tr.poses().cpu().numpy())
+    np.testing.assert_array_equal(tr.poses().cpu().numpy(), est)
 
 
 def test_hot_calls_replay_from_a_captured_graph(b3d):
