@@ -45,7 +45,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # FP32 lane-ops/s, non-packed: 39.
 # what the same counters read for a plain 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0).  Valid only for the kernel sources with this digest:
 # after any change to them the figure is reported as null until re-measured.
-TRAFFIC = {"sources_sha256": "503ccbcefb7f3b38a564648cd38d54694c38da8539933512f437265c6cf24c09", "fetch_KiB": 6369.13, "write_KiB": 312.5, "fetch_scale": 2.0, "write_scale": 1.0}
+TRAFFIC = {"sources_sha256": "1f80705d492532af41c9dc4eadcc07c38475cf4fb22426efb8e3a82758b66293", "fetch_KiB": 6368.54, "write_KiB": 312.5, "fetch_scale": 2.0, "write_scale": 1.0}
 KERNEL_SOURCES = ["k_fused.hip", "b3d_device.hpp", "b3d_launch.hpp"]
 
 
@@ -371,6 +371,50 @@ def bench_tracking(b3d, torch, p, n_frames=200):
             "note": "objects pass behind each other; an object hidden for several frames is lost by the local search"}
 
 
+def bench_camera_pan(b3d, torch, p, resolutions=(25, 50, 100, 200), n_frames=120):
+    """The setting of the paper's tracking table (Sec. IV, Table 1): a camera
+    circling one object on a table for 120 frames at square resolutions of
+    25 to 200 pixels, tracked from the known first pose by four stages of
+    hypotheses per frame (1,708 in all: rotations, translations, then two
+    joint stages, each around the best of the stage before) and no gradient
+    steps, one HIP graph per frame.  The tracked quantity is the scene's pose
+    in the camera frame; errors are of the camera's position in the scene
+    frame and of its orientation."""
+    from workloads import camera_pan_schedule, camera_pan_sequence
+
+    specs = camera_pan_schedule()
+    grids = [b3d.grid_of(g) for g in specs]  # (grid, rotations tensor): the tensors outlive the trackers
+    per_frame = sum(g.N for g in specs)
+    out = {}
+    for res in resolutions:
+        (v, t), truth, cam, noise = camera_pan_sequence(res=res, n_frames=n_frames)
+        frames = [noisy_observation(b3d, torch, gpu_depth(b3d, torch, [(v, t, truth[f])], cam), noise[f], cam)
+                  for f in range(n_frames)]
+        tr = b3d.Tracker([b3d.Mesh(v, t)], b3d.intrinsics_of(cam), p, [g for g, _ in grids], truth[:1], n_refine=0)
+        est = torch.empty((n_frames, 1, 4, 4), dtype=torch.float32, device="cuda")
+        est[0] = torch.as_tensor(truth[:1], dtype=torch.float32)
+        tr.frame(frames[1])  # captures the frame graph
+        est[1] = tr.poses()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for f in range(2, n_frames):
+            tr.frame(frames[f])
+            est[f] = tr.poses()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tr.close()
+        E = est[:, 0].cpu().numpy().astype(np.float64)
+        cam_pos = lambda T: -T[:, :3, :3].transpose(0, 2, 1) @ T[:, :3, 3:4]  # noqa: E731
+        pos = np.linalg.norm((cam_pos(E[1:]) - cam_pos(truth[1:]))[..., 0], axis=1) * 100.0
+        rot = np.array([rot_err_deg(E[f, :3, :3], truth[f, :3, :3]) for f in range(1, n_frames)])
+        out[f"{res}x{res}"] = {"frames_per_s": (n_frames - 2) / dt,
+                               "hypotheses_per_s": per_frame * (n_frames - 2) / dt,
+                               "position_error_cm": {"mean": float(pos.mean()), "max": float(pos.max())},
+                               "orientation_error_deg": {"mean": float(rot.mean()), "max": float(rot.max())}}
+    return {"frames": n_frames, "hypotheses_per_frame": per_frame, "triangles": int(t.shape[0]),
+            "by_resolution": out}
+
+
 def bench_table_c2f(b3d, torch, p):
     """Four objects on a table at 320x240: per object three coarse-to-fine
     stages of 10,000 hypotheses for 16 particles, then 20 Adam steps on the
@@ -436,7 +480,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fused-only", action="store_true", help="skip the split-path comparison")
     ap.add_argument("--no-extras", action="store_true", help="skip the batch, tracking and table workloads")
-    ap.add_argument("--only", choices=["batch", "tracking", "table", "noise_grid", "smc"],
+    ap.add_argument("--only", choices=["batch", "tracking", "camera_pan", "table", "noise_grid", "smc"],
                     help="run just one of the extra workloads and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (reference for HBM byte counters)")
@@ -455,7 +499,8 @@ def main():
     s = wl.score
     p = b3d.score_params(s.sigma, s.p_out, s.outlier_volume, s.window)
     if args.only and args.only != "noise_grid":
-        fn = {"batch": bench_batch, "tracking": bench_tracking, "table": bench_table_c2f, "smc": bench_smc}[args.only]
+        fn = {"batch": bench_batch, "tracking": bench_tracking, "camera_pan": bench_camera_pan,
+              "table": bench_table_c2f, "smc": bench_smc}[args.only]
         print(json.dumps({args.only: fn(b3d, torch, p)}), flush=True)
         return
     mesh = b3d.Mesh(wl.verts, wl.tris)
@@ -542,6 +587,7 @@ def main():
         for name, fn in (("smc_table_scene", lambda: bench_smc(b3d, torch)),
                          ("batch_64_scenes", lambda: bench_batch(b3d, torch, p)),
                          ("tracking_200_frames", lambda: bench_tracking(b3d, torch, p)),
+                         ("camera_pan_120_frames", lambda: bench_camera_pan(b3d, torch, p)),
                          ("table_c2f_adam", lambda: bench_table_c2f(b3d, torch, p))):
             t0 = time.perf_counter()
             extras[name] = fn()
@@ -566,7 +612,7 @@ def main():
                                "(10x10 translations x 50 rotations), 5x5 window, fused fwd+adjoint + sampling",
                    "hypotheses": N, "image": "160x120", "triangles": int(wl.tris.shape[0]), "window": s.window,
                    "samples_per_step": args.samples},
-        "roofline": {"bound": "alu", "kernel": "k_render_score<true>", "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": "k_render_score<true, 0>", "achieved": achieved,
                      "peak": VALU_PEAK_TOPS, "unit": "TOP/s (FP32 lane-ops)", "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": measured_traffic(), "kernel_ms": t_kernel * 1e3,
                      "kernel_ms_median": t_kernel_median * 1e3,

@@ -424,7 +424,9 @@ typedef struct b3d_tracker b3d_tracker;
  * object by object: the other objects, at their latest estimates, are drawn
  * as static background; the grid of hypotheses around the object's previous
  * estimate is scored with the fused kernel, stage by stage around the best
- * of the previous stage; the best hypothesis is refined by n_refine Adam
+ * of the previous stage (stage t enumerated as b3d_enumerate with seed 0 and
+ * stage t; ties go to the lowest index); the best hypothesis is refined by
+ * n_refine Adam
  * steps on the adjoint, each step's render, windows and adjoint spread over
  * row bands of the object's region (one workgroup per eight image rows) and
  * summed in band order.  The whole frame is captured once
@@ -436,9 +438,12 @@ b3d_status b3d_tracker_create(const b3d_mesh* const* meshes, int32_t M, const b3
                               const b3d_score_params* p, const b3d_track_params* tp, const float* init_poses,
                               b3d_tracker** out);
 /* Process one frame: observed is a device float[H][W][3] copied into the
- * tracker's own buffer before the graph runs.  Stream-ordered (the first
- * call captures the graph on an internal stream, then launches it on
- * `stream`). */
+ * tracker's own buffer before the graph runs.  Stream-ordered, except the
+ * first call: it chooses the fused kernel's depth-buffer tile by running
+ * this frame directly on `stream` once per candidate tile, timing each run
+ * and restoring the estimates after it (no result depends on the tile), and
+ * waits for `stream`; then it captures the graph on an internal stream and
+ * launches it on `stream`. */
 b3d_status b3d_tracker_frame(b3d_tracker* tr, const float* observed, void* stream);
 /* The same frame run directly on `stream`, without the graph (reference
  * for the captured path).  Stream-ordered. */

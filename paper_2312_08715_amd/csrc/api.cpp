@@ -254,7 +254,6 @@ b3d_status b3d_mesh_create(const float* verts, int32_t V, const int32_t* tris, i
   m->n_drawn = lay.n_drawn;
   m->n_hidden = lay.n_hidden;
   m->n_dropped = lay.n_dropped;
-  d.V = V;
   d.T = T;
   for (int k = 0; k < 3; ++k) {
     // widen by a relative epsilon so that float rounding keeps the bounds conservative
@@ -264,6 +263,19 @@ b3d_status b3d_mesh_create(const float* verts, int32_t V, const int32_t* tris, i
     d.sphere[k] = (float)ctr[k];
   }
   d.sphere[3] = (float)(rad * (1.0 + 1e-6) + 1e-7);
+  // large primitives (relative to the whole mesh) select the rasteriser's
+  // wave walk of large screen boxes; results are the same either way
+  double diag2 = 0.0;
+  for (int k = 0; k < 3; ++k) diag2 += (hi[k] - lo[k]) * (hi[k] - lo[k]);
+  d.has_big = 0;
+  for (size_t q = 0; q + 3 < lay.pverts.size() && !d.has_big; q += 4) {
+    for (int a = 0; a < 4 && !d.has_big; ++a)
+      for (int b = a + 1; b < 4; ++b) {
+        const float4 u = lay.pverts[q + a], w = lay.pverts[q + b];
+        const double dx = (double)u.x - w.x, dy = (double)u.y - w.y, dz = (double)u.z - w.z;
+        if (64.0 * (dx * dx + dy * dy + dz * dz) > diag2) d.has_big = 1;
+      }
+  }
   *out = m;
   return B3D_OK;
 }
@@ -957,6 +969,28 @@ struct b3d_tracker {
   hipGraphExec_t exec = nullptr;
 };
 
+// Object o's scene for the frame in T->obs: the other objects at their
+// current estimates drawn as its static background, then the background's
+// likelihood terms.
+static b3d_status tracker_background(b3d_tracker* T, int o, hipStream_t st) {
+  b3d_scene* S = T->scenes[o];
+  const size_t HW = (size_t)S->K.H * S->K.W;
+  if (T->M > 1) {
+    B3D_CHECK_HIP(launch_fill_keys(S->bg, HW, st), "tracker");
+    uint32_t base = (uint32_t)S->mesh->T;
+    for (int k = 0; k < T->M; ++k) {
+      if (k == o) continue;
+      B3D_CHECK_HIP(launch_raster_global_dev(T->meshes[k]->dev, S->dev.cam, T->poses + 16 * k, base, S->bg, st),
+                    "tracker");
+      B3D_CHECK_HIP(launch_refine_global(T->meshes[k]->dev, S->dev.cam, nullptr, T->poses + 16 * k, base, S->bg, st),
+                    "tracker");
+      base += (uint32_t)T->meshes[k]->T;
+    }
+  }
+  B3D_CHECK_HIP(launch_background_terms(S->dev, S->terms, st), "tracker");
+  return B3D_OK;
+}
+
 static b3d_status tracker_record(b3d_tracker* T, hipStream_t st) {
   const b3d_track_params& tp = T->tp;
   GridDev g[B3D_MAX_STAGES];
@@ -964,20 +998,7 @@ static b3d_status tracker_record(b3d_tracker* T, hipStream_t st) {
   for (int s = 0; s < tp.n_stages; ++s) (void)make_grid(&tp.stages[s], &g[s], &ns[s]);
   for (int o = 0; o < T->M; ++o) {
     b3d_scene* S = T->scenes[o];
-    const size_t HW = (size_t)S->K.H * S->K.W;
-    if (T->M > 1) {
-      B3D_CHECK_HIP(launch_fill_keys(S->bg, HW, st), "tracker");
-      uint32_t base = (uint32_t)S->mesh->T;
-      for (int k = 0; k < T->M; ++k) {
-        if (k == o) continue;
-        B3D_CHECK_HIP(launch_raster_global_dev(T->meshes[k]->dev, S->dev.cam, T->poses + 16 * k, base, S->bg, st),
-                      "tracker");
-        B3D_CHECK_HIP(launch_refine_global(T->meshes[k]->dev, S->dev.cam, nullptr, T->poses + 16 * k, base, S->bg, st),
-                      "tracker");
-        base += (uint32_t)T->meshes[k]->T;
-      }
-    }
-    B3D_CHECK_HIP(launch_background_terms(S->dev, S->terms, st), "tracker");
+    if (b3d_status s = tracker_background(T, o, st)) return s;
     for (int s = 0; s < tp.n_stages; ++s) {
       B3D_CHECK_HIP(launch_enumerate(g[s], T->poses + 16 * o, 1, 0u, 0u, (uint32_t)s, T->hyp, st), "tracker");
       B3D_CHECK_HIP(launch_render_score(S->dev, T->hyp, (int)ns[s], T->logL, nullptr, st), "tracker");
@@ -989,6 +1010,59 @@ static b3d_status tracker_record(b3d_tracker* T, hipStream_t st) {
                     "tracker");
   }
   return B3D_OK;
+}
+
+// Chooses the fused kernel's depth-buffer tile (the same for every object's
+// scene) by timing whole frames on the frame in T->obs, restoring the
+// estimates after each; no result depends on the tile.  Synchronises `st`.
+static b3d_status tracker_tune(b3d_tracker* T, hipStream_t st) {
+  const SceneDev& d0 = T->scenes[0]->dev;
+  std::vector<int> cands;
+  for (int b = 2; b <= 6; ++b) {
+    const int z = std::min(default_zcap(d0, b), max_zcap(d0));
+    SceneDev t = d0;
+    t.zcap = z;
+    if (z >= min_zcap(d0) && fused_lds_bytes(t) <= kLdsMax && (cands.empty() || cands.back() != z))
+      cands.push_back(z);
+  }
+  if (cands.size() < 2) return B3D_OK;
+  const size_t pose_bytes = sizeof(float) * 16 * (size_t)T->M;
+  float* saved = nullptr;
+  if (hipMalloc((void**)&saved, pose_bytes) != hipSuccess)
+    return fail(B3D_ENOMEM, "tracker_frame: tuning scratch allocation failed");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  b3d_status status = B3D_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+      hipMemcpyAsync(saved, T->poses, pose_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    status = fail(B3D_EHIP, "tracker_frame: tuning set-up failed");
+  const int keep = d0.zcap;
+  int best = keep;
+  float best_ms = 3.0e38f;
+  for (size_t c = 0; c < cands.size() && status == B3D_OK; ++c) {
+    for (b3d_scene* S : T->scenes) S->dev.zcap = cands[c];
+    float ms = 3.0e38f;
+    for (int rep = 0; rep < 3 && status == B3D_OK; ++rep) {  // the first run warms up
+      float t = 0.0f;
+      if (hipEventRecord(e0, st) != hipSuccess) status = fail(B3D_EHIP, "tracker_frame: tuning event failed");
+      if (status == B3D_OK) status = tracker_record(T, st);
+      if (status == B3D_OK &&
+          (hipEventRecord(e1, st) != hipSuccess ||
+           hipMemcpyAsync(T->poses, saved, pose_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+           hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        status = fail(B3D_EHIP, "tracker_frame: tuning run failed");
+      if (rep > 0) ms = std::min(ms, t);
+    }
+    if (status == B3D_OK && ms < best_ms) {
+      best_ms = ms;
+      best = cands[c];
+    }
+  }
+  for (b3d_scene* S : T->scenes) S->dev.zcap = status == B3D_OK ? best : keep;
+  if (hipStreamSynchronize(st) != hipSuccess && status == B3D_OK) status = fail(B3D_EHIP, "tracker_frame: tuning");
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(saved);
+  return status;
 }
 
 extern "C" {
@@ -1066,6 +1140,8 @@ b3d_status b3d_tracker_frame(b3d_tracker* T, const float* observed, void* stream
   if (!T || !observed) return fail(B3D_EINVAL, "tracker_frame: NULL pointer");
   hipStream_t st = (hipStream_t)stream;
   if (!T->exec) {
+    B3D_CHECK_HIP(hipMemcpyAsync(T->obs, observed, T->obs_bytes, hipMemcpyDeviceToDevice, st), "tracker_frame: copy");
+    if (b3d_status s = tracker_tune(T, st)) return s;
     B3D_CHECK_HIP(hipStreamBeginCapture(T->cap, hipStreamCaptureModeThreadLocal), "tracker_frame: capture");
     b3d_status s = tracker_record(T, T->cap);
     hipGraph_t g = nullptr;

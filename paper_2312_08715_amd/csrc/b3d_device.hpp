@@ -51,7 +51,9 @@ struct MeshDev {
   const float4* verts;         // caller's vertices
   const int4* tris;            // caller's triangles (w unused)
   const float4* normals;       // object-frame (v1 - v0) x (v2 - v0)
-  int n_clusters, n_visible, V, T;
+  int n_clusters, n_visible;
+  int has_big;                 // some primitive spans over 1/8 of the bounds' diagonal (table tops, walls)
+  int T;                       // triangles
   float sphere[4];             // bounding sphere centre and radius
   float lo[3], hi[3];          // axis-aligned bounds
 };
@@ -329,6 +331,13 @@ struct RasterLds {
 constexpr int kQueueCap = 1536;
 constexpr size_t kRasterLdsBytes = sizeof(uint2) * kQueueCap + sizeof(int) * kBlock + sizeof(int) * 16;
 
+constexpr int kBigCentres = 64;  // a box of more centres than this is walked by the whole wave
+constexpr int kBigSlots = 2;     // such boxes a wave takes together per cluster
+constexpr int kStageWords = 36;  // words of one staged box
+// the staged boxes take the queue's last entries
+constexpr int kStageQueueEntries = (int)((sizeof(float) * kWaves * kBigSlots * kStageWords + 7) / 8);
+static_assert(kStageQueueEntries < kQueueCap / 4, "staging area too large for the exact-test queue");
+
 __device__ __forceinline__ RasterLds carve_raster_lds(unsigned char* p) {
   RasterLds r;
   r.queue = reinterpret_cast<uint2*>(p);
@@ -336,6 +345,12 @@ __device__ __forceinline__ RasterLds carve_raster_lds(unsigned char* p) {
   r.counts = r.list + kBlock;
   r.qcap = kQueueCap;
   return r;
+}
+
+// Staging slots of the large-box walk (only meshes with large primitives use
+// them, with the queue shortened to kQueueCap - kStageQueueEntries).
+__device__ __forceinline__ float* raster_stage(const RasterLds& r) {
+  return reinterpret_cast<float*>(r.queue + (kQueueCap - kStageQueueEntries));
 }
 
 // Work counters of the counting instantiation (indices into a per-block
@@ -352,6 +367,74 @@ __device__ __forceinline__ float4 project_corner(const Pose& P, const Cam& cam, 
   return make_float4(cam.fx * p.x * iz + cam.cx, cam.fy * p.y * iz + cam.cy, p.z, iz);
 }
 
+// A centre of one triangle: queued for the exact test when within the
+// margin of an edge (or the triangle is nearly edge-on), else written.
+// (x0, x1, x2) are its edge functions, (m0, m1, m2) their margins, (i0, i1,
+// i2) the corners' 1/z and ia 1/area.
+template <bool COUNT>
+__device__ __forceinline__ void emit_centre(int pix, bool eon, float x0, float x1, float x2, float m0, float m1,
+                                            float m2, float i0, float i1, float i2, float ia, uint32_t tid,
+                                            uint32_t id_base, unsigned long long* zbuf, const RasterLds& lds,
+                                            unsigned& c_frag) {
+  if (eon || x0 >= -m0 || x1 >= -m1 || x2 >= -m2) {
+    const int slot = atomicAdd(&lds.counts[0], 1);
+    if (slot < lds.qcap) {
+      lds.queue[slot] = make_uint2((uint32_t)pix, tid);
+      return;
+    }
+    if (eon || x0 > 0.0f || x1 > 0.0f || x2 > 0.0f) return;  // queue full: single precision
+  }
+  // 1/z is affine in screen space: interpolate with barycentrics x_k/area
+  const float z = __builtin_amdgcn_rcpf((x0 * i0 + x1 * i1 + x2 * i2) * ia);
+  if (!(z > 0.0f)) return;
+  if (COUNT) ++c_frag;
+  atomicMin(&zbuf[pix], pack_key(z, id_base + tid));
+}
+
+// Word layout of a staged box: edge vectors e0, e1, e2, f0, f1 (x, y), edge
+// margins t0, t1, t2, s0, s1, 1/area of both triangles, the edge functions at
+// the box's first centre, the corners' 1/z, then (as ints) the box, the two
+// triangle ids and the flags act1 | act2 << 1 | eon1 << 2 | eon2 << 3.
+enum { kStE = 0, kStT = 10, kStIa = 15, kStW = 17, kStIz = 22, kStBox = 26, kStIds = 30, kStFlags = 32 };
+
+// The whole wave walks a staged box, lane l taking centres l, l + 64, ...;
+// each centre gets the coverage tests of the single-lane walk from the same
+// values (which walk a box takes depends only on the mesh and the pose).
+template <bool COUNT>
+__device__ __forceinline__ void walk_staged(const float* __restrict__ st, int lane, const Rect& buf, int pitch,
+                                            uint32_t id_base, unsigned long long* zbuf, const RasterLds& lds,
+                                            unsigned& c_frag) {
+  const int* si = reinterpret_cast<const int*>(st);
+  const int c0 = si[kStBox], c1 = si[kStBox + 1], r0 = si[kStBox + 2], r1 = si[kStBox + 3];
+  const uint32_t id1 = (uint32_t)si[kStIds], id2 = (uint32_t)si[kStIds + 1];
+  const int flags = si[kStFlags];
+  const bool act1 = flags & 1, act2 = flags & 2, eon1 = flags & 4, eon2 = flags & 8;
+  const float e0x = st[kStE], e0y = st[kStE + 1], e1x = st[kStE + 2], e1y = st[kStE + 3];
+  const float e2x = st[kStE + 4], e2y = st[kStE + 5], f0x = st[kStE + 6], f0y = st[kStE + 7];
+  const float f1x = st[kStE + 8], f1y = st[kStE + 9];
+  const float t0 = st[kStT], t1 = st[kStT + 1], t2 = st[kStT + 2], s0 = st[kStT + 3], s1 = st[kStT + 4];
+  const float ia1 = st[kStIa], ia2 = st[kStIa + 1];
+  const float w0b = st[kStW], w1b = st[kStW + 1], w2b = st[kStW + 2], v0b = st[kStW + 3], v1b = st[kStW + 4];
+  const float izA = st[kStIz], izB = st[kStIz + 1], izC = st[kStIz + 2], izD = st[kStIz + 3];
+  const int wc = c1 - c0 + 1, n_cent = wc * (r1 - r0 + 1);
+  for (int k = lane; k < n_cent; k += 64) {
+    const int dri = k / wc;
+    const int r = r0 + dri, col = c0 + (k - dri * wc);
+    const float dr = (float)dri, dc = (float)(col - c0);
+    const float w0 = __builtin_fmaf(-e0y, dc, __builtin_fmaf(e0x, dr, w0b));
+    const float w1 = __builtin_fmaf(-e1y, dc, __builtin_fmaf(e1x, dr, w1b));
+    const float w2 = __builtin_fmaf(-e2y, dc, __builtin_fmaf(e2x, dr, w2b));
+    const float v0 = __builtin_fmaf(-f0y, dc, __builtin_fmaf(f0x, dr, v0b));
+    const float v1 = __builtin_fmaf(-f1y, dc, __builtin_fmaf(f1x, dr, v1b));
+    const bool out1 = !act1 || w0 > t0 || w1 > t1 || w2 > t2;
+    const bool out2 = !act2 || v0 > s0 || v1 > s1 || -w1 > t1;
+    if (out1 && out2) continue;
+    const int pix = (r - buf.y0) * pitch + (col - buf.x0);
+    if (!out1) emit_centre<COUNT>(pix, eon1, w0, w1, w2, t0, t1, t2, izA, izB, izC, ia1, id1, id_base, zbuf, lds, c_frag);
+    if (!out2) emit_centre<COUNT>(pix, eon2, v0, v1, -w1, s0, s1, t1, izA, izC, izD, ia2, id2, id_base, zbuf, lds, c_frag);
+  }
+}
+
 // Rasterise the mesh under pose P into the pixels of the image rectangle
 // `band` of an LDS key buffer that covers the rectangle `buf` (row pitch
 // buf.w(); band inside buf).  Triangle ids written are
@@ -359,13 +442,16 @@ __device__ __forceinline__ float4 project_corner(const Pose& P, const Cam& cam, 
 // kBlock at a time, and the drawable ones compacted into a list; the four
 // waves then take clusters from the list independently: a wave transforms
 // its cluster's vertices into its own LDS buffer and each lane takes one
-// triangle, walking the pixel centres of its screen box.  A centre that single
+// primitive (a quad or a triangle), walking the pixel centres of its screen
+// box; with BIG, up to kBigSlots boxes of more than kBigCentres centres per
+// wave and cluster are walked by the whole wave instead (with the same
+// coverage tests from the same values).  A centre that single
 // precision places clearly inside all three edges is written at once (64-bit
 // atomicMin of the packed depth/id key); one that lies within a rounding
 // margin of an edge, or any centre of a triangle seen nearly edge-on, is
 // queued and decided afterwards by covered_exact.  Must be called by the whole
 // block; ends after a barrier with the buffer complete.
-template <bool COUNT = false>
+template <bool COUNT, bool BIG>
 __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, const Cam& cam, uint32_t id_base,
                                             const Rect& band, const Rect& buf, unsigned long long* zbuf,
                                             const RasterLds& lds, unsigned* cnt = nullptr) {
@@ -406,6 +492,7 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
       q = __shfl(q, 0, 64);
       if (q >= total) break;
       const ClusterDev cl = m.clusters[lds.list[q]];
+      bool staged = false;
       if (lane < cl.np) {
         const size_t pi = (size_t)cl.pfirst + lane;
         const uint2 ids = m.pids[pi];
@@ -459,22 +546,6 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
           const float s0 = tau * (fabsf(f0x) + fabsf(f0y)), s1 = tau * (fabsf(f1x) + fabsf(f1y));
           // a centre of triangle k: queued for the exact test when within the
           // margin of an edge (or the triangle is nearly edge-on), else written
-          auto emit = [&](int pix, bool eon, float x0, float x1, float x2, float m0, float m1, float m2, float i0,
-                          float i1, float i2, float ia, uint32_t tid) {
-            if (eon || x0 >= -m0 || x1 >= -m1 || x2 >= -m2) {
-              const int slot = atomicAdd(&lds.counts[0], 1);
-              if (slot < lds.qcap) {
-                lds.queue[slot] = make_uint2((uint32_t)pix, tid);
-                return;
-              }
-              if (eon || x0 > 0.0f || x1 > 0.0f || x2 > 0.0f) return;  // queue full: single precision
-            }
-            // 1/z is affine in screen space: interpolate with barycentrics x_k/area
-            const float z = __builtin_amdgcn_rcpf((x0 * i0 + x1 * i1 + x2 * i2) * ia);
-            if (!(z > 0.0f)) return;
-            if (COUNT) ++c_frag;
-            atomicMin(&zbuf[pix], pack_key(z, id_base + tid));
-          };
           // edge functions (each the negative area at the opposite corner) at the
           // box's first centre; at a centre dr rows and dc columns further they
           // are w + e_x dr - e_y dc with exact small integers dr, dc: two FMAs
@@ -487,7 +558,29 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
           const float v1b = f1x * (py0 - D.y) - f1y * (px0 - D.x);
           // one flat walk over the box's centres: a wave then iterates max(rows x cols)
           // times over its lanes, not max(rows) x max(cols)
-          const int n_cent = (c1 - c0 + 1) * (r1 - r0 + 1);
+          int n_cent = (c1 - c0 + 1) * (r1 - r0 + 1);
+          // a large box (a table top, a wall) would keep this lane walking long
+          // after the others are done: the first kBigSlots of them are staged in
+          // the wave's LDS slots and walked by the whole wave below
+          const unsigned long long bigm = BIG ? __ballot(n_cent > kBigCentres) : 0ull;
+          if (BIG && bigm != 0ull && n_cent > kBigCentres && __popcll(bigm & ((1ull << lane) - 1ull)) < kBigSlots) {
+            const int rank = __popcll(bigm & ((1ull << lane) - 1ull));
+            float* st = raster_stage(lds) + (wave * kBigSlots + rank) * kStageWords;
+            int* si = reinterpret_cast<int*>(st);
+            const float vals[26] = {e0x, e0y, e1x, e1y, e2x, e2y, f0x, f0y, f1x, f1y, t0,  t1,  t2,
+                                    s0,  s1,  ia1, ia2, w0b, w1b, w2b, v0b, v1b, A.w, B.w, C.w, D.w};
+#pragma unroll
+            for (int k = 0; k < 26; ++k) st[k] = vals[k];
+            si[kStBox] = c0;
+            si[kStBox + 1] = c1;
+            si[kStBox + 2] = r0;
+            si[kStBox + 3] = r1;
+            si[kStIds] = (int)ids.x;
+            si[kStIds + 1] = (int)ids.y;
+            si[kStFlags] = (act1 ? 1 : 0) | (act2 ? 2 : 0) | (eon1 ? 4 : 0) | (eon2 ? 8 : 0);
+            staged = true;
+            n_cent = 0;
+          }
           int rn = r0, cn = c0;
           for (int k = 0; k < n_cent; ++k) {
             const int r = rn, col = cn;
@@ -505,9 +598,23 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
             const bool out2 = !act2 || v0 > s0 || v1 > s1 || -w1 > t1;
             if (out1 && out2) continue;  // clearly outside both
             const int pix = (r - buf.y0) * pitch + (col - buf.x0);
-            if (!out1) emit(pix, eon1, w0, w1, w2, t0, t1, t2, A.w, B.w, C.w, ia1, ids.x);
-            if (!out2) emit(pix, eon2, v0, v1, -w1, s0, s1, t1, A.w, C.w, D.w, ia2, ids.y);
+            if (!out1)
+              emit_centre<COUNT>(pix, eon1, w0, w1, w2, t0, t1, t2, A.w, B.w, C.w, ia1, ids.x, id_base, zbuf, lds,
+                                 c_frag);
+            if (!out2)
+              emit_centre<COUNT>(pix, eon2, v0, v1, -w1, s0, s1, t1, A.w, C.w, D.w, ia2, ids.y, id_base, zbuf, lds,
+                                 c_frag);
           }
+        }
+      }
+      if constexpr (BIG) {
+        __builtin_amdgcn_wave_barrier();
+        const unsigned long long sm = __ballot(staged);
+        if (sm != 0ull) {
+          const int n_staged = __popcll(sm);
+          for (int j = 0; j < n_staged; ++j)
+            walk_staged<COUNT>(raster_stage(lds) + (wave * kBigSlots + j) * kStageWords, lane, buf, pitch, id_base,
+                               zbuf, lds, c_frag);
         }
       }
     }
@@ -533,6 +640,31 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
     atomicAdd(&cnt[kCntExact], c_exact);
   }
   __syncthreads();
+}
+
+// Which rasteriser a kernel holds: the plain one, the one with the wave walk
+// of large boxes, or both behind a test of the mesh's has_big (the large-box
+// walk costs meshes without large primitives a few per cent).
+enum RasterMode { kRasterSmall = 0, kRasterBig = 1, kRasterAny = 2 };
+
+template <bool COUNT, int MODE>
+__device__ __forceinline__ void raster_mesh_mode(const MeshDev& m, const Pose& P, const Cam& cam, uint32_t id_base,
+                                                 const Rect& band, const Rect& buf, unsigned long long* zbuf,
+                                                 const RasterLds& lds, unsigned* cnt = nullptr) {
+  if (MODE == kRasterBig || (MODE == kRasterAny && m.has_big)) {
+    RasterLds shorter = lds;
+    shorter.qcap = kQueueCap - kStageQueueEntries;
+    raster_mesh<COUNT, true>(m, P, cam, id_base, band, buf, zbuf, shorter, cnt);
+  } else {
+    raster_mesh<COUNT, false>(m, P, cam, id_base, band, buf, zbuf, lds, cnt);
+  }
+}
+
+template <bool COUNT = false>
+__device__ __forceinline__ void raster_mesh_any(const MeshDev& m, const Pose& P, const Cam& cam, uint32_t id_base,
+                                                const Rect& band, const Rect& buf, unsigned long long* zbuf,
+                                                const RasterLds& lds, unsigned* cnt = nullptr) {
+  raster_mesh_mode<COUNT, kRasterAny>(m, P, cam, id_base, band, buf, zbuf, lds, cnt);
 }
 
 // One Adam ascent step on logL for pose P (row-major 4x4), on the tangent

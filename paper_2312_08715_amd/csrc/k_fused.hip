@@ -187,7 +187,7 @@ __device__ __forceinline__ int first_of(unsigned t, int base) {
 // columns possibly beyond the image, which stay empty) initialised from the
 // background keys, the mesh rasterised into its image part, then the depth of
 // every slot the mesh drew recomputed on its triangle's plane.  Whole block.
-template <bool COUNT>
+template <bool COUNT, int RM = kRasterAny>
 __device__ __forceinline__ void raster_band(const SceneDev& s, const Pose& P, const Rect& L,
                                             unsigned long long* zbuf, unsigned char* smem, float* red, unsigned* cnt) {
   const Cam& cam = s.cam;
@@ -199,7 +199,7 @@ __device__ __forceinline__ void raster_band(const SceneDev& s, const Pose& P, co
     zbuf[k] = (in && s.bg) ? s.bg[(size_t)r * W + c] : kEmptyKey;
   }
   __syncthreads();
-  raster_mesh<COUNT>(s.mesh, P, cam, 0u, grow_clip(L, 0, W, H), L, zbuf, carve_raster_lds(smem), cnt);
+  raster_mesh_mode<COUNT, RM>(s.mesh, P, cam, 0u, grow_clip(L, 0, W, H), L, zbuf, carve_raster_lds(smem), cnt);
   // the slots this mesh drew (listed in the free scratch, which holds more
   // entries than the buffer has slots), then their depths on the planes
   unsigned short* rlist = reinterpret_cast<unsigned short*>(smem);
@@ -216,7 +216,7 @@ __device__ __forceinline__ void raster_band(const SceneDev& s, const Pose& P, co
 // One hypothesis: pose16 (16 floats), writes *logL_out and, when GRAD,
 // grad_out[0..8).  Must be called by the whole block; `smem` is at least
 // fused_lds_bytes(s).
-template <bool GRAD, bool COUNT = false>
+template <bool GRAD, bool COUNT = false, int RM = kRasterAny>
 __device__ __forceinline__ void render_score_one(const SceneDev& s, const float* __restrict__ pose16,
                                                  float* __restrict__ logL_out, float* __restrict__ grad_out,
                                                  unsigned char* smem, unsigned* cnt = nullptr, int row_lo = -1,
@@ -263,7 +263,7 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
       Rect L = lds;
       L.y0 = a - 2 * h;
       L.y1 = b + 2 * h;
-      raster_band<COUNT>(s, P, L, zbuf, smem, red, cnt);
+      raster_band<COUNT, RM>(s, P, L, zbuf, smem, red, cnt);
       // likelihood over observed rows [wa, wb); rows [a, b) are this band's own
       const int wa = GRAD ? max(a - h, region.y0) : a;
       const int wb = GRAD ? min(b + h, region.y1) : b;
@@ -405,13 +405,16 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
   }
 }
 
-template <bool GRAD>
+// RM: the rasteriser compiled in (the launcher picks it from the mesh, so
+// that meshes without large primitives run the plain one alone).
+template <bool GRAD, int RM>
 __global__ __launch_bounds__(kBlock, 4) void k_render_score(SceneDev s, const float* __restrict__ poses, int N,
                                                          float* __restrict__ logL, float* __restrict__ grad) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = blockIdx.x;
   if (n >= N) return;
-  render_score_one<GRAD>(s, poses + 16 * (size_t)n, logL + n, GRAD ? grad + 8 * (size_t)n : nullptr, smem);
+  render_score_one<GRAD, false, RM>(s, poses + 16 * (size_t)n, logL + n, GRAD ? grad + 8 * (size_t)n : nullptr,
+                                    smem);
 }
 
 // A group of scenes in one persistent launch: every block pulls the next
@@ -419,7 +422,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_render_score(SceneDev s, const fl
 // Items are numbered scene by scene in the order the host chose (costliest
 // hypotheses first), so the expensive scenes start early and the cheap ones
 // fill the tail.  Every block exits once the counter passes the group's total.
-template <bool GRAD>
+template <bool GRAD, int RM>
 __global__ __launch_bounds__(kBlock, 4) void k_batch(const BatchGroupDev G, unsigned long long* __restrict__ counter) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ long long work;
@@ -436,7 +439,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_batch(const BatchGroupDev G, unsi
     int k = 0;
     for (int j = 1; j < G.S; ++j) k = G.first[j] <= w ? j : k;
     const long long n = w - G.first[k];
-    render_score_one<GRAD>(G.s[k], G.poses[k] + 16 * n, G.logL[k] + n, GRAD ? G.grad[k] + 8 * n : nullptr, smem);
+    render_score_one<GRAD, false, RM>(G.s[k], G.poses[k] + 16 * n, G.logL[k] + n, GRAD ? G.grad[k] + 8 * n : nullptr,
+                                      smem);
   }
 }
 
@@ -445,17 +449,25 @@ __global__ void k_reset_counter(unsigned long long* c) {
 }
 
 hipError_t batch_occupancy(bool grad, size_t lds, int* blocks_per_cu) {
-  if (grad) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch<true>, kBlock, lds);
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch<false>, kBlock, lds);
+  // every raster variant has the same launch bounds and LDS
+  if (grad)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch<true, kRasterSmall>, kBlock, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch<false, kRasterSmall>, kBlock, lds);
 }
 
 hipError_t launch_batch(const BatchGroupDev& g, unsigned long long* counter, bool grad, size_t lds, int blocks,
                         hipStream_t st) {
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
-  if (grad)
-    hipLaunchKernelGGL(k_batch<true>, dim3(blocks), dim3(kBlock), lds, st, g, counter);
+  bool big = false;
+  for (int k = 0; k < g.S; ++k) big = big || g.s[k].mesh.has_big != 0;
+  if (grad && big)
+    hipLaunchKernelGGL((k_batch<true, kRasterAny>), dim3(blocks), dim3(kBlock), lds, st, g, counter);
+  else if (grad)
+    hipLaunchKernelGGL((k_batch<true, kRasterSmall>), dim3(blocks), dim3(kBlock), lds, st, g, counter);
+  else if (big)
+    hipLaunchKernelGGL((k_batch<false, kRasterAny>), dim3(blocks), dim3(kBlock), lds, st, g, counter);
   else
-    hipLaunchKernelGGL(k_batch<false>, dim3(blocks), dim3(kBlock), lds, st, g, counter);
+    hipLaunchKernelGGL((k_batch<false, kRasterSmall>), dim3(blocks), dim3(kBlock), lds, st, g, counter);
   return hipGetLastError();
 }
 
@@ -495,11 +507,13 @@ hipError_t launch_refine_pose(const SceneDev& s, float* poses, int N, int n_refi
 // writes its terms to partial[9 b .. 9 b + 9) (logL, d(dt, dw), d sigma,
 // d p_out, without the background outside the region, which the pose
 // gradient does not involve).
+template <int RM>
 __global__ __launch_bounds__(kBlock, 4) void k_refine_bands(SceneDev s, const float* __restrict__ pose, int R,
                                                             float* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = blockIdx.x;
-  render_score_one<true>(s, pose, partial + 9 * b, partial + 9 * b + 1, smem, nullptr, b * R, (b + 1) * R);
+  render_score_one<true, false, RM>(s, pose, partial + 9 * b, partial + 9 * b + 1, smem, nullptr, b * R,
+                                    (b + 1) * R);
 }
 
 // The band sums in band order (double), then the Adam update of the pose;
@@ -529,7 +543,12 @@ hipError_t launch_refine_banded(const SceneDev& s, float* pose, int n_refine, fl
                                 float b2, float eps, int R, float* partial, float* state, hipStream_t st) {
   const int nb = (s.cam.H + R - 1) / R;
   for (int it = 1; it <= n_refine; ++it) {
-    hipLaunchKernelGGL(k_refine_bands, dim3(nb), dim3(kBlock), fused_lds_bytes(s), st, s, pose, R, partial);
+    if (s.mesh.has_big)
+      hipLaunchKernelGGL(k_refine_bands<kRasterBig>, dim3(nb), dim3(kBlock), fused_lds_bytes(s), st, s, pose, R,
+                         partial);
+    else
+      hipLaunchKernelGGL(k_refine_bands<kRasterSmall>, dim3(nb), dim3(kBlock), fused_lds_bytes(s), st, s, pose, R,
+                         partial);
     hipLaunchKernelGGL(k_refine_update, dim3(1), dim3(64), 0, st, pose, partial, nb, state, it, lr_t, lr_r, b1, b2,
                        eps);
   }
@@ -802,10 +821,16 @@ hipError_t launch_render_score_count(const SceneDev& s, const float* poses, int 
 hipError_t launch_render_score(const SceneDev& s, const float* poses, int N, float* logL, float* grad,
                                hipStream_t st) {
   const size_t lds = fused_lds_bytes(s);
-  if (grad)
-    hipLaunchKernelGGL(k_render_score<true>, dim3(N), dim3(kBlock), lds, st, s, poses, N, logL, grad);
+  const bool big = s.mesh.has_big != 0;
+  if (grad && big)
+    hipLaunchKernelGGL((k_render_score<true, kRasterBig>), dim3(N), dim3(kBlock), lds, st, s, poses, N, logL, grad);
+  else if (grad)
+    hipLaunchKernelGGL((k_render_score<true, kRasterSmall>), dim3(N), dim3(kBlock), lds, st, s, poses, N, logL, grad);
+  else if (big)
+    hipLaunchKernelGGL((k_render_score<false, kRasterBig>), dim3(N), dim3(kBlock), lds, st, s, poses, N, logL, grad);
   else
-    hipLaunchKernelGGL(k_render_score<false>, dim3(N), dim3(kBlock), lds, st, s, poses, N, logL, grad);
+    hipLaunchKernelGGL((k_render_score<false, kRasterSmall>), dim3(N), dim3(kBlock), lds, st, s, poses, N, logL,
+                       grad);
   return hipGetLastError();
 }
 

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_render_batch(MeshDev m, Cam cam, con
     const int nk = band.h() * band.w();
     for (int k = threadIdx.x; k < nk; k += kBlock) zbuf[k] = kEmptyKey;
     __syncthreads();
-    raster_mesh(m, P, cam, 0u, band, band, zbuf, rl);
+    raster_mesh_any(m, P, cam, 0u, band, band, zbuf, rl);
     refine_depths(m, P, cam, 0u, band, zbuf);
     write_rows(cam, band.y0, band.y1, band, zbuf, 0u, xn, tn);
     __syncthreads();

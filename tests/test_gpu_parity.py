@@ -719,6 +719,75 @@ def test_tracker_graph_replays_match_eager_frames_and_follow_the_objects(b3d):
     np.testing.assert_array_equal(tr.poses().cpu().numpy(), est)
 
 
+def _oracle_stage_best(verts, tris, cam, obs, s, spec, stage, center, tol_rel):
+    """Poses of a stage's hypotheses around `center` and the indices whose
+    oracle log-likelihood is within tol_rel * L1 of the best, best first."""
+    P = oracle.enumerate_grid(spec, seed=0, stage=stage, center=center)
+    d, _ = oracle.render([(verts, tris, P)], cam)
+    L, l1 = oracle.score(obs, oracle.unproject(d, cam), s.sigma, s.p_out, s.outlier_volume, s.window)
+    order = np.argsort(-L, kind="stable")
+    ok = [int(j) for j in order if L[j] >= L[order[0]] - tol_rel * l1[j]]
+    return P, ok
+
+
+def _oracle_frame_ends(verts, tris, cam, obs, s, specs, center, tol_rel, stage=0, limit=3):
+    """Poses a frame of argmax-per-stage search can end on when near ties
+    (within the tolerance) may go either way, the all-best path first."""
+    P, ok = _oracle_stage_best(verts, tris, cam, obs, s, specs[stage], stage, center, tol_rel)
+    ends = []
+    for j in ok[:limit]:
+        nxt = f32(P[j]).astype(np.float64)  # the tracker keeps its poses in float32
+        ends += [nxt] if stage + 1 == len(specs) else _oracle_frame_ends(verts, tris, cam, obs, s, specs, nxt,
+                                                                         tol_rel, stage + 1, limit)
+    return ends
+
+
+@pytest.mark.parametrize("res", [25, 50])
+def test_camera_pan_tracker_takes_the_oracles_best_hypothesis_every_stage(b3d, res):
+    # a camera circling an object on a table, tracked with four stages of
+    # hypotheses per frame and no gradient steps: the oracle runs the same
+    # argmax-per-stage search from the known first pose, and every GPU frame
+    # must land on the pose the oracle's search ends on; where a stage holds a
+    # near tie (within the score tolerance) either candidate is correct, so the
+    # oracle follows each tied branch and the GPU's pose must equal the end of
+    # one of them, whose (oracle-computed) pose the oracle then continues from
+    from workloads import ScoreParams, camera_pan_schedule, camera_pan_sequence
+
+    F = 10
+    (v, t), truth, cam, noise = camera_pan_sequence(res=res, n_frames=120)  # its first F frames
+    v = f32(v)
+    say(f"camera pan tracker: {res}x{res}, {t.shape[0]} triangles, {F} frames")
+    s = ScoreParams(sigma=0.003, p_out=0.01, outlier_volume=1.0, window=5)
+    frames = []
+    for f in range(F):
+        d = oracle.render([(v, t, truth[f])], cam)[0][0]
+        d = np.where(d > 0, d + noise[f]["gauss"], 0.0)
+        d = np.where(noise[f]["outlier_mask"], noise[f]["outlier_depth"], d)
+        frames.append(f32(oracle.unproject(d, cam)))
+    specs = camera_pan_schedule()
+    for g in specs:
+        g.rotations = f32(g.rotations).astype(np.float64)  # both sides use the float32 rotations the GPU reads
+    grids = [b3d.grid_of(g) for g in specs]  # (grid, rotations tensor): the tensors outlive the tracker
+    tr = b3d.Tracker([b3d.Mesh(v, t)], b3d.intrinsics_of(cam), b3d.score_params(s.sigma, s.p_out, s.outlier_volume,
+                                                                               s.window),
+                     [g for g, _ in grids], f32(truth[:1]), n_refine=0)
+    cur = f32(truth[0]).astype(np.float64)
+    off_best = 0
+    for f in range(1, F):
+        tr.frame(dev(frames[f]))
+        g = tr.poses().cpu().numpy()[0].astype(np.float64)
+        ends = _oracle_frame_ends(v, t, cam, frames[f].astype(np.float64), s, specs, cur, LOGL_RTOL)
+        hit = [e for e in ends if np.allclose(e, g, atol=1e-5)]
+        assert hit, f"frame {f}: the GPU's pose is none of the ends of the oracle's search"
+        off_best += int(hit[0] is not ends[0])
+        cur = hit[0]
+    say(f"  {F - 1} frames; {off_best} took a tied candidate other than the oracle's first")
+    err_t = np.linalg.norm(cur[:3, 3] - truth[F - 1, :3, 3])
+    err_r = np.degrees(np.arccos(np.clip((np.trace(cur[:3, :3] @ truth[F - 1, :3, :3].T) - 1) / 2, -1, 1)))
+    say(f"  last frame: scene origin off by {err_t * 100:.3f} cm, orientation by {err_r:.3f} deg")
+    assert err_t < 0.005 and err_r < 3.0
+
+
 def test_hot_calls_replay_from_a_captured_graph(b3d):
     # enumerate -> fused render + score + adjoint -> sample, captured once into a
     # graph and replayed several times with eager work in between: every replay

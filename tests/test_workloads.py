@@ -44,3 +44,27 @@ def test_configs_are_deterministic_and_shaped_as_stated():
     occ = oracle.render([c1.occluder], c1.camera)[0][0] > 0
     assert abs((obj & occ).sum() / obj.sum() - 0.20) <= 0.005
     assert c1.occluder[2][2, 3] - 0.03 == np.float64(0.6) or abs(c1.occluder[2][2, 3] - 0.63) < 1e-12
+
+
+def test_camera_pan_keeps_the_object_centred_and_moves_a_little_per_frame():
+    from workloads import camera_pan_sequence
+
+    (v, t), P, cam, noise = camera_pan_sequence(res=50, n_frames=120)
+    assert t.shape == ((10 * 6 * 17 + 27) * 12 + 2, 3) and P.shape == (120, 4, 4) and (cam.H, cam.W) == (50, 50)
+    for T in P:
+        np.testing.assert_allclose(T[:3, :3] @ T[:3, :3].T, np.eye(3), atol=1e-12)
+        assert abs(T[0, 3]) < 1e-12 and abs(T[1, 3]) < 1e-12 and 0.54 <= T[2, 3] <= 0.66  # origin on the axis
+        up = T[:3, :3] @ np.array([0.0, 0.0, 1.0])
+        assert up[1] < -0.4  # scene +z points up in the image (image y runs down)
+    step_t = np.linalg.norm(np.diff(P[:, :3, 3], axis=0), axis=1)
+    step_r = [np.degrees(np.arccos(np.clip((np.trace(P[i + 1, :3, :3] @ P[i, :3, :3].T) - 1) / 2, -1, 1)))
+              for i in range(119)]
+    assert step_t.max() < 0.006 and max(step_r) < 1.5
+    # same object and path at every resolution; noise drawn per resolution
+    (v2, _), P2, cam2, noise2 = camera_pan_sequence(res=25, n_frames=120)
+    np.testing.assert_array_equal(v, v2)
+    np.testing.assert_array_equal(P, P2)
+    assert noise2[0]["gauss"].shape == (25, 25) and cam2.fx * 2 == cam.fx
+    # the object rests on the table: its lowest voxel face is at the table's height
+    obj = v[:-4]
+    assert abs(obj[:, 2].min() - v[-4:, 2].max()) < 1e-12

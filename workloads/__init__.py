@@ -16,12 +16,15 @@ from .scenes import (  # noqa: F401
     Workload,
     assemble_observed_depth,
     box_mesh,
+    camera_pan_schedule,
+    camera_pan_sequence,
     make_config,
     observation_noise,
     place_occluder,
     pose_matrix,
     random_poses,
     random_scene_batch,
+    rotation_grid,
     shoemake_rotations,
     smooth_trajectory,
     tracking_sequence,

@@ -175,6 +175,26 @@ def shoemake_rotations(n: int, rng: np.random.Generator) -> np.ndarray:
     return R
 
 
+def rotation_grid(n: int, max_angle: float) -> np.ndarray:
+    """Small rotations on a lattice of rotation vectors: every (i, j, k) with
+    each component one of linspace(-max_angle, max_angle, n) radians, turned
+    into a matrix by Rodrigues' formula.  Returns [n^3, 3, 3] float64 in
+    lattice order (k fastest); for odd n the middle entry is the identity."""
+    ax = np.linspace(-max_angle, max_angle, n) if n > 1 else np.zeros(1)
+    out = []
+    for a in ax:
+        for b in ax:
+            for c in ax:
+                w = np.array([a, b, c])
+                th = np.linalg.norm(w)
+                K = np.zeros((3, 3))
+                if th > 0:
+                    k = w / th
+                    K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+                out.append(np.eye(3) + np.sin(th) * K + (1 - np.cos(th)) * (K @ K))
+    return np.stack(out)
+
+
 def observation_noise(H: int, W: int, rng: np.random.Generator, depth_noise: float, outlier_frac: float,
                       depth_range: Tuple[float, float] = (0.3, 1.5)) -> dict:
     """Per-pixel draws for the synthetic observation process.
@@ -421,3 +441,79 @@ def table_scene(seed: int = 1002, voxels=(800, 1500, 3000, 6000), W: int = 320, 
     table = (tv, tt, Tcw.copy())
     noise = observation_noise(H, W, rng, 0.002, 0.03)
     return meshes, poses, table, cam, noise, Tcw
+
+
+def bottle_voxels(body=(10, 6, 17), cap=(3, 3, 3), cap_shift=(2, 0)) -> np.ndarray:
+    """Centres of a solid bottle of 1 cm voxels: a body box of body[0] x
+    body[1] x body[2] cells standing on z = 0 with its footprint centred on
+    the origin, and a cap box on top shifted by cap_shift cells in x and y.
+    The shape has no rotational symmetry about the vertical other than a
+    half turn of the body alone, which the shifted cap breaks."""
+    def box(n, lo):
+        ax = [np.arange(lo[k], lo[k] + n[k]) for k in range(3)]
+        return np.stack(np.meshgrid(*ax, indexing="ij"), -1).reshape(-1, 3)
+
+    b = box(body, (-(body[0] // 2), -(body[1] // 2), 0))
+    c = box(cap, (cap_shift[0] - cap[0] // 2, cap_shift[1] - cap[1] // 2, body[2]))
+    return (np.concatenate([b, c]).astype(np.float64) + 0.5) * VOXEL
+
+
+def camera_pan_sequence(seed: int = 1005, n_frames: int = 120, res: int = 100, distance: float = 0.6, sweep_deg: float = 90.0, fov_deg: float = 45.0,
+                        outlier_frac: float = 0.04):
+    """A camera circling one object that rests on a table (the setting of the
+    paper's real-time tracking experiment, Sec. IV and Table 1), at a square
+    resolution of res x res.
+
+    The object is a bottle of 1 cm voxels (``bottle_voxels``: a 10 x 6 x 17
+    cm body and an off-centre cap, about the size of the paper's mustard
+    bottle) at a seeded yaw.  The scene mesh is its voxels plus a 0.5 m x
+    0.5 m table quad,
+    expressed in a frame whose origin is the point the camera looks at (the
+    object's centre), so that camera motion appears as a pose of the whole
+    scene in the camera frame.  The camera's azimuth sweeps ``sweep_deg``
+    degrees over the sequence, its elevation swings between 25 and 40
+    degrees, and its distance varies by +-5 cm.  Returns (verts, tris),
+    the true scene poses [n_frames, 4, 4] (camera-from-scene), the camera
+    and per-frame noise draws.  The same seed gives the same object and
+    path at every resolution; only the noise draws depend on ``res``.
+    """
+    rng = np.random.default_rng(seed)
+    yaw = rng.uniform(0, 2 * np.pi)
+    Rz = np.array([[np.cos(yaw), -np.sin(yaw), 0.0], [np.sin(yaw), np.cos(yaw), 0.0], [0.0, 0.0, 1.0]])
+    ov, ot = voxel_mesh(bottle_voxels() @ Rz.T)
+    centre = np.array([0.0, 0.0, 0.5 * ov[:, 2].max()])  # the bottle's mid-height above the table
+    tv = np.array([[-0.25, -0.25, 0.0], [0.25, -0.25, 0.0], [0.25, 0.25, 0.0], [-0.25, 0.25, 0.0]])
+    tt = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)
+    verts = np.concatenate([ov, tv]) - centre
+    tris = np.concatenate([ot, tt + ov.shape[0]]).astype(np.int32)
+    az0 = rng.uniform(0, 2 * np.pi)
+    ph_el, ph_d = rng.uniform(0, 2 * np.pi, 2)
+    s = np.linspace(0.0, 1.0, n_frames)
+    az = az0 + np.deg2rad(sweep_deg) * s
+    el = np.deg2rad(32.5 + 7.5 * np.sin(2 * np.pi * s + ph_el))
+    d = distance + 0.05 * np.sin(2 * np.pi * 1.5 * s + ph_d)
+    poses = np.empty((n_frames, 4, 4))
+    for i in range(n_frames):
+        eye = d[i] * np.array([np.cos(el[i]) * np.cos(az[i]), np.cos(el[i]) * np.sin(az[i]), np.sin(el[i])])
+        poses[i] = look_at(eye)
+    f = 0.5 * res / np.tan(np.deg2rad(fov_deg) / 2.0)
+    cam = Camera(f, f, res / 2.0, res / 2.0, res, res)
+    nrng = np.random.default_rng([seed, res])
+    noise = [observation_noise(res, res, nrng, 0.002, outlier_frac) for _ in range(n_frames)]
+    return (verts, tris), poses, cam, noise
+
+
+def camera_pan_schedule() -> List[GridSpec]:
+    """Per-frame hypothesis stages for tracking ``camera_pan_sequence``, each
+    around the best pose of the stage before (1,708 hypotheses a frame):
+    rotations alone (5^3 rotation vectors within +-1.2 deg per axis), then
+    translations alone (5^3 within +-6 mm), then two joint stages of 3^3
+    translations x 3^3 rotations (+-1.5 mm x +-0.4 deg, then +-0.5 mm x
+    +-0.15 deg).  Rotations act in the camera frame about the scene origin,
+    which is where the camera looks, so the camera's orbit is a rotation the
+    first stage can follow."""
+    def spec(h, nt, a, nr):
+        return GridSpec(np.eye(4), (h, h, h), (nt, nt, nt), rotations=rotation_grid(nr, np.deg2rad(a)))
+
+    return [spec(0.0, 1, 1.2, 5), spec(0.006, 5, 0.0, 1), spec(0.0015, 3, 0.4, 3), spec(0.0005, 3, 0.15, 3)]
+
