@@ -574,8 +574,10 @@ def main():
 
     # the chip's peaks, re-measured by microbenchmarks: an FMA loop (lane-ops/s),
     # an HBM triad and an LDS read loop (bytes/s)
-    valu_measured = b3d.probe_fma() / 1e12
-    peaks = {"valu_TOPs": valu_measured, "hbm_GBps": b3d.probe_hbm() / 1e9, "lds_TBps": b3d.probe_lds() / 1e12}
+    from paper_2312_08715_amd import probe
+
+    valu_measured = probe.probe_fma() / 1e12
+    peaks = {"valu_TOPs": valu_measured, "hbm_GBps": probe.probe_hbm() / 1e9, "lds_TBps": probe.probe_lds() / 1e12}
     work = counted_work(b3d, scene, P)
     ops = lane_ops(work, adjoint=True)
     achieved = ops / t_kernel / 1e12

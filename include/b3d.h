@@ -198,6 +198,13 @@ b3d_status b3d_scene_set_observed(b3d_scene* scene, const float* observed, void*
 b3d_status b3d_render_score(const b3d_scene* scene, const float* poses, int32_t N, float* logL_out, float* grad_out,
                             void* stream);
 
+/* Nodes of the midpoint rule for Alg. 1's uniform noise priors: the centres
+ * of A equal cells of (0, sigma_max] (host float[A], sigma_max > 0) and of B
+ * equal cells of (0, 1) (host float[B]).  With equal weights 1/(A B) they are
+ * the grid whose marginal b3d_render_score_marginal computes (the prior
+ * density 1/sigma_max times the cell volume sigma_max/(A B)).  Host only. */
+b3d_status b3d_noise_midpoints(double sigma_max, int32_t A, int32_t B, float* sigma_out, float* p_out_out);
+
 /* Hierarchical likelihood (Alg. 1's priors p_out ~ U(0, 1) and
  * sigma ~ U(0, sigma_max) on the noise parameters of eq. (1), and the
  * marginal over them used to compare hypotheses under unknown noise, Sec.
@@ -330,39 +337,33 @@ typedef struct b3d_schedule {
 /* Device workspace (bytes) that b3d_c2f_step needs for K particles. */
 b3d_status b3d_c2f_workspace_size(const b3d_schedule* s, int32_t K, size_t* bytes);
 
+/* Number of floats b3d_c2f_step writes to weights_out: N_0 + K (N_1 + ...
+ * + N_{n_stages-1}), N_t the size of stages[t]'s grid. */
+b3d_status b3d_c2f_weights_count(const b3d_schedule* s, int32_t K, int64_t* count);
+
 /* One coarse-to-fine proposal for K particles (Sec. III-B and Fig. 1):
  * stage 0 scores stages[0] around `center` (host float[16]) once and draws
  * K cells; at each later stage t every particle k scores stages[t] around
  * its current pose and draws one cell (sampler counter (n, k, t, 0)), which
- * becomes its pose.  poses_out: device float[K][16] (the chosen cells'
- * representative poses); logq_out: device float[K], the sum over stages of
- * the log weight of each choice (for a partition schedule the proposal
- * density of a uniform draw in the final cell is exp(logq)/cell volume);
- * idx_out: device int32[n_stages][K] or NULL.  workspace: device memory of
- * at least b3d_c2f_workspace_size bytes.  Stream-ordered. */
+ * becomes its pose.  Each cell's probability is its normalised score,
+ * softmax(logL) over the cells one draw chooses among (the scoring
+ * strategy with one point per cell).
+ * weights_out: device float[b3d_c2f_weights_count] or NULL: stage 0's N_0
+ * cell probabilities, then for each later stage t the K particles' N_t
+ * probabilities, particle-major ([K][N_t]), stages in order.
+ * poses_out: device float[K][16] (the chosen cells' representative poses);
+ * logq_out: device float[K], the sum over stages of the log probability of
+ * each choice (for a partition schedule the proposal density of a uniform
+ * draw in the final cell is exp(logq)/cell volume); idx_out: device
+ * int32[n_stages][K] or NULL.  workspace: device memory of at least
+ * b3d_c2f_workspace_size bytes, owned by the caller, contents undefined on
+ * return.  Argument errors (NULL pointers, bad schedule or K, short
+ * workspace, no observed image) return before any launch.  Stream-ordered. */
 b3d_status b3d_c2f_step(const b3d_scene* scene, const float* center, const b3d_schedule* s, int32_t K, uint64_t seed,
-                        void* workspace, size_t ws_bytes, float* poses_out, float* logq_out, int32_t* idx_out,
-                        void* stream);
+                        void* workspace, size_t ws_bytes, float* weights_out, float* poses_out, float* logq_out,
+                        int32_t* idx_out, void* stream);
 
 /* ---- gradient refinement and tracking ---------------------------------- */
-
-/* Peak probe (not part of the method): blocks x 256 lanes each run
- * iters x 128 dependent-in-8-chains FP32 FMAs (2 flops each); out receives
- * one float per lane (device float[blocks * 256]).  Time it on `stream` to
- * measure the chip's FP32 vector FMA rate.  Stream-ordered. */
-b3d_status b3d_probe_fma(float* out, int32_t blocks, int32_t iters, void* stream);
-
-/* Peak probe (not part of the method): one pass of c = a + 1.5 b over n
- * floats (n a positive multiple of 4; device buffers, 16-byte aligned): 12 n
- * bytes of HBM traffic when the buffers exceed the caches.  Time it on
- * `stream`.  Stream-ordered. */
-b3d_status b3d_probe_hbm(const float* a, const float* b, float* c, int64_t n, void* stream);
-
-/* Peak probe (not part of the method): blocks x 256 lanes each read
- * iters x 32 16-byte LDS words (conflict-free); out: device float[blocks *
- * 256].  Time it on `stream` to measure LDS read bandwidth.
- * Stream-ordered. */
-b3d_status b3d_probe_lds(float* out, int32_t blocks, int32_t iters, void* stream);
 
 /* Retraction onto the pose manifold, the update convention of the adjoint
  * (Sec. III-B's pose grid composed as t = t_c + dt, R = dR R_c, with dR the
@@ -463,6 +464,16 @@ typedef struct b3d_table {
   float width, height;
 } b3d_table;
 
+/* A type library on a table, for placing objects by contact: each type's six
+ * resting faces (the faces of the axis-aligned bounding box of its vertices
+ * in its own frame) and their placement prior, uploaded to the device once.
+ * types: host array of n_types mesh handles (1..B3D_MAX_TYPES; the meshes
+ * only need to live during the call).  Allocates device memory. */
+typedef struct b3d_contact b3d_contact;
+b3d_status b3d_contact_create(const b3d_mesh* const* types, int32_t n_types, const b3d_table* table,
+                              b3d_contact** out);
+b3d_status b3d_contact_destroy(b3d_contact* contact);
+
 /* Object poses from contact placements (Alg. 1's type, contact face and
  * relative pose; Sec. III-A (i)).  Object k of type place[k][0] rests on face
  * c = place[k][1] of the axis-aligned bounding box of its vertices in its
@@ -470,12 +481,12 @@ typedef struct b3d_table {
  * normal to -z and d_c puts the face on z = 0 with the face's centre on the
  * origin; then
  *   pose = table.pose * [Rz(dth) R_c | Rz(dth) d_c + (dx, dy, 0)]
- * with (dx, dy, dth) = dphi[k].  types: host array of n_types mesh handles;
- * place: device int32[N][2]; dphi: device float[N][3]; poses_out: device
- * float[N][16].  The kernel clamps a type or face outside its range to the
- * nearest valid one (no error is reported).  Stream-ordered. */
-b3d_status b3d_contact_poses(const b3d_mesh* const* types, int32_t n_types, const b3d_table* table,
-                             const int32_t* place, const float* dphi, int32_t N, float* poses_out, void* stream);
+ * with (dx, dy, dth) = dphi[k].  place: device int32[N][2]; dphi: device
+ * float[N][3]; poses_out: device float[N][16].  The kernel clamps a type or
+ * face outside its range to the nearest valid one (no error is reported).
+ * Allocates nothing and copies nothing from the host.  Stream-ordered. */
+b3d_status b3d_contact_poses(const b3d_contact* contact, const int32_t* place, const float* dphi, int32_t N,
+                             float* poses_out, void* stream);
 
 #define B3D_MAX_SMC_OBJECTS 8
 #define B3D_MAX_TYPES 16

@@ -19,7 +19,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libb3d.so")
+LIB_DIR = os.path.join(_HERE, "_lib")
+LIB_PATH = os.path.join(LIB_DIR, "libb3d.so")
 
 B3D_MAX_STAGES = 8
 
@@ -107,15 +108,13 @@ _SIGNATURES = {
     "b3d_scene_autotune": ([_P, _P, _I32, _I32, ctypes.POINTER(_I32), _P], ctypes.c_int),
     "b3d_scene_set_tile": ([_P, _I32], ctypes.c_int),
     "b3d_scene_set_noise_grid": ([_P, _P, _I32, _P, _I32, _P, _P], ctypes.c_int),
+    "b3d_noise_midpoints": ([ctypes.c_double, _I32, _I32, _P, _P], ctypes.c_int),
     "b3d_render_score_marginal": ([_P, _P, _I32, _P, _P, _P], ctypes.c_int),
     "b3d_scene_tile_limits": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)], ctypes.c_int),
     "b3d_render_score_work": ([_P, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "b3d_batch_create": ([ctypes.POINTER(BatchItem), _I32, ctypes.POINTER(_P)], ctypes.c_int),
     "b3d_batch_run": ([_P, _P], ctypes.c_int),
     "b3d_batch_destroy": ([_P], ctypes.c_int),
-    "b3d_probe_fma": ([_P, _I32, _I32, _P], ctypes.c_int),
-    "b3d_probe_hbm": ([_P, _P, _P, ctypes.c_int64, _P], ctypes.c_int),
-    "b3d_probe_lds": ([_P, _I32, _I32, _P], ctypes.c_int),
     "b3d_pose_retract": ([_P, _I32, _P, _I32, _P, _P], ctypes.c_int),
     "b3d_pose_retract_backward": ([_P, _P, _P, _I32, _P, _P, _P], ctypes.c_int),
     "b3d_scene_set_params": ([_P, ctypes.POINTER(ScoreParams), _P], ctypes.c_int),
@@ -133,9 +132,12 @@ _SIGNATURES = {
     "b3d_enumerate": ([ctypes.POINTER(Grid), _U64, _I32, _P, _P], ctypes.c_int),
     "b3d_sample": ([_P, _I32, _I32, _I32, _U64, _U32, _U32, _P, _P, _P, _P], ctypes.c_int),
     "b3d_c2f_workspace_size": ([ctypes.POINTER(Schedule), _I32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
-    "b3d_c2f_step": ([_P, _P, ctypes.POINTER(Schedule), _I32, _U64, _P, ctypes.c_size_t, _P, _P, _P, _P],
+    "b3d_c2f_weights_count": ([ctypes.POINTER(Schedule), _I32, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "b3d_c2f_step": ([_P, _P, ctypes.POINTER(Schedule), _I32, _U64, _P, ctypes.c_size_t, _P, _P, _P, _P, _P],
                      ctypes.c_int),
-    "b3d_contact_poses": ([_P, _I32, ctypes.POINTER(Table), _P, _P, _I32, _P, _P], ctypes.c_int),
+    "b3d_contact_create": ([_P, _I32, ctypes.POINTER(Table), ctypes.POINTER(_P)], ctypes.c_int),
+    "b3d_contact_destroy": ([_P], ctypes.c_int),
+    "b3d_contact_poses": ([_P, _P, _P, _I32, _P, _P], ctypes.c_int),
     "b3d_smc_create": ([_P, _I32, _P, _P, _I32, ctypes.POINTER(Table), ctypes.POINTER(Intrinsics),
                         ctypes.POINTER(SMCParams), ctypes.POINTER(_P)], ctypes.c_int),
     "b3d_smc_reset": ([_P, _P, _P], ctypes.c_int),
@@ -388,51 +390,6 @@ def render_score(scene: Scene, poses: torch.Tensor, grad: bool = False):
 WORK_ITEMS = ("vertices", "triangles", "setup", "fragments", "pairs", "observed", "adjoint_pixels", "exact_tests")
 
 
-def probe_fma(blocks: int = 4096, iters: int = 256) -> float:
-    """Measured FP32 vector FMA rate in lane-FMAs/s (one FMA = 2 flops)."""
-    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
-    st = torch.cuda.current_stream()
-    _call("b3d_probe_fma", _ptr(out), blocks, iters, _stream())  # warm-up
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    _call("b3d_probe_fma", _ptr(out), blocks, iters, _stream())
-    e1.record(st)
-    e1.synchronize()
-    return blocks * 256.0 * iters * 128.0 / (e0.elapsed_time(e1) / 1e3)
-
-
-def probe_hbm(n_floats: int = 1 << 28, reps: int = 5) -> float:
-    """Measured HBM bandwidth in bytes/s: median of `reps` triads over three
-    n_floats buffers (3 GiB at the default)."""
-    a = torch.ones(n_floats, dtype=torch.float32, device="cuda")
-    b = torch.ones_like(a)
-    c = torch.empty_like(a)
-    st = torch.cuda.current_stream()
-    _call("b3d_probe_hbm", _ptr(a), _ptr(b), _ptr(c), n_floats, _stream())  # warm-up
-    ts = []
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        _call("b3d_probe_hbm", _ptr(a), _ptr(b), _ptr(c), n_floats, _stream())
-        e1.record(st)
-        e1.synchronize()
-        ts.append(e0.elapsed_time(e1) / 1e3)
-    return 12.0 * n_floats / float(np.median(ts))
-
-
-def probe_lds(blocks: int = 4096, iters: int = 256) -> float:
-    """Measured LDS read bandwidth in bytes/s over the whole chip."""
-    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
-    st = torch.cuda.current_stream()
-    _call("b3d_probe_lds", _ptr(out), blocks, iters, _stream())  # warm-up
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    _call("b3d_probe_lds", _ptr(out), blocks, iters, _stream())
-    e1.record(st)
-    e1.synchronize()
-    return blocks * 256.0 * iters * 32.0 * 16.0 / (e0.elapsed_time(e1) / 1e3)
-
-
 def pose_retract(base: torch.Tensor, xi: torch.Tensor) -> torch.Tensor:
     """Poses [N,4,4] = (exp([w]x) R_b, t_b + dt) for xi [N,6] = (dt, w); base [N,4,4] or [1,4,4]/[4,4]."""
     N = xi.shape[0]
@@ -485,10 +442,11 @@ class B3DScore(torch.autograd.Function):
 
 
 def noise_grid_midpoints(sigma_max: float, A: int, B: int):
-    """Cell centres of A equal cells of (0, sigma_max] and B of (0, 1]: with
+    """Cell centres of A equal cells of (0, sigma_max] and B of (0, 1] (b3d_noise_midpoints): with
     equal weights, the midpoint rule for the uniform priors on sigma and p_out."""
-    sig = sigma_max * (np.arange(A) + 0.5) / A
-    po = (np.arange(B) + 0.5) / B
+    sig = np.zeros(A, dtype=np.float32)
+    po = np.zeros(B, dtype=np.float32)
+    _call("b3d_noise_midpoints", float(sigma_max), int(A), int(B), sig.ctypes.data, po.ctypes.data)
     return sig, po
 
 
@@ -582,8 +540,10 @@ def make_schedule(stages: Sequence[Grid]) -> Schedule:
     return s
 
 
-def c2f_step(scene: Scene, center, schedule: Schedule, K: int, seed: int, device="cuda"):
-    """Coarse-to-fine proposal for K particles: poses [K,4,4], logq [K], idx [n_stages,K]."""
+def c2f_step(scene: Scene, center, schedule: Schedule, K: int, seed: int, device="cuda", weights: bool = False):
+    """Coarse-to-fine proposal for K particles: poses [K,4,4], logq [K], idx [n_stages,K]
+    (and, when weights, the cell probabilities of every stage: a list whose
+    entry 0 is [N_0] and entry t >= 1 is [K, N_t])."""
     nb = ctypes.c_size_t()
     _call("b3d_c2f_workspace_size", ctypes.byref(schedule), int(K), ctypes.byref(nb))
     ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=device)
@@ -591,9 +551,21 @@ def c2f_step(scene: Scene, center, schedule: Schedule, K: int, seed: int, device
     poses = torch.empty((K, 4, 4), dtype=torch.float32, device=device)
     logq = torch.empty(K, dtype=torch.float32, device=device)
     idx = torch.empty((schedule.n_stages, K), dtype=torch.int32, device=device)
+    w = None
+    if weights:
+        nw = ctypes.c_int64()
+        _call("b3d_c2f_weights_count", ctypes.byref(schedule), int(K), ctypes.byref(nw))
+        w = torch.empty(int(nw.value), dtype=torch.float32, device=device)
     _call("b3d_c2f_step", scene.handle, c.ctypes.data, ctypes.byref(schedule), int(K), int(seed), _ptr(ws),
-          int(nb.value), _ptr(poses), _ptr(logq), _ptr(idx), _stream())
-    return poses, logq, idx
+          int(nb.value), _ptr(w), _ptr(poses), _ptr(logq), _ptr(idx), _stream())
+    if not weights:
+        return poses, logq, idx
+    per, off = [], 0
+    for t in range(schedule.n_stages):
+        n = grid_size(schedule.stages[t])
+        per.append(w[off:off + n] if t == 0 else w[off:off + K * n].view(K, n))
+        off += n if t == 0 else K * n
+    return poses, logq, idx, per
 
 
 class Batch:
@@ -698,15 +670,39 @@ def table(pose, width: float, height: float) -> Table:
                  float(height))
 
 
-def contact_poses(types: Sequence[Mesh], tbl: Table, place: torch.Tensor, dphi: torch.Tensor) -> torch.Tensor:
-    """Camera-frame poses [N,4,4] of objects resting on the table: place [N,2]
-    (type, face) int32, dphi [N,3] (dx, dy, dtheta)."""
-    N = place.shape[0]
-    arr = (_P * len(types))(*[m.handle for m in types])
-    out = torch.empty((N, 4, 4), dtype=torch.float32, device=place.device)
-    _call("b3d_contact_poses", arr, len(types), ctypes.byref(tbl), _ptr(place, torch.int32), _ptr(dphi, torch.float32),
-          N, _ptr(out), _stream())
-    return out
+class Contact:
+    """A type library placed by contact on a table (b3d_contact_create): every
+    type's six resting faces uploaded once."""
+
+    def __init__(self, types: Sequence[Mesh], tbl: Table):
+        arr = (_P * len(types))(*[m.handle for m in types])
+        h = _P()
+        _call("b3d_contact_create", arr, len(types), ctypes.byref(tbl), ctypes.byref(h))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def poses(self, place: torch.Tensor, dphi: torch.Tensor) -> torch.Tensor:
+        """Camera-frame poses [N,4,4] of objects resting on the table: place [N,2]
+        (type, face) int32, dphi [N,3] (dx, dy, dtheta)."""
+        N = place.shape[0]
+        out = torch.empty((N, 4, 4), dtype=torch.float32, device=place.device)
+        _call("b3d_contact_poses", self._h, _ptr(place, torch.int32), _ptr(dphi, torch.float32), N, _ptr(out),
+              _stream())
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().b3d_contact_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def smc_params(n_particles, n_objects, counts, sigma_max, noise_A, noise_B, sigma0, p_out0, ess_threshold,

@@ -505,34 +505,6 @@ b3d_status b3d_scene_set_params(b3d_scene* S, const b3d_score_params* p, void* s
   return B3D_OK;
 }
 
-b3d_status b3d_probe_fma(float* out, int32_t blocks, int32_t iters, void* stream) {
-  if (!out) return fail(B3D_EINVAL, "probe_fma: NULL pointer");
-  if (blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > (1 << 20))
-    return fail(B3D_ESHAPE, "probe_fma: blocks and iters in 1..2^20");
-  B3D_CHECK_HIP(launch_probe_fma(out, blocks, iters, (hipStream_t)stream), "probe_fma");
-  return B3D_OK;
-}
-
-b3d_status b3d_probe_hbm(const float* a, const float* b, float* c, int64_t n, void* stream) {
-  if (!a || !b || !c) return fail(B3D_EINVAL, "probe_hbm: NULL pointer");
-  if (n < 4 || (n % 4) != 0) return fail(B3D_ESHAPE, "probe_hbm: n must be a positive multiple of 4");
-  if ((((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15) != 0)
-    return fail(B3D_EINVAL, "probe_hbm: buffers must be 16-byte aligned");
-  int dev = 0, cus = 0;
-  B3D_CHECK_HIP(hipGetDevice(&dev), "probe_hbm");
-  B3D_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "probe_hbm");
-  B3D_CHECK_HIP(launch_probe_triad(a, b, c, n / 4, cus * 8, (hipStream_t)stream), "probe_hbm");
-  return B3D_OK;
-}
-
-b3d_status b3d_probe_lds(float* out, int32_t blocks, int32_t iters, void* stream) {
-  if (!out) return fail(B3D_EINVAL, "probe_lds: NULL pointer");
-  if (blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > (1 << 20))
-    return fail(B3D_ESHAPE, "probe_lds: blocks and iters in 1..2^20");
-  B3D_CHECK_HIP(launch_probe_lds(out, blocks, iters, (hipStream_t)stream), "probe_lds");
-  return B3D_OK;
-}
-
 b3d_status b3d_pose_retract(const float* base, int32_t n_base, const float* xi, int32_t N, float* out, void* stream) {
   if (N < 0) return fail(B3D_ESHAPE, "pose_retract: N < 0");
   if (N == 0) return B3D_OK;
@@ -564,6 +536,15 @@ b3d_status b3d_refine_poses(const b3d_scene* S, float* poses, int32_t N, int32_t
     return fail(B3D_EINVAL, "refine_poses: bad Adam parameters");
   B3D_CHECK_HIP(launch_refine_pose(S->dev, poses, N, n_refine, lr_t, lr_r, beta1, beta2, eps, (hipStream_t)stream),
                 "refine_poses");
+  return B3D_OK;
+}
+
+b3d_status b3d_noise_midpoints(double sigma_max, int32_t A, int32_t B, float* sigma_out, float* p_out_out) {
+  if (!sigma_out || !p_out_out) return fail(B3D_EINVAL, "noise_midpoints: NULL output");
+  if (A < 1 || B < 1) return fail(B3D_ESHAPE, "noise_midpoints: need A, B >= 1");
+  if (!(sigma_max > 0) || !std::isfinite(sigma_max)) return fail(B3D_EINVAL, "noise_midpoints: sigma_max must be > 0");
+  for (int a = 0; a < A; ++a) sigma_out[a] = (float)(sigma_max * (a + 0.5) / A);
+  for (int b = 0; b < B; ++b) p_out_out[b] = (float)((b + 0.5) / B);
   return B3D_OK;
 }
 
@@ -895,9 +876,24 @@ b3d_status b3d_c2f_workspace_size(const b3d_schedule* s, int32_t K, size_t* byte
   return B3D_OK;
 }
 
+b3d_status b3d_c2f_weights_count(const b3d_schedule* s, int32_t K, int64_t* count) {
+  if (!count) return fail(B3D_EINVAL, "c2f_weights_count: NULL output");
+  C2FLayout L;
+  if (b3d_status st = c2f_layout(s, K, &L)) return st;
+  int64_t total = 0;
+  for (int t = 0; t < s->n_stages; ++t) {
+    GridDev d;
+    int64_t n;
+    (void)make_grid(&s->stages[t], &d, &n);
+    total += t == 0 ? n : n * K;
+  }
+  *count = total;
+  return B3D_OK;
+}
+
 b3d_status b3d_c2f_step(const b3d_scene* S, const float* center, const b3d_schedule* s, int32_t K, uint64_t seed,
-                        void* workspace, size_t ws_bytes, float* poses_out, float* logq_out, int32_t* idx_out,
-                        void* stream) {
+                        void* workspace, size_t ws_bytes, float* weights_out, float* poses_out, float* logq_out,
+                        int32_t* idx_out, void* stream) {
   if (!S || !center || !poses_out || !logq_out || !workspace) return fail(B3D_EINVAL, "c2f_step: NULL pointer");
   if (!S->observed) return fail(B3D_EINVAL, "c2f_step: call b3d_scene_set_observed first");
   if (!finite_all(center, 16)) return fail(B3D_EINVAL, "c2f_step: non-finite centre pose");
@@ -911,6 +907,7 @@ b3d_status b3d_c2f_step(const b3d_scene* S, const float* center, const b3d_sched
   float* logw = (float*)(ws + L.logw);
   hipStream_t st = (hipStream_t)stream;
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  size_t woff = 0;  // stage t's weights: segment p of stage t at woff + p n
   for (int t = 0; t < s->n_stages; ++t) {
     GridDev d;
     int64_t n;
@@ -919,8 +916,10 @@ b3d_status b3d_c2f_step(const b3d_scene* S, const float* center, const b3d_sched
     if (t == 0) std::memcpy(d.center, center, sizeof(d.center));
     B3D_CHECK_HIP(launch_enumerate(d, t == 0 ? nullptr : poses_out, P, k0, k1, (uint32_t)t, poses, st), "c2f_step");
     B3D_CHECK_HIP(launch_render_score(S->dev, poses, (int)(n * P), logL, nullptr, st), "c2f_step");
-    B3D_CHECK_HIP(launch_sample(logL, P, (int)n, t == 0 ? K : 1, k0, k1, (uint32_t)t, 0u, nullptr, idx, logw, st),
+    B3D_CHECK_HIP(launch_sample(logL, P, (int)n, t == 0 ? K : 1, k0, k1, (uint32_t)t, 0u,
+                                weights_out ? weights_out + woff : nullptr, idx, logw, st),
                   "c2f_step");
+    woff += (size_t)n * P;
     B3D_CHECK_HIP(launch_c2f_update(poses, P, (int)n, idx, logw, K, t > 0, poses_out, logq_out,
                                     idx_out ? idx_out + (size_t)t * K : nullptr, st),
                   "c2f_step");

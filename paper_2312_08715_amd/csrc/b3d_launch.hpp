@@ -222,9 +222,6 @@ hipError_t launch_c2f_update(const float* poses, int P, int N, const int* idx, c
                              int accumulate, float* centres, float* logq, int* idx_out, hipStream_t st);
 
 // refinement and tracking
-hipError_t launch_probe_fma(float* out, int blocks, int iters, hipStream_t st);
-hipError_t launch_probe_triad(const float* a, const float* b, float* c, long long n4, int blocks, hipStream_t st);
-hipError_t launch_probe_lds(float* out, int blocks, int iters, hipStream_t st);
 hipError_t launch_pose_retract(const float* base, int n_base, const float* xi, int N, float* out, hipStream_t st);
 hipError_t launch_pose_retract_backward(const float* xi, const float* grad, const float* dlogL, int N, float* dxi,
                                         float* dsp, hipStream_t st);

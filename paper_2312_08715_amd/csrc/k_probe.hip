@@ -1,9 +1,15 @@
+// Microbenchmarks of the chip's peaks, built into their own library
+// (libb3d_probe.so) for the benchmark; nothing in libb3d.so uses them.
+//
 // Peak probe: FP32 vector FMA throughput, for placing the kernels on the
 // chip's measured (not only published) VALU roofline.  Every lane runs 8
 // independent FMA chains; the result is stored so that nothing is elided.
-#include "b3d_launch.hpp"
+#include <hip/hip_runtime.h>
+#include <stdint.h>
 
-namespace b3d {
+#include "b3d_probe.h"
+
+namespace {
 
 __global__ __launch_bounds__(256) void k_probe_fma(float* __restrict__ out, int iters, float a, float b) {
   float x[8];
@@ -72,4 +78,28 @@ hipError_t launch_probe_lds(float* out, int blocks, int iters, hipStream_t st) {
   return hipGetLastError();
 }
 
-}  // namespace b3d
+}  // namespace
+
+extern "C" {
+
+int32_t b3d_probe_fma(float* out, int32_t blocks, int32_t iters, void* stream) {
+  if (!out || blocks < 1 || iters < 1 || blocks > (1 << 20) || iters > (1 << 20)) return -1;
+  return launch_probe_fma(out, blocks, iters, (hipStream_t)stream) == hipSuccess ? 0 : -3;
+}
+
+int32_t b3d_probe_hbm(const float* a, const float* b, float* c, int64_t n, void* stream) {
+  if (!a || !b || !c || n < 4 || (n % 4) != 0) return -1;
+  if (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15) return -1;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return -3;
+  return launch_probe_triad(a, b, c, n / 4, cus * 8, (hipStream_t)stream) == hipSuccess ? 0 : -3;
+}
+
+int32_t b3d_probe_lds(float* out, int32_t blocks, int32_t iters, void* stream) {
+  if (!out || blocks < 1 || iters < 1 || blocks > (1 << 20) || iters > (1 << 20)) return -1;
+  return launch_probe_lds(out, blocks, iters, (hipStream_t)stream) == hipSuccess ? 0 : -3;
+}
+
+}  // extern "C"

@@ -77,6 +77,10 @@ b3d_status dev_alloc(std::vector<void*>& owned, T** p, size_t n) {
 
 }  // namespace
 
+struct b3d_contact {
+  ContactDev C{};  // table pose and the device copy of every type's six resting faces
+};
+
 struct b3d_smc {
   b3d_smc_params p{};
   b3d_table table{};
@@ -151,25 +155,41 @@ static b3d_status whole_image_scores(b3d_smc* S, hipStream_t st, const std::vect
 
 extern "C" {
 
-b3d_status b3d_contact_poses(const b3d_mesh* const* types, int32_t n_types, const b3d_table* table,
-                             const int32_t* place, const float* dphi, int32_t N, float* poses_out, void* stream) {
+b3d_status b3d_contact_create(const b3d_mesh* const* types, int32_t n_types, const b3d_table* table,
+                              b3d_contact** out) {
+  if (!out) return fail(B3D_EINVAL, "contact_create: NULL output");
+  *out = nullptr;
   std::vector<FaceDev> faces;
   if (b3d_status s = make_contact(types, n_types, table, &faces)) return s;
+  FaceDev* fd = nullptr;
+  if (hipMalloc((void**)&fd, sizeof(FaceDev) * faces.size()) != hipSuccess)
+    return fail(B3D_ENOMEM, "contact_create: device allocation failed");
+  if (hipMemcpy(fd, faces.data(), sizeof(FaceDev) * faces.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(fd);
+    return fail(B3D_EHIP, "contact_create: upload failed");
+  }
+  b3d_contact* c = new b3d_contact();
+  std::memcpy(c->C.T, table->pose, sizeof(c->C.T));
+  c->C.faces = fd;
+  c->C.n_types = n_types;
+  *out = c;
+  return B3D_OK;
+}
+
+b3d_status b3d_contact_destroy(b3d_contact* c) {
+  if (!c) return B3D_OK;
+  (void)hipFree((void*)c->C.faces);
+  delete c;
+  return B3D_OK;
+}
+
+b3d_status b3d_contact_poses(const b3d_contact* c, const int32_t* place, const float* dphi, int32_t N,
+                             float* poses_out, void* stream) {
+  if (!c) return fail(B3D_EINVAL, "contact_poses: NULL contact set");
   if (N < 0) return fail(B3D_ESHAPE, "contact_poses: N < 0");
   if (N == 0) return B3D_OK;
   if (!place || !dphi || !poses_out) return fail(B3D_EINVAL, "contact_poses: NULL buffer");
-  hipStream_t st = (hipStream_t)stream;
-  FaceDev* fd = nullptr;
-  if (hipMallocAsync((void**)&fd, sizeof(FaceDev) * faces.size(), st) != hipSuccess)
-    return fail(B3D_ENOMEM, "contact_poses: device allocation failed");
-  ContactDev C{};
-  std::memcpy(C.T, table->pose, sizeof(C.T));
-  C.faces = fd;
-  C.n_types = n_types;
-  hipError_t e = hipMemcpyAsync(fd, faces.data(), sizeof(FaceDev) * faces.size(), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = launch_contact_poses(C, place, dphi, N, poses_out, st);
-  (void)hipFreeAsync(fd, st);
-  if (e != hipSuccess) return hip_fail(e, "contact_poses");
+  B3D_CHECK_HIP(launch_contact_poses(c->C, place, dphi, N, poses_out, (hipStream_t)stream), "contact_poses");
   return B3D_OK;
 }
 
@@ -235,8 +255,7 @@ b3d_status b3d_smc_create(const b3d_mesh* const* types, int32_t n_types, const b
   if (A < 1 || B < 1 || A > kMaxSigma || A * B > kMaxNoise)
     return fail(B3D_ESHAPE, "smc_create: need 1 <= noise_A <= %d, noise_A * noise_B <= %d", kMaxSigma, kMaxNoise);
   std::vector<float> sig(A), po(B);
-  for (int a = 0; a < A; ++a) sig[a] = (float)(p->sigma_max * (a + 0.5) / A);
-  for (int b = 0; b < B; ++b) po[b] = (float)((b + 0.5) / B);
+  if (b3d_status s = b3d_noise_midpoints(p->sigma_max, A, B, sig.data(), po.data())) return s;
   NoiseGridDev mid{};
   std::vector<b3d_score_params> per;
   if (b3d_status s = make_noise_grid(sp, K->H, K->W, sig.data(), A, po.data(), B, nullptr, &mid, &per)) return s;

@@ -10,10 +10,11 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "b3d.h")
+PROBE_HEADER = os.path.join(ROOT, "include", "b3d_probe.h")
 
 
-def declared_functions():
-    src = open(HEADER).read()
+def declared_functions(header=HEADER):
+    src = open(header).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(b3d_\w+)\s*\(", src, flags=re.M)))
 
@@ -39,6 +40,15 @@ def test_header_declares_the_boundary():
 def test_library_exports_every_declared_symbol(lib):
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
+    # the peak microbenchmarks live in their own library, outside the method's ABI
+    from paper_2312_08715_amd import probe
+
+    plib = probe.load_probe_library()
+    pnames = declared_functions(PROBE_HEADER)
+    assert pnames == ["b3d_probe_fma", "b3d_probe_hbm", "b3d_probe_lds"]
+    assert all(hasattr(plib, n) for n in pnames)
+    assert not any(hasattr(lib, n) for n in pnames)
+    assert plib.b3d_probe_fma(None, 1, 1, None) == -1  # argument errors before any launch
 
 
 def test_host_side_validation_without_a_device(lib):

@@ -1,0 +1,376 @@
+"""Parity of the HIP library against the FP64 oracle at the shapes of the
+larger workloads: the four-object table scene at 320x240 (coarse-to-fine
+stage and Adam refinement) and the three-object tracking sequence.
+
+Bars as in test_gpu_parity: logL within 1e-4 of the L1 mass of the
+per-pixel terms on hypotheses whose triangle ids all match the oracle's;
+pose gradients within 1e-3 ||g|| + 1e-6; draws equal wherever the oracle's
+top-two gap of logL + Gumbel noise exceeds 1e-4 of the L1 mass.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+LOGL_RTOL = 1e-4
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def b3d():
+    import paper_2312_08715_amd as b
+
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    b.load_library()
+    return b
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def agree(gz, gtri, od, oi):
+    return (gtri == oi) | ((gtri >= 0) & (oi >= 0) & (np.abs(gz - od) <= 1e-5))
+
+
+def rotvec(dR_angle_deg, rng):
+    w = rng.normal(size=3)
+    w *= np.deg2rad(dR_angle_deg) / np.linalg.norm(w)
+    th = np.linalg.norm(w)
+    k = w / th
+    Kx = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    return np.eye(3) + np.sin(th) * Kx + (1 - np.cos(th)) * Kx @ Kx
+
+
+class Composite:
+    """The oracle's render of one moving object in front of fixed content:
+    the fixed objects are rendered once and each hypothesis's object render
+    is merged by the nearest depth (the object's ids come first, so a tie
+    keeps the object, as a joint render does).  Equal to rendering all
+    objects together, which the constructor checks on a few poses."""
+
+    def __init__(self, mesh, fixed, cam, check_poses):
+        self.v, self.t = mesh
+        self.cam = cam
+        self.T0 = self.t.shape[0]
+        d, i = oracle.render(fixed, cam)
+        self.bd, self.bi = d[0], np.where(i[0] >= 0, i[0] + self.T0, -1)
+        jd, ji = oracle.render([(self.v, self.t, check_poses)] + list(fixed), cam)
+        cd, ci, _, _ = self(check_poses)
+        assert np.array_equal(jd, cd) and np.array_equal(ji, ci)
+
+    def __call__(self, P):
+        od, oi = oracle.render([(self.v, self.t, P)], self.cam)
+        take = (od > 0) & ((self.bd <= 0) | (od <= self.bd))
+        return np.where(take, od, self.bd), np.where(take, oi, self.bi), od, oi
+
+
+_table = {}
+
+
+def table_setup():
+    """The table scene (four objects of 800-6000 voxels on a 1 m table,
+    320x240, f = 300) observed through the oracle's FP64 render with 2 mm
+    noise and 3% outliers."""
+    if not _table:
+        from workloads import table_scene
+
+        meshes, poses, table, cam, noise, _ = table_scene()
+        meshes = [(f32(v), t) for v, t in meshes]
+        poses = [f32(P) for P in poses]
+        tv, tt, tT = table
+        table = (f32(tv), tt, f32(tT))
+        objs = [(v, t, P) for (v, t), P in zip(meshes, poses)] + [table]
+        d = oracle.render(objs, cam)[0][0]
+        d = np.where(d > 0, d + noise["gauss"], 0.0)
+        d = np.where(noise["outlier_mask"], noise["outlier_depth"], d)
+        _table.update(objs=objs, cam=cam, obs=f32(oracle.unproject(d, cam)), truth=poses)
+    return _table
+
+
+def table_object_scene(b3d, k):
+    ts = table_setup()
+    objs, cam = ts["objs"], ts["cam"]
+    ms = [b3d.Mesh(v, t) for v, t, _ in objs]
+    sc = b3d.Scene(ms[k], b3d.intrinsics_of(cam), b3d.score_params(0.003, 0.01, 1.0, 5))
+    others = [j for j in range(len(objs)) if j != k]
+    sc.set_background([ms[j] for j in others], np.stack([objs[j][2] for j in others]))
+    o = dev(ts["obs"])
+    sc.set_observed(o)
+    comp = Composite((objs[k][0], objs[k][1]), [objs[j] for j in others], cam, objs[k][2][None])
+    return sc, ms, o, comp
+
+
+def table_start(k, seed=2002):
+    """Object k's start: the truth moved 3 cm and turned 15 degrees (a
+    detection's error), the draws the table-scene benchmark makes."""
+    rng = np.random.default_rng(seed)
+    for _ in range(k + 1):
+        dR = rotvec(15.0, rng)
+        dt = rng.normal(size=3)
+        dt *= 0.03 / np.linalg.norm(dt)
+    truth = table_setup()["truth"][k]
+    s = truth.copy()
+    s[:3, :3] = dR @ truth[:3, :3]
+    s[:3, 3] += dt
+    return f32(s)
+
+
+def test_table_scene_first_stage_matches_oracle(b3d):
+    # The table scene's first coarse-to-fine stage for object 1 (1500
+    # voxels; the other three objects and the table as fixed content):
+    # 10,000 hypotheses (10^3 translations over +-8 cm x 10 rotations within
+    # 30 degrees) around a start 3 cm / 15 degrees off, 16 draws.  Every
+    # hypothesis's logL against the oracle's; the stage's cell probabilities
+    # and draws from b3d_c2f_step against the oracle's softmax and Gumbel-max.
+    from workloads import GridSpec
+
+    k, K, seed = 1, 16, 4003
+    ts = table_setup()
+    sc, ms, o, comp = table_object_scene(b3d, k)
+    start = table_start(k)
+    spec = GridSpec(center=start, half_extent=(0.08, 0.08, 0.08), count=(10, 10, 10), n_rot=10,
+                    rot_max_angle=np.deg2rad(30.0))
+    P = f32(oracle.enumerate_grid(spec, seed=seed, stage=0))
+    say(f"table scene stage 1: object {k}, N={P.shape[0]}, 320x240")
+    Lg = b3d.render_score(sc, dev(P)).cpu().numpy().astype(np.float64)
+    L64, l1, clean = np.zeros(len(P)), np.zeros(len(P)), np.zeros(len(P), dtype=bool)
+    K_ = b3d.intrinsics_of(ts["cam"])
+    for i in range(0, len(P), 1000):
+        cd, ci, od, oi = comp(P[i:i + 1000])
+        L64[i:i + 1000], l1[i:i + 1000] = oracle.score(ts["obs"], oracle.unproject(cd, ts["cam"]), 0.003, 0.01,
+                                                       1.0, 5)
+        xa, ta = b3d.render_batch(sc.mesh, dev(P[i:i + 1000]), K_)
+        clean[i:i + 1000] = np.all(agree(xa[..., 2].cpu().numpy(), ta.cpu().numpy(), od, oi).reshape(len(od), -1),
+                                   axis=1)
+        del xa, ta
+    err = np.abs(Lg - L64) / l1
+    say(f"  clean {clean.mean():.4f}; max rel-L1 logL err (clean) {err[clean].max():.3g}, (all) {err.max():.3g}")
+    assert clean.mean() >= 0.99 and err[clean].max() <= LOGL_RTOL
+    # the stage as b3d_c2f_step runs it (its own enumeration of the same grid)
+    g, _ = b3d.grid_of(spec)
+    sched = b3d.make_schedule([g])
+    Pc, logq, idx, W = b3d.c2f_step(sc, start, sched, K, seed, weights=True)
+    w = W[0].cpu().numpy().astype(np.float64)
+    lw64 = L64 - L64.max() - np.log(np.sum(np.exp(L64 - L64.max())))
+    # |d ln w| <= |dlogL_n| + |dLSE|: twice the logL bar
+    bound = 2 * LOGL_RTOL * l1.max()
+    big = lw64 > -30
+    assert np.all(np.abs(np.log(np.maximum(w[big], 1e-38)) - lw64[big]) <= bound)
+    assert abs(w.sum() - 1.0) <= 1e-5
+    _, idx64, lq64 = oracle.sample(L64, K, seed, 0)
+    idx = idx.cpu().numpy()[0]
+    decided = 0
+    for j in range(K):
+        G = -np.log(-np.log(np.array([oracle.uniform(seed, n, j, 0, 0) for n in range(len(P))])))
+        v = np.sort(L64 + G)
+        if v[-1] - v[-2] > LOGL_RTOL * l1.max():
+            assert idx[j] == idx64[j], (j, idx[j], idx64[j])
+            decided += 1
+    say(f"  draws {sorted(set(idx.tolist()))}; {decided} of {K} gap-decided")
+    assert decided >= K - 1
+    same = idx == idx64
+    np.testing.assert_allclose(Pc.cpu().numpy()[same], P[idx64[same]], atol=2e-6)
+    assert np.all(np.abs(logq.cpu().numpy()[same] - lq64[same]) <= bound)
+
+
+def test_table_scene_adam_steps_match_oracle(b3d):
+    # Twenty Adam steps on the 16 best cells of object 1's first stage (the
+    # oracle's scores): at every step the GPU's fused gradient at the
+    # oracle's current poses (rounded to FP32) against the oracle's, and the
+    # GPU's Adam update from the oracle's state against the oracle's update.
+    # The free-running one-workgroup refinement is compared over its first
+    # three steps: logL is only piecewise smooth in the pose, and two oracle
+    # chains whose gradients differ by 1e-5 relative (and whose poses are
+    # rounded to FP32) drift apart by up to 6e-7 after three steps but 3e-4
+    # after five and 1e-2 after twenty on this scene.
+    from oracle.refine import adam_pose_step
+    from workloads import GridSpec
+
+    k = 1
+    ts = table_setup()
+    sc, ms, o, comp = table_object_scene(b3d, k)
+    spec = GridSpec(center=table_start(k), half_extent=(0.08, 0.08, 0.08), count=(10, 10, 10), n_rot=10,
+                    rot_max_angle=np.deg2rad(30.0))
+    P = f32(oracle.enumerate_grid(spec, seed=4003, stage=0))
+    Lg = b3d.render_score(sc, dev(P)).cpu().numpy()
+    # the 16 best cells by the oracle's score, among the GPU's best 64
+    cand = np.argsort(-Lg, kind="stable")[:64]
+    cd, _, _, _ = comp(P[cand])
+    Lc, _ = oracle.score(ts["obs"], oracle.unproject(cd, ts["cam"]), 0.003, 0.01, 1.0, 5)
+    Q = P[cand[np.argsort(-Lc, kind="stable")[:16]]].copy()
+    Q0 = Q.copy()
+    c32 = [float(np.float32(x)) for x in (1e-3, 1e-2, 0.9, 0.999, 1e-8)]
+    st = np.zeros((16, 12))
+    K_ = b3d.intrinsics_of(ts["cam"])
+    say(f"table scene Adam: object {k}, 16 poses, 20 steps in lockstep")
+    worst_g, worst_p, n_clean = 0.0, 0.0, 0
+    for it in range(1, 21):
+        cd, ci, od, oi = comp(Q)
+        rend = oracle.unproject(cd, ts["cam"])
+        dr, _, _ = oracle.score_grad(ts["obs"], rend, 0.003, 0.01, 1.0, 5)
+        g64 = oracle.render_grad(comp.v, comp.t, Q, ts["cam"], ci, cd, dr)
+        _, G = b3d.render_score(sc, dev(Q), grad=True)
+        G = G.cpu().numpy().astype(np.float64)
+        xa, ta = b3d.render_batch(sc.mesh, dev(Q), K_)
+        clean = np.all(agree(xa[..., 2].cpu().numpy(), ta.cpu().numpy(), od, oi).reshape(16, -1), axis=1)
+        n_clean += clean.sum()
+        for n in np.nonzero(clean)[0]:
+            e = np.linalg.norm(G[n, :6] - g64[n])
+            assert e <= 1e-3 * np.linalg.norm(g64[n]) + 1e-6, (it, n, G[n, :6], g64[n])
+            worst_g = max(worst_g, e / np.linalg.norm(g64[n]))
+        Qn, stn = adam_pose_step(Q, g64, st, it, *c32)
+        Qd, sd = dev(Q), dev(st)
+        b3d.adam_pose_step(Qd, dev(g64), sd, it, *c32)
+        dp = np.abs(Qd.cpu().numpy() - Qn).max()
+        worst_p = max(worst_p, dp)
+        assert dp <= 2e-6, (it, dp)
+        Q, st = f32(Qn), f32(stn)
+    say(f"  worst relative gradient error {worst_g:.3g} over {n_clean} clean (pose, step) pairs; "
+        f"worst Adam update diff {worst_p:.3g}")
+    assert n_clean >= 0.99 * 16 * 20
+    moved = np.abs(Q - Q0).reshape(16, -1).max(1)
+    assert moved.min() >= 1e-2
+    # free-running: the one-workgroup refinement, three steps
+    A = dev(Q0)
+    b3d.refine_poses(sc, A, 3, *c32)
+    R, st = Q0.copy(), np.zeros((16, 12))
+    for it in range(1, 4):
+        cd, ci, _, _ = comp(R)
+        dr, _, _ = oracle.score_grad(ts["obs"], oracle.unproject(cd, ts["cam"]), 0.003, 0.01, 1.0, 5)
+        R, st = adam_pose_step(R, oracle.render_grad(comp.v, comp.t, R, ts["cam"], ci, cd, dr), st, it, *c32)
+    d = np.abs(A.cpu().numpy() - R).max()
+    say(f"  refine_poses, 3 steps: max pose diff from the oracle chain {d:.3g}")
+    assert d <= 1e-5
+
+
+_track = {}
+
+
+def tracking_setup(n_frames=5):
+    """The tracking sequence (three objects of 2000-5000 voxels on smooth
+    paths, 160x120, f = 150, 2 mm noise, 4% outliers): its first frames,
+    observed through the oracle's FP64 render."""
+    if not _track:
+        from workloads import tracking_sequence
+
+        meshes, paths, cam, noise = tracking_sequence(n_frames=200)
+        meshes = [(f32(v), t) for v, t in meshes]
+        frames = []
+        for f in range(n_frames):
+            d = oracle.render([(v, t, paths[f, k]) for k, (v, t) in enumerate(meshes)], cam)[0][0]
+            d = np.where(d > 0, d + noise[f]["gauss"], 0.0)
+            d = np.where(noise[f]["outlier_mask"], noise[f]["outlier_depth"], d)
+            frames.append(f32(oracle.unproject(d, cam)))
+        _track.update(meshes=meshes, paths=paths[:n_frames], cam=cam, frames=frames)
+    return _track
+
+
+def _tracker(b3d, ts, specs, init, n_refine):
+    ms = [b3d.Mesh(v, t) for v, t in ts["meshes"]]
+    grids = [b3d.grid_of(g) for g in specs]
+    tr = b3d.Tracker(ms, b3d.intrinsics_of(ts["cam"]), b3d.score_params(0.003, 0.01, 1.0, 5),
+                     [g for g, _ in grids], f32(init), n_refine=n_refine)
+    return tr, ms, grids
+
+
+def test_tracker_search_follows_the_oracle_on_three_objects(b3d):
+    # Four frames of the three-object sequence, two search stages per object
+    # (6^3 translations over +-3 cm x 8 rotations within 8 degrees, then 3^3
+    # over +-7.5 mm x 8 within 3 degrees) and no gradient steps.  Each frame
+    # starts both sides from the same poses (the oracle's previous frame);
+    # the oracle updates the objects in turn with the others at their current
+    # estimates drawn in front of or behind them, following near ties
+    # (scores within the logL bar) both ways; the GPU's three poses must be
+    # one of the oracle's outcomes.
+    from oracle import track
+    from workloads import GridSpec, ScoreParams
+
+    ts = tracking_setup()
+    sp = ScoreParams(sigma=0.003, p_out=0.01, outlier_volume=1.0, window=5)
+    specs = [GridSpec(center=np.eye(4), half_extent=(0.03, 0.03, 0.03), count=(6, 6, 6), n_rot=8,
+                      rot_max_angle=np.deg2rad(8.0)),
+             GridSpec(center=np.eye(4), half_extent=(0.0075, 0.0075, 0.0075), count=(3, 3, 3), n_rot=8,
+                      rot_max_angle=np.deg2rad(3.0))]
+    for g in specs:  # the GPU enumerates with key 0, as the oracle's tracking frame does
+        assert g.rotations is None
+    cur = [f32(P) for P in ts["paths"][0]]
+    M = len(cur)
+    say(f"tracker search vs oracle: {M} objects, {len(ts['frames']) - 1} frames")
+
+    def frame_ends(obs, poses, o):
+        if o == M:
+            return [np.stack(poses)]
+        out = []
+        for e in track.search_ends(ts["meshes"], poses, o, specs, obs, ts["cam"], sp, tol=LOGL_RTOL, limit=2):
+            nxt = list(poses)
+            nxt[o] = e
+            out += frame_ends(obs, nxt, o + 1)
+        return out
+
+    ties = 0
+    for f in range(1, len(ts["frames"])):
+        tr, ms, grids = _tracker(b3d, ts, specs, np.stack(cur), 0)
+        tr.frame(dev(ts["frames"][f]))
+        g = tr.poses().cpu().numpy().astype(np.float64)
+        ends = frame_ends(ts["frames"][f].astype(np.float64), cur, 0)
+        hit = [e for e in ends if np.allclose(e, g, atol=1e-5)]
+        assert hit, f"frame {f}: the GPU's poses are none of the oracle's {len(ends)} outcomes"
+        ties += int(hit[0] is not ends[0])
+        cur = list(hit[0])
+        err = [np.linalg.norm(cur[k][:3, 3] - ts["paths"][f, k, :3, 3]) * 100 for k in range(M)]
+        say(f"  frame {f}: {len(ends)} outcome(s); position errors (cm) {np.round(err, 3).tolist()}")
+    say(f"  frames where the GPU took a tied outcome other than the oracle's first: {ties}")
+
+
+def test_tracker_refinement_follows_the_oracle_on_three_objects(b3d):
+    # The tracker's refinement alone (a one-hypothesis search grid, one Adam
+    # step per object and frame), three frames: the objects are refined in
+    # turn, each in front of the others at their current estimates (the
+    # objects before it already refined), with the moments reset every frame;
+    # GPU (row-band gradient sums) against the oracle from the same start
+    # poses each frame.  One step: logL is only piecewise smooth in the pose,
+    # so longer free-running chains drift apart by more than rounding (two
+    # oracle chains perturbed at the rounding level differ by up to 3e-4 after
+    # five steps on the table scene), while one step is decided by the
+    # gradient's signs and sizes at the shared start.
+    from oracle import track
+    from workloads import GridSpec, ScoreParams
+
+    ts = tracking_setup()
+    sp = ScoreParams(sigma=0.003, p_out=0.01, outlier_volume=1.0, window=5)
+    one = [GridSpec(center=np.eye(4), half_extent=(0.0, 0.0, 0.0), count=(1, 1, 1))]
+    c32 = [float(np.float32(x)) for x in (1e-3, 1e-2, 0.9, 0.999, 1e-8)]
+    # start each object 6 mm and a few degrees off its true pose
+    rng = np.random.default_rng(8)
+    cur = []
+    for P in ts["paths"][0]:
+        Q = P.copy()
+        Q[:3, :3] = rotvec(4.0, rng) @ Q[:3, :3]
+        Q[:3, 3] += rng.normal(size=3) * 0.006 / np.sqrt(3)
+        cur.append(f32(Q))
+    say("tracker refinement vs oracle: 3 objects, 3 frames, 1 Adam step")
+    for f in range(1, 4):
+        tr, ms, grids = _tracker(b3d, ts, one, np.stack(cur), 1)
+        tr.frame(dev(ts["frames"][f]))
+        g = tr.poses().cpu().numpy().astype(np.float64)
+        want = list(cur)
+        for o in range(len(want)):
+            want[o] = track.refine(ts["meshes"], want, o, ts["frames"][f].astype(np.float64), ts["cam"], sp, 1, *c32)
+        want = np.stack(want)
+        d = np.abs(g - want).max()
+        moved = np.abs(want - np.stack(cur)).max()
+        say(f"  frame {f}: max pose diff {d:.3g}; poses moved by up to {moved:.3g}")
+        assert d <= 2e-6 and moved >= 1e-3
+        cur = list(want)

@@ -89,7 +89,8 @@ def test_contact_poses_match_oracle(b3d):
     N = 300
     place = np.stack([rng.integers(0, 2, N), rng.integers(0, 6, N)], 1).astype(np.int32)
     dphi = f32(np.stack([rng.uniform(-0.4, 0.4, N), rng.uniform(-0.4, 0.4, N), rng.uniform(0, 2 * np.pi, N)], 1))
-    P = b3d.contact_poses(types, b3d.table(tT, 1.0, 1.0), dev(place, torch.int32), dev(dphi)).cpu().numpy()
+    contact = b3d.Contact(types, b3d.table(tT, 1.0, 1.0))
+    P = contact.poses(dev(place, torch.int32), dev(dphi)).cpu().numpy()
     faces = [faces_of(v) for v, _ in meshes]
     T = Table(tT, 1.0, 1.0)
     want = np.stack([contact_pose(T, faces[o][c], *x) for (o, c), x in zip(place, dphi)])
@@ -139,7 +140,7 @@ def test_smc_stages_match_oracle(b3d, stage_noise, thr):
         # the posterior over the new object's type, marginal over face and placement
         tp = r["type_post"].cpu().numpy().astype(np.float64)
         say(f"  type posterior: max |dp| {np.abs(tp - diag['type_post']).max():.3g}")
-        assert np.allclose(tp, diag["type_post"], rtol=1e-2, atol=2e-3)
+        assert np.abs(tp - diag["type_post"]).max() <= 1e-4
         assert np.allclose(tp.sum(1), 1.0, atol=1e-5)
         # the state is gathered by ancestor (identity without resampling):
         # proposal j is seen at a survivor m with ancestors[m] == j
@@ -169,7 +170,7 @@ def test_smc_stages_match_oracle(b3d, stage_noise, thr):
         og = diag["noise_grid"]
         rel = np.abs(gg - og) / (np.abs(og) + 1.0)
         say(f"  noise grid: max rel err (agreeing proposals) {rel[same].max():.3g}")
-        assert np.median(rel[same]) <= 1e-4 and rel[same].max() <= 2e-3
+        assert rel[same].max() <= 1e-4
         g_noise = pre(r["noise"].cpu().numpy())
         nsame = same & np.all(np.isclose(g_noise, diag["noise"], rtol=1e-5, atol=1e-7), axis=1)
         say(f"  noise draws agree: {nsame.sum()}/{same.sum()}")
@@ -281,7 +282,7 @@ def test_smc_first_stage_at_bench_scale_matches_oracle(b3d):
     L0 = diag["stage0_logL"][0]
     tp = r["type_post"].cpu().numpy().astype(np.float64)
     say(f"  type posterior {np.round(tp[0], 4).tolist()} (oracle {np.round(diag['type_post'][0], 4).tolist()})")
-    assert np.allclose(tp, diag["type_post"], rtol=1e-2, atol=2e-3)
+    assert np.abs(tp - diag["type_post"]).max() <= 1e-4
     # the draws: equal wherever the oracle's top-two gap of logL + G exceeds the
     # logL tolerance (1e-4 of |logL|)
     ch = r["choice"].cpu().numpy()[0]
@@ -350,5 +351,5 @@ def test_smc_edge_cases_and_errors(b3d):
     with pytest.raises(b3d.B3DError):
         smc.step()  # both objects placed
     # contact poses of nothing
-    assert b3d.contact_poses(types, b3d.table(tT, 1.0, 1.0), torch.zeros((0, 2), dtype=torch.int32, device="cuda"),
-                             torch.zeros((0, 3), device="cuda")).shape == (0, 4, 4)
+    assert b3d.Contact(types, b3d.table(tT, 1.0, 1.0)).poses(torch.zeros((0, 2), dtype=torch.int32, device="cuda"),
+                                                            torch.zeros((0, 3), device="cuda")).shape == (0, 4, 4)
