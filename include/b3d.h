@@ -363,6 +363,22 @@ b3d_status b3d_c2f_step(const b3d_scene* scene, const float* center, const b3d_s
                         void* workspace, size_t ws_bytes, float* weights_out, float* poses_out, float* logq_out,
                         int32_t* idx_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): b3d_c2f_step with
+ * its workspace in a library-owned device array of B3D_C2F_SCRATCH_BYTES
+ * (16 MiB) on each GPU it runs on, held until the process ends.  Same
+ * arguments, results and errors as b3d_c2f_step without the workspace; a
+ * schedule whose b3d_c2f_workspace_size exceeds the limit is refused with
+ * B3D_ESHAPE before any launch (at 68 bytes per hypothesis, about 240,000
+ * hypotheses in the largest stage: N_0, or K N_t for t >= 1).  Runs on the
+ * current device; `stream` must belong to it.  Calls no allocating routine.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one GPU (on different streams, or from several threads) race. */
+#define B3D_C2F_SCRATCH_BYTES (16u << 20)
+b3d_status b3d_c2f_step_noalloc(const b3d_scene* scene, const float* center, const b3d_schedule* s, int32_t K,
+                                uint64_t seed, float* weights_out, float* poses_out, float* logq_out,
+                                int32_t* idx_out, void* stream);
+
 /* ---- gradient refinement and tracking ---------------------------------- */
 
 /* Retraction onto the pose manifold, the update convention of the adjoint

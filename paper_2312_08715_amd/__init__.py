@@ -133,6 +133,7 @@ _SIGNATURES = {
     "b3d_sample": ([_P, _I32, _I32, _I32, _U64, _U32, _U32, _P, _P, _P, _P], ctypes.c_int),
     "b3d_c2f_workspace_size": ([ctypes.POINTER(Schedule), _I32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "b3d_c2f_weights_count": ([ctypes.POINTER(Schedule), _I32, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "b3d_c2f_step_noalloc": ([_P, _P, ctypes.POINTER(Schedule), _I32, _U64, _P, _P, _P, _P, _P], ctypes.c_int),
     "b3d_c2f_step": ([_P, _P, ctypes.POINTER(Schedule), _I32, _U64, _P, ctypes.c_size_t, _P, _P, _P, _P, _P],
                      ctypes.c_int),
     "b3d_contact_create": ([_P, _I32, ctypes.POINTER(Table), ctypes.POINTER(_P)], ctypes.c_int),
@@ -566,6 +567,17 @@ def c2f_step(scene: Scene, center, schedule: Schedule, K: int, seed: int, device
         per.append(w[off:off + n] if t == 0 else w[off:off + K * n].view(K, n))
         off += n if t == 0 else K * n
     return poses, logq, idx, per
+
+
+def c2f_step_noalloc(scene: Scene, center, schedule: Schedule, K: int, seed: int, poses: torch.Tensor,
+                     logq: torch.Tensor, idx: Optional[torch.Tensor] = None,
+                     weights: Optional[torch.Tensor] = None) -> None:
+    """b3d_c2f_step_noalloc: c2f_step into caller-allocated outputs (poses
+    [K,4,4], logq [K], idx [n_stages,K] or None, weights [b3d_c2f_weights_count]
+    or None), its workspace in the library's fixed device array."""
+    c = np.ascontiguousarray(np.asarray(center, dtype=np.float32).reshape(16))
+    _call("b3d_c2f_step_noalloc", scene.handle, c.ctypes.data, ctypes.byref(schedule), int(K), int(seed), _ptr(weights),
+          _ptr(poses), _ptr(logq), _ptr(idx), _stream())
 
 
 class Batch:

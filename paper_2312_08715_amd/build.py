@@ -17,7 +17,8 @@ LIB_DIR = os.path.join(HERE, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "libb3d.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["api.cpp", "mesh.cpp", "smc.cpp", "k_render.hip", "k_score.hip", "k_fused.hip", "k_sample.hip", "k_track.hip"]
+SOURCES = ["api.cpp", "mesh.cpp", "smc.cpp", "k_render.hip", "k_score.hip", "k_fused.hip", "k_sample.hip", "k_track.hip",
+           "c2f_noalloc.hip"]
 # microbenchmarks of the chip's peaks: a library of their own, loaded by the benchmark only
 PROBE_SOURCES = ["k_probe.hip"]
 PROBE_LIB_PATH = os.path.join(LIB_DIR, "libb3d_probe.so")
