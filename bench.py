@@ -39,6 +39,7 @@ METRIC = "pose hypotheses scored/s (render+logL) at 160x120, 24k tris; fwd+adjoi
 # counters (every triangle of the mesh).
 COST = {"vert": 17, "tri": 12, "front": 27, "frag": 10, "pair": 12, "obs": 6, "adj_pair": 10, "adj_rpix": 30}
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # FP32 lane-ops/s, non-packed: 39.3 T
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
 
 # HBM bytes of one fused forward+adjoint launch on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch) scaled by
@@ -553,18 +554,30 @@ def main():
     # plain split path: point images through device memory
     P = b3d.enumerate_grid(grid, seed=seed)
 
+    split_ev = {}
+
+    def ev(name, fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        out = fn()
+        e1.record(stream)
+        split_ev.setdefault(name, []).append((e0, e1))
+        return out
+
     def split(adj):
-        xyz, tri = b3d.render_batch(mesh, P, K, want_tri=adj)
-        L = b3d.score(obs, xyz, p)
+        xyz, tri = ev("render_batch_ids" if adj else "render_batch", lambda: b3d.render_batch(mesh, P, K, want_tri=adj))
+        L = ev("score", lambda: b3d.score(obs, xyz, p))
         if adj:
-            dr, ds, dp = b3d.score_backward(obs, xyz, p)
-            b3d.render_backward(mesh, P, K, tri, dr)
+            dr, ds, dp = ev("score_backward", lambda: b3d.score_backward(obs, xyz, p))
+            ev("render_backward", lambda: b3d.render_backward(mesh, P, K, tri, dr))
         return L
 
     t_split = t_split_adj = float("nan")
+    split_kernels = {}
     if not args.fused_only:
         t_split = timed(lambda: split(False), max(3, args.steps // 4), 1)
         t_split_adj = timed(lambda: split(True), max(3, args.steps // 4), 1)
+        split_kernels = split_rooflines(split_ev, N, wl.camera.H * wl.camera.W)
     if args.copy_calibration:
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -579,8 +592,7 @@ def main():
     valu_measured = probe.probe_fma() / 1e12
     peaks = {"valu_TOPs": valu_measured, "hbm_GBps": probe.probe_hbm() / 1e9, "lds_TBps": probe.probe_lds() / 1e12}
     work = counted_work(b3d, scene, P)
-    ops = lane_ops(work, adjoint=True)
-    achieved = ops / t_kernel / 1e12
+    ops = lane_ops(work, adjoint=True)  # the kernel's own (culled) work
     extras = {}
     if not args.no_extras:
         extras["small_config"] = bench_small(b3d, torch, args.steps, args.warmup)
@@ -614,23 +626,61 @@ def main():
                                "(10x10 translations x 50 rotations), 5x5 window, fused fwd+adjoint + sampling",
                    "hypotheses": N, "image": "160x120", "triangles": int(wl.tris.shape[0]), "window": s.window,
                    "samples_per_step": args.samples},
-        "roofline": {"bound": "alu", "kernel": "k_render_score<true, 0>", "achieved": achieved,
-                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s (FP32 lane-ops)", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": measured_traffic(), "kernel_ms": t_kernel * 1e3,
-                     "kernel_ms_median": t_kernel_median * 1e3,
-                     "peak_measured": valu_measured, "frac_of_measured": achieved / valu_measured,
-                     "ops_per_hypothesis": ops / N,
-                     "work_per_hypothesis": {k: v / N for k, v in work.items()},
-                     "plain_method_ops_per_hypothesis": (lane_ops(plain_counts) if plain_counts else None)},
+        "roofline": roofline_line(t_kernel, t_kernel_median, N, ops, work, plain_counts, valu_measured),
         "fwd_only": {"value": N / t_fwd, "ms_per_step": t_fwd * 1e3},
         "plain_split": {"value": N / t_split, "ms_per_step": t_split * 1e3,
-                        "note": "render_batch -> score, point images in HBM"},
-        "plain_split_fwd_adjoint": {"value": N / t_split_adj, "ms_per_step": t_split_adj * 1e3},
+                        "note": "render_batch -> score, point images in HBM",
+                        "roofline": split_kernels.get("score")},
+        "plain_split_fwd_adjoint": {"value": N / t_split_adj, "ms_per_step": t_split_adj * 1e3,
+                                    "note": "render_batch (with ids) -> score -> score_backward -> render_backward",
+                                    "roofline": split_kernels.get("score_backward"), "kernels": split_kernels},
         "peaks_measured": peaks,
         "cpu_baseline": cpu,
     }
     line.update(extras)
     print(json.dumps(line), flush=True)
+
+
+# Algorithmic HBM bytes per pixel of each split-path kernel (one hypothesis's
+# point image is H x W x 12 bytes, its triangle ids H x W x 4): render_batch
+# writes points (and ids), score reads points, score_backward reads points and
+# writes their gradient, render_backward reads ids and point gradients.
+SPLIT_BYTES_PER_PIXEL = {"render_batch": 12, "render_batch_ids": 16, "score": 12, "score_backward": 24,
+                         "render_backward": 16}
+
+
+def split_rooflines(events, N, HW):
+    """HBM roofline of each split-path kernel from its HIP-event times (warm-up
+    excluded), against the 8 TB/s peak."""
+    out = {}
+    for name, evs in events.items():
+        ms = float(np.mean([a.elapsed_time(b) for a, b in evs[1:]])) if len(evs) > 1 else float("nan")
+        b = SPLIT_BYTES_PER_PIXEL[name] * HW * N
+        out[name] = {"bound": "hbm", "kernel": name, "achieved": b / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, "bytes": b, "kernel_ms": ms,
+                     "traffic": None}
+    return out
+
+
+def roofline_line(t_kernel, t_kernel_median, N, ops, work, plain_counts, valu_measured):
+    """VALU roofline of the fused kernel.  Algorithmic work per hypothesis is
+    the plain method's: the oracle's work counters (every triangle, every
+    fragment, every window pair of the definition) priced by the cost table
+    (`lane_ops`), from the CPU-baseline leg; the kernel's own, culled count
+    (the instrumented launch) is reported beside it.  Without the CPU leg the
+    kernel's count stands in."""
+    own = {"ops_per_hypothesis": ops / N, "achieved": ops / t_kernel / 1e12,
+           "frac": ops / t_kernel / 1e12 / VALU_PEAK_TOPS, "work_per_hypothesis": {k: v / N for k, v in work.items()}}
+    plain = lane_ops(plain_counts) if plain_counts else None
+    per_h = plain if plain else ops / N
+    achieved = per_h * N / t_kernel / 1e12
+    return {"bound": "alu", "kernel": "k_render_score<true, 0>", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+            "unit": "TOP/s (FP32 lane-ops)", "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(),
+            "counting": "plain method: oracle work counters x cost table" if plain else "kernel's own count",
+            "ops_per_hypothesis": per_h, "plain_method_counts_per_hypothesis": plain_counts,
+            "kernel_ms": t_kernel * 1e3, "kernel_ms_median": t_kernel_median * 1e3,
+            "peak_measured": valu_measured, "frac_of_measured": achieved / valu_measured,
+            "kernel_count": own}
 
 
 def cpu_model() -> str:

@@ -123,11 +123,20 @@ b3d_status b3d_unproject(const float* depth, int32_t B, const b3d_intrinsics* K,
 b3d_status b3d_render_batch(const b3d_mesh* mesh, const float* poses, int32_t N, const b3d_intrinsics* K,
                             float* xyz_out, int32_t* tri_out, void* stream);
 
+/* Device workspace (bytes) of b3d_score and b3d_score_backward for an
+ * H x W image: the observed image's valid pixels, listed once per call. */
+b3d_status b3d_score_workspace_size(int32_t H, int32_t W, size_t* bytes);
+
 /* Windowed robust likelihood (eq. (1) with the window of Sec. III-B).
  * observed: device float[H][W][3]; rendered: device float[N][H][W][3];
- * logL_out: device float[N].  Stream-ordered. */
+ * logL_out: device float[N].  workspace: device memory of at least
+ * b3d_score_workspace_size bytes, 16-byte aligned, owned by the caller
+ * (contents undefined on return), or NULL: the same result from a kernel
+ * that reads every observed pixel per hypothesis (slower).  A workspace
+ * smaller than required is refused (B3D_ESHAPE) before any launch.
+ * Stream-ordered. */
 b3d_status b3d_score(const float* observed, const float* rendered, int32_t N, int32_t H, int32_t W,
-                     const b3d_score_params* p, float* logL_out, void* stream);
+                     const b3d_score_params* p, float* logL_out, void* workspace, size_t ws_bytes, void* stream);
 
 /* Adjoint of b3d_score.  With a = p_out/V, b = (1-p_out)/M, K_ij =
  * N3(q~_i; q_j, sigma), D_ij = |q~_i - q_j|^2, S_i = sum_j K_ij and
@@ -137,10 +146,11 @@ b3d_status b3d_score(const float* observed, const float* rendered, int32_t N, in
  *   d_pout[n]        = g sum_i (1/V - S_i/M)/L_i
  * dlogL: device float[N] or NULL (= all ones).  d_rendered: device
  * float[N][H][W][3] (every element written) or NULL; d_sigma, d_pout:
- * device float[N] or NULL.  Stream-ordered. */
+ * device float[N] or NULL.  workspace, ws_bytes: as for b3d_score.
+ * Stream-ordered. */
 b3d_status b3d_score_backward(const float* observed, const float* rendered, int32_t N, int32_t H, int32_t W,
                               const b3d_score_params* p, const float* dlogL, float* d_rendered, float* d_sigma,
-                              float* d_pout, void* stream);
+                              float* d_pout, void* workspace, size_t ws_bytes, void* stream);
 
 /* Pose adjoint of the render with visibility held fixed: the triangle of
  * each pixel (tri) is kept and its depth z = (n.c0)/(n.d) is differentiated

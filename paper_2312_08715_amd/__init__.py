@@ -95,9 +95,10 @@ _SIGNATURES = {
     "b3d_mesh_info": ([_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)], ctypes.c_int),
     "b3d_unproject": ([_P, _I32, ctypes.POINTER(Intrinsics), _P, _P], ctypes.c_int),
     "b3d_render_batch": ([_P, _P, _I32, ctypes.POINTER(Intrinsics), _P, _P, _P], ctypes.c_int),
-    "b3d_score": ([_P, _P, _I32, _I32, _I32, ctypes.POINTER(ScoreParams), _P, _P], ctypes.c_int),
-    "b3d_score_backward": ([_P, _P, _I32, _I32, _I32, ctypes.POINTER(ScoreParams), _P, _P, _P, _P, _P],
-                           ctypes.c_int),
+    "b3d_score_workspace_size": ([_I32, _I32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "b3d_score": ([_P, _P, _I32, _I32, _I32, ctypes.POINTER(ScoreParams), _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "b3d_score_backward": ([_P, _P, _I32, _I32, _I32, ctypes.POINTER(ScoreParams), _P, _P, _P, _P, _P,
+                            ctypes.c_size_t, _P], ctypes.c_int),
     "b3d_render_backward": ([_P, _P, _I32, ctypes.POINTER(Intrinsics), _P, _P, _P, _P], ctypes.c_int),
     "b3d_scene_create": ([_P, ctypes.POINTER(Intrinsics), ctypes.POINTER(ScoreParams), ctypes.POINTER(_P)],
                          ctypes.c_int),
@@ -264,22 +265,39 @@ def render_batch(mesh: Mesh, poses: torch.Tensor, K: Intrinsics, want_tri: bool 
     return xyz, tri
 
 
-def score(observed: torch.Tensor, rendered: torch.Tensor, p: ScoreParams) -> torch.Tensor:
+_score_ws = {}
+
+
+def score_workspace(H: int, W: int, device) -> torch.Tensor:
+    """The split-path score's workspace for an H x W image (one per device and size, reused)."""
+    key = (H, W, str(device))
+    if key not in _score_ws:
+        nb = ctypes.c_size_t()
+        _call("b3d_score_workspace_size", int(H), int(W), ctypes.byref(nb))
+        _score_ws[key] = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+    return _score_ws[key]
+
+
+def score(observed: torch.Tensor, rendered: torch.Tensor, p: ScoreParams, workspace: bool = True) -> torch.Tensor:
+    """logL [N] of point images [N,H,W,3] (workspace=False: the kernel without the valid-pixel list)."""
     N, H, W = rendered.shape[0], rendered.shape[1], rendered.shape[2]
     out = torch.empty(N, dtype=torch.float32, device=rendered.device)
+    ws = score_workspace(H, W, rendered.device) if workspace else None
     _call("b3d_score", _ptr(observed, torch.float32), _ptr(rendered, torch.float32), N, H, W, ctypes.byref(p),
-          _ptr(out), _stream())
+          _ptr(out), _ptr(ws), 0 if ws is None else ws.numel(), _stream())
     return out
 
 
-def score_backward(observed, rendered, p: ScoreParams, dlogL=None, want_rendered=True):
+def score_backward(observed, rendered, p: ScoreParams, dlogL=None, want_rendered=True, workspace: bool = True):
     N, H, W = rendered.shape[0], rendered.shape[1], rendered.shape[2]
     dev = rendered.device
     dr = torch.empty_like(rendered) if want_rendered else None
     ds = torch.empty(N, dtype=torch.float32, device=dev)
     dp = torch.empty(N, dtype=torch.float32, device=dev)
+    ws = score_workspace(H, W, dev) if workspace else None
     _call("b3d_score_backward", _ptr(observed, torch.float32), _ptr(rendered, torch.float32), N, H, W,
-          ctypes.byref(p), _ptr(dlogL, torch.float32), _ptr(dr), _ptr(ds), _ptr(dp), _stream())
+          ctypes.byref(p), _ptr(dlogL, torch.float32), _ptr(dr), _ptr(ds), _ptr(dp), _ptr(ws),
+          0 if ws is None else ws.numel(), _stream())
     return dr, ds, dp
 
 

@@ -327,13 +327,16 @@ b3d_status b3d_render_batch(const b3d_mesh* mesh, const float* poses, int32_t N,
   if (N < 0) return fail(B3D_ESHAPE, "render_batch: N < 0");
   if (N == 0) return B3D_OK;
   if (!poses || !xyz_out) return fail(B3D_EINVAL, "render_batch: NULL pointer");
-  const int zcap = std::max(4096, K->W);
+  // a depth buffer of 2048 keys (or one image row) leaves room for five workgroups per CU
+  const int zcap = std::max(2048, K->W);
   if (kRasterLdsBytes + 8 * (size_t)zcap > kLdsMax)
     return fail(B3D_ESHAPE, "render_batch: image too wide for the LDS depth buffer");
   B3D_CHECK_HIP(launch_render_batch(mesh->dev, make_cam(K), poses, N, xyz_out, tri_out, zcap, (hipStream_t)stream),
                 "render_batch");
   return B3D_OK;
 }
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 static int score_cap(int W, int h, int planes, int halo_rows, int want) {
   // floats of LDS for staged rows: at least one output row plus halo
@@ -342,13 +345,28 @@ static int score_cap(int W, int h, int planes, int halo_rows, int want) {
   return std::max(need, want);
 }
 
+b3d_status b3d_score_workspace_size(int32_t H, int32_t W, size_t* bytes) {
+  if (!bytes) return fail(B3D_EINVAL, "score_workspace_size: NULL output");
+  if (H < 1 || W < 1 || H > kMaxImage || W > kMaxImage) return fail(B3D_ESHAPE, "score_workspace_size: bad H or W");
+  *bytes = score_workspace_bytes(H, W);
+  return B3D_OK;
+}
+
 b3d_status b3d_score(const float* observed, const float* rendered, int32_t N, int32_t H, int32_t W,
-                     const b3d_score_params* p, float* logL_out, void* stream) {
+                     const b3d_score_params* p, float* logL_out, void* workspace, size_t ws_bytes, void* stream) {
   if (N < 0 || H < 1 || W < 1 || H > kMaxImage || W > kMaxImage) return fail(B3D_ESHAPE, "score: bad N, H or W");
   ScoreConsts sc;
   if (b3d_status s = make_consts(p, H, W, &sc)) return s;
   if (N == 0) return B3D_OK;
   if (!observed || !rendered || !logL_out) return fail(B3D_EINVAL, "score: NULL pointer");
+  if (workspace && ws_bytes < score_workspace_bytes(H, W))
+    return fail(B3D_ESHAPE, "score: workspace of %zu bytes < %zu", ws_bytes, score_workspace_bytes(H, W));
+  const int R = score_ring_rows(H, W, sc.h);
+  if (workspace && R > 0 && aligned16(rendered) && aligned16(workspace)) {
+    B3D_CHECK_HIP(launch_score_ring(observed, rendered, N, H, W, sc, R, workspace, logL_out, (hipStream_t)stream),
+                  "score");
+    return B3D_OK;
+  }
   const int cap = score_cap(W, sc.h, 3, 2, 10240 - 64);  // four workgroups per CU
   if (cap < 0) return fail(B3D_ESHAPE, "score: image too wide for the LDS row buffer");
   B3D_CHECK_HIP(launch_score(observed, rendered, N, H, W, sc, logL_out, cap, (hipStream_t)stream), "score");
@@ -357,7 +375,7 @@ b3d_status b3d_score(const float* observed, const float* rendered, int32_t N, in
 
 b3d_status b3d_score_backward(const float* observed, const float* rendered, int32_t N, int32_t H, int32_t W,
                               const b3d_score_params* p, const float* dlogL, float* d_rendered, float* d_sigma,
-                              float* d_pout, void* stream) {
+                              float* d_pout, void* workspace, size_t ws_bytes, void* stream) {
   if (N < 0 || H < 1 || W < 1 || H > kMaxImage || W > kMaxImage)
     return fail(B3D_ESHAPE, "score_backward: bad N, H or W");
   ScoreConsts sc;
@@ -365,6 +383,15 @@ b3d_status b3d_score_backward(const float* observed, const float* rendered, int3
   if (N == 0) return B3D_OK;
   if (!observed || !rendered) return fail(B3D_EINVAL, "score_backward: NULL pointer");
   if (!d_rendered && !d_sigma && !d_pout) return B3D_OK;
+  if (workspace && ws_bytes < score_workspace_bytes(H, W))
+    return fail(B3D_ESHAPE, "score_backward: workspace of %zu bytes < %zu", ws_bytes, score_workspace_bytes(H, W));
+  const int R = score_backward_ring_rows(H, W, sc.h);
+  if (workspace && R > 0 && aligned16(rendered) && aligned16(d_rendered) && aligned16(workspace)) {
+    B3D_CHECK_HIP(launch_score_backward_ring(observed, rendered, N, H, W, sc, R, workspace, dlogL, d_rendered, d_sigma,
+                                             d_pout, (hipStream_t)stream),
+                  "score_backward");
+    return B3D_OK;
+  }
   const int cap = score_cap(W, sc.h, 4, 4, 16384 - 64);
   if (cap < 0) return fail(B3D_ESHAPE, "score_backward: image too wide for the LDS row buffer");
   B3D_CHECK_HIP(launch_score_backward(observed, rendered, N, H, W, sc, dlogL, d_rendered, d_sigma, d_pout, cap,

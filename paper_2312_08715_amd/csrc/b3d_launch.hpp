@@ -192,6 +192,19 @@ hipError_t launch_render_batch(const MeshDev& m, const Cam& cam, const float* po
 hipError_t launch_unproject(const float* depth, int B, const Cam& cam, float* xyz, hipStream_t st);
 hipError_t launch_render_backward(const MeshDev& m, const Cam& cam, const float* poses, int N, const int* tri,
                                   const float* d_rend, float* d_pose, hipStream_t st);
+// Split-path likelihood over a ring of rows (one pass over each point
+// image), the observed image's valid pixels listed first in a workspace of
+// score_workspace_bytes: rows per step for an H x W image and window
+// half-width h, 0 when the ring does not apply (W not a multiple of 4, or
+// the rows do not fit).
+int score_ring_rows(int H, int W, int h);
+int score_backward_ring_rows(int H, int W, int h);
+size_t score_workspace_bytes(int H, int W);
+hipError_t launch_score_ring(const float* obs, const float* rend, int N, int H, int W, const ScoreConsts& sc, int R,
+                             void* workspace, float* logL, hipStream_t st);
+hipError_t launch_score_backward_ring(const float* obs, const float* rend, int N, int H, int W, const ScoreConsts& sc,
+                                      int R, void* workspace, const float* dlogL, float* d_rend, float* d_sigma,
+                                      float* d_pout, hipStream_t st);
 hipError_t launch_score(const float* obs, const float* rend, int N, int H, int W, const ScoreConsts& sc, float* logL,
                         int cap, hipStream_t st);
 hipError_t launch_score_backward(const float* obs, const float* rend, int N, int H, int W, const ScoreConsts& sc,

@@ -42,8 +42,52 @@ __device__ __forceinline__ void write_rows(const Cam& cam, int y0, int y1, const
   }
 }
 
+// write_rows for W a multiple of 4: each thread writes four pixels at a time
+// (three 16-byte words of points, one of ids), so every store is a whole
+// 16-byte word of a contiguous row span.
+__device__ __forceinline__ void write_rows4(const Cam& cam, int y0, int y1, const Rect& band,
+                                            const unsigned long long* zbuf, uint32_t id_base, float* __restrict__ xyz,
+                                            int* __restrict__ tri) {
+  const int W = cam.W, qpr = W / 4;  // pixel quads per row
+  const int nq = (y1 - y0) * qpr;
+  float4* xo = reinterpret_cast<float4*>(xyz + (size_t)y0 * W * 3);
+  int4* to = tri ? reinterpret_cast<int4*>(tri + (size_t)y0 * W) : nullptr;
+  const bool rows_in = y0 < band.y1 && y1 > band.y0 && !band.empty();
+  for (int q = threadIdx.x; q < nq; q += kBlock) {
+    const int dr = q / qpr;
+    const int r = y0 + dr, c0 = 4 * (q - dr * qpr);
+    float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    int id[4] = {-1, -1, -1, -1};
+    if (rows_in && r >= band.y0 && r < band.y1 && c0 + 4 > band.x0 && c0 < band.x1) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + u;
+        if (c >= band.x0 && c < band.x1) {
+          const unsigned long long k = zbuf[(r - band.y0) * band.w() + (c - band.x0)];
+          if (k != kEmptyKey) {
+            z[u] = key_depth(k);
+            id[u] = (int)(key_id(k) - id_base);
+          }
+        }
+      }
+    }
+    const float ry = ray_y(cam, r);
+    float x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[u] = z[u] * ray_x(cam, c0 + u);
+      y[u] = z[u] * ry;
+    }
+    xo[3 * q + 0] = make_float4(x[0], y[0], z[0], x[1]);
+    xo[3 * q + 1] = make_float4(y[1], z[1], x[2], y[2]);
+    xo[3 * q + 2] = make_float4(z[2], x[3], y[3], z[3]);
+    if (to) to[q] = make_int4(id[0], id[1], id[2], id[3]);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_render_batch(MeshDev m, Cam cam, const float* __restrict__ poses, int N,
-                                                         float* __restrict__ xyz, int* __restrict__ tri, int zcap) {
+                                                         float* __restrict__ xyz, int* __restrict__ tri, int zcap,
+                                                         int vec) {
   extern __shared__ __align__(16) unsigned char smem[];
   const RasterLds rl = carve_raster_lds(smem);
   unsigned long long* zbuf = reinterpret_cast<unsigned long long*>(smem + kRasterLdsBytes);
@@ -51,17 +95,16 @@ __global__ __launch_bounds__(kBlock) void k_render_batch(MeshDev m, Cam cam, con
   if (n >= N) return;
   const Pose P = load_pose(poses + 16 * (size_t)n);
   const int H = cam.H, W = cam.W;
+#define WRITE_ROWS(...) (vec ? write_rows4(__VA_ARGS__) : write_rows(__VA_ARGS__))
   float* xn = xyz + (size_t)n * H * W * 3;
   int* tn = tri ? tri + (size_t)n * H * W : nullptr;
   const Rect obj = object_rect(m, P, cam);
   Rect none;
   none.x0 = none.x1 = none.y0 = none.y1 = 0;
   if (obj.empty()) {
-    write_rows(cam, 0, H, none, zbuf, 0, xn, tn);
+    WRITE_ROWS(cam, 0, H, none, zbuf, 0, xn, tn);
     return;
   }
-  write_rows(cam, 0, obj.y0, none, zbuf, 0, xn, tn);
-  write_rows(cam, obj.y1, H, none, zbuf, 0, xn, tn);
   const int band_rows = max(zcap / obj.w(), 1);
   for (int a = obj.y0; a < obj.y1; a += band_rows) {
     Rect band = obj;
@@ -72,15 +115,23 @@ __global__ __launch_bounds__(kBlock) void k_render_batch(MeshDev m, Cam cam, con
     __syncthreads();
     raster_mesh_any(m, P, cam, 0u, band, band, zbuf, rl);
     refine_depths(m, P, cam, 0u, band, zbuf);
-    write_rows(cam, band.y0, band.y1, band, zbuf, 0u, xn, tn);
+    WRITE_ROWS(cam, band.y0, band.y1, band, zbuf, 0u, xn, tn);
     __syncthreads();
   }
+  // the rows the object does not reach, last: their stores drain while the
+  // next workgroup on this CU rasterises (a barrier waits for every store
+  // issued before it)
+  WRITE_ROWS(cam, 0, obj.y0, none, zbuf, 0, xn, tn);
+  WRITE_ROWS(cam, obj.y1, H, none, zbuf, 0, xn, tn);
 }
+#undef WRITE_ROWS
 
 hipError_t launch_render_batch(const MeshDev& m, const Cam& cam, const float* poses, int N, float* xyz, int* tri,
                                int zcap, hipStream_t st) {
   const size_t lds = kRasterLdsBytes + sizeof(unsigned long long) * (size_t)zcap;
-  hipLaunchKernelGGL(k_render_batch, dim3(N), dim3(kBlock), lds, st, m, cam, poses, N, xyz, tri, zcap);
+  // quads of pixels as whole 16-byte words: rows of W % 4 == 0 pixels in 16-byte aligned buffers
+  const int vec = (cam.W % 4 == 0) && ((uintptr_t)xyz & 15) == 0 && ((uintptr_t)tri & 15) == 0;
+  hipLaunchKernelGGL(k_render_batch, dim3(N), dim3(kBlock), lds, st, m, cam, poses, N, xyz, tri, zcap, vec);
   return hipGetLastError();
 }
 

@@ -51,20 +51,46 @@ def test_library_exports_every_declared_symbol(lib):
     assert plib.b3d_probe_fma(None, 1, 1, None) == -1  # argument errors before any launch
 
 
+def declared_arity(header=HEADER):
+    """Number of parameters of each function the header declares."""
+    src = re.sub(r"/\*.*?\*/", "", open(header).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"^\s*(?:const\s+)?\w+\**\s+\**(b3d_\w+)\s*\(([^)]*)\)\s*;", src, flags=re.M):
+        params = m.group(2).strip()
+        out[m.group(1)] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_signatures_match_the_header(lib):
+    # every function the Python binding declares takes as many arguments as
+    # the C declaration (a mismatch would only show as a ctypes error on a GPU)
+    import paper_2312_08715_amd as b
+
+    arity = declared_arity()
+    assert set(b._SIGNATURES) <= set(arity), sorted(set(b._SIGNATURES) - set(arity))
+    bad = {n: (len(args), arity[n]) for n, (args, _) in b._SIGNATURES.items() if len(args) != arity[n]}
+    assert not bad, bad
+
+
 def test_host_side_validation_without_a_device(lib):
     import paper_2312_08715_amd as b
 
     assert b.version().startswith("b3d")
     bad = b.score_params(0.003, 0.0, 1.0, 5)
-    rc = lib.b3d_score(None, None, 4, 10, 10, ctypes.byref(bad), None, None)
+    rc = lib.b3d_score(None, None, 4, 10, 10, ctypes.byref(bad), None, None, 0, None)
     assert rc == -1 and b"p_out" in lib.b3d_last_error()
     even = b.score_params(0.003, 0.1, 1.0, 4)
-    assert lib.b3d_score(None, None, 4, 10, 10, ctypes.byref(even), None, None) == -1
+    assert lib.b3d_score(None, None, 4, 10, 10, ctypes.byref(even), None, None, 0, None) == -1
     neg = b.score_params(-1.0, 0.1, 1.0, 3)
-    assert lib.b3d_score(None, None, 4, 10, 10, ctypes.byref(neg), None, None) == -1
+    assert lib.b3d_score(None, None, 4, 10, 10, ctypes.byref(neg), None, None, 0, None) == -1
     ok = b.score_params(0.003, 0.1, 1.0, 3)
-    assert lib.b3d_score(None, None, 0, 10, 10, ctypes.byref(ok), None, None) == 0  # N = 0: no-op
-    assert lib.b3d_score(None, None, 3, 10, 10, ctypes.byref(ok), None, None) == -1  # NULL buffers
+    assert lib.b3d_score(None, None, 0, 10, 10, ctypes.byref(ok), None, None, 0, None) == 0  # N = 0: no-op
+    assert lib.b3d_score(None, None, 3, 10, 10, ctypes.byref(ok), None, None, 0, None) == -1  # NULL buffers
+    # a workspace smaller than b3d_score_workspace_size is refused before any launch
+    nb = ctypes.c_size_t()
+    assert lib.b3d_score_workspace_size(10, 12, ctypes.byref(nb)) == 0 and nb.value >= 10 * 12 * 16
+    fake = ctypes.c_void_p(16)
+    assert lib.b3d_score(fake, fake, 3, 10, 12, ctypes.byref(ok), fake, fake, nb.value - 1, None) == -4
     K = b.intrinsics(100, 100, 50, 40, 80, 100)
     assert lib.b3d_render_batch(None, None, 3, ctypes.byref(K), None, None, None) == -1
     Kbad = b.intrinsics(100, 100, 50, 40, 0, 100)

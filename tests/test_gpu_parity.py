@@ -110,8 +110,11 @@ def test_score_matches_oracle_on_identical_point_images(b3d, k):
     p = b3d.score_params(s.sigma, s.p_out, s.outlier_volume, s.window)
     Lg = b3d.score(dev(obs), dev(rend), p).cpu().numpy().astype(np.float64)
     err = np.abs(Lg - L64) / l1
-    say(f"  max rel-L1 error {err.max():.3g}")
-    assert err.max() <= LOGL_RTOL
+    # the kernel without the workspace's valid-pixel list (taken when W is not a multiple of 4)
+    Lp = b3d.score(dev(obs), dev(rend), p, workspace=False).cpu().numpy().astype(np.float64)
+    errp = np.abs(Lp - L64) / l1
+    say(f"  max rel-L1 error {err.max():.3g} (without the workspace {errp.max():.3g})")
+    assert err.max() <= LOGL_RTOL and errp.max() <= LOGL_RTOL
 
 
 def _scene(b3d, wl, obs, mesh=None):
@@ -253,13 +256,14 @@ def test_score_backward_matches_oracle(b3d):
     dl = f32(np.random.default_rng(3).normal(1.0, 0.5, len(sel)))
     dr64, ds64, dp64 = oracle.score_grad(obs, rend, s.sigma, s.p_out, s.outlier_volume, s.window, dlogL=dl)
     p = b3d.score_params(s.sigma, s.p_out, s.outlier_volume, s.window)
-    dr, ds, dp = b3d.score_backward(dev(obs), dev(rend), p, dlogL=dev(dl))
-    dr, ds, dp = dr.cpu().numpy(), ds.cpu().numpy(), dp.cpu().numpy()
-    for n in range(len(sel)):
-        e = np.linalg.norm(dr[n] - dr64[n])
-        assert e <= 1e-3 * np.linalg.norm(dr64[n]) + 1e-6, (n, e)
-    np.testing.assert_allclose(ds, ds64, rtol=1e-3, atol=1e-3 * np.abs(ds64).max())
-    np.testing.assert_allclose(dp, dp64, rtol=1e-4)
+    for ws in (True, False):  # with the workspace's valid-pixel list, and without
+        dr, ds, dp = b3d.score_backward(dev(obs), dev(rend), p, dlogL=dev(dl), workspace=ws)
+        dr, ds, dp = dr.cpu().numpy(), ds.cpu().numpy(), dp.cpu().numpy()
+        for n in range(len(sel)):
+            e = np.linalg.norm(dr[n] - dr64[n])
+            assert e <= 1e-3 * np.linalg.norm(dr64[n]) + 1e-6, (n, e)
+        np.testing.assert_allclose(ds, ds64, rtol=1e-3, atol=1e-3 * np.abs(ds64).max())
+        np.testing.assert_allclose(dp, dp64, rtol=1e-4)
 
 
 def test_render_backward_matches_oracle(b3d):
