@@ -257,10 +257,12 @@ def bench_smc(b3d, torch, p=None, n_particles=16, reps=2, seed=4242, stage_noise
                     "particle hypotheses), noise cells over the whole image, eq. (2)/(3) weights, resampling"}
 
 
-def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3, tune=True):
+def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3, tune=True, size=None, n_hyp=None):
     """Many scenes (1-8 objects of 500-8000 voxels, three image sizes, 1k-20k
     hypotheses each) in one persistent launch, forward + adjoint, against the
-    same scenes one launch at a time; depth-buffer tiles from the autotuner."""
+    same scenes one launch at a time; depth-buffer tiles from the autotuner.
+    size, n_hyp: one image size (H, W) and hypothesis count for every scene
+    instead of the drawn ones."""
     import tempfile
 
     from workloads import Camera, observation_noise, pose_matrix, random_scene_batch, shoemake_rotations, voxel_blob, \
@@ -271,6 +273,10 @@ def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3, tune=True):
     items, keep = [], []
     for i, sh in enumerate(random_scene_batch(rng, n_scenes)):
         H, W = sh["H"], sh["W"]
+        if size is not None:
+            H, W = size
+        if n_hyp is not None:
+            sh["N"] = n_hyp
         cam = Camera(W * 0.9375, W * 0.9375, W / 2.0, H / 2.0, H, W)
         objs = []
         for k, nv in enumerate(sh["voxels"]):
@@ -285,8 +291,10 @@ def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3, tune=True):
         if len(objs) > 1:
             scene.set_background(meshes[1:], np.stack([P for _, _, P in objs[1:]]))
         scene.set_observed(obs)
+        # 10 x ny x nz translations over +-2 cm x 10 rotations within 10 degrees
         nz = max(1, int(round(sh["N"] / 1000.0)))
-        grid = b3d.make_grid(objs[0][2], (0.02, 0.02, 0.02), (10, 10, nz), n_rot=10, rot_max_angle=np.deg2rad(10.0))
+        ny = 10 if sh["N"] >= 1000 else max(1, sh["N"] // 100)
+        grid = b3d.make_grid(objs[0][2], (0.02, 0.02, 0.02), (10, ny, nz), n_rot=10, rot_max_angle=np.deg2rad(10.0))
         P = b3d.enumerate_grid(grid, seed=3003 + i)
         if tune:  # the tile of each shape class (image size, window, mesh size), timed once
             scene.autotune(P[:2048], grad=True, cache=tile_cache)
@@ -310,9 +318,19 @@ def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3, tune=True):
             b3d.render_score(sc, P, grad=True)
     torch.cuda.synchronize()
     t_seq = (time.perf_counter() - t0) / reps
+    # VALU roofline of the batch: every scene's work as the instrumented kernel
+    # counts it (culled), priced by the cost table, over the batch's time
+    ops = 0.0
+    for sc, P in items:
+        ops += lane_ops(counted_work(b3d, sc, P), adjoint=True)
+    achieved = ops / t_batch / 1e12
     return {"scenes": n_scenes, "hypotheses": total, "value": total / t_batch, "ms": t_batch * 1e3,
             "one_at_a_time": {"value": total / t_seq, "ms": t_seq * 1e3}, "unit": "hypotheses/s",
             "tiles": "autotuned per shape class" if tune else "default",
+            "roofline": {"bound": "alu", "kernel": "k_batch<true>", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                         "unit": "TOP/s (FP32 lane-ops)", "frac": achieved / VALU_PEAK_TOPS,
+                         "counting": "kernel's own count (instrumented launch per scene) x cost table",
+                         "traffic": None},
             "note": "forward + adjoint; one persistent launch vs one launch per scene"}
 
 
@@ -355,11 +373,26 @@ def bench_tracking(b3d, torch, p, n_frames=200):
     rot = np.array([[rot_err_deg(E[f, k, :3, :3], paths[f, k, :3, :3]) for k in range(M)] for f in range(1, n_frames)])
     lost = pos > 5.0
     seen = vis[1:] >= 0.5
+    def hidden_before_loss(k):
+        """The frames just before object k is first lost: the run of frames in
+        which it was under 10% visible, and how far its true pose moved then
+        (the search reaches 3 cm around the previous estimate)."""
+        if not lost[:, k].any():
+            return None
+        f1 = int(np.argmax(lost[:, k]) + 1)
+        f0 = f1
+        while f0 > 1 and vis[f0 - 1, k] < 0.1:
+            f0 -= 1
+        moved = float(np.linalg.norm(paths[f1, k, :3, 3] - paths[f0, k, :3, 3]) * 100.0)
+        return {"hidden_from": f0, "frames_hidden": f1 - f0, "true_motion_cm": moved,
+                "visibility_at_loss": float(vis[f1, k])}
+
     per_obj = [{"mean_cm": float(pos[:, k].mean()), "max_cm": float(pos[:, k].max()),
                 "frames_over_5cm": int(lost[:, k].sum()),
                 "first_over_5cm": int(np.argmax(lost[:, k]) + 1) if lost[:, k].any() else None,
                 "frames_under_half_visible": int((~seen[:, k]).sum()),
-                "least_visible": float(vis[1:, k].min())}
+                "least_visible": float(vis[1:, k].min()),
+                "before_loss": hidden_before_loss(k)}
                for k in range(M)]
     return {"frames_per_s": (n_frames - 2) / dt, "frames": n_frames, "objects": M, "per_object": per_obj,
             "hypotheses_per_frame": int(M * 12500), "position_error_cm": {"mean": float(pos.mean()),
@@ -463,9 +496,14 @@ def bench_table_c2f(b3d, torch, p):
         n_h = 10000 + 2 * 16 * 10000 + 21 * 16
         total_h += n_h
         total_t += dtm
+        # is the true pose more likely than the one found?  (if not, an error is
+        # the object's near-symmetry under this noise, not a search failure)
+        L_truth = float(b3d.render_score(scene, torch.as_tensor(np.asarray(truth, np.float32)[None],
+                                                                device="cuda"))[0])
         out.append({"object": k, "triangles": int(meshes[k][1].shape[0]), "ms": dtm * 1e3,
                     "position_error_cm": float(np.linalg.norm(best[:3, 3] - truth[:3, 3]) * 100),
-                    "orientation_error_deg": rot_err_deg(best[:3, :3], truth[:3, :3])})
+                    "orientation_error_deg": rot_err_deg(best[:3, :3], truth[:3, :3]),
+                    "logL_found_minus_truth": float(L.max()) - L_truth})
     return {"hypotheses_per_s": total_h / total_t, "objects": out, "tiles": tiles,
             "note": "3 stages x 10,000 hypotheses (16 particles from stage 2), then 20 Adam steps on 16 poses; "
                     "depth-buffer tiles from the autotuner"}
@@ -600,6 +638,7 @@ def main():
         extras["noise_grid_4x4"] = bench_noise_grid(b3d, torch, scene, P)
         for name, fn in (("smc_table_scene", lambda: bench_smc(b3d, torch)),
                          ("batch_64_scenes", lambda: bench_batch(b3d, torch, p)),
+                         ("batch_64_small_scenes", lambda: bench_batch(b3d, torch, p, size=(120, 160), n_hyp=500)),
                          ("tracking_200_frames", lambda: bench_tracking(b3d, torch, p)),
                          ("camera_pan_120_frames", lambda: bench_camera_pan(b3d, torch, p)),
                          ("table_c2f_adam", lambda: bench_table_c2f(b3d, torch, p))):

@@ -281,8 +281,10 @@ __device__ __forceinline__ void rows_load(const float* __restrict__ img, int wpr
   const int nw = y1 > y0 ? (y1 - y0) * wpr : 0;
   if (nw == 0) return;
   const f4v* src = reinterpret_cast<const f4v*>(img) + (size_t)y0 * wpr;
+  const int rounds = (nw + kBlock - 1) / kBlock;  // uniform: whole rounds past the span are skipped
 #pragma unroll
-  for (int i = 0; i < PF; ++i) v[i] = src[min((int)threadIdx.x + i * kBlock, nw - 1)];
+  for (int i = 0; i < PF; ++i)
+    if (i < rounds) v[i] = src[min((int)threadIdx.x + i * kBlock, nw - 1)];
 }
 
 template <int PF>
@@ -296,8 +298,10 @@ __device__ __forceinline__ void rows_store(float* ring, int nrows, int wpr, int 
   int ro = (int)threadIdx.x / wpr;
   int col = (int)threadIdx.x - ro * wpr;
   int slot = (y0 + ro) % nrows;
+  const int rounds = (nw + kBlock - 1) / kBlock;
 #pragma unroll
   for (int i = 0; i < PF; ++i) {
+    if (i >= rounds) break;
     if ((int)threadIdx.x + i * kBlock < nw) dst[slot * wpr + col] = v[i];
     col += dm;
     int carry = dq;
@@ -503,12 +507,15 @@ hipError_t launch_obs_list(const float* obs, int H, int W, void* workspace, hipS
 template <int PP>
 __device__ __forceinline__ void entries_load(const float4* __restrict__ list, int e0, int e1, f4v (&v)[PP]) {
   const f4v* src = reinterpret_cast<const f4v*>(list);
+  const int rounds = (e1 - e0 + kBlock - 1) / kBlock;  // uniform
 #pragma unroll
   for (int i = 0; i < PP; ++i) {
-    const int e = e0 + (int)threadIdx.x + i * kBlock;
-    f4v x = src[min(e, max(e1 - 1, 0))];
-    if (e >= e1) x.z = 0.0f;
-    v[i] = x;
+    if (i < rounds) {
+      const int e = e0 + (int)threadIdx.x + i * kBlock;
+      f4v x = src[min(e, max(e1 - 1, 0))];
+      if (e >= e1) x.z = 0.0f;
+      v[i] = x;
+    }
   }
 }
 
