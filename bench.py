@@ -259,8 +259,9 @@ def bench_smc(b3d, torch, p=None, n_particles=16, reps=2, seed=4242, stage_noise
 
 def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3, tune=True, size=None, n_hyp=None):
     """Many scenes (1-8 objects of 500-8000 voxels, three image sizes, 1k-20k
-    hypotheses each) in one persistent launch, forward + adjoint, against the
-    same scenes one launch at a time; depth-buffer tiles from the autotuner.
+    hypotheses each) as one batch (b3d_batch_run), forward + adjoint, against
+    the same scenes one launch at a time; depth-buffer tiles from the
+    autotuner.
     size, n_hyp: one image size (H, W) and hypothesis count for every scene
     instead of the drawn ones."""
     import tempfile
@@ -331,10 +332,11 @@ def bench_batch(b3d, torch, p, n_scenes=64, seed=1003, reps=3, tune=True, size=N
                          "unit": "TOP/s (FP32 lane-ops)", "frac": achieved / VALU_PEAK_TOPS,
                          "counting": "kernel's own count (instrumented launch per scene) x cost table",
                          "traffic": None},
-            "note": "forward + adjoint; one persistent launch vs one launch per scene"}
+            "note": "forward + adjoint; launches of eight scenes, one workgroup per hypothesis, on two streams, "
+                    "vs one launch per scene"}
 
 
-def bench_tracking(b3d, torch, p, n_frames=200):
+def bench_tracking(b3d, torch, p, n_frames=200, min_visible=0.0, widen=1.0):
     """Three objects on smooth SE(3) paths, 160x120, 4% outliers; per frame and
     object two stages of hypotheses (10,000 over +-3 cm x 10 rotations within
     8 deg, then 2,500 over +-7.5 mm x 20 rotations within 3 deg around the best)
@@ -356,19 +358,24 @@ def bench_tracking(b3d, torch, p, n_frames=200):
     ms = [b3d.Mesh(v, t) for v, t in meshes]
     stages = [b3d.make_grid(np.eye(4), (0.03, 0.03, 0.03), (10, 10, 10), n_rot=10, rot_max_angle=np.deg2rad(8.0)),
               b3d.make_grid(np.eye(4), (0.0075, 0.0075, 0.0075), (5, 5, 5), n_rot=20, rot_max_angle=np.deg2rad(3.0))]
-    tr = b3d.Tracker(ms, b3d.intrinsics_of(cam), p, stages, paths[0], n_refine=10, lr_t=1e-3, lr_r=1e-2)
+    tr = b3d.Tracker(ms, b3d.intrinsics_of(cam), p, stages, paths[0], n_refine=10, lr_t=1e-3, lr_r=1e-2,
+                     min_visible=min_visible, widen=widen)
     est = torch.empty((n_frames, M, 4, 4), dtype=torch.float32, device="cuda")
+    gst = torch.zeros((n_frames, M, 3), dtype=torch.float32, device="cuda")
     est[0] = torch.as_tensor(paths[0], dtype=torch.float32)
     tr.frame(frames[1])  # captures the frame graph
     est[1] = tr.poses()
+    gst[1] = tr.state()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for f in range(2, n_frames):
         tr.frame(frames[f])
         est[f] = tr.poses()
+        gst[f] = tr.state()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     E = est.cpu().numpy().astype(np.float64)
+    G = gst.cpu().numpy()
     pos = np.linalg.norm(E[1:, :, :3, 3] - paths[1:, :, :3, 3], axis=2) * 100.0
     rot = np.array([[rot_err_deg(E[f, k, :3, :3], paths[f, k, :3, :3]) for k in range(M)] for f in range(1, n_frames)])
     lost = pos > 5.0
@@ -392,7 +399,8 @@ def bench_tracking(b3d, torch, p, n_frames=200):
                 "first_over_5cm": int(np.argmax(lost[:, k]) + 1) if lost[:, k].any() else None,
                 "frames_under_half_visible": int((~seen[:, k]).sum()),
                 "least_visible": float(vis[1:, k].min()),
-                "before_loss": hidden_before_loss(k)}
+                "before_loss": hidden_before_loss(k),
+                "updates_dropped": int((G[1:, k, 1] > 0).sum())}
                for k in range(M)]
     return {"frames_per_s": (n_frames - 2) / dt, "frames": n_frames, "objects": M, "per_object": per_obj,
             "hypotheses_per_frame": int(M * 12500), "position_error_cm": {"mean": float(pos.mean()),
@@ -402,7 +410,10 @@ def bench_tracking(b3d, torch, p, n_frames=200):
                                                                   "median": float(np.median(pos[seen]))},
                                            "orientation_error_deg": {"mean": float(rot[seen].mean()),
                                                                      "median": float(np.median(rot[seen]))}},
-            "note": "objects pass behind each other; an object hidden for several frames is lost by the local search"}
+            "min_visible": min_visible, "widen": widen,
+            "note": "objects pass behind each other; an object hidden for several frames is lost by the local search"
+                    + ("" if min_visible <= 0 else "; occlusion handling: updates less than min_visible seen are "
+                       "dropped for the last motion, the next first stage widened")}
 
 
 def bench_camera_pan(b3d, torch, p, resolutions=(25, 50, 100, 200), n_frames=120):
@@ -449,10 +460,15 @@ def bench_camera_pan(b3d, torch, p, resolutions=(25, 50, 100, 200), n_frames=120
             "by_resolution": out}
 
 
-def bench_table_c2f(b3d, torch, p):
+TABLE_STAGES = [((0.08, 0.08, 0.08), (10, 10, 10), 10, 30.0), ((0.02, 0.02, 0.02), (10, 10, 10), 10, 10.0),
+                ((0.005, 0.005, 0.005), (10, 10, 10), 10, 3.0)]
+
+
+def bench_table_c2f(b3d, torch, p, stages=None):
     """Four objects on a table at 320x240: per object three coarse-to-fine
     stages of 10,000 hypotheses for 16 particles, then 20 Adam steps on the
-    survivors with the adjoint."""
+    survivors with the adjoint.  stages: (half extents, translation counts,
+    rotations, rotation cone in degrees) per stage."""
     from workloads import shoemake_rotations, table_scene
 
     meshes, poses, table, cam, noise, Tcw = table_scene()
@@ -461,9 +477,9 @@ def bench_table_c2f(b3d, torch, p):
     ms = [b3d.Mesh(v, t) for v, t, _ in objs]
     K = b3d.intrinsics_of(cam)
     rng = np.random.default_rng(2002)
-    stages = [((0.08, 0.08, 0.08), 30.0), ((0.02, 0.02, 0.02), 10.0), ((0.005, 0.005, 0.005), 3.0)]
-    sched = b3d.make_schedule([b3d.make_grid(np.eye(4), h, (10, 10, 10), n_rot=10, rot_max_angle=np.deg2rad(a))
-                               for h, a in stages])
+    stages = TABLE_STAGES if stages is None else stages
+    sched = b3d.make_schedule([b3d.make_grid(np.eye(4), h, n, n_rot=r, rot_max_angle=np.deg2rad(a))
+                               for h, n, r, a in stages])
     out, total_h, total_t, tiles = [], 0, 0.0, []
     for k in range(len(meshes)):
         scene = b3d.Scene(ms[k], K, p)
@@ -483,7 +499,8 @@ def bench_table_c2f(b3d, torch, p):
         start[:3, :3] = dR @ truth[:3, :3]
         start[:3, 3] += dt
         # the depth-buffer tile from the autotuner, on the first stage's hypotheses (set-up, not timed)
-        g0 = b3d.make_grid(start, stages[0][0], (10, 10, 10), n_rot=10, rot_max_angle=np.deg2rad(stages[0][1]))
+        h0, n0, r0, a0 = stages[0]
+        g0 = b3d.make_grid(start, h0, n0, n_rot=r0, rot_max_angle=np.deg2rad(a0))
         tiles.append(scene.autotune(b3d.enumerate_grid(g0, seed=4002 + k)[:2048], grad=False))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -493,7 +510,8 @@ def bench_table_c2f(b3d, torch, p):
         torch.cuda.synchronize()
         dtm = time.perf_counter() - t0
         best = P[int(torch.argmax(L))].cpu().numpy().astype(np.float64)
-        n_h = 10000 + 2 * 16 * 10000 + 21 * 16
+        sizes = [int(np.prod(n)) * r for _, n, r, _ in stages]
+        n_h = sizes[0] + 16 * sum(sizes[1:]) + 21 * 16
         total_h += n_h
         total_t += dtm
         # is the true pose more likely than the one found?  (if not, an error is
@@ -615,7 +633,9 @@ def main():
     if not args.fused_only:
         t_split = timed(lambda: split(False), max(3, args.steps // 4), 1)
         t_split_adj = timed(lambda: split(True), max(3, args.steps // 4), 1)
-        split_kernels = split_rooflines(split_ev, N, wl.camera.H * wl.camera.W)
+        _, tri = b3d.render_batch(mesh, P, K, want_tri=True)  # the drawn pixels render_backward reads
+        split_kernels = split_rooflines(split_ev, N, wl.camera.H * wl.camera.W, int((tri >= 0).sum()))
+        del tri
     if args.copy_calibration:
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -638,8 +658,10 @@ def main():
         extras["noise_grid_4x4"] = bench_noise_grid(b3d, torch, scene, P)
         for name, fn in (("smc_table_scene", lambda: bench_smc(b3d, torch)),
                          ("batch_64_scenes", lambda: bench_batch(b3d, torch, p)),
-                         ("batch_64_small_scenes", lambda: bench_batch(b3d, torch, p, size=(120, 160), n_hyp=500)),
+                         ("batch_64_small_scenes", lambda: bench_batch(b3d, torch, p, size=(120, 160), n_hyp=1000)),
                          ("tracking_200_frames", lambda: bench_tracking(b3d, torch, p)),
+                         ("tracking_200_frames_occlusion_handling",
+                          lambda: bench_tracking(b3d, torch, p, min_visible=0.08, widen=2.0)),
                          ("camera_pan_120_frames", lambda: bench_camera_pan(b3d, torch, p)),
                          ("table_c2f_adam", lambda: bench_table_c2f(b3d, torch, p))):
             t0 = time.perf_counter()
@@ -680,24 +702,52 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-# Algorithmic HBM bytes per pixel of each split-path kernel (one hypothesis's
-# point image is H x W x 12 bytes, its triangle ids H x W x 4): render_batch
-# writes points (and ids), score reads points, score_backward reads points and
-# writes their gradient, render_backward reads ids and point gradients.
+# Algorithmic HBM bytes of each split-path kernel per pixel of every point
+# image (one hypothesis's point image is H x W x 12 bytes, its triangle ids
+# H x W x 4): render_batch writes points (and ids), score reads points,
+# score_backward reads points and writes their gradient.  render_backward
+# must read every id but only the point gradients of drawn pixels: 4 bytes a
+# pixel plus 12 per drawn pixel (counted on the launch's ids).
 SPLIT_BYTES_PER_PIXEL = {"render_batch": 12, "render_batch_ids": 16, "score": 12, "score_backward": 24,
-                         "render_backward": 16}
+                         "render_backward": 4}
+SPLIT_BYTES_PER_DRAWN = {"render_backward": 12}
+
+# HBM bytes per launch of the split kernels on this workload (5000 point
+# images of 160x120), from the same two rocprofv3 --pmc runs and copy
+# calibration as TRAFFIC (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB per
+# dispatch, mean over the run's dispatches); valid for the sources with this
+# digest only.
+SPLIT_SOURCES = ["k_render.hip", "k_score.hip", "b3d_device.hpp", "b3d_launch.hpp"]
+SPLIT_TRAFFIC = {"sources_sha256": "923f73f5623d0b85f435c894e82466e41e576a568e5c11bfab097be2d4b9c84a",
+                 "KiB": {"render_batch": [38333.0, 1126003.1], "render_batch_ids": [43717.0, 1500864.4],
+                         "score": [563816.5, 165.9], "score_backward": [565305.9, 1126020.3],
+                         "render_backward": [244256.3, 234.4]}}
 
 
-def split_rooflines(events, N, HW):
+def split_sources_digest() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in SPLIT_SOURCES:
+        with open(os.path.join(ROOT, "paper_2312_08715_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def split_rooflines(events, N, HW, drawn):
     """HBM roofline of each split-path kernel from its HIP-event times (warm-up
-    excluded), against the 8 TB/s peak."""
+    excluded), against the 8 TB/s peak; drawn: object pixels over the launch's
+    point images."""
     out = {}
+    valid = SPLIT_TRAFFIC["sources_sha256"] == split_sources_digest()
     for name, evs in events.items():
         ms = float(np.mean([a.elapsed_time(b) for a, b in evs[1:]])) if len(evs) > 1 else float("nan")
-        b = SPLIT_BYTES_PER_PIXEL[name] * HW * N
+        b = SPLIT_BYTES_PER_PIXEL[name] * HW * N + SPLIT_BYTES_PER_DRAWN.get(name, 0) * drawn
+        kib = SPLIT_TRAFFIC["KiB"].get(name)
+        traffic = (kib[0] * 2.0 + kib[1] * 1.0) * 1024.0 if valid and kib else None
         out[name] = {"bound": "hbm", "kernel": name, "achieved": b / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, "bytes": b, "kernel_ms": ms,
-                     "traffic": None}
+                     "traffic": traffic}
     return out
 
 

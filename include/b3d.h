@@ -266,7 +266,7 @@ b3d_status b3d_scene_set_tile(b3d_scene* scene, int32_t zcap);
 b3d_status b3d_render_score_work(const b3d_scene* scene, const float* poses, int32_t N, float* logL_out,
                                  float* grad_out, unsigned long long* work, void* stream);
 
-/* ---- many scenes in one persistent launch ------------------------------ */
+/* ---- many scenes in few launches ---------------------------------------- */
 
 /* One scene's share of a batch: N hypotheses of the scene's moving object. */
 typedef struct b3d_batch_item {
@@ -279,17 +279,24 @@ typedef struct b3d_batch_item {
 
 typedef struct b3d_batch b3d_batch;
 
-/* Freeze a list of scenes and their hypothesis buffers into one launch
- * plan: scenes are ordered by estimated cost per hypothesis (largest first)
- * and their hypotheses form one work list that a persistent grid of
- * workgroups drains through a device counter.  The plan copies each scene's
- * state (observed image pointer, background, parameters) at this call:
- * re-create it after changing a scene.  Scenes of different image sizes,
- * meshes and hypothesis counts may be mixed.  Allocates device memory (not
- * stream-ordered).  Results equal b3d_render_score per scene. */
+/* Freeze a list of scenes and their hypothesis buffers into a launch plan:
+ * scenes are ordered by estimated cost per hypothesis (largest first) and
+ * grouped eight to a launch of one workgroup per hypothesis, so that the
+ * launches keep the whole chip busy where one scene's hypotheses would not;
+ * each scene's depth-buffer tile is capped at the default (four workgroups
+ * per CU) so that one large tile does not lower every scene's occupancy.
+ * The plan copies each scene's state (observed image pointer, background,
+ * parameters, tile) at this call: re-create it after changing a scene.
+ * Scenes of different image sizes, meshes and hypothesis counts may be
+ * mixed.  Creates a stream and two events of its own when there is more
+ * than one launch (not stream-ordered).  Results equal b3d_render_score per
+ * scene, bit for bit. */
 b3d_status b3d_batch_create(const b3d_batch_item* items, int32_t S, b3d_batch** out);
-/* Run the plan: one counter reset and one persistent kernel.  Stream-ordered;
- * graph-capture safe. */
+/* Run the plan: the launches in order, every other one on the batch's own
+ * stream, forked from `stream` and joined back into it, so that one launch's
+ * last workgroups overlap the next launch.  Stream-ordered with respect to
+ * `stream`; graph-capture safe (the fork and join are event record/wait
+ * pairs). */
 b3d_status b3d_batch_run(const b3d_batch* batch, void* stream);
 b3d_status b3d_batch_destroy(b3d_batch* batch);
 
@@ -437,12 +444,25 @@ b3d_status b3d_refine_poses(const b3d_scene* scene, float* poses, int32_t N, int
 
 /* Per-frame tracking settings: n_stages grids of hypotheses, stage s centred
  * on the best hypothesis of stage s-1 (stage 0 on the previous estimate; the
- * grids' centers are ignored), then n_refine Adam steps on the best one. */
+ * grids' centers are ignored), then n_refine Adam steps on the best one.
+ *
+ * Occlusion handling (off when min_visible = 0), an addition to the method:
+ * after an object's update, its seen fraction is the share of the pixels it
+ * covers drawn alone at the new pose that lie in front of the other objects
+ * at their current estimates and have a valid observed point within 3 sigma
+ * of theirs among the window x window pixels around them.  Below min_visible
+ * the update is dropped: the object moves instead by its last accepted
+ * frame-to-frame motion (rotation R_new R_prev^T applied on the left,
+ * translation t_new - t_prev added; none before the first accepted frame),
+ * and the next frame's stage 0 searches translations widen times as far
+ * (same count of cells).  An accepted update restores the plain grid. */
 typedef struct b3d_track_params {
   int32_t n_stages; /* 1..B3D_MAX_STAGES */
   b3d_grid stages[B3D_MAX_STAGES];
   int32_t n_refine;
   float lr_t, lr_r, beta1, beta2, eps;
+  float min_visible; /* 0..1; 0 turns the occlusion handling off */
+  float widen;       /* >= 1: stage 0's translation half extents after a dropped update */
 } b3d_track_params;
 
 typedef struct b3d_tracker b3d_tracker;
@@ -477,6 +497,11 @@ b3d_status b3d_tracker_frame(b3d_tracker* tr, const float* observed, void* strea
 b3d_status b3d_tracker_frame_eager(b3d_tracker* tr, const float* observed, void* stream);
 /* Current estimates: device float[M][16].  Stream-ordered copy. */
 b3d_status b3d_tracker_poses(const b3d_tracker* tr, float* poses_out, void* stream);
+/* Occlusion state after the last frame, per object: state_out device
+ * float[M][3] = (seen fraction of the last update, frames in a row whose
+ * update was dropped, stage 0's translation scale for the next frame);
+ * (0, 0, 1) until a frame has run with min_visible > 0.  Stream-ordered copy. */
+b3d_status b3d_tracker_state(const b3d_tracker* tr, float* state_out, void* stream);
 b3d_status b3d_tracker_destroy(b3d_tracker* tr);
 
 /* ---- table scenes: contact placement and SMC over the objects ---------- */

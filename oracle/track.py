@@ -23,12 +23,26 @@ to it before the next stage enumerates around it (``round32``).
 scores within ``tol`` times the L1 mass of the best hypothesis are taken as
 ties: FP32 scores may order such near ties either way, so each is a correct
 outcome of the method at that precision.
+
+Occlusion handling (an addition to the method, off unless asked for): after
+object o's update, the fraction of the pixels it covers drawn alone at the
+new pose that are both in front of the other objects at their current
+estimates and have an observed point within 3 sigma of theirs in the
+likelihood's window is how much of it the observation confirms
+(``seen_fraction``).  Below a threshold the update is
+dropped: o takes its previous estimate moved by its last accepted
+frame-to-frame motion (``predict``), and the next frame's first stage
+searches translations over a wider box (``gate_update``, ``Gating``).  The
+observed depth has to take part: a hidden object's best hypothesis is often
+a wrong pose in an empty part of the image, where it is in view of the
+camera but the observation has nothing there to confirm it.
 """
 
 from __future__ import annotations
 
 import copy
-from typing import Callable, List, Sequence, Tuple
+import dataclasses
+from typing import Callable, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -44,6 +58,15 @@ def scene_objects(meshes, poses, o, P):
     """Object o at poses P [N,4,4] in front of the others at `poses`."""
     v, t = meshes[o]
     return [(v, t, P)] + [(meshes[k][0], meshes[k][1], poses[k]) for k in range(len(meshes)) if k != o]
+
+
+def scaled(spec, scale: float):
+    """The grid with its translation half extents times `scale`, each product
+    rounded to single precision as the device forms it."""
+    if scale == 1.0:
+        return spec
+    h = tuple(float(np.float32(np.float32(x) * np.float32(scale))) for x in spec.half_extent)
+    return dataclasses.replace(spec, half_extent=h)
 
 
 def stage_scores(meshes, poses, o, spec, stage, obs, cam, sp):
@@ -89,11 +112,95 @@ def refine(meshes, poses, o, obs, cam, sp, n_refine, lr_t, lr_r, beta1=0.9, beta
 
 
 def track_frame(meshes, poses, obs, cam, sp, stages, n_refine=0, lr_t=1e-3, lr_r=1e-2, beta1=0.9, beta2=0.999,
-                eps=1e-8) -> np.ndarray:
-    """All objects' poses [M,4,4] after one frame (plain argmax search, no ties followed)."""
+                eps=1e-8, gating: Optional[Gating] = None) -> np.ndarray:
+    """All objects' poses [M,4,4] after one frame (plain argmax search, no ties
+    followed); with `gating`, each update passes the occlusion decision."""
     cur = [round32(P) for P in poses]
     for o in range(len(meshes)):
-        cur[o] = search_ends(meshes, cur, o, stages, obs, cam, sp, tol=0.0, limit=1)[0]
+        prev = cur[o]
+        st = list(stages)
+        if gating is not None:
+            st[0] = scaled(st[0], gating.scale[o])
+        cur[o] = search_ends(meshes, cur, o, st, obs, cam, sp, tol=0.0, limit=1)[0]
         if n_refine > 0:
             cur[o] = refine(meshes, cur, o, obs, cam, sp, n_refine, lr_t, lr_r, beta1, beta2, eps)
+        if gating is not None:
+            seen = seen_fraction(meshes, cur, o, cam, obs, 3.0 * sp.sigma, sp.window)
+            cur[o] = round32(gate_update(gating, o, prev, cur[o], seen))
     return np.stack(cur)
+
+
+def seen_fraction(meshes, poses, o, cam, obs, tol: float, window: int = 1) -> float:
+    """Of the pixels object o covers drawn alone at poses[o], the fraction
+    that are not behind the other objects at their poses (equal depth counts
+    as in front) and that the observation confirms: some valid observed point
+    (obs [H,W,3], z = 0 invalid) among the window x window pixels centred on
+    the pixel lies within distance tol of the object's point there, as the
+    likelihood's window looks for one.  0 when o covers no pixel."""
+    v, t = meshes[o]
+    d_o = render([(v, t, round32(poses[o]))], cam)[0][0]
+    drawn = d_o > 0
+    n = int(drawn.sum())
+    if n == 0:
+        return 0.0
+    front = drawn
+    others = [(meshes[k][0], meshes[k][1], round32(poses[k])) for k in range(len(meshes)) if k != o]
+    if others:
+        d_b = render(others, cam)[0][0]
+        front = drawn & ((d_b <= 0) | (d_o <= d_b))
+    q = unproject(d_o, cam)
+    ob = np.asarray(obs, dtype=np.float64)
+    H, W = d_o.shape
+    h = window // 2
+    pad = np.zeros((H + 2 * h, W + 2 * h, 3))
+    pad[h:h + H, h:h + W] = ob
+    seen = np.zeros((H, W), dtype=bool)
+    for dy in range(-h, h + 1):
+        for dx in range(-h, h + 1):
+            oi = pad[h + dy:h + dy + H, h + dx:h + dx + W]
+            seen |= (oi[..., 2] > 0) & (np.linalg.norm(oi - q, axis=-1) <= tol)
+    return int((front & seen).sum()) / n
+
+
+@dataclasses.dataclass
+class Gating:
+    """Per-object occlusion state: the last accepted motion (rotation dR
+    applied on the left, translation dt added), dropped updates in a row and
+    the first stage's translation scale for the next frame."""
+
+    min_visible: float
+    widen: float
+    dR: List[np.ndarray]
+    dt: List[np.ndarray]
+    dropped: List[int]
+    scale: List[float]
+
+    @classmethod
+    def start(cls, M: int, min_visible: float, widen: float) -> "Gating":
+        return cls(min_visible, widen, [np.eye(3) for _ in range(M)], [np.zeros(3) for _ in range(M)], [0] * M,
+                   [1.0] * M)
+
+
+def predict(g: Gating, o: int, prev: np.ndarray) -> np.ndarray:
+    """prev moved by object o's kept motion: rotation dR on the left, dt added."""
+    P = np.array(prev, dtype=np.float64)
+    P[:3, :3] = g.dR[o] @ prev[:3, :3]
+    P[:3, 3] = prev[:3, 3] + g.dt[o]
+    return P
+
+
+def gate_update(g: Gating, o: int, prev: np.ndarray, new: np.ndarray, seen: float) -> np.ndarray:
+    """Object o's pose after the occlusion decision, given the seen fraction of
+    the update; updates g in place.  At least min_visible: the update stands
+    and its motion (R_new R_prev^T, t_new - t_prev) is kept; otherwise the
+    prediction replaces it and the next first stage widens."""
+    if seen >= g.min_visible:
+        g.dR[o] = new[:3, :3] @ prev[:3, :3].T
+        g.dt[o] = new[:3, 3] - prev[:3, 3]
+        g.dropped[o] = 0
+        g.scale[o] = 1.0
+        return new
+    P = predict(g, o, prev)
+    g.dropped[o] += 1
+    g.scale[o] = g.widen
+    return P

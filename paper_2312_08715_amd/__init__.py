@@ -53,7 +53,8 @@ class BatchItem(ctypes.Structure):
 class TrackParams(ctypes.Structure):
     _fields_ = [("n_stages", ctypes.c_int32), ("stages", Grid * B3D_MAX_STAGES), ("n_refine", ctypes.c_int32),
                 ("lr_t", ctypes.c_float), ("lr_r", ctypes.c_float), ("beta1", ctypes.c_float),
-                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("min_visible", ctypes.c_float),
+                ("widen", ctypes.c_float)]
 
 
 class Schedule(ctypes.Structure):
@@ -128,6 +129,7 @@ _SIGNATURES = {
     "b3d_tracker_frame": ([_P, _P, _P], ctypes.c_int),
     "b3d_tracker_frame_eager": ([_P, _P, _P], ctypes.c_int),
     "b3d_tracker_poses": ([_P, _P, _P], ctypes.c_int),
+    "b3d_tracker_state": ([_P, _P, _P], ctypes.c_int),
     "b3d_tracker_destroy": ([_P], ctypes.c_int),
     "b3d_grid_size": ([ctypes.POINTER(Grid)], ctypes.c_int64),
     "b3d_enumerate": ([ctypes.POINTER(Grid), _U64, _I32, _P, _P], ctypes.c_int),
@@ -599,7 +601,7 @@ def c2f_step_noalloc(scene: Scene, center, schedule: Schedule, K: int, seed: int
 
 
 class Batch:
-    """Many scenes in one persistent launch (b3d_batch_create / b3d_batch_run).
+    """Many scenes in few launches (b3d_batch_create / b3d_batch_run).
 
     ``items`` is a list of (scene, poses [N,4,4]); outputs are allocated here:
     ``logL[i]`` [N_i] and, with grad, ``grad[i]`` [N_i, 8]."""
@@ -655,8 +657,12 @@ class Tracker:
 
     def __init__(self, meshes: Sequence[Mesh], K: Intrinsics, p: ScoreParams, grid, init_poses,
                  n_refine: int = 10, lr_t: float = 1e-3, lr_r: float = 1e-2, beta1: float = 0.9,
-                 beta2: float = 0.999, eps: float = 1e-8):
-        """grid: one Grid, or a sequence of Grids searched stage by stage each frame."""
+                 beta2: float = 0.999, eps: float = 1e-8, min_visible: float = 0.0, widen: float = 1.0):
+        """grid: one Grid, or a sequence of Grids searched stage by stage each frame.
+        min_visible > 0: drop an object's update when less than that fraction
+        of its pixels is in front of the others and confirmed by the
+        observation (it then moves by its last accepted motion) and widen the
+        next frame's stage 0 translations by `widen`."""
         self.meshes = list(meshes)
         M = len(self.meshes)
         arr = (_P * M)(*[m.handle for m in self.meshes])
@@ -666,7 +672,7 @@ class Tracker:
             raise B3DError(f"tracker: 1..{B3D_MAX_STAGES} stages")
         st = (Grid * B3D_MAX_STAGES)(*grids)
         tp = TrackParams(len(grids), st, int(n_refine), float(lr_t), float(lr_r), float(beta1), float(beta2),
-                         float(eps))
+                         float(eps), float(min_visible), float(widen))
         h = _P()
         _call("b3d_tracker_create", arr, M, ctypes.byref(K), ctypes.byref(p), ctypes.byref(tp), P0.ctypes.data,
               ctypes.byref(h))
@@ -680,6 +686,12 @@ class Tracker:
     def poses(self) -> torch.Tensor:
         out = torch.empty((self.M, 4, 4), dtype=torch.float32, device="cuda")
         _call("b3d_tracker_poses", self._h, _ptr(out), _stream())
+        return out
+
+    def state(self) -> torch.Tensor:
+        """[M, 3]: seen fraction of the last update, dropped updates in a row, next stage 0 scale."""
+        out = torch.empty((self.M, 3), dtype=torch.float32, device="cuda")
+        _call("b3d_tracker_state", self._h, _ptr(out), _stream())
         return out
 
     def close(self):

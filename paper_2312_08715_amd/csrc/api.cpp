@@ -149,7 +149,10 @@ using namespace b3d_api;
 
 struct b3d_batch {
   BatchPlan plan;
-  unsigned long long* counters = nullptr;  // one work counter per launch (256 B apart)
+  // a second stream for every other launch, forked from and joined back into
+  // the caller's stream on each run (default priority, non-blocking)
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 struct b3d_tracker;
@@ -627,7 +630,15 @@ b3d_status b3d_render_score(const b3d_scene* S, const float* poses, int32_t N, f
 
 namespace b3d_api {
 
-b3d_status plan_batch(const std::vector<BatchItemDev>& items, bool grad, BatchPlan* plan) {
+b3d_status plan_batch(const std::vector<BatchItemDev>& items_in, bool grad, BatchPlan* plan, bool cap_tiles) {
+  // One launch shares one LDS size, the largest of its scenes', which sets
+  // how many blocks fit a CU for all of them: with cap_tiles each scene's
+  // depth-buffer tile is capped at the default one (four blocks per CU), or
+  // at the smallest the scene allows when that is larger.  No result depends
+  // on the tile.
+  std::vector<BatchItemDev> items = items_in;
+  if (cap_tiles)
+    for (BatchItemDev& it : items) it.s.zcap = std::max(min_zcap(it.s), std::min(it.s.zcap, default_zcap(it.s, 4)));
   const int S = (int)items.size();
   std::vector<int> order((size_t)S);
   std::vector<double> cost((size_t)S);
@@ -640,14 +651,9 @@ b3d_status plan_batch(const std::vector<BatchItemDev>& items, bool grad, BatchPl
   }
   if (lds > kLdsMax) return fail(B3D_ESHAPE, "batch: LDS budget exceeded");
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-  int dev = 0, cus = 0, occ = 0;
-  B3D_CHECK_HIP(hipGetDevice(&dev), "batch");
-  B3D_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "batch");
-  B3D_CHECK_HIP(batch_occupancy(grad, lds, &occ), "batch");
   plan->grad = grad;
   plan->lds = lds;
   plan->groups.clear();
-  plan->blocks.clear();
   for (int k0 = 0; k0 < S; k0 += kBatchGroup) {
     BatchGroupDev g{};
     g.S = std::min(kBatchGroup, S - k0);
@@ -663,15 +669,24 @@ b3d_status plan_batch(const std::vector<BatchItemDev>& items, bool grad, BatchPl
     }
     g.first[g.S] = first;
     if (first == 0) continue;
+    if (first > 0x7fffffffLL) return fail(B3D_ESHAPE, "batch: more than 2^31 - 1 hypotheses in one launch");
     plan->groups.push_back(g);
-    plan->blocks.push_back((int)std::max<long long>(1, std::min<long long>((long long)cus * std::max(occ, 1), first)));
   }
   return B3D_OK;
 }
 
-b3d_status run_batch(const BatchPlan& plan, unsigned long long* counters, hipStream_t st) {
+b3d_status run_batch(const BatchPlan& plan, hipStream_t st, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
+  const bool two = side && plan.groups.size() > 1;
+  if (two) {
+    B3D_CHECK_HIP(hipEventRecord(fork, st), "batch");
+    B3D_CHECK_HIP(hipStreamWaitEvent(side, fork, 0), "batch");
+  }
   for (size_t k = 0; k < plan.groups.size(); ++k)
-    B3D_CHECK_HIP(launch_batch(plan.groups[k], counters + 32 * k, plan.grad, plan.lds, plan.blocks[k], st), "batch");
+    B3D_CHECK_HIP(launch_batch(plan.groups[k], plan.grad, plan.lds, two && k % 2 ? side : st), "batch");
+  if (two) {
+    B3D_CHECK_HIP(hipEventRecord(join, side), "batch");
+    B3D_CHECK_HIP(hipStreamWaitEvent(st, join, 0), "batch");
+  }
   return B3D_OK;
 }
 
@@ -695,13 +710,16 @@ b3d_status b3d_batch_create(const b3d_batch_item* items, int32_t S, b3d_batch** 
     its[i] = BatchItemDev{it.scene->dev, it.poses, it.N, it.logL_out, it.grad_out};
   }
   b3d_batch* b = new b3d_batch();
-  if (b3d_status s = plan_batch(its, grad, &b->plan)) {
+  if (b3d_status s = plan_batch(its, grad, &b->plan, true)) {
     delete b;
     return s;
   }
-  if (!b->plan.groups.empty() && hipMalloc((void**)&b->counters, 256 * b->plan.groups.size()) != hipSuccess) {
-    delete b;
-    return fail(B3D_ENOMEM, "batch_create: device allocation failed");
+  if (b->plan.groups.size() > 1 &&
+      (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+       hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess)) {
+    b3d_batch_destroy(b);
+    return fail(B3D_EHIP, "batch_create: stream or event creation failed");
   }
   *out = b;
   return B3D_OK;
@@ -709,13 +727,15 @@ b3d_status b3d_batch_create(const b3d_batch_item* items, int32_t S, b3d_batch** 
 
 b3d_status b3d_batch_run(const b3d_batch* b, void* stream) {
   if (!b) return fail(B3D_EINVAL, "batch_run: NULL batch");
-  return run_batch(b->plan, b->counters, (hipStream_t)stream);
+  return run_batch(b->plan, (hipStream_t)stream, b->side, b->fork, b->join);
 }
 
 b3d_status b3d_batch_destroy(b3d_batch* b) {
   if (!b) return B3D_OK;
   (void)hipDeviceSynchronize();
-  (void)hipFree(b->counters);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->join) (void)hipEventDestroy(b->join);
+  if (b->side) (void)hipStreamDestroy(b->side);
   delete b;
   return B3D_OK;
 }
@@ -984,7 +1004,15 @@ struct b3d_tracker {
   std::vector<const b3d_mesh*> meshes;
   std::vector<b3d_scene*> scenes;
   float* obs = nullptr;      // [H][W][3] frame buffer read by the graph
-  float* poses = nullptr;    // [M][16] current estimates
+  // per-object state, one allocation: poses [M][16] (current estimates),
+  // prev [M][16] (estimates before the frame's update), motion [M][12] (last
+  // accepted frame-to-frame rotation and translation), gate [M][4]
+  // (visibility, dropped updates in a row, stage 0's translation scale, 0)
+  float* poses = nullptr;
+  float* prev = nullptr;
+  float* motion = nullptr;
+  float* gate = nullptr;
+  unsigned long long* objkeys = nullptr;  // [H][W] the updated object drawn alone
   float* hyp = nullptr;      // [N][16]
   float* logL = nullptr;     // [N]
   float* partial = nullptr;  // [ceil(H / kRefineRows)][9] band sums of a refinement step
@@ -1017,16 +1045,23 @@ static b3d_status tracker_background(b3d_tracker* T, int o, hipStream_t st) {
   return B3D_OK;
 }
 
+// Floats of per-object state in the tracker's state allocation.
+constexpr int kTrackStateFloats = 16 + 16 + 12 + 4;
+
 static b3d_status tracker_record(b3d_tracker* T, hipStream_t st) {
   const b3d_track_params& tp = T->tp;
+  const bool gating = tp.min_visible > 0.0f;
   GridDev g[B3D_MAX_STAGES];
   int64_t ns[B3D_MAX_STAGES];
   for (int s = 0; s < tp.n_stages; ++s) (void)make_grid(&tp.stages[s], &g[s], &ns[s]);
   for (int o = 0; o < T->M; ++o) {
     b3d_scene* S = T->scenes[o];
     if (b3d_status s = tracker_background(T, o, st)) return s;
+    if (gating) B3D_CHECK_HIP(launch_copy_f32(T->poses + 16 * o, 16, T->prev + 16 * o, st), "tracker");
     for (int s = 0; s < tp.n_stages; ++s) {
-      B3D_CHECK_HIP(launch_enumerate(g[s], T->poses + 16 * o, 1, 0u, 0u, (uint32_t)s, T->hyp, st), "tracker");
+      // stage 0's translations scaled after a dropped update
+      const float* hscale = gating && s == 0 ? T->gate + 4 * o + 2 : nullptr;
+      B3D_CHECK_HIP(launch_enumerate(g[s], T->poses + 16 * o, 1, 0u, 0u, (uint32_t)s, T->hyp, st, hscale), "tracker");
       B3D_CHECK_HIP(launch_render_score(S->dev, T->hyp, (int)ns[s], T->logL, nullptr, st), "tracker");
       B3D_CHECK_HIP(launch_argmax_pose(T->logL, T->hyp, (int)ns[s], T->poses + 16 * o, st), "tracker");
     }
@@ -1034,6 +1069,19 @@ static b3d_status tracker_record(b3d_tracker* T, hipStream_t st) {
       B3D_CHECK_HIP(launch_refine_banded(S->dev, T->poses + 16 * o, tp.n_refine, tp.lr_t, tp.lr_r, tp.beta1, tp.beta2,
                                          tp.eps, kRefineRows, T->partial, T->adam + 12 * o, st),
                     "tracker");
+    if (gating) {
+      // the object alone at its new pose, then how much of it is in front of
+      // the others and confirmed by the observation, and the decision
+      const SceneDev& d = S->dev;
+      const size_t HW = (size_t)d.cam.H * d.cam.W;
+      B3D_CHECK_HIP(launch_fill_keys(T->objkeys, HW, st), "tracker");
+      B3D_CHECK_HIP(launch_raster_global_dev(d.mesh, d.cam, T->poses + 16 * o, 0u, T->objkeys, st), "tracker");
+      B3D_CHECK_HIP(launch_refine_global(d.mesh, d.cam, nullptr, T->poses + 16 * o, 0u, T->objkeys, st), "tracker");
+      B3D_CHECK_HIP(launch_track_gate(T->objkeys, T->M > 1 ? S->bg : nullptr, T->obs, d.cam, d.sc.h,
+                                      3.0f * S->params.sigma, tp.min_visible, tp.widen, T->prev + 16 * o,
+                                      T->poses + 16 * o, T->motion + 12 * o, T->gate + 4 * o, st),
+                    "tracker");
+    }
   }
   return B3D_OK;
 }
@@ -1052,7 +1100,7 @@ static b3d_status tracker_tune(b3d_tracker* T, hipStream_t st) {
       cands.push_back(z);
   }
   if (cands.size() < 2) return B3D_OK;
-  const size_t pose_bytes = sizeof(float) * 16 * (size_t)T->M;
+  const size_t pose_bytes = sizeof(float) * kTrackStateFloats * (size_t)T->M;  // estimates and occlusion state
   float* saved = nullptr;
   if (hipMalloc((void**)&saved, pose_bytes) != hipSuccess)
     return fail(B3D_ENOMEM, "tracker_frame: tuning scratch allocation failed");
@@ -1112,6 +1160,10 @@ b3d_status b3d_tracker_create(const b3d_mesh* const* meshes, int32_t M, const b3
     n = std::max(n, ns);
   }
   if (tp->n_refine < 0 || tp->n_refine > 1000) return fail(B3D_EINVAL, "tracker_create: n_refine in 0..1000");
+  if (!(tp->min_visible >= 0.0f && tp->min_visible <= 1.0f))
+    return fail(B3D_EINVAL, "tracker_create: min_visible must be in [0, 1]");
+  if (tp->min_visible > 0.0f && !(tp->widen >= 1.0f && tp->widen <= 100.0f))
+    return fail(B3D_EINVAL, "tracker_create: widen must be in [1, 100]");
   if (!(tp->beta1 >= 0 && tp->beta1 < 1) || !(tp->beta2 >= 0 && tp->beta2 < 1) || !(tp->eps > 0))
     return fail(B3D_EINVAL, "tracker_create: bad Adam parameters");
   if (!finite_all(init_poses, (size_t)M * 16)) return fail(B3D_EINVAL, "tracker_create: non-finite pose");
@@ -1131,18 +1183,30 @@ b3d_status b3d_tracker_create(const b3d_mesh* const* meshes, int32_t M, const b3
     (void)hipFree(T->logL);
     (void)hipFree(T->partial);
     (void)hipFree(T->adam);
+    (void)hipFree(T->objkeys);
     if (T->cap) (void)hipStreamDestroy(T->cap);
     delete T;
     return fail(s, "%s", msg);
   };
   if (hipMalloc((void**)&T->obs, T->obs_bytes) != hipSuccess ||
-      hipMalloc((void**)&T->poses, sizeof(float) * 16 * M) != hipSuccess ||
+      hipMalloc((void**)&T->poses, sizeof(float) * kTrackStateFloats * M) != hipSuccess ||
+      hipMalloc((void**)&T->objkeys, sizeof(unsigned long long) * (size_t)K->H * K->W) != hipSuccess ||
       hipMalloc((void**)&T->hyp, sizeof(float) * 16 * (size_t)n) != hipSuccess ||
       hipMalloc((void**)&T->logL, sizeof(float) * (size_t)n) != hipSuccess ||
       hipMalloc((void**)&T->partial, sizeof(float) * 9 * (size_t)((K->H + kRefineRows - 1) / kRefineRows)) != hipSuccess ||
       hipMalloc((void**)&T->adam, sizeof(float) * 12 * (size_t)M) != hipSuccess)
     return cleanup(B3D_ENOMEM, "tracker_create: device allocation failed");
-  if (hipMemcpy(T->poses, init_poses, sizeof(float) * 16 * M, hipMemcpyHostToDevice) != hipSuccess ||
+  T->prev = T->poses + 16 * M;
+  T->motion = T->prev + 16 * M;
+  T->gate = T->motion + 12 * M;
+  std::vector<float> state((size_t)kTrackStateFloats * M, 0.0f);
+  for (int o = 0; o < M; ++o) {
+    for (int k = 0; k < 16; ++k) state[16 * o + k] = state[16 * (M + o) + k] = init_poses[16 * o + k];
+    float* mo = state.data() + 32 * M + 12 * o;  // no motion: identity rotation, zero translation
+    mo[0] = mo[4] = mo[8] = 1.0f;
+    state[44 * M + 4 * o + 2] = 1.0f;  // stage 0 at its own extents
+  }
+  if (hipMemcpy(T->poses, state.data(), sizeof(float) * state.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(T->obs, 0, T->obs_bytes) != hipSuccess)
     return cleanup(B3D_EHIP, "tracker_create: initial copy failed");
   for (int o = 0; o < M; ++o) {
@@ -1192,6 +1256,14 @@ b3d_status b3d_tracker_frame_eager(b3d_tracker* T, const float* observed, void* 
   return tracker_record(T, st);
 }
 
+b3d_status b3d_tracker_state(const b3d_tracker* T, float* state_out, void* stream) {
+  if (!T || !state_out) return fail(B3D_EINVAL, "tracker_state: NULL pointer");
+  B3D_CHECK_HIP(hipMemcpy2DAsync(state_out, sizeof(float) * 3, T->gate, sizeof(float) * 4, sizeof(float) * 3, T->M,
+                                 hipMemcpyDeviceToDevice, (hipStream_t)stream),
+                "tracker_state");
+  return B3D_OK;
+}
+
 b3d_status b3d_tracker_poses(const b3d_tracker* T, float* poses_out, void* stream) {
   if (!T || !poses_out) return fail(B3D_EINVAL, "tracker_poses: NULL pointer");
   B3D_CHECK_HIP(hipMemcpyAsync(poses_out, T->poses, sizeof(float) * 16 * T->M, hipMemcpyDeviceToDevice,
@@ -1212,6 +1284,7 @@ b3d_status b3d_tracker_destroy(b3d_tracker* T) {
   (void)hipFree(T->logL);
   (void)hipFree(T->partial);
   (void)hipFree(T->adam);
+  (void)hipFree(T->objkeys);
   if (T->cap) (void)hipStreamDestroy(T->cap);
   delete T;
   return B3D_OK;

@@ -39,7 +39,7 @@ b3d_status make_noise_grid(const b3d_score_params& base, int H, int W, const flo
                            int B, const float* log_w, NoiseGridDev* g, std::vector<b3d_score_params>* per_point);
 
 // One scene's share of a multi-scene launch, and the launch plan: scenes
-// ordered by estimated cost, kBatchGroup per persistent launch.
+// ordered by estimated cost, kBatchGroup per launch.
 struct BatchItemDev {
   SceneDev s;
   const float* poses;
@@ -49,13 +49,19 @@ struct BatchItemDev {
 };
 struct BatchPlan {
   std::vector<BatchGroupDev> groups;
-  std::vector<int> blocks;  // persistent workgroups per launch
   bool grad = false;
   size_t lds = 0;
 };
-b3d_status plan_batch(const std::vector<BatchItemDev>& items, bool grad, BatchPlan* plan);
-// counters: device, 256 B per group.
-b3d_status run_batch(const BatchPlan& plan, unsigned long long* counters, hipStream_t st);
+// cap_tiles: cap each scene's depth-buffer tile at the default (four
+// workgroups per CU), for callers whose scenes carry tiles tuned for lone
+// launches; callers that chose one tile for the whole batch by timing it
+// keep theirs.
+b3d_status plan_batch(const std::vector<BatchItemDev>& items, bool grad, BatchPlan* plan, bool cap_tiles = false);
+// The plan's launches in order on st; with a side stream (and two events),
+// every other launch goes there, forked from and joined back into st, so
+// that one launch's tail overlaps the next one's start.
+b3d_status run_batch(const BatchPlan& plan, hipStream_t st, hipStream_t side = nullptr, hipEvent_t fork = nullptr,
+                     hipEvent_t join = nullptr);
 
 }  // namespace b3d_api
 

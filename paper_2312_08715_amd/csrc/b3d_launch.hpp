@@ -214,9 +214,8 @@ hipError_t launch_render_score(const SceneDev& s, const float* poses, int N, flo
 hipError_t launch_render_score_count(const SceneDev& s, const float* poses, int N, float* logL, float* grad,
                                      unsigned long long* work, hipStream_t st);
 
-hipError_t batch_occupancy(bool grad, size_t lds, int* blocks_per_cu);
-hipError_t launch_batch(const BatchGroupDev& g, unsigned long long* counter, bool grad, size_t lds, int blocks,
-                        hipStream_t st);
+// One workgroup per hypothesis of the group's scenes.
+hipError_t launch_batch(const BatchGroupDev& g, bool grad, size_t lds, hipStream_t st);
 
 // scene preparation
 hipError_t launch_fill_keys(unsigned long long* keys, size_t n, hipStream_t st);
@@ -228,7 +227,8 @@ hipError_t launch_background_terms(const SceneDev& s, double* terms, hipStream_t
 
 // hypotheses and sampling
 hipError_t launch_enumerate(const GridDev& g, const float* centres, int P, uint32_t key0, uint32_t key1,
-                            uint32_t stage, float* poses, hipStream_t st);
+                            uint32_t stage, float* poses, hipStream_t st,
+                            const float* hscale = nullptr);
 hipError_t launch_sample(const float* logL, int P, int N, int K, uint32_t key0, uint32_t key1, uint32_t stage,
                          uint32_t k0, float* w, int* idx, float* logw, hipStream_t st);
 hipError_t launch_c2f_update(const float* poses, int P, int N, const int* idx, const float* logw, int K_draws,
@@ -248,6 +248,16 @@ hipError_t launch_refine_banded(const SceneDev& s, float* pose, int n_refine, fl
 hipError_t launch_adam_pose(float* poses, const float* grad, int gstride, float* state, int N, int iter, float lr_t,
                             float lr_r, float b1, float b2, float eps, hipStream_t st);
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t st);
+hipError_t launch_copy_f32(const float* src, int n, float* dst, hipStream_t st);
+// The tracker's occlusion decision for one object (one block): the fraction
+// of its pixels in objkeys that are in front of bg (null: no other objects)
+// and have an observed point within tol of theirs in their (2h + 1)^2
+// window; then either keep the update (and record its motion from prev) or
+// replace it by prev moved by the last motion; gate: (that fraction, dropped
+// in a row, next stage 0 translation scale, 0).
+hipError_t launch_track_gate(const unsigned long long* objkeys, const unsigned long long* bg, const float* obs,
+                             const Cam& cam, int h, float tol, float min_visible, float widen, const float* prev,
+                             float* pose, float* motion, float* gate, hipStream_t st);
 hipError_t launch_argmax_pose(const float* logL, const float* poses, int N, float* out, hipStream_t st);
 hipError_t launch_raster_global_dev(const MeshDev& m, const Cam& cam, const float* pose16_dev, uint32_t id_base,
                                     unsigned long long* keys, hipStream_t st);

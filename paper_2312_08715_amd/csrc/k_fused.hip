@@ -417,57 +417,50 @@ __global__ __launch_bounds__(kBlock, 4) void k_render_score(SceneDev s, const fl
                                     smem);
 }
 
-// A group of scenes in one persistent launch: every block pulls the next
-// (scene, hypothesis) item from a device counter until the group is drained.
-// Items are numbered scene by scene in the order the host chose (costliest
-// hypotheses first), so the expensive scenes start early and the cheap ones
-// fill the tail.  Every block exits once the counter passes the group's total.
+// A group of scenes in one launch, one workgroup per (scene, hypothesis)
+// item.  Items are numbered scene by scene in the order the host chose
+// (costliest hypotheses first), so the expensive scenes start early and the
+// cheap ones fill the tail; the hardware dispatcher hands them out in order.
+// The item's scene is copied from the argument member by member at constant
+// positions: indexing the argument with the scene number would move it to
+// scratch memory.  No static LDS either, which would cost a resident block
+// per CU at the default tile.
 template <bool GRAD, int RM>
-__global__ __launch_bounds__(kBlock, 4) void k_batch(const BatchGroupDev G, unsigned long long* __restrict__ counter) {
+__global__ __launch_bounds__(kBlock, 4) void k_batch(const BatchGroupDev G) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ long long work;
-  const long long total = G.first[G.S];
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) work = (long long)atomicAdd(counter, 1ull);
-    __syncthreads();
-    // the same value in every lane: keep it (and the scene it selects) scalar
-    const unsigned long long wr = (unsigned long long)work;
-    const long long w = (long long)(((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(wr >> 32)) << 32) |
-                                    (unsigned)__builtin_amdgcn_readfirstlane((unsigned)wr));
-    if (w >= total) break;
-    int k = 0;
-    for (int j = 1; j < G.S; ++j) k = G.first[j] <= w ? j : k;
-    const long long n = w - G.first[k];
-    render_score_one<GRAD, false, RM>(G.s[k], G.poses[k] + 16 * n, G.logL[k] + n, GRAD ? G.grad[k] + 8 * n : nullptr,
-                                      smem);
-  }
+  const long long w = blockIdx.x;
+  if (w >= G.first[G.S]) return;
+  int k = 0;
+  for (int j = 1; j < G.S; ++j) k = G.first[j] <= w ? j : k;
+  SceneDev s;
+  const float* poses = nullptr;
+  float *logL = nullptr, *grad = nullptr;
+  long long first = 0;
+#pragma unroll
+  for (int j = 0; j < kBatchGroup; ++j)
+    if (k == j) {
+      s = G.s[j];
+      poses = G.poses[j];
+      logL = G.logL[j];
+      grad = G.grad[j];
+      first = G.first[j];
+    }
+  const long long n = w - first;
+  render_score_one<GRAD, false, RM>(s, poses + 16 * n, logL + n, GRAD ? grad + 8 * n : nullptr, smem);
 }
 
-__global__ void k_reset_counter(unsigned long long* c) {
-  if (threadIdx.x == 0) c[threadIdx.x] = 0ull;
-}
-
-hipError_t batch_occupancy(bool grad, size_t lds, int* blocks_per_cu) {
-  // every raster variant has the same launch bounds and LDS
-  if (grad)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch<true, kRasterSmall>, kBlock, lds);
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch<false, kRasterSmall>, kBlock, lds);
-}
-
-hipError_t launch_batch(const BatchGroupDev& g, unsigned long long* counter, bool grad, size_t lds, int blocks,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
+hipError_t launch_batch(const BatchGroupDev& g, bool grad, size_t lds, hipStream_t st) {
   bool big = false;
   for (int k = 0; k < g.S; ++k) big = big || g.s[k].mesh.has_big != 0;
+  const dim3 grid((unsigned)g.first[g.S]);
   if (grad && big)
-    hipLaunchKernelGGL((k_batch<true, kRasterAny>), dim3(blocks), dim3(kBlock), lds, st, g, counter);
+    hipLaunchKernelGGL((k_batch<true, kRasterAny>), grid, dim3(kBlock), lds, st, g);
   else if (grad)
-    hipLaunchKernelGGL((k_batch<true, kRasterSmall>), dim3(blocks), dim3(kBlock), lds, st, g, counter);
+    hipLaunchKernelGGL((k_batch<true, kRasterSmall>), grid, dim3(kBlock), lds, st, g);
   else if (big)
-    hipLaunchKernelGGL((k_batch<false, kRasterAny>), dim3(blocks), dim3(kBlock), lds, st, g, counter);
+    hipLaunchKernelGGL((k_batch<false, kRasterAny>), grid, dim3(kBlock), lds, st, g);
   else
-    hipLaunchKernelGGL((k_batch<false, kRasterSmall>), dim3(blocks), dim3(kBlock), lds, st, g, counter);
+    hipLaunchKernelGGL((k_batch<false, kRasterSmall>), grid, dim3(kBlock), lds, st, g);
   return hipGetLastError();
 }
 

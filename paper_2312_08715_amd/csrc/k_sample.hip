@@ -65,7 +65,7 @@ __device__ __forceinline__ float grid_offset(int i, int n, float h, int cell) {
 
 // One thread per (segment p, hypothesis n): pose p*N + n.
 __global__ void k_enumerate(GridDev g, const float* __restrict__ centres, int P, uint32_t k0, uint32_t k1,
-                            uint32_t stage, float* __restrict__ poses) {
+                            uint32_t stage, float* __restrict__ poses, const float* __restrict__ hscale) {
   const int nt = g.count[0] * g.count[1] * g.count[2];
   const long long N = (long long)nt * g.n_rot;
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -84,9 +84,10 @@ __global__ void k_enumerate(GridDev g, const float* __restrict__ centres, int P,
     perturbation(k0, k1, stage, r, g.max_angle, dR);
   }
   float* out = poses + 16 * (size_t)i;
-  const float off[3] = {grid_offset(ix, g.count[0], g.half[0], g.cell_centres),
-                        grid_offset(iy, g.count[1], g.half[1], g.cell_centres),
-                        grid_offset(iz, g.count[2], g.half[2], g.cell_centres)};
+  const float sc = hscale ? *hscale : 1.0f;  // translation half extents scaled (a widened search)
+  const float off[3] = {grid_offset(ix, g.count[0], g.half[0] * sc, g.cell_centres),
+                        grid_offset(iy, g.count[1], g.half[1] * sc, g.cell_centres),
+                        grid_offset(iz, g.count[2], g.half[2] * sc, g.cell_centres)};
   for (int a = 0; a < 3; ++a) {
     for (int b = 0; b < 3; ++b)
       out[4 * a + b] = dR[3 * a + 0] * C[b] + dR[3 * a + 1] * C[4 + b] + dR[3 * a + 2] * C[8 + b];
@@ -99,10 +100,10 @@ __global__ void k_enumerate(GridDev g, const float* __restrict__ centres, int P,
 }
 
 hipError_t launch_enumerate(const GridDev& g, const float* centres, int P, uint32_t key0, uint32_t key1,
-                            uint32_t stage, float* poses, hipStream_t st) {
+                            uint32_t stage, float* poses, hipStream_t st, const float* hscale) {
   const long long N = (long long)g.count[0] * g.count[1] * g.count[2] * g.n_rot * P;
   const int blocks = (int)((N + 255) / 256);
-  hipLaunchKernelGGL(k_enumerate, dim3(blocks), dim3(256), 0, st, g, centres, P, key0, key1, stage, poses);
+  hipLaunchKernelGGL(k_enumerate, dim3(blocks), dim3(256), 0, st, g, centres, P, key0, key1, stage, poses, hscale);
   return hipGetLastError();
 }
 

@@ -131,6 +131,111 @@ hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t st) {
   return hipGetLastError();
 }
 
+__global__ void k_copy_f32(const float* __restrict__ src, int n, float* __restrict__ dst) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+hipError_t launch_copy_f32(const float* src, int n, float* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_f32, dim3((n + 255) / 256), dim3(256), 0, st, src, n, dst);
+  return hipGetLastError();
+}
+
+// The tracker's occlusion decision for one object; one block.  Seen pixels:
+// those the object (drawn alone into objkeys) covers, whose key is below the
+// other objects' key (nearer; the object's ids, numbered first, win equal
+// depths, as in the fused kernel's composite), that have a valid observed
+// point within distance sqrt(tol2) of the object's point among the
+// (2h + 1)^2 pixels centred on them.  seen = seen pixels / covered pixels (0
+// when none).  At or above min_visible the update stands and its motion is
+// kept: rotation R_pose R_prev^T, translation t_pose - t_prev.  Below it the
+// pose becomes prev moved by the kept motion (R <- dR R_prev,
+// t <- t_prev + dt).  gate = (seen, dropped updates in a row, stage 0's
+// translation scale for the next frame, 0).
+__global__ __launch_bounds__(kBlock) void k_track_gate(const unsigned long long* __restrict__ objkeys,
+                                                       const unsigned long long* __restrict__ bg,
+                                                       const float* __restrict__ obs, Cam cam, int h, float tol2,
+                                                       float min_visible, float widen, const float* __restrict__ prev,
+                                                       float* __restrict__ pose, float* __restrict__ motion,
+                                                       float* __restrict__ gate) {
+  __shared__ unsigned sd[kWaves], sv[kWaves];
+  unsigned drawn = 0, seen = 0;
+  const int HW = cam.H * cam.W;
+  // some valid observed point in the window of pixel (r, c) within the
+  // tolerance of the point at depth z on that pixel's ray
+  auto confirmed = [&](int r, int c, float z) {
+    const float qx = z * ray_x(cam, c), qy = z * ray_y(cam, r);
+    for (int dy = -h; dy <= h; ++dy) {
+      const int ri = r + dy;
+      if (ri < 0 || ri >= cam.H) continue;
+      for (int dx = -h; dx <= h; ++dx) {
+        const int ci = c + dx;
+        if (ci < 0 || ci >= cam.W) continue;
+        const float* o = obs + 3 * ((size_t)ri * cam.W + ci);
+        const float ex = o[0] - qx, ey = o[1] - qy, ez = o[2] - z;
+        if (o[2] > 0.0f && ex * ex + ey * ey + ez * ez <= tol2) return true;
+      }
+    }
+    return false;
+  };
+  for (int p = threadIdx.x; p < HW; p += kBlock) {
+    const unsigned long long k = objkeys[p];
+    if (k == kEmptyKey) continue;
+    ++drawn;
+    if (bg && !(k < bg[p])) continue;  // behind the others
+    const int r = p / cam.W, c = p - r * cam.W;
+    if (confirmed(r, c, key_depth(k))) ++seen;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    drawn += __shfl_xor(drawn, o, 64);
+    seen += __shfl_xor(seen, o, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sd[wave] = drawn;
+    sv[wave] = seen;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  drawn = 0;
+  seen = 0;
+  for (int w = 0; w < kWaves; ++w) {
+    drawn += sd[w];
+    seen += sv[w];
+  }
+  const float frac = drawn ? (float)seen / (float)drawn : 0.0f;
+  gate[0] = frac;
+  if (frac >= min_visible) {
+    // keep the update; its motion: dR = R R_prev^T, dt = t - t_prev
+    for (int a = 0; a < 3; ++a) {
+      for (int b = 0; b < 3; ++b)
+        motion[3 * a + b] = pose[4 * a + 0] * prev[4 * b + 0] + pose[4 * a + 1] * prev[4 * b + 1] +
+                            pose[4 * a + 2] * prev[4 * b + 2];
+      motion[9 + a] = pose[4 * a + 3] - prev[4 * a + 3];
+    }
+    gate[1] = 0.0f;
+    gate[2] = 1.0f;
+  } else {
+    // drop it: prev moved by the kept motion
+    for (int a = 0; a < 3; ++a) {
+      for (int b = 0; b < 3; ++b)
+        pose[4 * a + b] = motion[3 * a + 0] * prev[b] + motion[3 * a + 1] * prev[4 + b] + motion[3 * a + 2] * prev[8 + b];
+      pose[4 * a + 3] = prev[4 * a + 3] + motion[9 + a];
+    }
+    for (int k = 12; k < 16; ++k) pose[k] = prev[k];
+    gate[1] += 1.0f;
+    gate[2] = widen;
+  }
+  gate[3] = 0.0f;
+}
+
+hipError_t launch_track_gate(const unsigned long long* objkeys, const unsigned long long* bg, const float* obs,
+                             const Cam& cam, int h, float tol, float min_visible, float widen, const float* prev,
+                             float* pose, float* motion, float* gate, hipStream_t st) {
+  hipLaunchKernelGGL(k_track_gate, dim3(1), dim3(kBlock), 0, st, objkeys, bg, obs, cam, h, tol * tol, min_visible,
+                     widen, prev, pose, motion, gate);
+  return hipGetLastError();
+}
+
 // out = poses[argmax logL] (ties to the lowest index); one block.
 __global__ __launch_bounds__(kBlock) void k_argmax_pose(const float* __restrict__ logL, const float* __restrict__ poses,
                                                         int N, float* __restrict__ out) {

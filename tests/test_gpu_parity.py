@@ -672,7 +672,11 @@ def test_edge_cases(b3d):
 
 def test_multi_scene_batch_equals_per_scene_calls(b3d):
     # scenes of different image sizes, meshes and hypothesis counts in
-    # persistent launches of up to eight scenes each (here two launches)
+    # launches of up to eight scenes each (here two, on two streams): every
+    # result equals the per-scene call's bit for bit (the per-hypothesis body
+    # is the same and no result depends on the tile the batch caps), run
+    # eagerly twice and replayed from a captured graph with eager work in
+    # between
     rng = np.random.default_rng(21)
     items, refs, keep = [], [], []
     sizes = [(120, 160), (180, 240), (240, 320), (120, 160), (180, 240), (120, 160), (240, 320), (120, 160),
@@ -696,15 +700,27 @@ def test_multi_scene_batch_equals_per_scene_calls(b3d):
     say(f"batch: {len(items)} scenes, {sum(p.shape[0] for _, p in items)} hypotheses")
     batch = b3d.Batch(items, grad=True)
     L, G = batch.run()
-    bitwise = True
-    for (Lr, Gr), Lb, Gb in zip(refs, L, G):
-        bitwise &= torch.equal(Lb, Lr) and torch.equal(Gb, Gr)
-        np.testing.assert_allclose(Lb.cpu().numpy(), Lr.cpu().numpy(), rtol=1e-6, atol=1e-3)
-        np.testing.assert_allclose(Gb.cpu().numpy(), Gr.cpu().numpy(), rtol=1e-5, atol=1e-2)
-    say(f"  batch results bitwise equal to per-scene calls: {bitwise}")
+    torch.cuda.synchronize()
+    for k, ((Lr, Gr), Lb, Gb) in enumerate(zip(refs, L, G)):
+        assert torch.equal(Lb, Lr) and torch.equal(Gb, Gr), f"scene {k}: batch differs from the per-scene call"
+    say("  batch results bitwise equal to per-scene calls")
     L2, _ = batch.run()
-    for a, b in zip(L, L2):
-        assert torch.equal(a, b)
+    torch.cuda.synchronize()
+    for a, (Lr, _) in zip(L2, refs):
+        assert torch.equal(a, Lr)
+    for a in L:
+        a.fill_(0.0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batch.run()
+    for rep in range(3):
+        x = b3d.render_score(items[0][0], items[0][1])  # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        ok = all(torch.equal(Lb, Lr) and torch.equal(Gb, Gr) for (Lr, Gr), Lb, Gb in zip(refs, L, G))
+        say(f"  graph replay {rep}: equal to the per-scene calls {ok}")
+        assert ok and torch.equal(x, refs[0][0])
 
 
 def _batch_scene(rng, H, W, vox):
@@ -728,7 +744,7 @@ def _batch_scene(rng, H, W, vox):
 
 
 def test_multi_scene_batch_matches_oracle(b3d):
-    # The many-scenes mix in persistent launches: two scenes of each image
+    # The many-scenes mix as one batch: two scenes of each image
     # size (160x120, 240x180, 320x240) with 2-4 objects, the others drawn as
     # static background; hypotheses of object 0 on the benchmark's grid
     # (10x10 translations over +-2 cm x layers x 10 rotations within 10

@@ -374,3 +374,101 @@ def test_tracker_refinement_follows_the_oracle_on_three_objects(b3d):
         say(f"  frame {f}: max pose diff {d:.3g}; poses moved by up to {moved:.3g}")
         assert d <= 2e-6 and moved >= 1e-3
         cur = list(want)
+
+
+def occlusion_sequence(n_frames=13, seed=77):
+    """A 16 x 16 x 4 cm panel at 0.55 m and a 5 cm blob of 150 voxels 30 cm
+    behind it, crossing from x = -18 cm to +18 cm at 3 cm a frame while
+    turning 2 degrees a frame about the vertical: it is fully hidden for a
+    few frames in the middle.  160x120, f = 150, 2 mm noise, 2% outliers,
+    observed through the oracle's FP64 render."""
+    from workloads import Camera, box_mesh, observation_noise, pose_matrix, voxel_blob, voxel_mesh
+
+    rng = np.random.default_rng(seed)
+    cam = Camera(150.0, 150.0, 80.0, 60.0, 120, 160)
+    panel = box_mesh((0.16, 0.16, 0.04))
+    blob = voxel_mesh(voxel_blob(150, rng, radius=0.05))
+    meshes = [(f32(panel[0]), panel[1]), (f32(blob[0]), blob[1])]
+
+    def rot_y(deg):
+        a = np.deg2rad(deg)
+        return np.array([[np.cos(a), 0.0, np.sin(a)], [0.0, 1.0, 0.0], [-np.sin(a), 0.0, np.cos(a)]])
+
+    paths = np.stack([np.stack([pose_matrix(np.eye(3), (0.0, 0.0, 0.55)),
+                                pose_matrix(rot_y(2.0 * f), (-0.18 + 0.03 * f, 0.01, 0.85))])
+                      for f in range(n_frames)])
+    frames = []
+    for f in range(n_frames):
+        d = oracle.render([(v, t, paths[f, k]) for k, (v, t) in enumerate(meshes)], cam)[0][0]
+        nz = observation_noise(cam.H, cam.W, rng, 0.002, 0.02)
+        d = np.where(d > 0, d + nz["gauss"], 0.0)
+        d = np.where(nz["outlier_mask"], nz["outlier_depth"], d)
+        frames.append(f32(oracle.unproject(d, cam)))
+    return meshes, paths, cam, frames
+
+
+def test_tracker_occlusion_handling_follows_the_oracle(b3d):
+    # The tracker with occlusion handling (updates under 30% seen dropped, the
+    # next first stage twice as wide) on a blob that passes behind a panel,
+    # two search stages (4^3 translations over +-4 cm x 4 rotations within 6
+    # degrees, then 3^3 over +-1 cm x 4 within 2 degrees), free running on
+    # the GPU.  Object by object and frame by frame, from the GPU's own
+    # previous estimates and occlusion state: a kept update must be one of
+    # the oracle's search outcomes (near ties followed), its seen fraction
+    # the oracle's within 2% and at least the threshold; a dropped one must
+    # have every oracle outcome under the threshold (within 2%) and equal the
+    # oracle's prediction from the kept motion; the next frame's search scale
+    # must be the oracle's.  The blob must be dropped and re-acquired.
+    from oracle import track
+    from workloads import GridSpec, ScoreParams
+
+    meshes, paths, cam, frames = occlusion_sequence()
+    sp = ScoreParams(sigma=0.003, p_out=0.01, outlier_volume=1.0, window=5)
+    specs = [GridSpec(center=np.eye(4), half_extent=(0.04, 0.04, 0.04), count=(4, 4, 4), n_rot=4,
+                      rot_max_angle=np.deg2rad(6.0)),
+             GridSpec(center=np.eye(4), half_extent=(0.01, 0.01, 0.01), count=(3, 3, 3), n_rot=4,
+                      rot_max_angle=np.deg2rad(2.0))]
+    min_visible, widen, vtol = 0.3, 2.0, 0.02
+    ms = [b3d.Mesh(v, t) for v, t in meshes]
+    tr = b3d.Tracker(ms, b3d.intrinsics_of(cam), b3d.score_params(0.003, 0.01, 1.0, 5),
+                     [b3d.grid_of(g)[0] for g in specs], f32(paths[0]), n_refine=0, min_visible=min_visible,
+                     widen=widen)
+    g = track.Gating.start(2, min_visible, widen)
+    cur = [f32(P) for P in paths[0]]
+    dropped_frames, reacquired = [], False
+    say(f"tracker occlusion handling vs oracle: 2 objects, {len(frames) - 1} frames")
+    for f in range(1, len(frames)):
+        tr.frame(dev(frames[f]))
+        new = tr.poses().cpu().numpy().astype(np.float64)
+        st = tr.state().cpu().numpy().astype(np.float64)
+        obs = frames[f].astype(np.float64)
+        for o in range(2):
+            prev = cur[o]
+            stages = [track.scaled(specs[0], g.scale[o]), specs[1]]
+            ends = track.search_ends(meshes, cur, o, stages, obs, cam, sp, tol=LOGL_RTOL, limit=2)
+            vis_ends = []
+            for e in ends:
+                nxt = list(cur)
+                nxt[o] = e
+                vis_ends.append(track.seen_fraction(meshes, nxt, o, cam, obs, 3 * sp.sigma, sp.window))
+            if st[o, 1] > g.dropped[o]:  # dropped on the GPU
+                assert all(v < min_visible + vtol for v in vis_ends), \
+                    f"frame {f} object {o}: dropped at seen {st[o, 0]:.3f}, oracle outcomes {vis_ends}"
+                assert st[o, 0] < min_visible
+                want = track.gate_update(g, o, prev, ends[0], 0.0)
+                np.testing.assert_allclose(new[o], want, atol=1e-5, err_msg=f"frame {f} object {o}: prediction")
+                dropped_frames.append(f)
+            else:
+                hit = [k for k, e in enumerate(ends) if np.allclose(e, new[o], atol=1e-5)]
+                assert hit, f"frame {f} object {o}: the GPU's pose is none of the oracle's {len(ends)} outcomes"
+                v = vis_ends[hit[0]]
+                assert abs(st[o, 0] - v) <= vtol, f"frame {f} object {o}: seen {st[o, 0]:.4f} vs {v:.4f}"
+                assert st[o, 0] >= min_visible and v >= min_visible - vtol
+                reacquired = reacquired or g.dropped[o] > 0
+                track.gate_update(g, o, prev, new[o], 1.0)
+            assert st[o, 1] == g.dropped[o] and st[o, 2] == g.scale[o]
+            cur[o] = new[o]
+        err = [np.linalg.norm(cur[k][:3, 3] - paths[f, k, :3, 3]) * 100 for k in range(2)]
+        say(f"  frame {f}: seen {np.round(st[:, 0], 3).tolist()}, dropped {st[:, 1].astype(int).tolist()}, "
+            f"position errors (cm) {np.round(err, 2).tolist()}")
+    assert dropped_frames and reacquired, f"dropped at {dropped_frames}, re-acquired {reacquired}"
