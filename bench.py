@@ -46,7 +46,7 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
 # what the same counters read for a plain 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0).  Valid only for the kernel sources with this digest:
 # after any change to them the figure is reported as null until re-measured.
-TRAFFIC = {"sources_sha256": "1f80705d492532af41c9dc4eadcc07c38475cf4fb22426efb8e3a82758b66293", "fetch_KiB": 6368.54, "write_KiB": 312.5, "fetch_scale": 2.0, "write_scale": 1.0}
+TRAFFIC = {"sources_sha256": "91ef5397d61affe84da9eab7138b166143bdc19f22b676961d79570ba3b28893", "fetch_KiB": 6368.9, "write_KiB": 312.5, "fetch_scale": 2.0, "write_scale": 1.0}
 KERNEL_SOURCES = ["k_fused.hip", "b3d_device.hpp", "b3d_launch.hpp"]
 
 
@@ -718,10 +718,10 @@ SPLIT_BYTES_PER_DRAWN = {"render_backward": 12}
 # dispatch, mean over the run's dispatches); valid for the sources with this
 # digest only.
 SPLIT_SOURCES = ["k_render.hip", "k_score.hip", "b3d_device.hpp", "b3d_launch.hpp"]
-SPLIT_TRAFFIC = {"sources_sha256": "923f73f5623d0b85f435c894e82466e41e576a568e5c11bfab097be2d4b9c84a",
-                 "KiB": {"render_batch": [38333.0, 1126003.1], "render_batch_ids": [43717.0, 1500864.4],
-                         "score": [563816.5, 165.9], "score_backward": [565305.9, 1126020.3],
-                         "render_backward": [244256.3, 234.4]}}
+SPLIT_TRAFFIC = {"sources_sha256": "3c9983f31ded3e043d31e2b5cb279503b2bc68137a08b22b6d41df2ca1531da2",
+                 "KiB": {"render_batch": [38266.7, 1126089.3], "render_batch_ids": [43856.2, 1500829.3],
+                         "score": [563816.1, 166.6], "score_backward": [565339.9, 1126036.4],
+                         "render_backward": [244243.9, 234.4]}}
 
 
 def split_sources_digest() -> str:
