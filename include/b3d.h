@@ -592,9 +592,8 @@ typedef struct b3d_smc b3d_smc;
  * library; fixed, fixed_poses (host float[n_fixed][16]): content drawn in
  * every hypothesis's background (the table's own mesh, for instance).  Mesh
  * handles must outlive the sampler.  Every face footprint must be smaller
- * than the table (B3D_ESHAPE).  Allocates device memory and creates a
- * stream and two events of its own, used by the scoring launches of a step
- * (forked from and joined back into the step's stream); not stream-ordered. */
+ * than the table (B3D_ESHAPE).  Allocates device memory (not
+ * stream-ordered). */
 b3d_status b3d_smc_create(const b3d_mesh* const* types, int32_t n_types, const b3d_mesh* const* fixed,
                           const float* fixed_poses, int32_t n_fixed, const b3d_table* table, const b3d_intrinsics* K,
                           const b3d_smc_params* p, b3d_smc** out);

@@ -690,6 +690,20 @@ b3d_status run_batch(const BatchPlan& plan, hipStream_t st, hipStream_t side, hi
   return B3D_OK;
 }
 
+b3d_status run_batch_queue(const BatchPlan& plan, unsigned long long* counters, hipStream_t st) {
+  if (plan.groups.empty()) return B3D_OK;
+  int dev = 0, cus = 0, occ = 0;
+  B3D_CHECK_HIP(hipGetDevice(&dev), "batch");
+  B3D_CHECK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "batch");
+  B3D_CHECK_HIP(batch_queue_occupancy(plan.grad, plan.lds, &occ), "batch");
+  for (size_t k = 0; k < plan.groups.size(); ++k) {
+    const BatchGroupDev& g = plan.groups[k];
+    const int blocks = (int)std::max<long long>(1, std::min<long long>((long long)cus * std::max(occ, 1), g.first[g.S]));
+    B3D_CHECK_HIP(launch_batch_queue(g, counters + 32 * k, plan.grad, plan.lds, blocks, st), "batch");
+  }
+  return B3D_OK;
+}
+
 }  // namespace b3d_api
 
 extern "C" {

@@ -62,6 +62,9 @@ b3d_status plan_batch(const std::vector<BatchItemDev>& items, bool grad, BatchPl
 // that one launch's tail overlaps the next one's start.
 b3d_status run_batch(const BatchPlan& plan, hipStream_t st, hipStream_t side = nullptr, hipEvent_t fork = nullptr,
                      hipEvent_t join = nullptr);
+// The plan's launches in order on st, each drained by a persistent grid
+// through its counter (counters: device, 256 B per launch).
+b3d_status run_batch_queue(const BatchPlan& plan, unsigned long long* counters, hipStream_t st);
 
 }  // namespace b3d_api
 

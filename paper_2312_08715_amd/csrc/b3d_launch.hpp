@@ -216,6 +216,11 @@ hipError_t launch_render_score_count(const SceneDev& s, const float* poses, int 
 
 // One workgroup per hypothesis of the group's scenes.
 hipError_t launch_batch(const BatchGroupDev& g, bool grad, size_t lds, hipStream_t st);
+// The same by `blocks` persistent workgroups draining a device counter (256
+// bytes of device memory per launch).
+hipError_t batch_queue_occupancy(bool grad, size_t lds, int* blocks_per_cu);
+hipError_t launch_batch_queue(const BatchGroupDev& g, unsigned long long* counter, bool grad, size_t lds, int blocks,
+                              hipStream_t st);
 
 // scene preparation
 hipError_t launch_fill_keys(unsigned long long* keys, size_t n, hipStream_t st);

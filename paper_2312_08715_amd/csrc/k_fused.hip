@@ -464,6 +464,63 @@ hipError_t launch_batch(const BatchGroupDev& g, bool grad, size_t lds, hipStream
   return hipGetLastError();
 }
 
+// The same work drained by a persistent grid instead: as many workgroups as
+// fit the chip, each pulling the next item from a device counter (reset by
+// a one-thread kernel, not a memset, so that launches can be captured) and
+// exiting once the counter passes the group's total.  Its loop keeps more
+// state live (some of it spills) and `work` takes static LDS, so it loses
+// where items are short, but it keeps every slot busy to the end of long
+// launches of long items.
+template <bool GRAD, int RM>
+__global__ __launch_bounds__(kBlock, 4) void k_batch_queue(const BatchGroupDev G,
+                                                           unsigned long long* __restrict__ counter) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ long long work;
+  const long long total = G.first[G.S];
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) work = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    // the same value in every lane: keep it (and the scene it selects) scalar
+    const unsigned long long wr = (unsigned long long)work;
+    const long long w = (long long)(((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(wr >> 32)) << 32) |
+                                    (unsigned)__builtin_amdgcn_readfirstlane((unsigned)wr));
+    if (w >= total) break;
+    int k = 0;
+    for (int j = 1; j < G.S; ++j) k = G.first[j] <= w ? j : k;
+    const long long n = w - G.first[k];
+    render_score_one<GRAD, false, RM>(G.s[k], G.poses[k] + 16 * n, G.logL[k] + n, GRAD ? G.grad[k] + 8 * n : nullptr,
+                                      smem);
+  }
+}
+
+__global__ void k_reset_counter(unsigned long long* c) {
+  if (threadIdx.x == 0) c[threadIdx.x] = 0ull;
+}
+
+hipError_t batch_queue_occupancy(bool grad, size_t lds, int* blocks_per_cu) {
+  // every raster variant has the same launch bounds and LDS
+  if (grad)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_queue<true, kRasterSmall>, kBlock, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_queue<false, kRasterSmall>, kBlock, lds);
+}
+
+hipError_t launch_batch_queue(const BatchGroupDev& g, unsigned long long* counter, bool grad, size_t lds, int blocks,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
+  bool big = false;
+  for (int k = 0; k < g.S; ++k) big = big || g.s[k].mesh.has_big != 0;
+  if (grad && big)
+    hipLaunchKernelGGL((k_batch_queue<true, kRasterAny>), dim3(blocks), dim3(kBlock), lds, st, g, counter);
+  else if (grad)
+    hipLaunchKernelGGL((k_batch_queue<true, kRasterSmall>), dim3(blocks), dim3(kBlock), lds, st, g, counter);
+  else if (big)
+    hipLaunchKernelGGL((k_batch_queue<false, kRasterAny>), dim3(blocks), dim3(kBlock), lds, st, g, counter);
+  else
+    hipLaunchKernelGGL((k_batch_queue<false, kRasterSmall>), dim3(blocks), dim3(kBlock), lds, st, g, counter);
+  return hipGetLastError();
+}
+
 // n_refine Adam steps on each of N poses of a scene, one workgroup per pose:
 // the fused render + score + adjoint, then the update, with the pose kept in
 // LDS between steps (the same arithmetic as render_score + adam_pose launched

@@ -111,10 +111,11 @@ struct b3d_smc {
   int rows_R = 0, n_bands = 0;
   long long scored = 0;  // hypotheses rendered and scored since the last reset
   int zcap = 0;          // depth-buffer tile of the particles' scenes, tuned on the first step
+  // one work counter per launch of a step's scoring (persistent grids: the
+  // sampler's launches are few, long and of long items)
+  unsigned long long* counters = nullptr;
+  int max_groups = 0;
   std::vector<void*> owned;
-  // a second stream for every other scoring launch (see run_batch)
-  hipStream_t side = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 // Whole-image logL of each particle's scene with its proposed object at
@@ -269,10 +270,6 @@ b3d_status b3d_smc_create(const b3d_mesh* const* types, int32_t n_types, const b
   S->p = *p;
   S->table = *table;
   S->K = *K;
-  if (hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&S->fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&S->join, hipEventDisableTiming) != hipSuccess)
-    return bail(fail(B3D_EHIP, "smc_create: stream or event creation failed"));
   S->types.assign(types, types + n_types);
   if (n_fixed > 0) {
     S->fixed.assign(fixed, fixed + n_fixed);
@@ -329,6 +326,8 @@ b3d_status b3d_smc_create(const b3d_mesh* const* types, int32_t n_types, const b
     S->n_bands = (K->H + S->rows_R - 1) / S->rows_R;
     if ((s = dev_alloc(S->owned, &S->partial, (size_t)M * S->n_bands * kMaxNoise))) return bail(s);
   }
+  S->max_groups = (M * n_types + kBatchGroup - 1) / kBatchGroup;
+  if ((s = dev_alloc(S->owned, &S->counters, 32 * (size_t)S->max_groups))) return bail(s);
   // the root cells (every type and face: dx, dy over the table less the
   // footprint, dth over a full turn) and the stage-0 hypotheses, the same
   // for every particle
@@ -490,7 +489,7 @@ b3d_status b3d_smc_step(b3d_smc* S, void* stream) {
                                      S->logL_h + (size_t)m * N0 + (size_t)o * 6 * n0, nullptr});
   BatchPlan plan;
   if (b3d_status s = plan_batch(items, false, &plan)) return s;
-  if (b3d_status s = run_batch(plan, st, S->side, S->fork, S->join)) return s;
+  if (b3d_status s = run_batch_queue(plan, S->counters, st)) return s;
   for (const BatchItemDev& it : items) S->scored += it.N;
   for (int m = 0; m < M; ++m)
     if (rep[m] != m)
@@ -522,7 +521,7 @@ b3d_status b3d_smc_step(b3d_smc* S, void* stream) {
       items.push_back(BatchItemDev{scene_of(m, type_of[m]), S->hyp + 16 * (size_t)m * ns, ns,
                                    S->logL_h + (size_t)m * ns, nullptr});
     if (b3d_status s = plan_batch(items, false, &plan)) return s;
-    if (b3d_status s = run_batch(plan, st, S->side, S->fork, S->join)) return s;
+    if (b3d_status s = run_batch_queue(plan, S->counters, st)) return s;
     S->scored += (long long)M * ns;
     B3D_CHECK_HIP(launch_sample(S->logL_h, M, ns, 1, key0, key1, ((uint32_t)i << 8) | (uint32_t)t, 0u, nullptr, S->idx,
                                 S->logw, st),
@@ -591,9 +590,6 @@ b3d_status b3d_smc_destroy(b3d_smc* S) {
   (void)hipDeviceSynchronize();
   for (b3d_scene* sc : S->scenes) b3d_scene_destroy(sc);
   for (void* q : S->owned) (void)hipFree(q);
-  if (S->fork) (void)hipEventDestroy(S->fork);
-  if (S->join) (void)hipEventDestroy(S->join);
-  if (S->side) (void)hipStreamDestroy(S->side);
   delete S;
   return B3D_OK;
 }
