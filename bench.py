@@ -46,7 +46,7 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
 # what the same counters read for a plain 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0).  Valid only for the kernel sources with this digest:
 # after any change to them the figure is reported as null until re-measured.
-TRAFFIC = {"sources_sha256": "a64e1c6fa1d269932465275b3ca8e0d59ae073ed2d922c87d9b579f5daf3a85e", "fetch_KiB": 6367.0, "write_KiB": 312.5, "fetch_scale": 2.0, "write_scale": 1.0}
+TRAFFIC = {"sources_sha256": "ce08f47d0ce432358e6a3b22e16b36a108ba208fff0368fc4fdc81cb7b2edd06", "fetch_KiB": 6369.7, "write_KiB": 312.5, "fetch_scale": 2.0, "write_scale": 1.0}
 KERNEL_SOURCES = ["k_fused.hip", "b3d_device.hpp", "b3d_launch.hpp"]
 
 
@@ -718,10 +718,10 @@ SPLIT_BYTES_PER_DRAWN = {"render_backward": 12}
 # dispatch, mean over the run's dispatches); valid for the sources with this
 # digest only.
 SPLIT_SOURCES = ["k_render.hip", "k_score.hip", "b3d_device.hpp", "b3d_launch.hpp"]
-SPLIT_TRAFFIC = {"sources_sha256": "ddc4d3f2b783fa5f3a7e74d06fcec8310531ef64b88fc6f8b9dea19b65e6273a",
-                 "KiB": {"render_batch": [38183.2, 1125962.9], "render_batch_ids": [43822.4, 1500885.2],
-                         "score": [563817.6, 166.5], "score_backward": [565336.5, 1126033.3],
-                         "render_backward": [244243.2, 234.4]}}
+SPLIT_TRAFFIC = {"sources_sha256": "47fa578138c9ed91af9b40bb4f7f1616b029f8a663451880d268f717caf8b526",
+                 "KiB": {"render_batch": [39210.7, 1125996.8], "render_batch_ids": [44446.1, 1500873.9],
+                         "score": [563817.4, 166.4], "score_backward": [565346.4, 1126030.5],
+                         "render_backward": [244248.0, 234.4]}}
 
 
 def split_sources_digest() -> str:

@@ -581,14 +581,13 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
             staged = true;
             n_cent = 0;
           }
-          int rn = r0, cn = c0;
-          for (int k = 0; k < n_cent; ++k) {
-            const int r = rn, col = cn;
-            if (++cn > c1) {
-              cn = c0;
-              ++rn;
-            }
-            const float dr = (float)(r - r0), dc = (float)(col - c0);
+          // the offsets from the box's first centre as exact small floats,
+          // stepped along the row and wrapped to the next one
+          const float dcmax = (float)(c1 - c0), drmax = n_cent > 0 ? (float)(r1 - r0) : -1.0f;
+          float dr = 0.0f, dc = 0.0f;
+          while (dr <= drmax) {
+            const float drn = dc < dcmax ? dr : dr + 1.0f;
+            const float dcn = dc < dcmax ? dc + 1.0f : 0.0f;
             const float w0 = __builtin_fmaf(-e0y, dc, __builtin_fmaf(e0x, dr, w0b));
             const float w1 = __builtin_fmaf(-e1y, dc, __builtin_fmaf(e1x, dr, w1b));
             const float w2 = __builtin_fmaf(-e2y, dc, __builtin_fmaf(e2x, dr, w2b));
@@ -596,7 +595,11 @@ __device__ __forceinline__ void raster_mesh(const MeshDev& m, const Pose& P, con
             const float v1 = __builtin_fmaf(-f1y, dc, __builtin_fmaf(f1x, dr, v1b));
             const bool out1 = !act1 || w0 > t0 || w1 > t1 || w2 > t2;
             const bool out2 = !act2 || v0 > s0 || v1 > s1 || -w1 > t1;
+            const float drc = dr, dcc = dc;
+            dr = drn;
+            dc = dcn;
             if (out1 && out2) continue;  // clearly outside both
+            const int r = r0 + (int)drc, col = c0 + (int)dcc;
             const int pix = (r - buf.y0) * pitch + (col - buf.x0);
             if (!out1)
               emit_centre<COUNT>(pix, eon1, w0, w1, w2, t0, t1, t2, A.w, B.w, C.w, ia1, ids.x, id_base, zbuf, lds,
