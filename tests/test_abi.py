@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -101,6 +102,18 @@ def test_host_side_validation_without_a_device(lib):
     assert b.grid_size(g) == 60
     g.count[1] = 0
     assert b.grid_size(g) == 0
+    # the tracker's occlusion settings are checked before anything is allocated
+    g.count[1] = 4
+    stages = (b.Grid * b.B3D_MAX_STAGES)(g)
+    fake_meshes = (ctypes.c_void_p * 1)(16)
+    P0 = np.eye(4, dtype=np.float32).reshape(16)
+    out = ctypes.c_void_p()
+    for mv, wd, why in ((1.5, 2.0, b"min_visible"), (-0.1, 2.0, b"min_visible"), (0.2, 0.5, b"widen")):
+        tp = b.TrackParams(1, stages, 0, 1e-3, 1e-2, 0.9, 0.999, 1e-8, mv, wd)
+        rc = lib.b3d_tracker_create(fake_meshes, 1, ctypes.byref(K), ctypes.byref(ok), ctypes.byref(tp),
+                                    P0.ctypes.data, ctypes.byref(out))
+        assert rc == -1 and why in lib.b3d_last_error(), (mv, wd, lib.b3d_last_error())
+    assert lib.b3d_tracker_state(None, None, None) == -1
 
 
 def test_mesh_layout_sets_aside_only_faces_no_outside_camera_sees(lib):
