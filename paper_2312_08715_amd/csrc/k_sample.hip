@@ -107,42 +107,46 @@ hipError_t launch_enumerate(const GridDev& g, const float* centres, int P, uint3
   return hipGetLastError();
 }
 
-// Block (p, k): logsumexp of segment p and its draw k by Gumbel-max.
-__global__ __launch_bounds__(kBlock) void k_sample(const float* __restrict__ logL, int P, int N, int K, uint32_t k0,
-                                                   uint32_t k1, uint32_t stage, uint32_t kbase, float* __restrict__ w,
-                                                   int* __restrict__ idx, float* __restrict__ logw) {
-  __shared__ float rv[kWaves];
-  __shared__ int ri[kWaves];
-  __shared__ float red[kWaves];
+// Block (p, k): logsumexp of segment p and its draw k by Gumbel-max, BS
+// threads (each block reads its segment three times; a draw is one block, so
+// long segments take the larger block to cut each thread's serial share).
+template <int BS>
+__global__ __launch_bounds__(BS) void k_sample(const float* __restrict__ logL, int P, int N, int K, uint32_t k0,
+                                               uint32_t k1, uint32_t stage, uint32_t kbase, float* __restrict__ w,
+                                               int* __restrict__ idx, float* __restrict__ logw) {
+  constexpr int NW = BS / 64;
+  __shared__ float rv[NW];
+  __shared__ int ri[NW];
+  __shared__ float red[NW];
   const int blk = blockIdx.x;
   const int p = blk / K, k = blk - p * K;
   const float* L = logL + (size_t)p * N;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // max
   float m = -INFINITY;
-  for (int n = threadIdx.x; n < N; n += kBlock) m = fmaxf(m, L[n]);
+  for (int n = threadIdx.x; n < N; n += BS) m = fmaxf(m, L[n]);
   for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
   if (lane == 0) red[wave] = m;
   __syncthreads();
   m = red[0];
-  for (int i = 1; i < kWaves; ++i) m = fmaxf(m, red[i]);
+  for (int i = 1; i < NW; ++i) m = fmaxf(m, red[i]);
   __syncthreads();
   // sum of exp(l - m), fixed order
   float s = 0.0f;
-  for (int n = threadIdx.x; n < N; n += kBlock) s += expf(L[n] - m);
+  for (int n = threadIdx.x; n < N; n += BS) s += expf(L[n] - m);
   s = wave_sum(s);
   if (lane == 0) red[wave] = s;
   __syncthreads();
   s = red[0];
-  for (int i = 1; i < kWaves; ++i) s += red[i];
+  for (int i = 1; i < NW; ++i) s += red[i];
   const float lse = m + logf(s);
   if (k == 0 && w)
-    for (int n = threadIdx.x; n < N; n += kBlock) w[(size_t)p * N + n] = expf(L[n] - lse);
+    for (int n = threadIdx.x; n < N; n += BS) w[(size_t)p * N + n] = expf(L[n] - lse);
   // argmax of l + G, ties to the lowest index
   const uint32_t draw = kbase + (uint32_t)(p * K + k);
   float bv = -INFINITY;
   int bi = -1;
-  for (int n = threadIdx.x; n < N; n += kBlock) {
+  for (int n = threadIdx.x; n < N; n += BS) {
     U4 c = {(uint32_t)n, draw, stage, 0u};
     const float u = to_unit(philox4x32_10(c, k0, k1).x);
     const float v = L[n] - logf(-logf(u));
@@ -167,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(const float* __restrict__ log
   if (threadIdx.x == 0) {
     bv = rv[0];
     bi = ri[0];
-    for (int i = 1; i < kWaves; ++i)
+    for (int i = 1; i < NW; ++i)
       if (ri[i] >= 0 && (bi < 0 || rv[i] > bv || (rv[i] == bv && ri[i] < bi))) {
         bv = rv[i];
         bi = ri[i];
@@ -179,7 +183,12 @@ __global__ __launch_bounds__(kBlock) void k_sample(const float* __restrict__ log
 
 hipError_t launch_sample(const float* logL, int P, int N, int K, uint32_t key0, uint32_t key1, uint32_t stage,
                          uint32_t k0, float* w, int* idx, float* logw, hipStream_t st) {
-  hipLaunchKernelGGL(k_sample, dim3(P * K), dim3(kBlock), 0, st, logL, P, N, K, key0, key1, stage, k0, w, idx, logw);
+  if (N > 2048)
+    hipLaunchKernelGGL(k_sample<1024>, dim3(P * K), dim3(1024), 0, st, logL, P, N, K, key0, key1, stage, k0, w, idx,
+                       logw);
+  else
+    hipLaunchKernelGGL(k_sample<kBlock>, dim3(P * K), dim3(kBlock), 0, st, logL, P, N, K, key0, key1, stage, k0, w,
+                       idx, logw);
   return hipGetLastError();
 }
 
