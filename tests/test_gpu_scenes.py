@@ -472,3 +472,35 @@ def test_tracker_occlusion_handling_follows_the_oracle(b3d):
         say(f"  frame {f}: seen {np.round(st[:, 0], 3).tolist()}, dropped {st[:, 1].astype(int).tolist()}, "
             f"position errors (cm) {np.round(err, 2).tolist()}")
     assert dropped_frames and reacquired, f"dropped at {dropped_frames}, re-acquired {reacquired}"
+
+
+def test_tracker_occlusion_handling_graph_equals_eager(b3d):
+    # The occlusion handling inside the captured frame graph (stage-0 scale
+    # read from device memory, the seen-fraction decision, the kept motion):
+    # two trackers from the same start, one replaying its graph and one
+    # issuing the frame's launches directly, agree bit for bit on every
+    # frame's poses and occlusion state, drops included.
+    from workloads import GridSpec
+
+    meshes, paths, cam, frames = occlusion_sequence()
+    specs = [GridSpec(center=np.eye(4), half_extent=(0.04, 0.04, 0.04), count=(4, 4, 4), n_rot=4,
+                      rot_max_angle=np.deg2rad(6.0)),
+             GridSpec(center=np.eye(4), half_extent=(0.01, 0.01, 0.01), count=(3, 3, 3), n_rot=4,
+                      rot_max_angle=np.deg2rad(2.0))]
+    ms = [b3d.Mesh(v, t) for v, t in meshes]
+    mk = lambda: b3d.Tracker(ms, b3d.intrinsics_of(cam), b3d.score_params(0.003, 0.01, 1.0, 5),
+                             [b3d.grid_of(g)[0] for g in specs], f32(paths[0]), n_refine=2, min_visible=0.3,
+                             widen=2.0)
+    tg, te = mk(), mk()
+    drops = 0
+    for f in range(1, len(frames)):
+        o = dev(frames[f])
+        tg.frame(o)
+        te.frame(o, eager=True)
+        pg, pe = tg.poses(), te.poses()
+        sg, se = tg.state(), te.state()
+        torch.cuda.synchronize()
+        assert torch.equal(pg, pe) and torch.equal(sg, se), f"frame {f}"
+        drops += int((sg[:, 1] > 0).sum())
+    say(f"tracker with occlusion handling: graph equals eager over {len(frames) - 1} frames ({drops} drops)")
+    assert drops > 0
