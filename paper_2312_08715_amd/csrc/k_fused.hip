@@ -136,6 +136,25 @@ __device__ __forceinline__ float window_grad(const float* __restrict__ wbuf, int
   float g = 0.0f;
   if (HH > 0) {
     constexpr int n = 2 * HH + 1;
+    if (r - HH >= wa && r + HH < wb && c - HH >= region.x0 && c + HH < region.x1) {
+      // the whole window inside the weights' rows and the region's columns
+      // (every pixel away from the image border): no clamping, one address
+      // per window row; the same terms in the same order as below
+      const float* wr = wbuf + (r - HH - wa) * rw + (c - HH - region.x0);
+      const float* orow = obs + 3 * ((size_t)(r - HH) * W + (c - HH));
+#pragma unroll 1
+      for (int j = 0; j < n; ++j, wr += rw, orow += 3 * (size_t)W) {
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+          const float wv = wr[k];
+          const float* q = orow + 3 * k;
+          const float ex = q[0] - qx, ey = q[1] - qy, ez = q[2] - qz;
+          const float e = f_exp2(-(ex * ex + ey * ey + ez * ez) * c2);
+          g += wv * e * __builtin_fmaf(ex, dx, __builtin_fmaf(ey, dy, ez));
+        }
+      }
+      return g;
+    }
     int cc[n];
     bool cv[n];
 #pragma unroll
@@ -178,6 +197,16 @@ __device__ __forceinline__ float window_grad(const float* __restrict__ wbuf, int
   return g;
 }
 
+// Row r and column c of slot k (0 <= k < 2^20) of a rectangle of width w,
+// given inv_w = 1/w correctly rounded: (k + 1/2) inv_w is formed with one
+// rounding, a relative error below 2^-22, so it lies within 1/(4w) of
+// (k + 1/2)/w, whose fractional part is in [1/(2w), 1 - 1/(2w)]: truncating it
+// gives floor(k/w) exactly, with no integer division.
+__device__ __forceinline__ void row_col(int k, int w, float inv_w, int& r, int& c) {
+  r = (int)__builtin_fmaf((float)k, inv_w, 0.5f * inv_w);
+  c = k - __mul24(r, w);
+}
+
 // First local index k >= 0 with (base + k) mod kBlock == t.
 __device__ __forceinline__ int first_of(unsigned t, int base) {
   return ((int)t - base % kBlock + kBlock) % kBlock;
@@ -193,8 +222,12 @@ __device__ __forceinline__ void raster_band(const SceneDev& s, const Pose& P, co
   const Cam& cam = s.cam;
   const int H = cam.H, W = cam.W, lw = L.w();
   const int nk = L.h() * lw;
+  const float inv_lw = 1.0f / (float)lw;
   for (int k = threadIdx.x; k < nk; k += kBlock) {
-    const int r = L.y0 + k / lw, c = L.x0 + (k - (k / lw) * lw);
+    int r, c;
+    row_col(k, lw, inv_lw, r, c);
+    r += L.y0;
+    c += L.x0;
     const bool in = r >= 0 && r < H && c >= 0 && c < W;
     zbuf[k] = (in && s.bg) ? s.bg[(size_t)r * W + c] : kEmptyKey;
   }
@@ -207,8 +240,9 @@ __device__ __forceinline__ void raster_band(const SceneDev& s, const Pose& P, co
   for (int k = threadIdx.x; k < nr; k += kBlock) {
     const int off = rlist[k];
     const unsigned long long key = zbuf[off];
-    const int r = L.y0 + off / lw, c = L.x0 + (off - (off / lw) * lw);
-    zbuf[off] = pack_key(plane_depth(s.mesh, P, cam, key_id(key), r, c), key_id(key));
+    int r, c;
+    row_col(off, lw, inv_lw, r, c);
+    zbuf[off] = pack_key(plane_depth(s.mesh, P, cam, key_id(key), L.y0 + r, L.x0 + c), key_id(key));
   }
   __syncthreads();
 }
@@ -272,8 +306,12 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
       // pixel g of the region (row-major from its corner) always goes to
       // thread g mod kBlock, so every thread adds its terms in the same order
       // however the rows are banded: results do not depend on the band height
+      const float inv_rw = 1.0f / (float)rw;
       for (int k = first_of(threadIdx.x, (wa - region.y0) * rw); k < nw; k += kBlock) {
-        const int r = wa + k / rw, c = region.x0 + (k - (k / rw) * rw);
+        int r, c;
+        row_col(k, rw, inv_rw, r, c);
+        r += wa;
+        c += region.x0;
         const float* q = s.obs + 3 * ((size_t)r * W + c);
         const float ox = q[0], oy = q[1], oz = q[2];
         float wv = 0.0f;
@@ -345,6 +383,7 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
         // order does not depend on banding
         const int ga = max(a, obj.y0), gb = min(b, obj.y1);
         const int ng = max(gb - ga, 0) * ow;
+        const float inv_ow = 1.0f / (float)ow;
         unsigned short* glist = reinterpret_cast<unsigned short*>(smem + 4 * nw);
         const int gcap = ((int)kRasterLdsBytes - 4 * nw) / 2;
         for (int pos = 0; pos < ng;) {
@@ -354,14 +393,19 @@ __device__ __forceinline__ void render_score_one(const SceneDev& s, const float*
             const int k = pos + (int)threadIdx.x;
             bool d = false;
             if (k < ng) {
-              const int r = ga + k / ow, c = obj.x0 + (k - (k / ow) * ow);
+              int r, c;
+              row_col(k, ow, inv_ow, r, c);
+              r += ga;
+              c += obj.x0;
               d = key_id(zbuf[(r - L.y0) * lw + (c - L.x0)]) < (uint32_t)s.mesh.T;
             }
             n += append_flagged(d, k, glist, n, reinterpret_cast<int*>(red));
           }
           for (int i = first_of(threadIdx.x, gcarry); i < n; i += kBlock) {
-            const int k = glist[i];
-            const int r = ga + k / ow, c = obj.x0 + (k - (k / ow) * ow);
+            int r, c;
+            row_col(glist[i], ow, inv_ow, r, c);
+            r += ga;
+            c += obj.x0;
             gather(r, c, zbuf[(r - L.y0) * lw + (c - L.x0)]);
           }
           gcarry += n;
@@ -706,8 +750,12 @@ __device__ __forceinline__ void render_score_grid_one(const SceneDev& s, const N
       raster_band<false>(s, P, L, zbuf, smem, red, nullptr);
       const int nw = (b - a) * rw;
       // observed pixel g of the region always goes to thread g mod kBlock
+      const float inv_rw = 1.0f / (float)rw;
       for (int k = first_of(threadIdx.x, (a - region.y0) * rw); k < nw; k += kBlock) {
-        const int r = a + k / rw, c = region.x0 + (k - (k / rw) * rw);
+        int r, c;
+        row_col(k, rw, inv_rw, r, c);
+        r += a;
+        c += region.x0;
         const float* q = s.obs + 3 * ((size_t)r * W + c);
         const float ox = q[0], oy = q[1], oz = q[2];
         if (!(oz > 0.0f)) continue;
