@@ -16,6 +16,7 @@
 // When the rectangle does not fit the LDS budget it is processed in bands of
 // rows, re-rasterising per band.
 #include "b3d_launch.hpp"
+#include <type_traits>
 
 namespace b3d {
 
@@ -652,8 +653,9 @@ hipError_t launch_refine_banded(const SceneDev& s, float* pose, int n_refine, fl
 // Window sums under each deviation of a noise grid: S[a] = sum_j
 // exp(-D_ij c2[a]) over the rendered points of the window of observed point
 // (ox, oy, oz) at pixel (r, c) (as window_sums, with each distance computed
-// once).
-template <int HH>
+// once).  NA > 0: the grid's number of deviations known at compile time (no
+// exponential for the unused ones); NA = 0: any number up to kMaxSigma.
+template <int HH, int NA>
 __device__ __forceinline__ void window_sums_grid(const unsigned long long* __restrict__ zbuf, const Rect& L, int lw,
                                                  const float* __restrict__ dxt, const float* __restrict__ dyt, int r,
                                                  int c, int h, float ox, float oy, float oz, const NoiseGridDev& g,
@@ -662,8 +664,8 @@ __device__ __forceinline__ void window_sums_grid(const unsigned long long* __res
   for (int a = 0; a < kMaxSigma; ++a) S[a] = 0.0f;
   auto add = [&](float D) {
 #pragma unroll
-    for (int a = 0; a < kMaxSigma; ++a)
-      if (a < g.A) S[a] += f_exp2(-D * g.c2[a]);
+    for (int a = 0; a < (NA > 0 ? NA : kMaxSigma); ++a)
+      if (NA > 0 || a < g.A) S[a] += f_exp2(-D * g.c2[a]);
   };
   if (HH > 0) {
     constexpr int n = 2 * HH + 1;
@@ -749,33 +751,53 @@ __device__ __forceinline__ void render_score_grid_one(const SceneDev& s, const N
       L.y1 = b + 2 * h;
       raster_band<false>(s, P, L, zbuf, smem, red, nullptr);
       const int nw = (b - a) * rw;
-      // observed pixel g of the region always goes to thread g mod kBlock
+      // observed pixel g of the region always goes to thread g mod kBlock;
+      // na: the grid's number of deviations as a compile-time constant (0: any)
       const float inv_rw = 1.0f / (float)rw;
-      for (int k = first_of(threadIdx.x, (a - region.y0) * rw); k < nw; k += kBlock) {
-        int r, c;
-        row_col(k, rw, inv_rw, r, c);
-        r += a;
-        c += region.x0;
-        const float* q = s.obs + 3 * ((size_t)r * W + c);
-        const float ox = q[0], oy = q[1], oz = q[2];
-        if (!(oz > 0.0f)) continue;
-        float S[kMaxSigma];
-        switch (h) {
-          case 1:
-            window_sums_grid<1>(zbuf, L, lw, dxt, dyt, r, c, h, ox, oy, oz, g, S);
-            break;
-          case 2:
-            window_sums_grid<2>(zbuf, L, lw, dxt, dyt, r, c, h, ox, oy, oz, g, S);
-            break;
-          default:
-            window_sums_grid<0>(zbuf, L, lw, dxt, dyt, r, c, h, ox, oy, oz, g, S);
+      auto pixels = [&](auto na) {
+        constexpr int NA = decltype(na)::value;
+        for (int k = first_of(threadIdx.x, (a - region.y0) * rw); k < nw; k += kBlock) {
+          int r, c;
+          row_col(k, rw, inv_rw, r, c);
+          r += a;
+          c += region.x0;
+          const float* q = s.obs + 3 * ((size_t)r * W + c);
+          const float ox = q[0], oy = q[1], oz = q[2];
+          if (!(oz > 0.0f)) continue;
+          float S[kMaxSigma];
+          switch (h) {
+            case 1:
+              window_sums_grid<1, NA>(zbuf, L, lw, dxt, dyt, r, c, h, ox, oy, oz, g, S);
+              break;
+            case 2:
+              window_sums_grid<2, NA>(zbuf, L, lw, dxt, dyt, r, c, h, ox, oy, oz, g, S);
+              break;
+            default:
+              window_sums_grid<0, NA>(zbuf, L, lw, dxt, dyt, r, c, h, ox, oy, oz, g, S);
+          }
+#pragma unroll
+          for (int ai = 0; ai < (NA > 0 ? NA : kMaxSigma); ++ai)
+            if (NA > 0 || ai < g.A) sbuf[ai * kBlock + threadIdx.x] = S[ai] * g.normM[ai];
+#pragma unroll
+          for (int kk = 0; kk < kMaxNoise; ++kk)
+            if (kk < nk_grid) acc[kk] += f_ln(g.pa[kk] + g.pomp[kk] * sbuf[g.ka[kk] * kBlock + threadIdx.x]);
         }
-#pragma unroll
-        for (int ai = 0; ai < kMaxSigma; ++ai)
-          if (ai < g.A) sbuf[ai * kBlock + threadIdx.x] = S[ai] * g.normM[ai];
-#pragma unroll
-        for (int kk = 0; kk < kMaxNoise; ++kk)
-          if (kk < nk_grid) acc[kk] += f_ln(g.pa[kk] + g.pomp[kk] * sbuf[g.ka[kk] * kBlock + threadIdx.x]);
+      };
+      switch (g.A) {
+        case 1:
+          pixels(std::integral_constant<int, 1>{});
+          break;
+        case 2:
+          pixels(std::integral_constant<int, 2>{});
+          break;
+        case 3:
+          pixels(std::integral_constant<int, 3>{});
+          break;
+        case 4:
+          pixels(std::integral_constant<int, 4>{});
+          break;
+        default:
+          pixels(std::integral_constant<int, 0>{});
       }
       __syncthreads();
     }
