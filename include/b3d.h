@@ -128,7 +128,9 @@ b3d_status b3d_render_batch(const b3d_mesh* mesh, const float* poses, int32_t N,
 b3d_status b3d_score_workspace_size(int32_t H, int32_t W, size_t* bytes);
 
 /* Windowed robust likelihood (eq. (1) with the window of Sec. III-B).
- * observed: device float[H][W][3]; rendered: device float[N][H][W][3];
+ * observed: device float[H][W][3] (a pixel with z <= 0 holds no observation
+ * and adds no term; every value must be finite); rendered: device
+ * float[N][H][W][3] (z <= 0: empty);
  * logL_out: device float[N].  workspace: device memory of at least
  * b3d_score_workspace_size bytes, 16-byte aligned, owned by the caller
  * (contents undefined on return), or NULL: the same result from a kernel
@@ -190,7 +192,8 @@ b3d_status b3d_scene_set_background(b3d_scene* scene, const b3d_mesh* const* mes
 
 /* Point the scene at an observed image (device float[H][W][3], caller-owned,
  * read by later b3d_render_score calls; keep it alive and unchanged while
- * they run) and precompute the per-pixel terms of the background.  Call it
+ * they run; pixels with z <= 0 hold no observation, every value finite) and
+ * precompute the per-pixel terms of the background.  Call it
  * again whenever the image's contents or the background change.
  * Stream-ordered. */
 b3d_status b3d_scene_set_observed(b3d_scene* scene, const float* observed, void* stream);
