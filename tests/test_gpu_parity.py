@@ -308,6 +308,44 @@ def test_fused_adjoint_matches_oracle(b3d, k):
         assert abs(G[n, 7] - dp[n]) <= 1e-4 * abs(dp[n]) + 1e-3
 
 
+def test_fused_adjoint_at_the_image_border_matches_oracle(b3d):
+    # objects straddling each edge and corner of the image: the gather of
+    # d logL / d z then clips its window at the border (the clamped path)
+    wl, obs, P = workload(0)
+    cam = wl.camera
+    Q = []
+    for n, (u, v) in enumerate([(1.0, cam.cy), (cam.W - 1.0, cam.cy), (cam.cx, 1.0), (cam.cx, cam.H - 1.0),
+                                 (0.0, 0.0), (cam.W, cam.H)]):
+        q = P[(37 * n) % P.shape[0]].copy()
+        z = q[2, 3]
+        q[0, 3] = (u - cam.cx) * z / cam.fx
+        q[1, 3] = (v - cam.cy) * z / cam.fy
+        Q.append(q)
+    Q = f32(np.stack(Q))
+    say(f"fused adjoint at the border: {len(Q)} hypotheses")
+    scene, mesh, o = _scene(b3d, wl, obs)
+    logL, G = b3d.render_score(scene, dev(Q), grad=True)
+    G = G.cpu().numpy()
+    xyz, tri = b3d.render_batch(mesh, dev(Q), b3d.intrinsics_of(cam))
+    s = wl.score
+    od, oi = oracle.render([(wl.verts, wl.tris, Q)], cam)
+    # every pose leaves part of the object outside the image and part inside
+    drawn = (oi >= 0).reshape(len(Q), -1).sum(1)
+    assert np.all(drawn > 0), drawn
+    rend = oracle.unproject(od, cam)
+    L64, l1 = oracle.score(obs, rend, s.sigma, s.p_out, s.outlier_volume, s.window)
+    dr, ds, dp = oracle.score_grad(obs, rend, s.sigma, s.p_out, s.outlier_volume, s.window)
+    gp = oracle.render_grad(wl.verts, wl.tris, Q, cam, oi, od, dr)
+    clean = clean_hypotheses(xyz[..., 2].cpu().numpy(), tri.cpu().numpy(), od, oi)
+    say(f"  clean {clean.sum()} of {len(Q)}; drawn pixels {drawn.tolist()}")
+    assert clean.sum() >= len(Q) - 1
+    assert np.max((np.abs(logL.cpu().numpy() - L64) / l1)[clean]) <= LOGL_RTOL
+    for n in np.nonzero(clean)[0]:
+        assert np.linalg.norm(G[n, :6] - gp[n]) <= 1e-3 * np.linalg.norm(gp[n]) + 1e-6, (n, G[n, :6], gp[n])
+        assert abs(G[n, 6] - ds[n]) <= 1e-3 * abs(ds[n]) + 1e-3
+        assert abs(G[n, 7] - dp[n]) <= 1e-4 * abs(dp[n]) + 1e-3
+
+
 def test_enumerate_matches_oracle(b3d):
     wl, _, _ = workload(1)
     g, rots = b3d.grid_of(wl.grid)
